@@ -1,0 +1,211 @@
+"""FP64 CPU oracle for the MDLG hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It wraps the plain C oracle
+(``mdlg_oracle.c``) with numpy arrays and re-exports the closed forms of
+``closed_form``.  It shares no code with the HIP path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import closed_form  # noqa: F401  (re-export)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liborc_mdlg.so")
+_lib = None
+
+
+class OrcMD(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int), ("box", C.c_double * 3),
+                ("eps", C.c_double), ("sigma", C.c_double), ("mass", C.c_double),
+                ("rc", C.c_double), ("forces_off", C.c_int), ("dt", C.c_double)]
+
+
+class OrcLattice(C.Structure):
+    _fields_ = [("M", C.c_int * 3), ("dx", C.c_double), ("V", C.c_int)]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from .build import build
+        build()
+    lib = C.CDLL(_LIB_PATH)
+    P = C.POINTER
+    dp, ip, up, lp = P(C.c_double), P(C.c_int32), P(C.c_uint64), P(C.c_int64)
+    lib.orc_lj_potential.restype = C.c_double
+    lib.orc_lj_potential.argtypes = [C.c_double, C.c_double, C.c_double]
+    lib.orc_lj_force_over_r.restype = C.c_double
+    lib.orc_lj_force_over_r.argtypes = [C.c_double, C.c_double, C.c_double]
+    for name in ("orc_forces_brute", "orc_forces_cells"):
+        f = getattr(lib, name)
+        f.restype = C.c_int
+        f.argtypes = [P(OrcMD), dp, dp, dp]
+    lib.orc_vv.restype = C.c_int
+    lib.orc_vv.argtypes = [P(OrcMD), dp, ip, dp, dp, C.c_long, P(C.c_long), C.c_int,
+                           C.c_double, C.c_int]
+    lib.orc_equilibrate.restype = C.c_int
+    lib.orc_equilibrate.argtypes = lib.orc_vv.argtypes
+    lib.orc_num_moments.restype = C.c_int
+    lib.orc_num_moments.argtypes = [C.c_int]
+    lib.orc_bin.restype = C.c_int
+    lib.orc_bin.argtypes = [P(OrcLattice), C.c_int, C.c_int, dp, dp, up, lp, dp, dp]
+    lib.orc_ni_literal.restype = C.c_int
+    lib.orc_ni_literal.argtypes = [P(OrcLattice), C.c_int, C.c_int, dp, dp, up]
+    lib.orc_mdlg_run.restype = C.c_int
+    lib.orc_mdlg_run.argtypes = [P(OrcMD), P(OrcLattice), C.c_int, C.c_long, dp, ip, dp,
+                                 dp, P(C.c_long), C.c_int, up, lp, dp, dp, up]
+    lib.orc_kinetics.restype = None
+    lib.orc_kinetics.argtypes = [P(OrcMD), dp, dp, dp]
+    _lib = lib
+    return lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _up(a):
+    return a.ctypes.data_as(C.POINTER(C.c_uint64))
+
+
+def _lp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+
+
+def num_moments(dim):
+    return int(_load().orc_num_moments(dim))
+
+
+def lj_potential(r, eps=1.0, sigma=1.0):
+    return float(_load().orc_lj_potential(float(r), eps, sigma))
+
+
+def lj_force_over_r(r, eps=1.0, sigma=1.0):
+    return float(_load().orc_lj_force_over_r(float(r), eps, sigma))
+
+
+def make_md(dim, n, box, eps=1.0, sigma=1.0, mass=1.0, rc=2.5, dt=0.005, forces_off=False):
+    p = OrcMD()
+    p.dim = dim
+    p.n = n
+    b = np.broadcast_to(np.asarray(box, dtype=np.float64), (dim,))
+    for a in range(3):
+        p.box[a] = float(b[a]) if a < dim else 1.0
+    p.eps, p.sigma, p.mass, p.rc, p.dt = eps, sigma, mass, rc, dt
+    p.forces_off = int(bool(forces_off))
+    return p
+
+
+def make_lattice(dim, M, dx, vmax):
+    L = OrcLattice()
+    m = np.broadcast_to(np.asarray(M, dtype=np.int64), (dim,))
+    for a in range(3):
+        L.M[a] = int(m[a]) if a < dim else 1
+    L.dx = float(dx)
+    L.V = int(vmax)
+    return L
+
+
+def forces(md, x, brute=False):
+    """Accelerations a_i = F_i / m (FP64) and the shifted potential energy."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    acc = np.zeros_like(x)
+    ep = C.c_double(0.0)
+    f = _load().orc_forces_brute if brute else _load().orc_forces_cells
+    _check(f(C.byref(md), _dp(x), _dp(acc), C.byref(ep)), "forces")
+    return acc, ep.value
+
+
+class OracleState:
+    """Particle state of the FP64 oracle: wrapped positions in [0, L), image
+    counters, velocities and the accelerations at the current positions."""
+
+    def __init__(self, md, pos, vel, img=None, use_cells=True):
+        self.md = md
+        self.use_cells = int(bool(use_cells))
+        self.x = np.ascontiguousarray(pos, dtype=np.float64).copy()
+        self.v = np.ascontiguousarray(vel, dtype=np.float64).copy()
+        self.img = (np.zeros(self.x.shape, dtype=np.int32) if img is None
+                    else np.ascontiguousarray(img, dtype=np.int32).copy())
+        self.step = C.c_long(0)
+        self.acc, _ = forces(md, self.x, brute=not use_cells)
+
+    @property
+    def unwrapped(self):
+        box = np.array([self.md.box[a] for a in range(self.md.dim)])
+        return self.x + self.img * box
+
+    def run(self, nsteps, thermo_every=0, kT=0.0):
+        _check(_load().orc_vv(C.byref(self.md), _dp(self.x), _ip(self.img), _dp(self.v),
+                              _dp(self.acc), int(nsteps), C.byref(self.step),
+                              int(thermo_every), float(kT), self.use_cells), "vv")
+
+    def kinetics(self):
+        ke = C.c_double(0.0)
+        mom = np.zeros(3)
+        _load().orc_kinetics(C.byref(self.md), _dp(self.v), C.byref(ke), _dp(mom))
+        return ke.value, mom[: self.md.dim].copy()
+
+    def mdlg(self, lattice, md_per_lattice, n_lattice, per_step_hist=False):
+        """Run n_lattice lattice steps; returns a dict of accumulators."""
+        dim = self.md.dim
+        nsite = int(np.prod([lattice.M[a] for a in range(dim)]))
+        q = (2 * lattice.V + 1) ** dim
+        nm = num_moments(dim)
+        A = np.zeros((nsite, q), dtype=np.uint64)
+        mom = np.zeros((nsite, nm), dtype=np.int64)
+        dsum = np.zeros(dim)
+        dsq = np.zeros(dim)
+        hist = np.zeros((n_lattice, q), dtype=np.uint64) if per_step_hist else None
+        hp = _up(hist) if per_step_hist else C.cast(None, C.POINTER(C.c_uint64))
+        _check(_load().orc_mdlg_run(C.byref(self.md), C.byref(lattice), int(md_per_lattice),
+                                    int(n_lattice), _dp(self.x), _ip(self.img), _dp(self.v),
+                                    _dp(self.acc), C.byref(self.step), self.use_cells,
+                                    _up(A), _lp(mom), _dp(dsum), _dp(dsq), hp), "mdlg_run")
+        return {"A": A, "mom": mom, "dsum": dsum, "dsq": dsq, "hist": hist,
+                "n_lattice": n_lattice, "n_sites": nsite}
+
+
+def bin_step(lattice, dim, xu_prev, xu_now):
+    """One lattice step of binning on given unwrapped FP64 positions."""
+    xu_prev = np.ascontiguousarray(xu_prev, dtype=np.float64)
+    xu_now = np.ascontiguousarray(xu_now, dtype=np.float64)
+    n = xu_now.shape[0]
+    nsite = int(np.prod([lattice.M[a] for a in range(dim)]))
+    q = (2 * lattice.V + 1) ** dim
+    A = np.zeros((nsite, q), dtype=np.uint64)
+    mom = np.zeros((nsite, num_moments(dim)), dtype=np.int64)
+    dsum = np.zeros(dim)
+    dsq = np.zeros(dim)
+    _check(_load().orc_bin(C.byref(lattice), dim, n, _dp(xu_prev), _dp(xu_now), _up(A),
+                           _lp(mom), _dp(dsum), _dp(dsq)), "bin")
+    return {"A": A, "mom": mom, "dsum": dsum, "dsq": dsq}
+
+
+def ni_literal(lattice, dim, xu_prev, xu_now):
+    """eq. (MDni) evaluated literally with interval indicators (tiny inputs)."""
+    xu_prev = np.ascontiguousarray(xu_prev, dtype=np.float64)
+    xu_now = np.ascontiguousarray(xu_now, dtype=np.float64)
+    n = xu_now.shape[0]
+    nsite = int(np.prod([lattice.M[a] for a in range(dim)]))
+    q = (2 * lattice.V + 1) ** dim
+    out = np.zeros((nsite, q), dtype=np.uint64)
+    _check(_load().orc_ni_literal(C.byref(lattice), dim, n, _dp(xu_prev), _dp(xu_now),
+                                  _up(out)), "ni_literal")
+    return out
