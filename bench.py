@@ -1,0 +1,230 @@
+"""Throughput of the MDLG hot path on one MI355X: particle-steps/s of LJ MD
+fused with MDLG binning.
+
+One bench step is one lattice time step: md_steps_per_lattice_step MD steps
+(forces + velocity Verlet + periodic wrap + cell-list rebuilds) followed by
+the binning of every particle (eq. MDni) and the per-site accumulation.
+value = particles x MD steps / wall time over the timed lattice steps, with
+the state resident in HBM.  Inputs are seeded and synthetic (the paper's own
+MD trajectories are not available); see the workload table below.
+
+The JSON line also carries the roofline of the dominant kernel (event-timed
+per launch inside this run) and the FP64 oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# Workloads (synthetic stand-ins for the paper's LAMMPS runs; parameters of the
+# configurations this build measures).
+WORKLOADS = {
+    "2d_scale": dict(dim=2, n=262144, M=181, dx=4.0, kT=1.0, dt=0.005, steps=20, vmax=3,
+                     desc="2D LJ N=262144, 724 sigma box (rho=0.5), kT=1, dt=0.005, "
+                          "181x181 lattice of 4 sigma, Delta t=20 MD steps, V=3 (Q=49)"),
+    "2d_small": dict(dim=2, n=2048, M=16, dx=4.0, kT=1.0, dt=0.005, steps=20, vmax=3,
+                     desc="2D LJ N=2048, 64 sigma box (rho=0.5), kT=1, dt=0.005, "
+                          "16x16 lattice of 4 sigma, Delta t=20 MD steps, V=3 (Q=49)"),
+    "3d": dict(dim=3, n=4194304, M=48, dx=4.0, kT=1.5, dt=0.004, steps=20, vmax=2,
+               desc="3D LJ N=4194304, 192 sigma cube (rho=0.593), kT=1.5, dt=0.004, "
+                    "48^3 lattice of 4 sigma, Delta t=20 MD steps, V=2 (Q=125)"),
+}
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector, published
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E, published
+FLOP_PER_PAIR = {2: 18, 3: 23}  # interacting pair: differences, r^2, rcp, LJ factor, accumulate
+
+
+def pairs_per_particle(dim, rho, rc=2.5):
+    """Ordered neighbours inside r_c at uniform density (the force kernel's
+    useful work per particle per step)."""
+    return math.pi * rc * rc * rho if dim == 2 else 4.0 / 3.0 * math.pi * rc ** 3 * rho
+
+
+def sort_bytes_per_particle(dim):
+    """Algorithmic HBM bytes per particle of one cell-list rebuild: read
+    offsets, velocity, image, id, cell; write the key/slot word; read it back
+    and write the permuted offsets, velocity, image, id, cell."""
+    state = 4 * dim * 3 + 8          # off, vel, img + id, cell
+    return state + 8 + 8 + state     # read state, write key+slot, read key+slot, write state
+
+
+def bin_bytes_per_particle(dim, q, nm, per_site_particles):
+    """Algorithmic HBM bytes per particle of one binning pass: read offset,
+    image, id, cell; gather and write back the snapshot (unwrapped cell and
+    offset, by id); per site one read-modify-write of the Q counters and the
+    moment accumulators, shared by the particles of the site."""
+    per_particle = 4 * dim * 2 + 8 + 2 * (8 * dim)
+    per_site = 2 * 4 * q + 2 * 8 * nm
+    return per_particle + per_site / per_site_particles
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for f in ("mdlg_kernels.hip", "mdlg_args.h", "mdlg_device.h"):
+        with open(os.path.join(ROOT, "paper_1705_04368_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload, kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, when
+    it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_digest") != source_digest():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else float(k["bytes_per_launch"])
+
+
+def cpu_baseline(w, pos, vel, lattice_steps):
+    """The FP64 oracle, single-threaded on the host, on a bounded sample: the
+    full system for `lattice_steps` lattice steps from the same initial state."""
+    import oracle
+    dim, n = w["dim"], w["n"]
+    box = w["M"] * w["dx"]
+    md = oracle.make_md(dim, n, box, dt=w["dt"])
+    st = oracle.OracleState(md, pos, vel)
+    lat = oracle.make_lattice(dim, (w["M"],) * dim, w["dx"], w["vmax"])
+    t0 = time.perf_counter()
+    st.mdlg(lat, w["steps"], lattice_steps)
+    t = time.perf_counter() - t0
+    return {"value": n * w["steps"] * lattice_steps / t, "unit": "particle-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"full system, {lattice_steps} lattice steps ({lattice_steps * w['steps']} MD "
+                      f"steps + binning), FP64 single thread, {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50, help="timed lattice steps")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed lattice steps")
+    ap.add_argument("--workload", default="2d_scale", choices=sorted(WORKLOADS))
+    ap.add_argument("--equilibrate", type=int, default=2000, help="thermostatted MD steps")
+    ap.add_argument("--timing-steps", type=int, default=10,
+                    help="lattice steps of the event-timed per-kernel pass")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-lattice-steps", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(replicas or domains would shard across GPUs; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_1705_04368_amd import System, make_config
+
+    w = WORKLOADS[args.workload]
+    dim, n, M = w["dim"], w["n"], w["M"]
+    box = M * w["dx"]
+    rho = n / box ** dim
+    dev = torch.device("cuda:0")
+    pos, vel = synth.lj_initial_state(dim, n, box, w["kT"], seed=2 if dim == 2 else 3)
+    cfg = make_config(dim, n, M, lattice_dx=w["dx"], dt=w["dt"],
+                      md_steps_per_lattice_step=w["steps"], vmax=w["vmax"], thermostat_every=10,
+                      kT=w["kT"])
+    sysg = System(cfg, torch.from_numpy(pos).to(dev), torch.from_numpy(vel).to(dev))
+    lay = sysg.layout
+    print(f"# workload {args.workload}: {w['desc']}; layout {lay}", file=sys.stderr, flush=True)
+    sysg.step(args.equilibrate)
+    sysg.sync()
+    print("# equilibrated", file=sys.stderr, flush=True)
+    sysg.coarse_grain(args.warmup)
+    sysg.sync()
+    sysg.reset_accumulators()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sysg.coarse_grain(args.steps)
+    sysg.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    md_steps = args.steps * w["steps"]
+    value = n * md_steps / elapsed
+    print(f"# timed {args.steps} lattice steps in {elapsed:.4f} s", file=sys.stderr, flush=True)
+    f = sysg.get_f()
+    assert f["counts"].sum() + f["n_overflow"] == n * f["n_lattice_steps"]
+
+    # per-kernel event timing over a separate pass of the same lattice steps
+    sysg.set_timing(True)
+    sysg.coarse_grain(args.timing_steps)
+    tim = sysg.get_timing()
+    sysg.set_timing(False)
+    q, nm = lay["n_velocities"], lay["n_moments"]
+    per_site = n / (M ** dim)
+    kernels = {}
+    for k, (ms, cnt) in tim.items():
+        if cnt == 0:
+            continue
+        avg = ms / cnt
+        if k == "force":
+            work = n * pairs_per_particle(dim, rho) * FLOP_PER_PAIR[dim]
+            ach = work / (avg * 1e-3) / 1e12
+            kernels[k] = {"avg_ms": avg, "launches": cnt, "bound": "alu", "achieved": ach,
+                          "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
+                          "work_per_launch": work}
+        elif k in ("count", "scatter", "scan"):
+            if k == "scan":
+                work = 8.0 * lay["n_cells"]
+            else:
+                half = sort_bytes_per_particle(dim) / 2
+                work = n * half
+            ach = work / (avg * 1e-3) / 1e9
+            kernels[k] = {"avg_ms": avg, "launches": cnt, "bound": "hbm", "achieved": ach,
+                          "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                          "work_per_launch": work}
+        elif k == "bin":
+            work = n * bin_bytes_per_particle(dim, q, nm, per_site)
+            ach = work / (avg * 1e-3) / 1e9
+            kernels[k] = {"avg_ms": avg, "launches": cnt, "bound": "hbm", "achieved": ach,
+                          "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                          "work_per_launch": work}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    kd = kernels[dom]
+    roofline = {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
+                "unit": kd["unit"], "frac": kd["frac"],
+                "traffic": load_traffic(args.workload, dom)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w, pos, vel, args.cpu_lattice_steps)
+
+    out = {
+        "metric": "particle-steps/s (LJ MD + MDLG binning)",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "lattice_steps": args.steps, "md_steps": md_steps,
+                   "md_cell_split": lay["md_cell_split"], "sort_every": lay["sort_every"],
+                   "brick": list(lay["brick"])},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kernels.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,239 @@
+/*
+ * mdlg.h -- C ABI of the MI355X (gfx950) MDLG library.
+ *
+ * The library runs Lennard-Jones molecular dynamics in periodic boxes and
+ * coarse-grains it on the fly into the Molecular-Dynamics lattice gas (MDLG)
+ * of Parsa & Wagner, "Lattice Gas with Molecular Dynamics Collision Operator":
+ *
+ *   - MD (section "Lattice Gas with Molecular Dynamics collision operator",
+ *     Newton's equations for N particles with a pair potential in a periodic
+ *     container; section "MDLG for a two-dimensional Lennard-Jones gas", the
+ *     LJ potential V(r) = 4 eps [(sigma/r)^12 - (sigma/r)^6]).  Velocity-Verlet
+ *     integration, cut off at r_cut (the paper does not state the integrator or
+ *     the cutoff).
+ *   - MDLG binning (eq. MDni): every lattice time step Delta t, each particle's
+ *     lattice cell at t - Delta t and at t gives its lattice velocity
+ *     v_i = C(t) - C(t - Delta t); n_i(x,t) counts the particles arriving in
+ *     site x with velocity v_i.  Per site the library accumulates sum_t n_i,
+ *     the local number N(x,t), the lattice momentum N u = sum_i v_i n_i and the
+ *     second moment sum_i v_i v_i n_i, all exact integers.
+ *   - the equilibrium distribution f_i^eq = <n_i> (eq. fieq) as the site and
+ *     time average, and the continuous displacement moments behind a^2
+ *     (eq. eqn:a).
+ *
+ * Conventions
+ *   - All entry points return mdlg_status (0 = MDLG_OK, negative = error) and
+ *     never throw.  Config errors are found synchronously on the host.
+ *   - Device-side failures (a particle leaving the cell-list margin between
+ *     rebuilds, non-finite coordinates, a velocity so large that a particle
+ *     crosses more than one cell per step) set a device error word; it is
+ *     reported as MDLG_E_UNSTABLE by the next call that synchronises
+ *     (mdlg_get_f, mdlg_get_state, mdlg_sync), and mdlg_last_error() explains.
+ *   - The caller owns all device memory: one workspace of
+ *     mdlg_workspace_bytes() bytes (256-byte aligned) that must outlive the
+ *     handle, plus the input arrays of mdlg_create.  The library never
+ *     allocates device memory.  The caller owns every host array it passes.
+ *   - Work is enqueued asynchronously on the HIP stream given at creation.
+ *     One handle must be used from one host thread at a time.
+ *   - Lattice: a cubic lattice of spacing lattice_dx with lattice[r][a] sites
+ *     along axis a of replica r; the periodic box side is lattice[r][a] *
+ *     lattice_dx.  A particle belongs to site c along an axis when
+ *     c * dx <= x < (c+1) * dx (the paper writes the interval closed above;
+ *     the two readings differ on a set of measure zero).
+ *   - Velocities: lattice velocities with |v_a| <= vmax on every axis are
+ *     binned into Q = (2 vmax + 1)^dim bins with index
+ *     i = sum_a (v_a + vmax) (2 vmax + 1)^a (x fastest); other particles are
+ *     counted as overflow at their arrival site.  N(x,t) and the moments include
+ *     every particle.
+ *   - Several independent replicas (boxes of different sizes) can share one
+ *     handle; they run in the same kernel launches.  Particle arrays are the
+ *     concatenation of the replicas in order; site arrays likewise.
+ */
+#ifndef MDLG_H
+#define MDLG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MDLG_OK = 0,
+    MDLG_E_INVALID = -1,   /* bad argument or configuration */
+    MDLG_E_DEVICE = -2,    /* a HIP runtime call failed */
+    MDLG_E_NOMEM = -3,     /* workspace too small */
+    MDLG_E_UNSTABLE = -4,  /* device error word set (see mdlg_last_error) */
+    MDLG_E_STATE = -5      /* call not valid in the current state */
+} mdlg_status;
+
+typedef struct mdlg_system mdlg_system; /* opaque, library-owned host handle */
+
+typedef struct {
+    int32_t dim;                /* 2 or 3 */
+    int32_t n_replicas;         /* >= 1 */
+    const int32_t *n_particles; /* host [n_replicas], each >= 1 */
+    const int32_t *lattice;     /* host [n_replicas][dim], sites per axis M >= 1 */
+    double lattice_dx;          /* lattice spacing Delta x (> 0) */
+    double epsilon;             /* LJ eps (> 0) */
+    double sigma;               /* LJ sigma (> 0) */
+    double mass;                /* particle mass m (> 0) */
+    double r_cut;               /* cutoff radius (> 0); box sides must exceed 2 r_cut */
+    int32_t forces_off;         /* 1: ideal gas (no interactions) */
+    double dt;                  /* MD time step (> 0) */
+    int32_t md_steps_per_lattice_step; /* Delta t / dt (>= 1) */
+    int32_t vmax;               /* velocity window half-width V (0..7) */
+    int32_t thermostat_every;   /* rescale velocities to kT every this many MD steps in
+                                   mdlg_step (0 = off); never during mdlg_coarse_grain */
+    double kT;                  /* thermostat target k_B T */
+    int32_t md_cell_split;      /* k: MD cells of side s = dx / k per lattice cell;
+                                   power of two 1..8, or 0 = choose automatically */
+    int32_t sort_every;         /* cell-list rebuild interval in MD steps (>= 1),
+                                   or 0 = choose from kT, mass and dt */
+    int32_t brick_x;            /* force-kernel brick extent along x in MD cells, 0 = auto */
+    int32_t brick_y;            /* along y, 0 = auto */
+    int32_t brick_z;            /* along z (3D), 0 = auto */
+} mdlg_config;
+
+/* Particle state in particle-id order (id = index in the concatenated input).
+ * Every pointer is a host array of n_total * dim elements, or NULL to skip.
+ *   ucell:      unwrapped MD-cell index per axis: wrapped cell + Mc * image,
+ *               with Mc = lattice * k MD cells per axis and image the number of
+ *               periodic box crossings;
+ *   off:        position inside that MD cell, in [0, s), s = dx / k;
+ *               the unwrapped position is ucell * s + off;
+ *   vel:        velocity at the current time;
+ *   acc:        acceleration F/m at the current time (mdlg_get_state only);
+ *   prev_ucell, prev_off: the same two quantities at the last lattice snapshot
+ *               (the positions the next lattice step is binned against). */
+typedef struct {
+    int32_t *ucell;
+    float *off;
+    float *vel;
+    float *acc;
+    int32_t *prev_ucell;
+    float *prev_off;
+} mdlg_particles;
+
+/* Derived parameters of a configuration (host only, no device needed). */
+typedef struct {
+    int32_t md_cell_split;      /* k actually used */
+    int32_t sort_every;         /* rebuild interval actually used */
+    int32_t stencil;            /* neighbour-cell half-width ceil(r_cut / s) */
+    int32_t n_velocities;       /* Q */
+    int32_t n_moments;          /* per-site moments: 2 + dim + dim(dim+1)/2 */
+    int32_t brick[3];           /* force-kernel brick extent in MD cells */
+    int64_t n_total;            /* particles over all replicas */
+    int64_t n_sites;            /* lattice sites over all replicas */
+    int64_t n_cells;            /* MD cells over all replicas */
+    int64_t n_bricks;           /* force-kernel work units per MD step */
+    double cell_side;           /* s */
+    double margin;              /* allowed excursion outside the cell between rebuilds */
+} mdlg_layout;
+
+/* Validate cfg and report the derived layout.  Host only.  MDLG_E_INVALID on
+ * any inconsistent field; *out untouched on error. */
+mdlg_status mdlg_describe(const mdlg_config *cfg, mdlg_layout *out);
+
+/* Workspace size in bytes for cfg.  Host only. */
+mdlg_status mdlg_workspace_bytes(const mdlg_config *cfg, size_t *bytes);
+
+/* Create a system.  workspace_dev: device buffer of at least
+ * mdlg_workspace_bytes(cfg) bytes, 256-byte aligned, owned by the caller.
+ * hip_stream: the hipStream_t all work is enqueued on (NULL = null stream).
+ * pos_dev: device float [n_total][dim] positions in [0, box) (the initial x_i(0)
+ * of the paper's problem statement); vel_dev: device float [n_total][dim]
+ * initial velocities v_i(0).  Both are read before the call returns (the call
+ * synchronises the stream once).  The initial positions become the first
+ * lattice snapshot. */
+mdlg_status mdlg_create(const mdlg_config *cfg, void *workspace_dev, size_t workspace_bytes,
+                        void *hip_stream, const float *pos_dev, const float *vel_dev,
+                        mdlg_system **out);
+
+/* Advance n_md_steps velocity-Verlet steps (asynchronous).  With
+ * thermostat_every > 0 the velocities are rescaled to kT every that many steps
+ * (equilibration).  Invalidates the lattice snapshot: the next
+ * mdlg_coarse_grain takes a fresh one first. */
+mdlg_status mdlg_step(mdlg_system *sys, int64_t n_md_steps);
+
+/* Run n_lattice_steps lattice time steps (asynchronous): each is
+ * md_steps_per_lattice_step MD steps (no thermostat) followed by binning of
+ * every particle against the previous snapshot (eq. MDni) and accumulation of
+ * n_i, N, N u, the second moment and the continuous displacement moments. */
+mdlg_status mdlg_coarse_grain(mdlg_system *sys, int64_t n_lattice_steps);
+
+/* Read back the averages (synchronises).  Every output is optional (NULL):
+ *   f        [Q]      f_i^eq = sum over sites and lattice steps of n_i divided by
+ *                     (lattice steps * sites), over all replicas (eq. fieq);
+ *   f_site   [n_sites][Q]   per-site time average of n_i;
+ *   mom_site [n_sites][n_moments] per-site time averages of
+ *            (N, overflow, sum_i v_a n_i for each axis a, then sum_i v_a v_b n_i
+ *             for a <= b in row-major order: xx, xy, [xz], yy, [yz], [zz]);
+ *   counts   [Q]      the raw integer sums behind f (uint64);
+ *   n_samples         lattice steps * sites;
+ *   n_overflow        particle-steps outside the velocity window;
+ *   disp     [2*dim]  sum of delta x_a and of delta x_a^2 of the continuous
+ *                     displacement x(t) - x(t - Delta t) over particles and
+ *                     lattice steps (divide by n_total * lattice steps for
+ *                     <delta x_a> and <delta x_a^2>);
+ *   n_lattice_steps   lattice steps accumulated.
+ * Returns MDLG_E_UNSTABLE if the device error word is set. */
+mdlg_status mdlg_get_f(mdlg_system *sys, double *f, double *f_site, double *mom_site,
+                       uint64_t *counts, int64_t *n_samples, int64_t *n_overflow, double *disp,
+                       int64_t *n_lattice_steps);
+
+/* Diagnostics per replica at the last lattice step or thermostat step (FP64):
+ * out[r][0..dim-1] = total momentum sum m v, out[r][dim] = kinetic energy
+ * sum m v^2 / 2.  Synchronises.  out is host [n_replicas][dim + 1]. */
+mdlg_status mdlg_get_kinetics(mdlg_system *sys, double *out);
+
+/* Zero all accumulators (n_i sums, moments, displacement sums, lattice-step
+ * count) and invalidate the snapshot.  Asynchronous. */
+mdlg_status mdlg_reset_accumulators(mdlg_system *sys);
+
+/* Copy the particle state at the current time to host arrays in id order
+ * (synchronises).  Completes the pending half kick to report full-step
+ * velocities and accelerations; the trajectory is unchanged. */
+mdlg_status mdlg_get_state(mdlg_system *sys, mdlg_particles *out);
+
+/* Replace the particle state from host arrays in id order (ucell, off and vel
+ * required; prev_ucell and prev_off optional: when NULL the new positions become
+ * the snapshot).  Offsets must lie in [0, s).  Accumulators are kept. */
+mdlg_status mdlg_set_state(mdlg_system *sys, const mdlg_particles *in);
+
+/* Kernel classes of the hot path, for mdlg_get_timing. */
+typedef enum {
+    MDLG_K_FORCE = 0,   /* LJ forces fused with the velocity-Verlet kicks and drift */
+    MDLG_K_COUNT = 1,   /* cell-list rebuild: canonicalise and count per cell */
+    MDLG_K_SCAN = 2,    /* cell-list rebuild: exclusive scan of the counts */
+    MDLG_K_SCATTER = 3, /* cell-list rebuild: permute the particle state */
+    MDLG_K_BIN = 4,     /* MDLG binning and per-site accumulation (eq. MDni) */
+    MDLG_K_NCLASS = 5
+} mdlg_kernel_class;
+
+/* Enable (1) or disable (0) per-kernel timing with HIP events on the handle's
+ * stream.  While enabled, lattice steps run as individual launches (no graph
+ * replay) with an event pair around each launch.  Enabling resets the
+ * counters.  This is a measurement aid for callers profiling the hot path. */
+mdlg_status mdlg_set_timing(mdlg_system *sys, int enable);
+
+/* Total event-timed milliseconds and launch counts per kernel class since
+ * timing was enabled (synchronises).  Both arrays are host [MDLG_K_NCLASS]. */
+mdlg_status mdlg_get_timing(mdlg_system *sys, double *total_ms, int64_t *launches);
+
+/* Wait for all work queued on the handle's stream; report the error word. */
+mdlg_status mdlg_sync(mdlg_system *sys);
+
+/* Human-readable description of the last error on sys (or of the last
+ * creation failure when sys is NULL).  Never NULL. */
+const char *mdlg_last_error(const mdlg_system *sys);
+
+/* Release the handle (the caller still owns the workspace). */
+void mdlg_destroy(mdlg_system *sys);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDLG_H */

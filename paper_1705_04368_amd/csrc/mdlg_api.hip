@@ -1,0 +1,1115 @@
+// Host side of the MDLG C ABI (include/mdlg.h): configuration checks, the
+// workspace layout, the launch sequence of an MD step and of a lattice step,
+// HIP-graph replay of lattice steps, readout and state I/O.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "mdlg.h"
+#include "mdlg_args.h"
+
+using namespace mdlg;
+
+namespace {
+
+thread_local std::string g_create_error = "no error";
+
+constexpr int kPartChunk = kPartChunkMax;  // particles per block of the per-particle kernels
+
+struct Layout {
+  mdlg_layout pub;
+  int D = 0;
+  int k = 1;
+  int log2k = 0;
+  int ns = 1;
+  int Q = 1;
+  int nm = 0;
+  int BX = 1, BY = 1, BZ = 1;
+  int BSX = 1;
+  long long n_total = 0, n_cells = 0, n_sites = 0;
+  int nbricks = 0, nchunks = 0, nstrips = 0, ntiles = 0;
+  std::vector<Replica> reps;
+  std::vector<int4> bricks, chunks, strips;
+  double s = 0, margin = 0;
+  int sort_every = 1;
+};
+
+// Workspace carve-out, in the order buffers are laid out.
+struct Carve {
+  size_t off = 0;
+  template <typename T>
+  T* take(char* base, size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+int ilog2_exact(int k) {
+  int l = 0;
+  while ((1 << l) < k) ++l;
+  return (1 << l) == k ? l : -1;
+}
+
+bool set_err(std::string* msg, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+bool set_err(std::string* msg, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (msg) *msg = buf;
+  return false;
+}
+
+// Validate cfg and derive the layout.  Host only.
+bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
+  if (!c) return set_err(msg, "config is NULL");
+  if (c->dim != 2 && c->dim != 3) return set_err(msg, "dim must be 2 or 3 (got %d)", c->dim);
+  const int D = c->dim;
+  if (c->n_replicas < 1) return set_err(msg, "n_replicas must be >= 1");
+  if (!c->n_particles || !c->lattice) return set_err(msg, "n_particles and lattice are required");
+  if (!(c->lattice_dx > 0) || !std::isfinite(c->lattice_dx)) return set_err(msg, "lattice_dx must be > 0");
+  if (!(c->epsilon > 0) || !(c->sigma > 0) || !(c->mass > 0) || !(c->r_cut > 0))
+    return set_err(msg, "epsilon, sigma, mass and r_cut must be > 0");
+  if (!(c->dt > 0) || !std::isfinite(c->dt)) return set_err(msg, "dt must be > 0");
+  if (c->md_steps_per_lattice_step < 1) return set_err(msg, "md_steps_per_lattice_step must be >= 1");
+  if (c->vmax < 0 || c->vmax > 7) return set_err(msg, "vmax must be in 0..7");
+  if (c->thermostat_every < 0) return set_err(msg, "thermostat_every must be >= 0");
+  if (c->thermostat_every > 0 && !(c->kT > 0)) return set_err(msg, "thermostat needs kT > 0");
+  if (c->kT < 0 || !std::isfinite(c->kT)) return set_err(msg, "kT must be >= 0");
+  if (c->sort_every < 0) return set_err(msg, "sort_every must be >= 0");
+  if (c->brick_x < 0 || c->brick_y < 0 || c->brick_z < 0) return set_err(msg, "brick extents must be >= 0");
+  L->D = D;
+  int Q = 1;
+  for (int a = 0; a < D; ++a) Q *= 2 * c->vmax + 1;
+  if (Q > kMaxQ) return set_err(msg, "velocity window too large: Q = %d > %d", Q, kMaxQ);
+  L->Q = Q;
+  L->nm = 2 + D + D * (D + 1) / 2;
+  long long n_total = 0;
+  int min_m = 1 << 30;
+  double vol = 0;
+  for (int r = 0; r < c->n_replicas; ++r) {
+    if (c->n_particles[r] < 1) return set_err(msg, "replica %d has no particles", r);
+    n_total += c->n_particles[r];
+    long long ns = 1;
+    double v = 1;
+    for (int a = 0; a < D; ++a) {
+      const int m = c->lattice[r * D + a];
+      if (m < 1) return set_err(msg, "replica %d: lattice sites per axis must be >= 1", r);
+      if (m * c->lattice_dx <= 2 * c->r_cut)
+        return set_err(msg, "replica %d: box side %g must exceed 2 r_cut = %g", r,
+                       m * c->lattice_dx, 2 * c->r_cut);
+      min_m = std::min(min_m, m);
+      ns *= m;
+      v *= m * c->lattice_dx;
+    }
+    (void)ns;
+    vol += v;
+  }
+  if (n_total > (1ll << 30)) return set_err(msg, "too many particles (%lld)", n_total);
+  const double rho = n_total / vol;
+  // MD cell split k: the cell side s = dx / k
+  int k = c->md_cell_split;
+  auto margin_of = [&](int kk, int* ns_out) {
+    const double s = c->lattice_dx / kk;
+    const int ns = (int)std::ceil(c->r_cut / s - 1e-12);
+    if (ns_out) *ns_out = ns;
+    return (ns * s - c->r_cut) / 2;
+  };
+  if (k == 0) {
+    // fewest candidates per target: the force kernel visits the cells that
+    // overlap a cube of side 2 (r_cut + margin) around each target, i.e.
+    // about (2 (r_cut + m) + s)^D rho candidates in (2 (r_cut + m) / s + 1)^(D-1)
+    // contiguous rows; a row costs about eight candidates of loop overhead.
+    // Splits whose rebuild margin is below sigma / 2 are skipped (the cell
+    // list would be rebuilt every few steps).
+    double best = 1e300;
+    for (int kk = 1; kk <= 8; kk *= 2) {
+      int ns;
+      const double m = margin_of(kk, &ns);
+      if (m < 0.5 * c->sigma) continue;
+      if (min_m * kk < 2 * ns + 1) continue;
+      const double s = c->lattice_dx / kk;
+      const double reach = 2 * (c->r_cut + m);
+      const double cost = std::pow(reach + s, D) * rho + 8.0 * std::pow(reach / s + 1, D - 1);
+      if (cost < best) {
+        best = cost;
+        k = kk;
+      }
+    }
+    if (k == 0) k = 1;
+  }
+  const int lk = ilog2_exact(k);
+  if (lk < 0 || k > 8) return set_err(msg, "md_cell_split must be a power of two in 1..8 (got %d)", k);
+  if (D == 3 && k * k > 64) return set_err(msg, "md_cell_split too large for 3D");
+  L->k = k;
+  L->log2k = lk;
+  L->s = c->lattice_dx / k;
+  L->ns = (int)std::ceil(c->r_cut / L->s - 1e-12);
+  // largest excursion outside the cell that the stencil still covers
+  const double m_max = (L->ns * L->s - c->r_cut) / 2;
+  if (min_m * k < 2 * L->ns + 1)
+    return set_err(msg, "too few MD cells per axis (%d) for the stencil half-width %d", min_m * k, L->ns);
+  // rebuild interval and the margin it needs: eight standard deviations of
+  // the Maxwell speed per axis times the interval (the kernel checks the bound)
+  const double vfast = c->kT > 0 ? 8.0 * std::sqrt(c->kT / c->mass) : 0.0;
+  int R = c->sort_every;
+  if (R == 0) {
+    if (m_max <= 0 || !(vfast > 0)) {
+      R = 1;
+    } else {
+      R = (int)std::floor(m_max / (vfast * c->dt));
+      R = std::max(1, std::min(R, c->md_steps_per_lattice_step));
+    }
+  }
+  if (R > 1 && m_max <= 0)
+    return set_err(msg, "sort_every > 1 needs a positive margin (stencil reach %g vs r_cut %g)",
+                   L->ns * L->s, c->r_cut);
+  L->sort_every = R;
+  L->margin = (vfast > 0) ? std::min(m_max, R * vfast * c->dt) : m_max;
+  if (L->margin < 0) L->margin = 0;
+  // force bricks
+  int BX = c->brick_x, BY = c->brick_y, BZ = c->brick_z;
+  const double per_cell = rho * std::pow(L->s, D);
+  if (D == 2) {
+    // about 128 targets per block of 256 threads measured best (more blocks
+    // in flight hide the staging latency)
+    const double cells = 128.0 / std::max(per_cell, 0.05);
+    if (BY == 0) BY = cells >= 32 ? 2 : 1;
+    if (BX == 0) BX = std::max(4, std::min(256, (int)std::lround(cells / BY)));
+    BZ = 1;
+  } else {
+    if (BX == 0 || BY == 0) {
+      const double cells = 256.0 / std::max(per_cell, 0.05);
+      int bx = 1;
+      while (bx * bx * 2 <= cells && bx < 16) bx *= 2;
+      if (BX == 0) BX = bx;
+      if (BY == 0) BY = std::max(1, (int)std::lround(cells / BX));
+      BY = std::min(BY, 16);
+    }
+    if (BZ == 0) BZ = 1;
+  }
+  const int nsz = (D == 3) ? L->ns : 0;
+  const int maxh = (D == 2) ? kMaxHalo2 : kMaxHalo3;
+  auto halo_of = [&](int bx, int by, int bz) {
+    return (long long)(bx + 2 * L->ns) * (by + 2 * L->ns) * (bz + 2 * nsz);
+  };
+  // automatic extents shrink until the halo fits the LDS cell table
+  while (c->brick_x == 0 && BX > 1 && halo_of(BX, BY, BZ) > maxh) BX = (BX + 1) / 2;
+  while (c->brick_y == 0 && BY > 1 && halo_of(BX, BY, BZ) > maxh) BY = (BY + 1) / 2;
+  const long long halo = halo_of(BX, BY, BZ);
+  if (halo > maxh) return set_err(msg, "brick %dx%dx%d with stencil %d needs %lld halo cells > %d",
+                                  BX, BY, BZ, L->ns, halo, maxh);
+  if ((long long)BY * BZ > kMaxRows) return set_err(msg, "brick has more than %d rows", kMaxRows);
+  L->BX = BX;
+  L->BY = BY;
+  L->BZ = BZ;
+  // binning strip width (LDS budget 60 kB)
+  L->BSX = std::max(1, std::min(kMaxStripSites, 60000 / ((L->Q + L->nm) * 4)));
+  // tables
+  L->reps.clear();
+  L->bricks.clear();
+  L->chunks.clear();
+  L->strips.clear();
+  long long cell_off = 0, part_off = 0, site_off = 0;
+  for (int r = 0; r < c->n_replicas; ++r) {
+    Replica rep{};
+    long long ncell = 1, nsite = 1;
+    for (int a = 0; a < 3; ++a) {
+      rep.M[a] = a < D ? c->lattice[r * D + a] : 1;
+      rep.Mc[a] = a < D ? rep.M[a] * k : 1;
+      ncell *= rep.Mc[a];
+      nsite *= rep.M[a];
+    }
+    if (cell_off + ncell > (1ll << 30)) return set_err(msg, "too many MD cells");
+    rep.cell_off = (int)cell_off;
+    rep.part_off = (int)part_off;
+    rep.site_off = (int)site_off;
+    rep.n = c->n_particles[r];
+    rep.brick_off = (int)L->bricks.size();
+    const int nbx = (rep.Mc[0] + BX - 1) / BX, nby = (rep.Mc[1] + BY - 1) / BY;
+    const int nbz = (D == 3) ? (rep.Mc[2] + BZ - 1) / BZ : 1;
+    for (int bz = 0; bz < nbz; ++bz)
+      for (int by = 0; by < nby; ++by)
+        for (int bx = 0; bx < nbx; ++bx) L->bricks.push_back(make_int4(r, bx, by, bz));
+    rep.nbricks = (int)L->bricks.size() - rep.brick_off;
+    for (long long g = part_off; g < part_off + rep.n; g += kPartChunk)
+      L->chunks.push_back(make_int4(r, (int)g, (int)std::min(part_off + rep.n, g + kPartChunk), 0));
+    const int nsz_rows = (D == 3) ? rep.M[2] : 1;
+    for (int sz = 0; sz < nsz_rows; ++sz)
+      for (int sy = 0; sy < rep.M[1]; ++sy)
+        for (int sx = 0; sx < rep.M[0]; sx += L->BSX) L->strips.push_back(make_int4(r, sx, sy, sz));
+    L->reps.push_back(rep);
+    cell_off += ncell;
+    part_off += rep.n;
+    site_off += nsite;
+  }
+  L->n_total = n_total;
+  L->n_cells = cell_off;
+  L->n_sites = site_off;
+  L->nbricks = (int)L->bricks.size();
+  L->nchunks = (int)L->chunks.size();
+  L->nstrips = (int)L->strips.size();
+  L->ntiles = (int)((L->n_cells + kScanTile - 1) / kScanTile);
+  mdlg_layout& P = L->pub;
+  P.md_cell_split = k;
+  P.sort_every = R;
+  P.stencil = L->ns;
+  P.n_velocities = Q;
+  P.n_moments = L->nm;
+  P.brick[0] = BX;
+  P.brick[1] = BY;
+  P.brick[2] = BZ;
+  P.n_total = n_total;
+  P.n_sites = L->n_sites;
+  P.n_cells = L->n_cells;
+  P.n_bricks = L->nbricks;
+  P.cell_side = L->s;
+  P.margin = L->margin;
+  return true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- the handle
+
+struct mdlg_system {
+  mdlg_config cfg{};
+  std::vector<int32_t> n_particles, lattice;
+  Layout L;
+  Phys P{};
+  hipStream_t stream = nullptr;
+  int D = 2;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  // device buffers
+  float* pos[2] = {nullptr, nullptr};
+  float* vel[2] = {nullptr, nullptr};
+  int* img[2] = {nullptr, nullptr};
+  int* id[2] = {nullptr, nullptr};
+  int* cell[2] = {nullptr, nullptr};
+  int2* keyslot = nullptr;
+  int* count = nullptr;
+  int* cell_start = nullptr;
+  int* tile_sum = nullptr;
+  int* prev_u = nullptr;
+  float* prev_off = nullptr;
+  unsigned* A = nullptr;
+  long long* mom = nullptr;
+  double* dpart = nullptr;
+  double* kpart = nullptr;
+  double* kin = nullptr;
+  float* lambda = nullptr;
+  unsigned* err = nullptr;
+  Replica* reps = nullptr;
+  int4* bricks = nullptr;
+  int4* chunks = nullptr;
+  int4* strips = nullptr;
+  unsigned long long* fcount = nullptr;
+  long long* momsum = nullptr;
+  double* fout = nullptr;
+  double* dispout = nullptr;
+  float* acc_sorted = nullptr;
+  char* staging = nullptr;
+  size_t staging_bytes = 0;
+  // host-side state
+  int pcur = 0, scur = 0;
+  bool vel_full = true;
+  int since_sort = 0;
+  long long md_step = 0;
+  long long n_lattice = 0;
+  bool snapshot_valid = false;
+  bool lambda_pending = false;  // a thermostat factor waits for the next kModeStart
+  int xcd_remap = 1;
+  bool use_graph = true;
+  hipStream_t cap_stream = nullptr;
+  struct GraphEntry {
+    hipGraphExec_t exec;
+    int pcur, scur, since_sort;
+    bool vel_full;
+  };
+  std::map<std::tuple<int, int, int, bool, bool>, GraphEntry> graphs;
+  // per-kernel event timing (measurement aid)
+  bool timing = false;
+  struct Timed {
+    int cls;
+    int launches;
+    hipEvent_t a, b;
+  };
+  std::vector<Timed> timed;
+  Timed open_run{-1, 0, nullptr, nullptr};  // consecutive launches of one class
+  std::vector<hipEvent_t> event_pool;
+  double timed_ms[MDLG_K_NCLASS] = {0, 0, 0, 0, 0};
+  int64_t timed_n[MDLG_K_NCLASS] = {0, 0, 0, 0, 0};
+  std::string last_error = "no error";
+};
+
+namespace {
+
+size_t carve(mdlg_system* S, char* base) {
+  const Layout& L = S->L;
+  const int D = L.D;
+  const size_t N = (size_t)L.n_total;
+  Carve c;
+  for (int i = 0; i < 2; ++i) {
+    S->pos[i] = c.take<float>(base, N * D);
+    S->vel[i] = c.take<float>(base, N * D);
+    S->img[i] = c.take<int>(base, N * D);
+    S->id[i] = c.take<int>(base, N);
+    S->cell[i] = c.take<int>(base, N);
+  }
+  S->keyslot = c.take<int2>(base, N);
+  S->count = c.take<int>(base, (size_t)L.n_cells);
+  S->cell_start = c.take<int>(base, (size_t)L.n_cells + 1);
+  S->tile_sum = c.take<int>(base, (size_t)L.ntiles);
+  S->prev_u = c.take<int>(base, N * D);
+  S->prev_off = c.take<float>(base, N * D);
+  S->A = c.take<unsigned>(base, (size_t)L.n_sites * L.Q);
+  S->mom = c.take<long long>(base, (size_t)L.n_sites * L.nm);
+  S->dpart = c.take<double>(base, (size_t)L.nstrips * 2 * D);
+  S->kpart = c.take<double>(base, (size_t)L.nbricks * (D + 1));
+  S->kin = c.take<double>(base, L.reps.size() * (D + 1));
+  S->lambda = c.take<float>(base, L.reps.size());
+  S->err = c.take<unsigned>(base, 64);
+  S->reps = c.take<Replica>(base, L.reps.size());
+  S->bricks = c.take<int4>(base, L.bricks.size());
+  S->chunks = c.take<int4>(base, L.chunks.size());
+  S->strips = c.take<int4>(base, L.strips.size());
+  S->fcount = c.take<unsigned long long>(base, kMaxQ);
+  S->momsum = c.take<long long>(base, 16);
+  S->fout = c.take<double>(base, kMaxQ);
+  S->dispout = c.take<double>(base, 8);
+  S->acc_sorted = c.take<float>(base, N * D);
+  S->staging_bytes = std::max<size_t>(N * D * 4 * 4, size_t(4) << 20);
+  S->staging = c.take<char>(base, S->staging_bytes);
+  return c.off + 256;
+}
+
+Phys make_phys(const mdlg_config* c, const Layout& L) {
+  Phys P{};
+  P.s = (float)L.s;
+  P.inv_s = (float)(1.0 / L.s);
+  // fixed-point frame of the force kernel: coordinates reach at most the
+  // widest halo extent plus the cutoff reach, which must stay below 2^31
+  // units; at most 26 bits per cell keep pair separations exact in float
+  // after the integer difference (|dX| < (2 ns + 1) 2^F < 2^30)
+  const int nsz = (L.D == 3) ? L.ns : 0;
+  const int hmax = std::max(std::max(L.BX + 2 * L.ns, L.BY + 2 * L.ns), L.BZ + 2 * nsz) + L.ns + 2;
+  int lg = 0;
+  while ((1 << lg) < hmax) ++lg;
+  P.F = std::min(26, 31 - lg);
+  const double u = L.s / std::ldexp(1.0, P.F);
+  P.fscale = (float)(std::ldexp(1.0, P.F) / L.s);
+  P.rcq = (int)std::ceil((c->r_cut + L.margin) / u) + 1;
+  P.rc2_u = (float)((c->r_cut / u) * (c->r_cut / u));
+  P.sig2_u = (float)((c->sigma / u) * (c->sigma / u));
+  P.eps24m_u = (float)(24.0 * c->epsilon / (c->mass * u));
+  P.dt = (float)c->dt;
+  P.half_dt = (float)(0.5 * c->dt);
+  P.lo = (float)(-L.margin);
+  P.hi = (float)(L.s + L.margin);
+  P.mass = (float)c->mass;
+  P.ns = L.ns;
+  P.log2k = L.log2k;
+  P.vmax = c->vmax;
+  P.Q = L.Q;
+  P.nm = L.nm;
+  P.BX = L.BX;
+  P.BY = L.BY;
+  P.BZ = L.BZ;
+  P.forces_off = c->forces_off ? 1 : 0;
+  P.n_rep = (int)L.reps.size();
+  P.n_total = (int)L.n_total;
+  P.n_cells = (int)L.n_cells;
+  P.n_sites = (int)L.n_sites;
+  P.s_d = L.s;
+  return P;
+}
+
+mdlg_status hip_fail(mdlg_system* S, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  if (S) S->last_error = m; else g_create_error = m;
+  return MDLG_E_DEVICE;
+}
+
+#define HIPCHK(S, expr)                                  \
+  do {                                                   \
+    hipError_t e_ = (expr);                              \
+    if (e_ != hipSuccess) return hip_fail(S, e_, #expr); \
+  } while (0)
+
+mdlg_status check_launch(mdlg_system* S, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(S, e, what);
+  return MDLG_OK;
+}
+
+// ----- launch sequence
+
+hipEvent_t pool_event(mdlg_system* S) {
+  if (!S->event_pool.empty()) {
+    hipEvent_t e = S->event_pool.back();
+    S->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Close the open run of same-class launches with its stop event.
+void close_run(mdlg_system* S) {
+  if (S->open_run.cls < 0) return;
+  (void)hipEventRecord(S->open_run.b, S->stream);
+  S->timed.push_back(S->open_run);
+  S->open_run = {-1, 0, nullptr, nullptr};
+}
+
+// With timing on, consecutive launches of one kernel class share one event
+// pair, so the per-launch average carries the event overhead only once per
+// run (the gaps between the launches of a run are included).
+struct TimedLaunch {
+  TimedLaunch(mdlg_system* S, int cls) {
+    if (!S->timing) return;
+    if (S->open_run.cls == cls) {
+      S->open_run.launches += 1;
+      return;
+    }
+    close_run(S);
+    hipEvent_t a = pool_event(S), b = pool_event(S);
+    if (!a || !b) return;
+    (void)hipEventRecord(a, S->stream);
+    S->open_run = {cls, 1, a, b};
+  }
+};
+
+void drain_timing(mdlg_system* S) {
+  close_run(S);
+  for (auto& t : S->timed) {
+    float ms = 0.f;
+    if (hipEventSynchronize(t.b) == hipSuccess && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      S->timed_ms[t.cls] += ms;
+      S->timed_n[t.cls] += t.launches;
+    }
+    S->event_pool.push_back(t.a);
+    S->event_pool.push_back(t.b);
+  }
+  S->timed.clear();
+}
+
+SortArgs sort_args(mdlg_system* S) {
+  SortArgs a{};
+  a.P = S->P;
+  a.reps = S->reps;
+  a.chunks = S->chunks;
+  a.cell_start = S->cell_start;
+  a.pos = S->pos[S->pcur];
+  a.vel = S->vel[S->scur];
+  a.img = S->img[S->scur];
+  a.id = S->id[S->scur];
+  a.cell = S->cell[S->scur];
+  a.keyslot = S->keyslot;
+  a.count = S->count;
+  a.tile_sum = S->tile_sum;
+  a.pos_out = S->pos[S->pcur ^ 1];
+  a.vel_out = S->vel[S->scur ^ 1];
+  a.img_out = S->img[S->scur ^ 1];
+  a.id_out = S->id[S->scur ^ 1];
+  a.cell_out = S->cell[S->scur ^ 1];
+  a.err = S->err;
+  a.ntiles = S->L.ntiles;
+  return a;
+}
+
+void enqueue_sort(mdlg_system* S) {
+  SortArgs a = sort_args(S);
+  {
+    TimedLaunch t(S, MDLG_K_COUNT);
+    launch_count(S->D, S->L.nchunks, a, S->stream);
+  }
+  ScanArgs sc{};
+  sc.count = S->count;
+  sc.cell_start = S->cell_start;
+  sc.tile_sum = S->tile_sum;
+  sc.n = (int)S->L.n_cells;
+  sc.ntiles = S->L.ntiles;
+  {
+    TimedLaunch t(S, MDLG_K_SCAN);
+    launch_scan(sc, S->stream);
+  }
+  {
+    TimedLaunch t(S, MDLG_K_SCATTER);
+    launch_scatter(S->D, S->L.nchunks, a, S->stream);
+  }
+  S->pcur ^= 1;
+  S->scur ^= 1;
+  S->since_sort = 0;
+}
+
+void enqueue_force(mdlg_system* S, int mode, bool sort_follows, float* acc_out, double* kpart) {
+  ForceArgs a{};
+  a.P = S->P;
+  if (sort_follows) {
+    // the rebuild that follows canonicalises any move of up to one cell
+    a.P.lo = -S->P.s;
+    a.P.hi = 2.f * S->P.s;
+  }
+  a.reps = S->reps;
+  a.bricks = S->bricks;
+  a.cell_start = S->cell_start;
+  a.pos_in = S->pos[S->pcur];
+  a.pos_out = S->pos[S->pcur ^ 1];
+  a.vel = S->vel[S->scur];
+  a.acc_out = acc_out;
+  a.lambda = (mode == kModeStart && S->lambda_pending) ? S->lambda : nullptr;
+  a.kpart = kpart;
+  a.err = S->err;
+  a.mode = mode;
+  a.nbricks = S->L.nbricks;
+  a.xcd_remap = S->xcd_remap;
+  {
+    TimedLaunch t(S, MDLG_K_FORCE);
+    launch_force(S->D, a, S->stream);
+  }
+  if (mode == kModeStep || mode == kModeStart) S->pcur ^= 1;
+  if (mode == kModeStart) S->lambda_pending = false;
+}
+
+void enqueue_kin(mdlg_system* S, bool thermostat) {
+  if (S->timing) close_run(S);
+  KinArgs k{};
+  k.reps = S->reps;
+  k.kpart = S->kpart;
+  k.kin = S->kin;
+  k.lambda = S->lambda;
+  k.n_rep = (int)S->L.reps.size();
+  k.D = S->D;
+  k.thermostat = thermostat ? 1 : 0;
+  k.kT = S->cfg.kT;
+  k.mass = S->cfg.mass;
+  launch_kin(k, S->stream);
+}
+
+// One velocity-Verlet step; force_sort requests a rebuild right after it.
+void enqueue_md_step(mdlg_system* S, bool force_sort) {
+  const int mode = S->vel_full ? kModeStart : kModeStep;
+  const bool sort_next = force_sort || (S->since_sort + 1 >= S->L.sort_every);
+  enqueue_force(S, mode, sort_next, nullptr, nullptr);
+  S->vel_full = false;
+  S->since_sort += 1;
+  S->md_step += 1;
+  if (sort_next) enqueue_sort(S);
+}
+
+void enqueue_bin(mdlg_system* S, bool snapshot_only) {
+  BinArgs b{};
+  b.P = S->P;
+  b.reps = S->reps;
+  b.strips = S->strips;
+  b.cell_start = S->cell_start;
+  b.pos = S->pos[S->pcur];
+  b.img = S->img[S->scur];
+  b.id = S->id[S->scur];
+  b.cell = S->cell[S->scur];
+  b.prev_u = S->prev_u;
+  b.prev_off = S->prev_off;
+  b.A = S->A;
+  b.mom = S->mom;
+  b.dpart = S->dpart;
+  b.err = S->err;
+  b.snapshot_only = snapshot_only ? 1 : 0;
+  b.BSX = S->L.BSX;
+  {
+    TimedLaunch t(S, MDLG_K_BIN);
+    launch_bin(S->D, S->L.nstrips, b, S->stream);
+  }
+}
+
+void enqueue_snapshot(mdlg_system* S) {
+  if (S->since_sort != 0) enqueue_sort(S);
+  enqueue_bin(S, true);
+  S->snapshot_valid = true;
+}
+
+void enqueue_lattice_step(mdlg_system* S) {
+  const int steps = S->cfg.md_steps_per_lattice_step;
+  for (int s = 1; s <= steps; ++s) enqueue_md_step(S, s == steps);
+  enqueue_bin(S, false);
+  S->n_lattice += 1;
+}
+
+mdlg_status read_err(mdlg_system* S) {
+  unsigned e = 0;
+  HIPCHK(S, hipMemcpyAsync(&e, S->err, sizeof e, hipMemcpyDeviceToHost, S->stream));
+  HIPCHK(S, hipStreamSynchronize(S->stream));
+  if (e) {
+    std::string m = "device error word 0x" + std::to_string(e) + ":";
+    if (e & kErrMargin) m += " a particle left its cell by more than the rebuild margin (lower sort_every or dt);";
+    if (e & kErrNonFinite) m += " non-finite coordinates;";
+    if (e & kErrJump) m += " a particle moved more than one cell between rebuilds or started outside the box;";
+    if (e & kErrImage) m += " image counter out of range;";
+    if (e & kErrOverflow) m += " cell occupancy overflow;";
+    S->last_error = m;
+    return MDLG_E_UNSTABLE;
+  }
+  return MDLG_OK;
+}
+
+void zero_accumulators(mdlg_system* S) {
+  const Layout& L = S->L;
+  launch_fill_u32(S->A, 0u, (long long)L.n_sites * L.Q, S->stream);
+  launch_fill_u32(reinterpret_cast<unsigned*>(S->mom), 0u, (long long)L.n_sites * L.nm * 2, S->stream);
+  launch_fill_u32(reinterpret_cast<unsigned*>(S->dpart), 0u, (long long)L.nstrips * 2 * L.D * 2,
+                  S->stream);
+  S->n_lattice = 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+mdlg_status mdlg_describe(const mdlg_config* cfg, mdlg_layout* out) {
+  Layout L;
+  std::string msg;
+  if (!build_layout(cfg, &L, &msg)) {
+    g_create_error = msg;
+    return MDLG_E_INVALID;
+  }
+  if (out) *out = L.pub;
+  return MDLG_OK;
+}
+
+mdlg_status mdlg_workspace_bytes(const mdlg_config* cfg, size_t* bytes) {
+  if (!bytes) {
+    g_create_error = "bytes is NULL";
+    return MDLG_E_INVALID;
+  }
+  mdlg_system tmp;
+  std::string msg;
+  if (!build_layout(cfg, &tmp.L, &msg)) {
+    g_create_error = msg;
+    return MDLG_E_INVALID;
+  }
+  *bytes = carve(&tmp, nullptr);
+  return MDLG_OK;
+}
+
+mdlg_status mdlg_create(const mdlg_config* cfg, void* workspace_dev, size_t workspace_bytes,
+                        void* hip_stream, const float* pos_dev, const float* vel_dev,
+                        mdlg_system** out) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return MDLG_E_INVALID;
+  }
+  *out = nullptr;
+  if (!workspace_dev || !pos_dev || !vel_dev) {
+    g_create_error = "workspace, positions and velocities are required";
+    return MDLG_E_INVALID;
+  }
+  if (reinterpret_cast<uintptr_t>(workspace_dev) & 255) {
+    g_create_error = "workspace must be 256-byte aligned";
+    return MDLG_E_INVALID;
+  }
+  mdlg_system* S = new mdlg_system();
+  std::string msg;
+  if (!build_layout(cfg, &S->L, &msg)) {
+    g_create_error = msg;
+    delete S;
+    return MDLG_E_INVALID;
+  }
+  S->cfg = *cfg;
+  S->D = cfg->dim;
+  S->n_particles.assign(cfg->n_particles, cfg->n_particles + cfg->n_replicas);
+  S->lattice.assign(cfg->lattice, cfg->lattice + (size_t)cfg->n_replicas * cfg->dim);
+  S->cfg.n_particles = S->n_particles.data();
+  S->cfg.lattice = S->lattice.data();
+  const size_t need = carve(S, nullptr);
+  if (workspace_bytes < need) {
+    g_create_error = "workspace too small: need " + std::to_string(need) + " bytes";
+    delete S;
+    return MDLG_E_NOMEM;
+  }
+  S->ws = static_cast<char*>(workspace_dev);
+  S->ws_bytes = workspace_bytes;
+  carve(S, S->ws);
+  S->P = make_phys(cfg, S->L);
+  S->stream = static_cast<hipStream_t>(hip_stream);
+  if (const char* g = getenv("MDLG_NO_GRAPH")) S->use_graph = !(g[0] == '1');
+  if (const char* x = getenv("MDLG_NO_XCD_REMAP")) S->xcd_remap = !(x[0] == '1');
+  auto fail = [&](mdlg_status st) {
+    g_create_error = S->last_error;
+    delete S;
+    return st;
+  };
+#define CREATE_HIP(expr)                                              \
+  do {                                                                \
+    hipError_t e_ = (expr);                                           \
+    if (e_ != hipSuccess) return fail(hip_fail(S, e_, #expr));        \
+  } while (0)
+  const Layout& L = S->L;
+  CREATE_HIP(hipMemcpyAsync(S->reps, L.reps.data(), L.reps.size() * sizeof(Replica),
+                            hipMemcpyHostToDevice, S->stream));
+  CREATE_HIP(hipMemcpyAsync(S->bricks, L.bricks.data(), L.bricks.size() * sizeof(int4),
+                            hipMemcpyHostToDevice, S->stream));
+  CREATE_HIP(hipMemcpyAsync(S->chunks, L.chunks.data(), L.chunks.size() * sizeof(int4),
+                            hipMemcpyHostToDevice, S->stream));
+  CREATE_HIP(hipMemcpyAsync(S->strips, L.strips.data(), L.strips.size() * sizeof(int4),
+                            hipMemcpyHostToDevice, S->stream));
+  launch_fill_u32(reinterpret_cast<unsigned*>(S->count), 0u, L.n_cells, S->stream);
+  launch_fill_u32(reinterpret_cast<unsigned*>(S->tile_sum), 0u, L.ntiles, S->stream);
+  launch_fill_u32(S->err, 0u, 64, S->stream);
+  launch_fill_f32(S->lambda, 1.f, (long long)L.reps.size(), S->stream);
+  zero_accumulators(S);
+  // ingest into set 0, then the first counting sort
+  IngestArgs ia{};
+  ia.P = S->P;
+  ia.reps = S->reps;
+  ia.chunks = S->chunks;
+  ia.pos_abs = pos_dev;
+  ia.vel_in = vel_dev;
+  ia.pos = S->pos[0];
+  ia.vel = S->vel[0];
+  ia.img = S->img[0];
+  ia.id = S->id[0];
+  ia.cell = S->cell[0];
+  ia.err = S->err;
+  launch_ingest(S->D, L.nchunks, ia, S->stream);
+  S->pcur = 0;
+  S->scur = 0;
+  enqueue_sort(S);
+  enqueue_bin(S, true);
+  S->snapshot_valid = true;
+  S->vel_full = true;
+  if (check_launch(S, "mdlg_create kernels") != MDLG_OK) return fail(MDLG_E_DEVICE);
+  CREATE_HIP(hipStreamSynchronize(S->stream));
+  mdlg_status st = read_err(S);
+  if (st != MDLG_OK) return fail(st);
+  *out = S;
+  return MDLG_OK;
+}
+
+mdlg_status mdlg_step(mdlg_system* S, int64_t n) {
+  if (!S) return MDLG_E_INVALID;
+  if (n < 0) {
+    S->last_error = "n_md_steps must be >= 0";
+    return MDLG_E_INVALID;
+  }
+  const int te = S->cfg.thermostat_every;
+  for (int64_t i = 0; i < n; ++i) {
+    enqueue_md_step(S, false);
+    if (te > 0 && S->md_step % te == 0) {
+      enqueue_force(S, kModeFinish, false, nullptr, S->kpart);
+      enqueue_kin(S, true);
+      S->vel_full = true;
+      S->lambda_pending = true;
+    }
+  }
+  if (n > 0) S->snapshot_valid = false;
+  return check_launch(S, "mdlg_step");
+}
+
+mdlg_status mdlg_coarse_grain(mdlg_system* S, int64_t T) {
+  if (!S) return MDLG_E_INVALID;
+  if (T < 0) {
+    S->last_error = "n_lattice_steps must be >= 0";
+    return MDLG_E_INVALID;
+  }
+  if (T == 0) return MDLG_OK;
+  if (!S->snapshot_valid) enqueue_snapshot(S);
+  for (int64_t t = 0; t < T; ++t) {
+    if (!S->use_graph || S->timing) {
+      enqueue_lattice_step(S);
+      continue;
+    }
+    auto key = std::make_tuple(S->pcur, S->scur, S->since_sort, S->vel_full, S->lambda_pending);
+    auto it = S->graphs.find(key);
+    if (it == S->graphs.end()) {
+      if (!S->cap_stream) HIPCHK(S, hipStreamCreateWithFlags(&S->cap_stream, hipStreamNonBlocking));
+      hipStream_t user = S->stream;
+      const long long md0 = S->md_step, nl0 = S->n_lattice;
+      const int p0 = S->pcur, s0 = S->scur, ss0 = S->since_sort;
+      const bool v0 = S->vel_full, l0 = S->lambda_pending;
+      S->stream = S->cap_stream;
+      HIPCHK(S, hipStreamBeginCapture(S->cap_stream, hipStreamCaptureModeThreadLocal));
+      enqueue_lattice_step(S);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(S->cap_stream, &g);
+      S->stream = user;
+      if (e != hipSuccess) return hip_fail(S, e, "hipStreamEndCapture");
+      mdlg_system::GraphEntry ent{};
+      e = hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return hip_fail(S, e, "hipGraphInstantiate");
+      ent.pcur = S->pcur;
+      ent.scur = S->scur;
+      ent.since_sort = S->since_sort;
+      ent.vel_full = S->vel_full;
+      // the capture only recorded work; restore the state it started from
+      S->md_step = md0;
+      S->n_lattice = nl0;
+      S->pcur = p0;
+      S->scur = s0;
+      S->since_sort = ss0;
+      S->vel_full = v0;
+      S->lambda_pending = l0;
+      it = S->graphs.emplace(key, ent).first;
+    }
+    HIPCHK(S, hipGraphLaunch(it->second.exec, S->stream));
+    S->pcur = it->second.pcur;
+    S->scur = it->second.scur;
+    S->since_sort = it->second.since_sort;
+    S->vel_full = it->second.vel_full;
+    S->lambda_pending = false;
+    S->md_step += S->cfg.md_steps_per_lattice_step;
+    S->n_lattice += 1;
+  }
+  return check_launch(S, "mdlg_coarse_grain");
+}
+
+mdlg_status mdlg_get_f(mdlg_system* S, double* f, double* f_site, double* mom_site, uint64_t* counts,
+                       int64_t* n_samples, int64_t* n_overflow, double* disp,
+                       int64_t* n_lattice_steps) {
+  if (!S) return MDLG_E_INVALID;
+  const Layout& L = S->L;
+  const int D = S->D;
+  if (S->timing) close_run(S);
+  launch_fill_u32(reinterpret_cast<unsigned*>(S->fcount), 0u, kMaxQ * 2, S->stream);
+  launch_fill_u32(reinterpret_cast<unsigned*>(S->momsum), 0u, 32, S->stream);
+  FsumArgs fs{};
+  fs.A = S->A;
+  fs.mom = S->mom;
+  fs.fcount = S->fcount;
+  fs.momsum = S->momsum;
+  fs.n_sites = (int)L.n_sites;
+  fs.Q = L.Q;
+  fs.nm = L.nm;
+  fs.sites_per_block = 64;
+  launch_fsum(fs, S->stream);
+  FfinalArgs ff{};
+  ff.fcount = S->fcount;
+  ff.dpart = S->dpart;
+  ff.f = S->fout;
+  ff.disp = S->dispout;
+  ff.denom = (double)S->n_lattice * (double)L.n_sites;
+  ff.Q = L.Q;
+  ff.nstrips = L.nstrips;
+  ff.nd = 2 * D;
+  launch_ffinal(ff, S->stream);
+  mdlg_status st = check_launch(S, "mdlg_get_f kernels");
+  if (st != MDLG_OK) return st;
+  std::vector<double> fh(L.Q), dh(2 * D);
+  std::vector<unsigned long long> ch(L.Q);
+  std::vector<long long> mh(16);
+  HIPCHK(S, hipMemcpyAsync(fh.data(), S->fout, L.Q * sizeof(double), hipMemcpyDeviceToHost, S->stream));
+  HIPCHK(S, hipMemcpyAsync(ch.data(), S->fcount, L.Q * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           S->stream));
+  HIPCHK(S, hipMemcpyAsync(mh.data(), S->momsum, 16 * sizeof(long long), hipMemcpyDeviceToHost, S->stream));
+  HIPCHK(S, hipMemcpyAsync(dh.data(), S->dispout, 2 * D * sizeof(double), hipMemcpyDeviceToHost, S->stream));
+  if (f_site || mom_site) {
+    const double inv_T = S->n_lattice > 0 ? 1.0 / (double)S->n_lattice : 0.0;
+    const size_t per_site = (size_t)std::max(L.Q, L.nm) * sizeof(double);
+    const long long chunk = std::max<long long>(1, (long long)(S->staging_bytes / (2 * per_site)));
+    double* sf = reinterpret_cast<double*>(S->staging);
+    double* sm = sf + chunk * L.Q;
+    for (long long s0 = 0; s0 < L.n_sites; s0 += chunk) {
+      const long long cnt = std::min(chunk, L.n_sites - s0);
+      SiteAvgArgs sa{};
+      sa.A = S->A;
+      sa.mom = S->mom;
+      sa.f_site = f_site ? sf : nullptr;
+      sa.mom_site = mom_site ? sm : nullptr;
+      sa.first = s0;
+      sa.count = cnt;
+      sa.Q = L.Q;
+      sa.nm = L.nm;
+      sa.inv_T = inv_T;
+      launch_site_avg(sa, S->stream);
+      if (f_site)
+        HIPCHK(S, hipMemcpyAsync(f_site + s0 * L.Q, sf, cnt * L.Q * sizeof(double), hipMemcpyDeviceToHost,
+                                 S->stream));
+      if (mom_site)
+        HIPCHK(S, hipMemcpyAsync(mom_site + s0 * L.nm, sm, cnt * L.nm * sizeof(double),
+                                 hipMemcpyDeviceToHost, S->stream));
+      HIPCHK(S, hipStreamSynchronize(S->stream));
+    }
+  }
+  st = read_err(S);  // synchronises
+  if (f) std::memcpy(f, fh.data(), L.Q * sizeof(double));
+  if (counts) std::memcpy(counts, ch.data(), L.Q * sizeof(uint64_t));
+  if (disp) std::memcpy(disp, dh.data(), 2 * D * sizeof(double));
+  if (n_samples) *n_samples = S->n_lattice * L.n_sites;
+  if (n_overflow) *n_overflow = mh[1];
+  if (n_lattice_steps) *n_lattice_steps = S->n_lattice;
+  return st;
+}
+
+mdlg_status mdlg_get_kinetics(mdlg_system* S, double* out) {
+  if (!S || !out) return MDLG_E_INVALID;
+  enqueue_force(S, S->vel_full ? kModeProbe : kModeFinish, false, nullptr, S->kpart);
+  S->vel_full = true;
+  enqueue_kin(S, false);
+  mdlg_status st = check_launch(S, "mdlg_get_kinetics");
+  if (st != MDLG_OK) return st;
+  const size_t n = S->L.reps.size() * (S->D + 1);
+  HIPCHK(S, hipMemcpyAsync(out, S->kin, n * sizeof(double), hipMemcpyDeviceToHost, S->stream));
+  return read_err(S);
+}
+
+mdlg_status mdlg_reset_accumulators(mdlg_system* S) {
+  if (!S) return MDLG_E_INVALID;
+  zero_accumulators(S);
+  S->snapshot_valid = false;
+  return check_launch(S, "mdlg_reset_accumulators");
+}
+
+mdlg_status mdlg_get_state(mdlg_system* S, mdlg_particles* out) {
+  if (!S || !out) return MDLG_E_INVALID;
+  const Layout& L = S->L;
+  const int D = S->D;
+  const size_t nd = (size_t)L.n_total * D;
+  enqueue_force(S, S->vel_full ? kModeProbe : kModeFinish, false, S->acc_sorted, nullptr);
+  S->vel_full = true;
+  XportArgs x{};
+  x.P = S->P;
+  x.reps = S->reps;
+  x.chunks = S->chunks;
+  x.pos = S->pos[S->pcur];
+  x.vel = S->vel[S->scur];
+  x.img = S->img[S->scur];
+  x.id = S->id[S->scur];
+  x.cell = S->cell[S->scur];
+  x.acc = S->acc_sorted;
+  x.x_u = reinterpret_cast<int*>(S->staging);
+  x.x_off = reinterpret_cast<float*>(S->staging) + nd;
+  x.x_vel = reinterpret_cast<float*>(S->staging) + 2 * nd;
+  x.x_acc = reinterpret_cast<float*>(S->staging) + 3 * nd;
+  x.err = S->err;
+  launch_export(D, L.nchunks, x, S->stream);
+  mdlg_status st = check_launch(S, "mdlg_get_state");
+  if (st != MDLG_OK) return st;
+  if (out->ucell) HIPCHK(S, hipMemcpyAsync(out->ucell, x.x_u, nd * 4, hipMemcpyDeviceToHost, S->stream));
+  if (out->off) HIPCHK(S, hipMemcpyAsync(out->off, x.x_off, nd * 4, hipMemcpyDeviceToHost, S->stream));
+  if (out->vel) HIPCHK(S, hipMemcpyAsync(out->vel, x.x_vel, nd * 4, hipMemcpyDeviceToHost, S->stream));
+  if (out->acc) HIPCHK(S, hipMemcpyAsync(out->acc, x.x_acc, nd * 4, hipMemcpyDeviceToHost, S->stream));
+  if (out->prev_ucell)
+    HIPCHK(S, hipMemcpyAsync(out->prev_ucell, S->prev_u, nd * 4, hipMemcpyDeviceToHost, S->stream));
+  if (out->prev_off)
+    HIPCHK(S, hipMemcpyAsync(out->prev_off, S->prev_off, nd * 4, hipMemcpyDeviceToHost, S->stream));
+  return read_err(S);
+}
+
+mdlg_status mdlg_set_state(mdlg_system* S, const mdlg_particles* in) {
+  if (!S || !in) return MDLG_E_INVALID;
+  if (!in->ucell || !in->off || !in->vel) {
+    S->last_error = "set_state needs ucell, off and vel";
+    return MDLG_E_INVALID;
+  }
+  if ((in->prev_ucell == nullptr) != (in->prev_off == nullptr)) {
+    S->last_error = "prev_ucell and prev_off go together";
+    return MDLG_E_INVALID;
+  }
+  const Layout& L = S->L;
+  const int D = S->D;
+  const size_t nd = (size_t)L.n_total * D;
+  const float s = S->P.s;
+  for (size_t i = 0; i < nd; ++i) {
+    if (!(in->off[i] >= 0.f && in->off[i] < s) || !std::isfinite(in->vel[i])) {
+      S->last_error = "offset outside [0, s) or non-finite velocity at element " + std::to_string(i);
+      return MDLG_E_INVALID;
+    }
+    if (in->prev_off && !(in->prev_off[i] >= 0.f && in->prev_off[i] < s)) {
+      S->last_error = "prev offset outside [0, s) at element " + std::to_string(i);
+      return MDLG_E_INVALID;
+    }
+  }
+  // wait for queued work before overwriting the staging area
+  HIPCHK(S, hipStreamSynchronize(S->stream));
+  XportArgs x{};
+  x.P = S->P;
+  x.reps = S->reps;
+  x.chunks = S->chunks;
+  x.pos = S->pos[S->pcur];
+  x.vel = S->vel[S->scur];
+  x.img = S->img[S->scur];
+  x.id = S->id[S->scur];
+  x.cell = S->cell[S->scur];
+  x.x_u = reinterpret_cast<int*>(S->staging);
+  x.x_off = reinterpret_cast<float*>(S->staging) + nd;
+  x.x_vel = reinterpret_cast<float*>(S->staging) + 2 * nd;
+  x.err = S->err;
+  HIPCHK(S, hipMemcpyAsync(x.x_u, in->ucell, nd * 4, hipMemcpyHostToDevice, S->stream));
+  HIPCHK(S, hipMemcpyAsync(x.x_off, in->off, nd * 4, hipMemcpyHostToDevice, S->stream));
+  HIPCHK(S, hipMemcpyAsync(x.x_vel, in->vel, nd * 4, hipMemcpyHostToDevice, S->stream));
+  launch_import(D, L.nchunks, x, S->stream);
+  S->since_sort = 1;  // the imported arrays are in id order: rebuild
+  enqueue_sort(S);
+  if (in->prev_ucell) {
+    HIPCHK(S, hipMemcpyAsync(S->prev_u, in->prev_ucell, nd * 4, hipMemcpyHostToDevice, S->stream));
+    HIPCHK(S, hipMemcpyAsync(S->prev_off, in->prev_off, nd * 4, hipMemcpyHostToDevice, S->stream));
+  } else {
+    enqueue_bin(S, true);
+  }
+  S->snapshot_valid = true;
+  S->vel_full = true;
+  S->lambda_pending = false;
+  mdlg_status st = check_launch(S, "mdlg_set_state");
+  if (st != MDLG_OK) return st;
+  HIPCHK(S, hipStreamSynchronize(S->stream));
+  return read_err(S);
+}
+
+mdlg_status mdlg_set_timing(mdlg_system* S, int enable) {
+  if (!S) return MDLG_E_INVALID;
+  HIPCHK(S, hipStreamSynchronize(S->stream));
+  drain_timing(S);
+  for (int i = 0; i < MDLG_K_NCLASS; ++i) {
+    S->timed_ms[i] = 0.0;
+    S->timed_n[i] = 0;
+  }
+  S->timing = enable != 0;
+  return MDLG_OK;
+}
+
+mdlg_status mdlg_get_timing(mdlg_system* S, double* total_ms, int64_t* launches) {
+  if (!S) return MDLG_E_INVALID;
+  HIPCHK(S, hipStreamSynchronize(S->stream));
+  drain_timing(S);
+  for (int i = 0; i < MDLG_K_NCLASS; ++i) {
+    if (total_ms) total_ms[i] = S->timed_ms[i];
+    if (launches) launches[i] = S->timed_n[i];
+  }
+  return read_err(S);
+}
+
+mdlg_status mdlg_sync(mdlg_system* S) {
+  if (!S) return MDLG_E_INVALID;
+  return read_err(S);
+}
+
+const char* mdlg_last_error(const mdlg_system* S) {
+  return S ? S->last_error.c_str() : g_create_error.c_str();
+}
+
+void mdlg_destroy(mdlg_system* S) {
+  if (!S) return;
+  if (S->stream) (void)hipStreamSynchronize(S->stream);
+  for (auto& kv : S->graphs) (void)hipGraphExecDestroy(kv.second.exec);
+  drain_timing(S);
+  for (hipEvent_t e : S->event_pool) (void)hipEventDestroy(e);
+  if (S->cap_stream) (void)hipStreamDestroy(S->cap_stream);
+  delete S;
+}
+
+}  // extern "C"

@@ -1,0 +1,167 @@
+// Kernel argument blocks of the MDLG HIP library, shared by the kernels and
+// the host-side launch sequence.
+#pragma once
+
+#include "mdlg_device.h"
+
+namespace mdlg {
+
+struct IngestArgs {
+  Phys P;
+  const Replica* reps;
+  const int4* chunks;  // {replica, g0, g1, -}
+  const float* pos_abs;
+  const float* vel_in;
+  float* pos;
+  float* vel;
+  int* img;
+  int* id;
+  int* cell;
+  unsigned* err;
+};
+
+struct SortArgs {
+  Phys P;
+  const Replica* reps;
+  const int4* chunks;
+  const int* cell_start;
+  const float* pos;
+  const float* vel;
+  const int* img;
+  const int* id;
+  const int* cell;
+  int2* keyslot;
+  int* count;
+  int* tile_sum;
+  float* pos_out;
+  float* vel_out;
+  int* img_out;
+  int* id_out;
+  int* cell_out;
+  unsigned* err;
+  int ntiles;
+};
+
+struct ScanArgs {
+  int* count;
+  int* cell_start;
+  int* tile_sum;
+  int n;
+  int ntiles;
+};
+
+struct ForceArgs {
+  Phys P;
+  const Replica* reps;
+  const int4* bricks;  // {replica, bx, by, bz}
+  const int* cell_start;
+  const float* pos_in;
+  float* pos_out;
+  float* vel;
+  float* acc_out;      // optional
+  const float* lambda; // per replica rescale factor (kModeStart), null = 1
+  double* kpart;       // optional per-brick partials [nbricks][D + 1]
+  unsigned* err;
+  int mode;
+  int nbricks;
+  int xcd_remap;
+};
+
+struct KinArgs {
+  const Replica* reps;
+  const double* kpart;
+  double* kin;     // [n_rep][D + 1]
+  float* lambda;   // [n_rep]
+  int n_rep;
+  int D;
+  int thermostat;
+  double kT;
+  double mass;
+};
+
+struct BinArgs {
+  Phys P;
+  const Replica* reps;
+  const int4* strips;  // {replica, sx0, sy, sz}
+  const int* cell_start;
+  const float* pos;
+  const int* img;
+  const int* id;
+  const int* cell;
+  int* prev_u;
+  float* prev_off;
+  unsigned* A;
+  long long* mom;
+  double* dpart;       // [nstrips][2D]
+  unsigned* err;
+  int snapshot_only;
+  int BSX;
+};
+
+struct FsumArgs {
+  const unsigned* A;
+  const long long* mom;
+  unsigned long long* fcount;  // [Q]
+  long long* momsum;           // [nm]
+  int n_sites;
+  int Q;
+  int nm;
+  int sites_per_block;
+};
+
+struct FfinalArgs {
+  const unsigned long long* fcount;
+  const double* dpart;
+  double* f;       // [Q]
+  double* disp;    // [2D]
+  double denom;    // lattice steps * sites
+  int Q;
+  int nstrips;
+  int nd;          // 2D
+};
+
+struct SiteAvgArgs {
+  const unsigned* A;
+  const long long* mom;
+  double* f_site;    // [count][Q] or null
+  double* mom_site;  // [count][nm] or null
+  long long first;   // first site
+  long long count;   // sites in this chunk
+  int Q;
+  int nm;
+  double inv_T;
+};
+
+struct XportArgs {
+  Phys P;
+  const Replica* reps;
+  const int4* chunks;
+  float* pos;        // sorted state
+  float* vel;
+  int* img;
+  int* id;
+  int* cell;
+  const float* acc;  // sorted accelerations (export, optional)
+  int* x_u;          // id-ordered staging
+  float* x_off;
+  float* x_vel;
+  float* x_acc;      // optional
+  unsigned* err;
+};
+
+void launch_fill_u32(unsigned* p, unsigned v, long long n, hipStream_t s);
+void launch_fill_f32(float* p, float v, long long n, hipStream_t s);
+void launch_ingest(int D, int nchunks, const IngestArgs& a, hipStream_t s);
+void launch_count(int D, int nchunks, const SortArgs& a, hipStream_t s);
+void launch_scan(const ScanArgs& a, hipStream_t s);
+void launch_scatter(int D, int nchunks, const SortArgs& a, hipStream_t s);
+void launch_force(int D, const ForceArgs& a, hipStream_t s);
+void launch_kin(const KinArgs& a, hipStream_t s);
+void launch_bin(int D, int nstrips, const BinArgs& a, hipStream_t s);
+void launch_fsum(const FsumArgs& a, hipStream_t s);
+void launch_ffinal(const FfinalArgs& a, hipStream_t s);
+void launch_site_avg(const SiteAvgArgs& a, hipStream_t s);
+void launch_export(int D, int nchunks, const XportArgs& a, hipStream_t s);
+void launch_import(int D, int nchunks, const XportArgs& a, hipStream_t s);
+
+}  // namespace mdlg

@@ -1,0 +1,79 @@
+// Shared host/device definitions of the MDLG HIP library (kernels + host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mdlg {
+
+constexpr int kBlock = 256;          // threads per block for every kernel
+constexpr int kWaves = kBlock / 64;  // wave64
+constexpr int kScanTile = 1024;      // cells per block of the cell-start scan
+constexpr int kScanItems = kScanTile / kBlock;
+constexpr int kPartChunkMax = 512;   // particles per block of the per-particle kernels
+constexpr int kMaxStripSites = 16;   // lattice sites per block of the binning kernel
+constexpr int kMaxQ = 225;           // largest velocity window handled (V <= 7 in 2D, V <= 2 in 3D)
+
+// LDS budgets of the force kernel
+constexpr int kMaxHalo2 = 1024;      // halo cells per brick (2D)
+constexpr int kCap2 = 2048;          // staged particles per chunk (2D)
+constexpr int kMaxHalo3 = 2048;      // halo cells per brick (3D)
+constexpr int kCap3 = 2048;          // staged particles per chunk (3D)
+constexpr int kMaxRows = 64;         // brick rows (BY * BZ)
+
+// device error word bits
+constexpr unsigned kErrMargin = 1u;     // particle left its cell by more than the rebuild margin
+constexpr unsigned kErrNonFinite = 2u;  // non-finite position or velocity
+constexpr unsigned kErrJump = 4u;       // moved more than one cell between rebuilds / bad input
+constexpr unsigned kErrImage = 8u;      // image counter or unwrapped cell out of range
+constexpr unsigned kErrOverflow = 16u;  // more particles in one cell than a slot can index
+
+// force-kernel modes (what the velocity buffer holds on entry)
+enum StepMode : int {
+  kModeStep = 0,    // v(t - dt/2): complete the kick, kick again, drift
+  kModeStart = 1,   // v(t) (times lambda): kick, drift
+  kModeFinish = 2,  // v(t - dt/2): complete the kick only, store v(t)
+  kModeProbe = 3    // v(t): forces only (for readout of accelerations)
+};
+
+struct Replica {
+  int Mc[3];     // MD cells per axis
+  int M[3];      // lattice sites per axis
+  int cell_off;  // first global MD cell
+  int part_off;  // first global particle
+  int site_off;  // first global lattice site
+  int n;         // particles
+  int brick_off; // first force brick
+  int nbricks;   // force bricks
+};
+
+// Global physical and layout parameters (identical for all replicas).
+struct Phys {
+  float s;          // MD cell side
+  float inv_s;
+  int F;            // fixed-point bits per MD cell in the force kernel (unit u = s / 2^F)
+  float fscale;     // 2^F / s
+  int rcq;          // (r_cut + margin) / u, rounded up
+  float rc2_u;      // (r_cut / u)^2
+  float sig2_u;     // (sigma / u)^2
+  float eps24m_u;   // 24 eps / (m u)
+  float dt;
+  float half_dt;
+  float lo;         // -margin
+  float hi;         // s + margin
+  float mass;
+  int ns;           // stencil half-width in cells
+  int log2k;        // MD cells per lattice cell = 1 << log2k
+  int vmax;
+  int Q;
+  int nm;           // per-site moments
+  int BX, BY, BZ;   // brick extent
+  int forces_off;
+  int n_rep;
+  int n_total;
+  int n_cells;
+  int n_sites;
+  double s_d;       // MD cell side in double (displacement sums)
+};
+
+}  // namespace mdlg

@@ -1,0 +1,1040 @@
+// HIP kernels of the MDLG hot path for gfx950 (wave64).
+//
+// Particle state lives in HBM as structure-of-arrays sorted by MD cell:
+//   pos  float[N][D]  offset of the particle inside its MD cell (side s)
+//   vel  float[N][D]  velocity (half-step or full-step, see StepMode)
+//   img  int  [N][D]  periodic image counters
+//   id   int  [N]     particle id (index in the input)
+//   cell int  [N]     global MD-cell index at the last rebuild
+// MD cells of side s = dx / k tile every replica's box; cell_start[c] is the
+// first particle of cell c after the last counting sort.  Between rebuilds a
+// particle may leave its cell by at most the rebuild margin, which the force
+// stencil covers.
+//
+// Kernels:
+//   k_ingest   absolute positions -> (cell, offset), unsorted
+//   k_count    canonicalise (cell, offset, image) and count particles per cell
+//   k_scan     exclusive scan of the counts into cell_start
+//   k_scatter  stable-by-slot permutation of the state into cell order
+//   k_force    LJ forces with the neighbour cells of a brick staged in LDS, fused
+//              with the velocity-Verlet half kicks and the drift
+//   k_bin      MDLG binning (eq. MDni): lattice velocity from the unwrapped
+//              lattice cells at t and at the previous snapshot, LDS histogram
+//              per site strip with wave-aggregated atomics, flush to HBM
+//   k_fsum / k_ffinal / k_site_avg   f_i^eq readout (eq. fieq)
+//   k_kin      FP64 momentum / kinetic energy per replica, thermostat factor
+//   k_export / k_import              state in id order
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "mdlg_args.h"
+
+namespace mdlg {
+
+// ---------------------------------------------------------------- helpers
+
+template <int D>
+__device__ __forceinline__ void ldv(const float* __restrict__ p, int g, float (&v)[D]) {
+  if constexpr (D == 2) {
+    const float2 t = reinterpret_cast<const float2*>(p)[g];
+    v[0] = t.x;
+    v[1] = t.y;
+  } else {
+    const float* q = p + 3 * (size_t)g;
+    v[0] = q[0];
+    v[1] = q[1];
+    v[2] = q[2];
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void stv(float* __restrict__ p, int g, const float (&v)[D]) {
+  if constexpr (D == 2) {
+    reinterpret_cast<float2*>(p)[g] = make_float2(v[0], v[1]);
+  } else {
+    float* q = p + 3 * (size_t)g;
+    q[0] = v[0];
+    q[1] = v[1];
+    q[2] = v[2];
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void ldi(const int* __restrict__ p, int g, int (&v)[D]) {
+  if constexpr (D == 2) {
+    const int2 t = reinterpret_cast<const int2*>(p)[g];
+    v[0] = t.x;
+    v[1] = t.y;
+  } else {
+    const int* q = p + 3 * (size_t)g;
+    v[0] = q[0];
+    v[1] = q[1];
+    v[2] = q[2];
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void sti(int* __restrict__ p, int g, const int (&v)[D]) {
+  if constexpr (D == 2) {
+    reinterpret_cast<int2*>(p)[g] = make_int2(v[0], v[1]);
+  } else {
+    int* q = p + 3 * (size_t)g;
+    q[0] = v[0];
+    q[1] = v[1];
+    q[2] = v[2];
+  }
+}
+
+__device__ __forceinline__ int wrap_cell(int c, int m) {
+  return c < 0 ? c + m : (c >= m ? c - m : c);
+}
+
+__device__ __forceinline__ int floor_div(int a, int b) {
+  int q = a / b;
+  return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+template <int D>
+__device__ __forceinline__ void cell_coords(int local, const Replica& R, int (&c)[D]) {
+  c[0] = local % R.Mc[0];
+  if constexpr (D == 2) {
+    c[1] = local / R.Mc[0];
+  } else {
+    int r = local / R.Mc[0];
+    c[1] = r % R.Mc[1];
+    c[2] = r / R.Mc[1];
+  }
+}
+
+template <int D>
+__device__ __forceinline__ int cell_linear(const int (&c)[D], const Replica& R) {
+  if constexpr (D == 2)
+    return c[0] + R.Mc[0] * c[1];
+  else
+    return c[0] + R.Mc[0] * (c[1] + R.Mc[1] * c[2]);
+}
+
+// Bring an offset back into [0, s) by moving at most one cell, carrying the
+// wrap of the cell index into the image counter.  o - s is exact for o in
+// [s, 2s) (Sterbenz); when o + s rounds up to s the particle sits on the
+// boundary and stays in its cell with offset 0.  Returns false for a jump of
+// more than one cell or a non-finite offset (indices stay in range anyway).
+__device__ __forceinline__ bool canon(float& o, int& c, int& im, int mc, float s) {
+  if (o < 0.f) {
+    o = o + s;
+    c -= 1;
+    if (o >= s) {
+      o = 0.f;
+      c += 1;
+    }
+  } else if (o >= s) {
+    o = o - s;
+    c += 1;
+  }
+  const bool ok = (o >= 0.f) && (o < s);
+  if (c < 0) {
+    c += mc;
+    im -= 1;
+  } else if (c >= mc) {
+    c -= mc;
+    im += 1;
+  }
+  return ok;
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Exclusive scan of one int per thread over the block; *total gets the sum.
+__device__ __forceinline__ int block_excl_scan(int v, int* s_tmp, int* total) {
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) s_tmp[w] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int i = 0; i < kWaves; ++i) {
+      int t = s_tmp[i];
+      s_tmp[i] = run;
+      run += t;
+    }
+    s_tmp[kWaves] = run;
+  }
+  __syncthreads();
+  const int excl = incl - v + s_tmp[w];
+  *total = s_tmp[kWaves];
+  __syncthreads();
+  return excl;
+}
+
+__device__ __forceinline__ int block_sum(int v, int* s_tmp) {
+  int total;
+  (void)block_excl_scan(v, s_tmp, &total);
+  return total;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Add 1 per valid lane to base[key], one LDS/global atomic per distinct key of
+// the wave (lanes of a wave mostly share keys because particles are sorted).
+__device__ __forceinline__ void wave_agg_add(unsigned* base, int key, bool valid) {
+  unsigned long long act = __ballot(valid);
+  while (act) {
+    const int leader = __ffsll((long long)act) - 1;
+    const int lk = __shfl(key, leader, 64);
+    const unsigned long long same = __ballot(valid && key == lk) & act;
+    if (lane_id() == leader) atomicAdd(base + lk, (unsigned)__popcll(same));
+    act &= ~same;
+  }
+}
+
+__device__ __forceinline__ void wave_agg_add_i(int* base, int key, bool valid) {
+  unsigned long long act = __ballot(valid);
+  while (act) {
+    const int leader = __ffsll((long long)act) - 1;
+    const int lk = __shfl(key, leader, 64);
+    const unsigned long long same = __ballot(valid && key == lk) & act;
+    if (lane_id() == leader) atomicAdd(base + lk, (int)__popcll(same));
+    act &= ~same;
+  }
+}
+
+// ---------------------------------------------------------------- utilities
+
+__global__ void k_fill_u32(unsigned* __restrict__ p, unsigned v, long long n) {
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock)
+    p[i] = v;
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, float v, long long n) {
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock)
+    p[i] = v;
+}
+
+// ---------------------------------------------------------------- ingest
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_ingest(IngestArgs a) {
+  const int4 ch = a.chunks[blockIdx.x];
+  const Replica R = a.reps[ch.x];
+  for (int g = ch.y + threadIdx.x; g < ch.z; g += kBlock) {
+    float x[D], v[D], o[D];
+    int c[D], im[D];
+    ldv<D>(a.pos_abs, g, x);
+    ldv<D>(a.vel_in, g, v);
+    bool ok = true;
+    for (int k = 0; k < D; ++k) {
+      float q = floorf(x[k] * a.P.inv_s);
+      int ci = (q >= 0.f && q < (float)R.Mc[k]) ? (int)q : 0;
+      ok = ok && (q >= 0.f && q < (float)R.Mc[k]);
+      o[k] = x[k] - (float)ci * a.P.s;
+      im[k] = 0;
+      c[k] = ci;
+      ok = canon(o[k], c[k], im[k], R.Mc[k], a.P.s) && ok;
+      ok = ok && isfinite(v[k]);
+    }
+    if (!ok) atomicOr(a.err, kErrJump);
+    stv<D>(a.pos, g, o);
+    stv<D>(a.vel, g, v);
+    sti<D>(a.img, g, im);
+    a.id[g] = g;
+    a.cell[g] = R.cell_off + cell_linear<D>(c, R);
+  }
+}
+
+// ---------------------------------------------------------------- counting sort
+
+template <int D>
+__device__ __forceinline__ bool canon_particle(const SortArgs& a, const Replica& R, int g,
+                                               float (&o)[D], int (&c)[D], int (&im)[D]) {
+  ldv<D>(a.pos, g, o);
+  ldi<D>(a.img, g, im);
+  cell_coords<D>(a.cell[g] - R.cell_off, R, c);
+  bool ok = true;
+  for (int k = 0; k < D; ++k) ok = canon(o[k], c[k], im[k], R.Mc[k], a.P.s) && ok;
+  return ok;
+}
+
+// Slot of each particle inside its new cell.  A chunk of particles sorted by
+// their old cell maps into a narrow range of new cells: the block counts them
+// in an LDS histogram over that range (rank inside the block from the LDS
+// atomic), then takes one global atomic per distinct cell for its base.  A
+// chunk whose key range does not fit falls back to one global atomic per
+// particle.  Scan-tile totals are added without waiting for a result.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
+  constexpr int kHist = 2048;
+  constexpr int kPer = kPartChunkMax / kBlock;
+  constexpr int kTiles = kHist / kScanTile + 2;
+  __shared__ int s_cnt[kHist];
+  __shared__ int s_tile[kTiles];
+  __shared__ int s_lo, s_hi;
+  const int4 ch = a.chunks[blockIdx.x];
+  const Replica R = a.reps[ch.x];
+  if (threadIdx.x == 0) {
+    s_lo = 0x7fffffff;
+    s_hi = -1;
+  }
+  for (int i = threadIdx.x; i < kHist; i += kBlock) s_cnt[i] = 0;
+  if (threadIdx.x < kTiles) s_tile[threadIdx.x] = 0;
+  __syncthreads();
+  int key[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int g = ch.y + u * kBlock + (int)threadIdx.x;
+    key[u] = -1;
+    if (g < ch.z) {
+      float o[D];
+      int c[D], im[D];
+      if (!canon_particle<D>(a, R, g, o, c, im)) atomicOr(a.err, kErrJump);
+      key[u] = R.cell_off + cell_linear<D>(c, R);
+    }
+  }
+  int kmin = 0x7fffffff, kmax = -1;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u)
+    if (key[u] >= 0) {
+      kmin = min(kmin, key[u]);
+      kmax = max(kmax, key[u]);
+    }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    kmin = min(kmin, __shfl_xor(kmin, o, 64));
+    kmax = max(kmax, __shfl_xor(kmax, o, 64));
+  }
+  if (lane_id() == 0) {
+    atomicMin(&s_lo, kmin);
+    atomicMax(&s_hi, kmax);
+  }
+  __syncthreads();
+  const int lo = s_lo, span = s_hi - s_lo + 1;
+  if (span > kHist) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int g = ch.y + u * kBlock + (int)threadIdx.x;
+      if (key[u] >= 0) a.keyslot[g] = make_int2(key[u], atomicAdd(a.count + key[u], 1));
+      wave_agg_add_i(a.tile_sum, key[u] >= 0 ? key[u] / kScanTile : 0, key[u] >= 0);
+    }
+    return;
+  }
+  int rank[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) rank[u] = key[u] >= 0 ? atomicAdd(&s_cnt[key[u] - lo], 1) : 0;
+  __syncthreads();
+  // same-address global atomics serialise across the device: sum the scan
+  // tiles of this block in LDS and add each once
+  const int tile0 = lo / kScanTile;
+  for (int i = threadIdx.x; i < span; i += kBlock) {
+    const int c = s_cnt[i];
+    if (c) {
+      s_cnt[i] = atomicAdd(a.count + lo + i, c);
+      atomicAdd(&s_tile[(lo + i) / kScanTile - tile0], c);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kTiles && s_tile[threadIdx.x]) atomicAdd(a.tile_sum + tile0 + threadIdx.x, s_tile[threadIdx.x]);
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int g = ch.y + u * kBlock + (int)threadIdx.x;
+    if (key[u] >= 0) a.keyslot[g] = make_int2(key[u], s_cnt[key[u] - lo] + rank[u]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan(ScanArgs a) {
+  __shared__ int s_tmp[kWaves + 1];
+  const int b = blockIdx.x;
+  int pre = 0;
+  for (int t = threadIdx.x; t < b; t += kBlock) pre += a.tile_sum[t];
+  pre = block_sum(pre, s_tmp);
+  const int base = b * kScanTile + threadIdx.x * kScanItems;
+  int vals[kScanItems];
+  int sum = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int idx = base + i;
+    vals[i] = idx < a.n ? a.count[idx] : 0;
+    sum += vals[i];
+  }
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < a.n) a.count[base + i] = 0;
+  int total;
+  int run = pre + block_excl_scan(sum, s_tmp, &total);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int idx = base + i;
+    if (idx < a.n) a.cell_start[idx] = run;
+    run += vals[i];
+  }
+  if (b == a.ntiles - 1 && threadIdx.x == 0) a.cell_start[a.n] = pre + total;
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_scatter(SortArgs a) {
+  if (blockIdx.x == 0)
+    for (int t = threadIdx.x; t < a.ntiles; t += kBlock) a.tile_sum[t] = 0;
+  const int4 ch = a.chunks[blockIdx.x];
+  const Replica R = a.reps[ch.x];
+  for (int g = ch.y + threadIdx.x; g < ch.z; g += kBlock) {
+    float o[D];
+    int c[D], im[D];
+    (void)canon_particle<D>(a, R, g, o, c, im);
+    const int2 ks = a.keyslot[g];
+    const int dst = a.cell_start[ks.x] + ks.y;
+    float v[D];
+    ldv<D>(a.vel, g, v);
+    stv<D>(a.pos_out, dst, o);
+    stv<D>(a.vel_out, dst, v);
+    sti<D>(a.img_out, dst, im);
+    a.id_out[dst] = a.id[g];
+    a.cell_out[dst] = ks.x;
+  }
+}
+
+// ---------------------------------------------------------------- forces + VV
+//
+// One block per brick of MD cells.  The brick and a halo of `ns` cells on every
+// side are staged in LDS as int32 fixed-point coordinates in the brick frame,
+// X = hx * 2^F + rint(off * 2^F / s), so that a pair separation is an exact
+// integer difference converted to float once (no per-cell shifts, and no loss
+// of precision from large float coordinates).  Each target then visits only the
+// cell columns / rows / layers its cutoff sphere (widened by the rebuild
+// margin) can reach, reading contiguous LDS ranges row by row.  The LJ sum is
+// computed in units of u = s / 2^F; the acceleration comes out in physical
+// units because 24 eps / m was divided by u on the host.
+
+template <int D>
+struct ForceLds {
+  static constexpr int MAXH = (D == 2) ? kMaxHalo2 : kMaxHalo3;
+  static constexpr int CAP = (D == 2) ? kCap2 : kCap3;
+  using Coord = typename std::conditional<D == 2, int2, int4>::type;
+  int hs[MAXH + 1];   // LDS start of every halo cell (exclusive scan of counts)
+  int gs[MAXH];       // global start of every halo cell
+  Coord p[CAP];       // fixed-point coordinates of the staged particles
+  int rowpre[kMaxRows + 1];
+  int tmp[kWaves + 1];
+  double red[kWaves][D + 1];
+};
+
+__device__ __forceinline__ int fixed_coord(int h, float off, const Phys& P) {
+  return (h << P.F) + __float2int_rn(off * P.fscale);
+}
+
+// Accumulate the LJ acceleration of one candidate on the target at (X, Y, Z).
+// Branch-free: outside the cutoff, and for the target itself (r2 = 0), the
+// inverse square distance is replaced by 0 so that the term vanishes.
+template <int D, typename C>
+__device__ __forceinline__ void lj_pair(const C& q, int X, int Y, int Z, const Phys& P,
+                                        float (&f)[D]) {
+  const float dx = (float)(q.x - X);
+  const float dy = (float)(q.y - Y);
+  float r2 = dx * dx + dy * dy;
+  float dz = 0.f;
+  if constexpr (D == 3) {
+    dz = (float)(q.z - Z);
+    r2 += dz * dz;
+  }
+  const bool in = (r2 < P.rc2_u) && (r2 > 0.f);
+  const float ir2 = in ? __builtin_amdgcn_rcpf(r2) : 0.f;
+  const float sr2 = P.sig2_u * ir2;
+  const float sr6 = sr2 * sr2 * sr2;
+  const float gg = P.eps24m_u * ir2 * sr6 * (2.f * sr6 - 1.f);
+  f[0] -= gg * dx;
+  f[1] -= gg * dy;
+  if constexpr (D == 3) f[D - 1] -= gg * dz;
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
+  constexpr int CAP = ForceLds<D>::CAP;
+  __shared__ ForceLds<D> L;
+  int b = blockIdx.x;
+  if (a.xcd_remap) {
+    // blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous range of bricks so neighbouring bricks share an L2
+    const int per = gridDim.x >> 3;
+    b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  if (b >= a.nbricks) return;
+  const Phys& P = a.P;
+  const int4 br = a.bricks[b];
+  const Replica R = a.reps[br.x];
+  const int ns = P.ns;
+  const int nsz = (D == 3) ? ns : 0;
+  const int x0 = br.y * P.BX, y0 = br.z * P.BY, z0 = (D == 3) ? br.w * P.BZ : 0;
+  const int wx = min(P.BX, R.Mc[0] - x0);
+  const int wy = min(P.BY, R.Mc[1] - y0);
+  const int wz = (D == 3) ? min(P.BZ, R.Mc[2] - z0) : 1;
+  const int HX = wx + 2 * ns, HY = wy + 2 * ns, HZ = wz + 2 * nsz;
+  const int HXY = HX * HY;
+  const int nh = HXY * HZ;
+
+  // 1) particle count of every halo cell, exclusive scan -> LDS starts
+  const int ipt = (nh + kBlock - 1) / kBlock;
+  const int h0 = threadIdx.x * ipt, h1 = min(nh, h0 + ipt);
+  int mysum = 0;
+  for (int h = h0; h < h1; ++h) {
+    const int hx = h % HX, r = h / HX, hy = r % HY, hz = r / HY;
+    const int cx = wrap_cell(x0 - ns + hx, R.Mc[0]);
+    const int cy = wrap_cell(y0 - ns + hy, R.Mc[1]);
+    const int cz = (D == 3) ? wrap_cell(z0 - nsz + hz, R.Mc[2]) : 0;
+    const int gc = R.cell_off + cx + R.Mc[0] * (cy + R.Mc[1] * cz);
+    const int st = a.cell_start[gc], en = a.cell_start[gc + 1];
+    L.gs[h] = st;
+    L.hs[h] = en - st;
+    mysum += en - st;
+  }
+  int total;
+  int run = block_excl_scan(mysum, L.tmp, &total);
+  for (int h = h0; h < h1; ++h) {
+    const int cnt = L.hs[h];
+    L.hs[h] = run;
+    run += cnt;
+  }
+  const int nrows = wy * wz;
+  if (threadIdx.x == 0) L.hs[nh] = total;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int r = 0; r < nrows; ++r) {
+      const int hlo = ns + HX * ((ns + r % wy) + HY * (nsz + r / wy));
+      L.rowpre[r] = acc;
+      acc += L.hs[hlo + wx] - L.hs[hlo];
+    }
+    L.rowpre[nrows] = acc;
+  }
+  __syncthreads();
+  const int ntg = L.rowpre[nrows];
+  const int nchunks = (total + CAP - 1) / CAP;
+
+  // 2) staging of halo particles [cb, ce) as fixed-point coordinates
+  auto stage = [&](int cb, int ce) {
+    for (int v0 = cb + (int)threadIdx.x; v0 < ce; v0 += 4 * kBlock) {
+      int hh[4], g[4];
+      float p[4][D];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int v = v0 + u * kBlock;
+        int lo = 0;
+        if (v < ce) {
+          int hi = nh - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (L.hs[mid] <= v) lo = mid; else hi = mid - 1;
+          }
+        }
+        hh[u] = lo;
+        g[u] = L.gs[lo] + (v - L.hs[lo]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (v0 + u * kBlock < ce) ldv<D>(a.pos_in, g[u], p[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int v = v0 + u * kBlock;
+        if (v < ce) {
+          const int hx = hh[u] % HX, r = hh[u] / HX;
+          if constexpr (D == 2)
+            L.p[v - cb] = make_int2(fixed_coord(hx, p[u][0], P), fixed_coord(r, p[u][1], P));
+          else
+            L.p[v - cb] = make_int4(fixed_coord(hx, p[u][0], P), fixed_coord(r % HY, p[u][1], P),
+                                    fixed_coord(r / HY, p[u][2], P), 0);
+        }
+      }
+    }
+  };
+
+  const bool interact = !P.forces_off;
+  if (interact && nchunks == 1) {
+    stage(0, total);
+    __syncthreads();
+  }
+
+  double kin[D + 1];
+#pragma unroll
+  for (int k = 0; k <= D; ++k) kin[k] = 0.0;
+
+  for (int tb = 0; tb < ntg; tb += kBlock) {
+    const int t = tb + (int)threadIdx.x;
+    const bool valid = t < ntg;
+    int hxi = ns, hyi = ns, hzi = nsz, gi = 0;
+    if (valid) {
+      int lo = 0, hi = nrows - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.rowpre[mid] <= t) lo = mid; else hi = mid - 1;
+      }
+      const int row = lo;
+      hyi = ns + row % wy;
+      hzi = nsz + row / wy;
+      const int hbase = HX * (hyi + HY * hzi);
+      const int vi = L.hs[hbase + ns] + (t - L.rowpre[row]);
+      int clo = ns, chi = ns + wx - 1;
+      while (clo < chi) {
+        const int mid = (clo + chi + 1) >> 1;
+        if (L.hs[hbase + mid] <= vi) clo = mid; else chi = mid - 1;
+      }
+      hxi = clo;
+      const int hc = hbase + hxi;
+      gi = L.gs[hc] + (vi - L.hs[hc]);
+    }
+    float o[D], f[D], v[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      o[k] = 0.f;
+      f[k] = 0.f;
+      v[k] = 0.f;
+    }
+    if (valid) {
+      ldv<D>(a.pos_in, gi, o);
+      ldv<D>(a.vel, gi, v);
+    }
+    if (interact) {
+      const int X = fixed_coord(hxi, o[0], P);
+      const int Y = fixed_coord(hyi, o[1], P);
+      const int Z = (D == 3) ? fixed_coord(hzi, o[D - 1], P) : 0;
+      const int cx0 = max(0, (X - P.rcq) >> P.F), cx1 = min(HX - 1, (X + P.rcq) >> P.F);
+      const int cy0 = max(0, (Y - P.rcq) >> P.F), cy1 = min(HY - 1, (Y + P.rcq) >> P.F);
+      const int cz0 = (D == 3) ? max(0, (Z - P.rcq) >> P.F) : 0;
+      const int cz1 = (D == 3) ? min(HZ - 1, (Z + P.rcq) >> P.F) : 0;
+      for (int ci = 0; ci < nchunks; ++ci) {
+        const int cb = ci * CAP, ce = min(total, cb + CAP);
+        if (nchunks > 1) {
+          __syncthreads();
+          stage(cb, ce);
+          __syncthreads();
+        }
+        if (valid) {
+          for (int cz = cz0; cz <= cz1; ++cz) {
+            for (int cy = cy0; cy <= cy1; ++cy) {
+              const int hrow = HX * (cy + HY * cz);
+              const int jlo = max(L.hs[hrow + cx0], cb) - cb;
+              const int jhi = min(L.hs[hrow + cx1 + 1], ce) - cb;
+              int j = jlo;
+              for (; j + 3 < jhi; j += 4) {
+                typename ForceLds<D>::Coord q[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) q[u] = L.p[j + u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) lj_pair<D>(q[u], X, Y, Z, P, f);
+              }
+              for (; j < jhi; ++j) lj_pair<D>(L.p[j], X, Y, Z, P, f);
+            }
+          }
+        }
+      }
+    }
+    if (valid) {
+      float vf[D];
+      const float lam = (a.mode == kModeStart && a.lambda) ? a.lambda[br.x] : 1.f;
+      const bool drift = (a.mode == kModeStep || a.mode == kModeStart);
+      float on[D], vh[D];
+      bool ok = true;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        if (a.mode == kModeStep || a.mode == kModeFinish)
+          vf[k] = fmaf(P.half_dt, f[k], v[k]);
+        else
+          vf[k] = lam * v[k];
+        vh[k] = fmaf(P.half_dt, f[k], vf[k]);
+        on[k] = fmaf(vh[k], P.dt, o[k]);
+        ok = ok && (on[k] >= P.lo) && (on[k] < P.hi);
+      }
+      if (drift) {
+        if (!ok) atomicOr(a.err, kErrMargin);
+        stv<D>(a.pos_out, gi, on);
+        stv<D>(a.vel, gi, vh);
+      } else if (a.mode == kModeFinish) {
+        stv<D>(a.vel, gi, vf);
+      }
+      if (a.acc_out) stv<D>(a.acc_out, gi, f);
+      if (a.kpart) {
+        double e = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          kin[k] += (double)P.mass * (double)vf[k];
+          e += (double)vf[k] * (double)vf[k];
+        }
+        kin[D] += 0.5 * (double)P.mass * e;
+      }
+    }
+  }
+  if (a.kpart) {
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+      const double s = wave_sum_d(kin[k]);
+      if (lane_id() == 0) L.red[w][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x <= D) {
+      double s = 0.0;
+      for (int i = 0; i < kWaves; ++i) s += L.red[i][threadIdx.x];
+      a.kpart[(size_t)b * (D + 1) + threadIdx.x] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- kinetics
+
+// One block per replica: FP64 sums of the per-brick partials in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_kin(KinArgs a) {
+  __shared__ double s_red[kWaves][4];
+  const int r = blockIdx.x;
+  const Replica R = a.reps[r];
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = R.brick_off + threadIdx.x; b < R.brick_off + R.nbricks; b += kBlock)
+    for (int k = 0; k <= a.D; ++k) s[k] += a.kpart[(size_t)b * (a.D + 1) + k];
+  const int w = threadIdx.x >> 6;
+  for (int k = 0; k <= a.D; ++k) {
+    const double t = wave_sum_d(s[k]);
+    if (lane_id() == 0) s_red[w][k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < kWaves; ++i)
+      for (int k = 0; k <= a.D; ++k) tot[k] += s_red[i][k];
+    for (int k = 0; k <= a.D; ++k) a.kin[(size_t)r * (a.D + 1) + k] = tot[k];
+    if (a.thermostat) {
+      const double ke = tot[a.D];
+      a.lambda[r] = (ke > 0.0 && R.n > 1)
+                        ? (float)sqrt(a.kT * a.D * (R.n - 1) / (2.0 * ke))
+                        : 1.f;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- MDLG binning
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_bin(BinArgs a) {
+  extern __shared__ int s_dyn[];
+  __shared__ int s_rp[65];
+  __shared__ int s_rg[64];
+  __shared__ double s_red[kWaves][2 * D];
+  const Phys& P = a.P;
+  const int4 st = a.strips[blockIdx.x];
+  const Replica R = a.reps[st.x];
+  const int k = 1 << P.log2k;
+  const int sx0 = st.y, sy = st.z, sz = st.w;
+  const int wsx = min(a.BSX, R.M[0] - sx0);
+  const int Q = P.Q, nm = P.nm;
+  unsigned* s_h = reinterpret_cast<unsigned*>(s_dyn);  // [wsx][Q]
+  int* s_m = s_dyn + a.BSX * Q;                        // [wsx][nm]
+  if (!a.snapshot_only) {
+    for (int e = threadIdx.x; e < a.BSX * (Q + nm); e += kBlock) s_dyn[e] = 0;
+  }
+  // MD-cell rows covering this strip of sites
+  const int nrows = (D == 2) ? k : k * k;
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int r = 0; r < nrows; ++r) {
+      const int ry = sy * k + (r % k);
+      const int rz = (D == 3) ? sz * k + r / k : 0;
+      const int rowbase = R.cell_off + R.Mc[0] * (ry + R.Mc[1] * rz);
+      const int c0 = rowbase + sx0 * k, c1 = rowbase + (sx0 + wsx) * k;
+      s_rg[r] = a.cell_start[c0];
+      s_rp[r] = acc;
+      acc += a.cell_start[c1] - a.cell_start[c0];
+    }
+    s_rp[nrows] = acc;
+  }
+  __syncthreads();
+  const int np = s_rp[nrows];
+  double ds[D], dq[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    ds[q] = 0.0;
+    dq[q] = 0.0;
+  }
+  const int W = 2 * P.vmax + 1;
+  for (int base = 0; base < np; base += kBlock) {
+    const int t = base + (int)threadIdx.x;
+    const bool valid = t < np;
+    int sitek = 0, bink = 0;
+    bool inside = false;
+    int v[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) v[q] = 0;
+    if (valid) {
+      int lo = 0, hi = nrows - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_rp[mid] <= t) lo = mid; else hi = mid - 1;
+      }
+      const int g = s_rg[lo] + (t - s_rp[lo]);
+      int c[D], im[D], u[D], pu[D];
+      float o[D], po[D];
+      cell_coords<D>(a.cell[g] - R.cell_off, R, c);
+      ldi<D>(a.img, g, im);
+      ldv<D>(a.pos, g, o);
+      const int pid = a.id[g];
+#pragma unroll
+      for (int q = 0; q < D; ++q) u[q] = c[q] + R.Mc[q] * im[q];
+      if (!a.snapshot_only) {
+        ldi<D>(a.prev_u, pid, pu);
+        ldv<D>(a.prev_off, pid, po);
+        inside = true;
+        int bin = 0, stride = 1;
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+          v[q] = (u[q] >> P.log2k) - (pu[q] >> P.log2k);
+          inside = inside && (v[q] >= -P.vmax) && (v[q] <= P.vmax);
+          bin += (v[q] + P.vmax) * stride;
+          stride *= W;
+          const double dd = (double)(u[q] - pu[q]) * P.s_d + ((double)o[q] - (double)po[q]);
+          ds[q] += dd;
+          dq[q] += dd * dd;
+        }
+        sitek = (c[0] >> P.log2k) - sx0;
+        bink = sitek * Q + (inside ? bin : 0);
+      }
+      sti<D>(a.prev_u, pid, u);
+      stv<D>(a.prev_off, pid, o);
+    }
+    if (!a.snapshot_only) {
+      wave_agg_add(s_h, bink, valid && inside);
+      wave_agg_add_i(s_m, sitek * nm, valid);
+      if (valid) {
+        int* m = s_m + sitek * nm;
+        if (!inside) atomicAdd(m + 1, 1);
+        int kk = 2 + D;
+#pragma unroll
+        for (int p = 0; p < D; ++p) {
+          if (v[p] != 0) atomicAdd(m + 2 + p, v[p]);
+#pragma unroll
+          for (int q = p; q < D; ++q) {
+            const int pr = v[p] * v[q];
+            if (pr != 0) atomicAdd(m + kk, pr);
+            ++kk;
+          }
+        }
+      }
+    }
+  }
+  if (a.snapshot_only) return;
+  __syncthreads();
+  const int sy_lin = (D == 2) ? R.M[0] * sy : R.M[0] * (sy + R.M[1] * sz);
+  const size_t site0 = (size_t)R.site_off + sy_lin + sx0;
+  // flush: this block is the only writer of its sites; atomics without a
+  // return value let every update leave without waiting for the read
+  for (int e = threadIdx.x; e < wsx * Q; e += kBlock) {
+    const unsigned c = s_h[e];
+    if (c) atomicAdd(a.A + site0 * Q + e, c);
+  }
+  for (int e = threadIdx.x; e < wsx * nm; e += kBlock) {
+    const int c = s_m[e];
+    if (c)
+      atomicAdd(reinterpret_cast<unsigned long long*>(a.mom) + site0 * nm + e,
+                (unsigned long long)(long long)c);
+  }
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    const double s1 = wave_sum_d(ds[q]);
+    const double s2 = wave_sum_d(dq[q]);
+    if (lane_id() == 0) {
+      s_red[w][q] = s1;
+      s_red[w][D + q] = s2;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * D) {
+    double s = 0.0;
+    for (int i = 0; i < kWaves; ++i) s += s_red[i][threadIdx.x];
+    a.dpart[(size_t)blockIdx.x * 2 * D + threadIdx.x] += s;
+  }
+}
+
+// ---------------------------------------------------------------- readout
+
+__global__ __launch_bounds__(kBlock) void k_fsum(FsumArgs a) {
+  __shared__ unsigned long long s_q[kMaxQ];
+  __shared__ long long s_m[16];
+  for (int i = threadIdx.x; i < a.Q; i += kBlock) s_q[i] = 0ull;
+  if (threadIdx.x < 16) s_m[threadIdx.x] = 0;
+  __syncthreads();
+  const long long s0 = (long long)blockIdx.x * a.sites_per_block;
+  const long long s1 = min((long long)a.n_sites, s0 + a.sites_per_block);
+  for (long long e = s0 * a.Q + threadIdx.x; e < s1 * a.Q; e += kBlock) {
+    const unsigned c = a.A[e];
+    if (c) atomicAdd(&s_q[e % a.Q], (unsigned long long)c);
+  }
+  for (long long e = s0 * a.nm + threadIdx.x; e < s1 * a.nm; e += kBlock) {
+    const long long c = a.mom[e];
+    if (c) atomicAdd(reinterpret_cast<unsigned long long*>(&s_m[e % a.nm]),
+                     (unsigned long long)c);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < a.Q; i += kBlock)
+    if (s_q[i]) atomicAdd(a.fcount + i, s_q[i]);
+  if (threadIdx.x < a.nm && s_m[threadIdx.x])
+    atomicAdd(reinterpret_cast<unsigned long long*>(a.momsum + threadIdx.x),
+              (unsigned long long)s_m[threadIdx.x]);
+}
+
+__global__ void k_ffinal(FfinalArgs a) {
+  for (int i = threadIdx.x; i < a.Q; i += kBlock)
+    a.f[i] = a.denom > 0.0 ? (double)a.fcount[i] / a.denom : 0.0;
+  if (threadIdx.x < a.nd) {
+    double s = 0.0;
+    for (int b = 0; b < a.nstrips; ++b) s += a.dpart[(size_t)b * a.nd + threadIdx.x];
+    a.disp[threadIdx.x] = s;
+  }
+}
+
+__global__ void k_site_avg(SiteAvgArgs a) {
+  const long long tid = blockIdx.x * (long long)kBlock + threadIdx.x;
+  const long long stride = (long long)gridDim.x * kBlock;
+  if (a.f_site)
+    for (long long e = tid; e < a.count * a.Q; e += stride)
+      a.f_site[e] = (double)a.A[a.first * a.Q + e] * a.inv_T;
+  if (a.mom_site)
+    for (long long e = tid; e < a.count * a.nm; e += stride)
+      a.mom_site[e] = (double)a.mom[a.first * a.nm + e] * a.inv_T;
+}
+
+// ---------------------------------------------------------------- state I/O
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_export(XportArgs a) {
+  const int4 ch = a.chunks[blockIdx.x];
+  const Replica R = a.reps[ch.x];
+  for (int g = ch.y + threadIdx.x; g < ch.z; g += kBlock) {
+    float o[D], v[D];
+    int c[D], im[D], u[D];
+    ldv<D>(a.pos, g, o);
+    ldi<D>(a.img, g, im);
+    cell_coords<D>(a.cell[g] - R.cell_off, R, c);
+    for (int k = 0; k < D; ++k) {
+      (void)canon(o[k], c[k], im[k], R.Mc[k], a.P.s);
+      u[k] = c[k] + R.Mc[k] * im[k];
+    }
+    ldv<D>(a.vel, g, v);
+    const int pid = a.id[g];
+    sti<D>(a.x_u, pid, u);
+    stv<D>(a.x_off, pid, o);
+    stv<D>(a.x_vel, pid, v);
+    if (a.acc && a.x_acc) {
+      float f[D];
+      ldv<D>(a.acc, g, f);
+      stv<D>(a.x_acc, pid, f);
+    }
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_import(XportArgs a) {
+  const int4 ch = a.chunks[blockIdx.x];
+  const Replica R = a.reps[ch.x];
+  for (int g = ch.y + threadIdx.x; g < ch.z; g += kBlock) {
+    int u[D], c[D], im[D];
+    float o[D], v[D];
+    ldi<D>(a.x_u, g, u);
+    ldv<D>(a.x_off, g, o);
+    ldv<D>(a.x_vel, g, v);
+    for (int k = 0; k < D; ++k) {
+      im[k] = floor_div(u[k], R.Mc[k]);
+      c[k] = u[k] - im[k] * R.Mc[k];
+    }
+    stv<D>(a.pos, g, o);
+    stv<D>(a.vel, g, v);
+    sti<D>(a.img, g, im);
+    a.id[g] = g;
+    a.cell[g] = R.cell_off + cell_linear<D>(c, R);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+#define MDLG_LAUNCH_DIM(D, kern, grid, lds, stream, args)                        \
+  do {                                                                           \
+    if ((D) == 2)                                                                \
+      hipLaunchKernelGGL(kern<2>, dim3(grid), dim3(kBlock), lds, stream, args);  \
+    else                                                                         \
+      hipLaunchKernelGGL(kern<3>, dim3(grid), dim3(kBlock), lds, stream, args);  \
+  } while (0)
+
+void launch_fill_u32(unsigned* p, unsigned v, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  long long blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(kBlock), 0, s, p, v, n);
+}
+
+void launch_fill_f32(float* p, float v, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  long long blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)blocks), dim3(kBlock), 0, s, p, v, n);
+}
+
+void launch_ingest(int D, int nchunks, const IngestArgs& a, hipStream_t s) {
+  MDLG_LAUNCH_DIM(D, k_ingest, nchunks, 0, s, a);
+}
+
+void launch_count(int D, int nchunks, const SortArgs& a, hipStream_t s) {
+  MDLG_LAUNCH_DIM(D, k_count, nchunks, 0, s, a);
+}
+
+void launch_scan(const ScanArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3(a.ntiles), dim3(kBlock), 0, s, a);
+}
+
+void launch_scatter(int D, int nchunks, const SortArgs& a, hipStream_t s) {
+  MDLG_LAUNCH_DIM(D, k_scatter, nchunks, 0, s, a);
+}
+
+void launch_force(int D, const ForceArgs& a, hipStream_t s) {
+  int grid = a.nbricks;
+  if (a.xcd_remap) grid = ((a.nbricks + 7) / 8) * 8;
+  MDLG_LAUNCH_DIM(D, k_force, grid, 0, s, a);
+}
+
+void launch_kin(const KinArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_kin, dim3(a.n_rep), dim3(kBlock), 0, s, a);
+}
+
+void launch_bin(int D, int nstrips, const BinArgs& a, hipStream_t s) {
+  const size_t lds = (size_t)a.BSX * (a.P.Q + a.P.nm) * sizeof(int);
+  MDLG_LAUNCH_DIM(D, k_bin, nstrips, lds, s, a);
+}
+
+void launch_fsum(const FsumArgs& a, hipStream_t s) {
+  const int blocks = (a.n_sites + a.sites_per_block - 1) / a.sites_per_block;
+  hipLaunchKernelGGL(k_fsum, dim3(blocks), dim3(kBlock), 0, s, a);
+}
+
+void launch_ffinal(const FfinalArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_ffinal, dim3(1), dim3(kBlock), 0, s, a);
+}
+
+void launch_site_avg(const SiteAvgArgs& a, hipStream_t s) {
+  long long n = a.count * (a.Q > a.nm ? a.Q : a.nm);
+  long long blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_site_avg, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+}
+
+void launch_export(int D, int nchunks, const XportArgs& a, hipStream_t s) {
+  MDLG_LAUNCH_DIM(D, k_export, nchunks, 0, s, a);
+}
+
+void launch_import(int D, int nchunks, const XportArgs& a, hipStream_t s) {
+  MDLG_LAUNCH_DIM(D, k_import, nchunks, 0, s, a);
+}
+
+}  // namespace mdlg

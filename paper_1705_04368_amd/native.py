@@ -1,0 +1,294 @@
+"""ctypes binding of libmdlg.so (include/mdlg.h): argument marshalling only.
+
+Every computation runs in the HIP library; torch supplies device memory (the
+workspace and the initial arrays) and the stream.  Loading fails loudly when
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmdlg.so")
+
+MDLG_OK = 0
+STATUS = {0: "MDLG_OK", -1: "MDLG_E_INVALID", -2: "MDLG_E_DEVICE", -3: "MDLG_E_NOMEM",
+          -4: "MDLG_E_UNSTABLE", -5: "MDLG_E_STATE"}
+
+EXPORTED = ["mdlg_describe", "mdlg_workspace_bytes", "mdlg_create", "mdlg_step",
+            "mdlg_coarse_grain", "mdlg_get_f", "mdlg_get_kinetics", "mdlg_reset_accumulators",
+            "mdlg_get_state", "mdlg_set_state", "mdlg_set_timing", "mdlg_get_timing", "mdlg_sync",
+            "mdlg_last_error", "mdlg_destroy"]
+KERNEL_CLASSES = ["force", "count", "scan", "scatter", "bin"]
+
+
+class MdlgConfig(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_replicas", C.c_int32),
+                ("n_particles", C.POINTER(C.c_int32)), ("lattice", C.POINTER(C.c_int32)),
+                ("lattice_dx", C.c_double), ("epsilon", C.c_double), ("sigma", C.c_double),
+                ("mass", C.c_double), ("r_cut", C.c_double), ("forces_off", C.c_int32),
+                ("dt", C.c_double), ("md_steps_per_lattice_step", C.c_int32),
+                ("vmax", C.c_int32), ("thermostat_every", C.c_int32), ("kT", C.c_double),
+                ("md_cell_split", C.c_int32), ("sort_every", C.c_int32),
+                ("brick_x", C.c_int32), ("brick_y", C.c_int32), ("brick_z", C.c_int32)]
+
+
+class MdlgParticles(C.Structure):
+    _fields_ = [("ucell", C.POINTER(C.c_int32)), ("off", C.POINTER(C.c_float)),
+                ("vel", C.POINTER(C.c_float)), ("acc", C.POINTER(C.c_float)),
+                ("prev_ucell", C.POINTER(C.c_int32)), ("prev_off", C.POINTER(C.c_float))]
+
+
+class MdlgLayout(C.Structure):
+    _fields_ = [("md_cell_split", C.c_int32), ("sort_every", C.c_int32),
+                ("stencil", C.c_int32), ("n_velocities", C.c_int32), ("n_moments", C.c_int32),
+                ("brick", C.c_int32 * 3), ("n_total", C.c_int64), ("n_sites", C.c_int64),
+                ("n_cells", C.c_int64), ("n_bricks", C.c_int64), ("cell_side", C.c_double),
+                ("margin", C.c_double)]
+
+
+_lib = None
+
+
+def library_path():
+    return LIB_PATH
+
+
+def load():
+    """Load libmdlg.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "or python -m paper_1705_04368_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    st = C.c_int
+    lib.mdlg_describe.restype = st
+    lib.mdlg_describe.argtypes = [P(MdlgConfig), P(MdlgLayout)]
+    lib.mdlg_workspace_bytes.restype = st
+    lib.mdlg_workspace_bytes.argtypes = [P(MdlgConfig), P(C.c_size_t)]
+    lib.mdlg_create.restype = st
+    lib.mdlg_create.argtypes = [P(MdlgConfig), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
+                                C.c_void_p, P(C.c_void_p)]
+    lib.mdlg_step.restype = st
+    lib.mdlg_step.argtypes = [C.c_void_p, C.c_int64]
+    lib.mdlg_coarse_grain.restype = st
+    lib.mdlg_coarse_grain.argtypes = [C.c_void_p, C.c_int64]
+    lib.mdlg_get_f.restype = st
+    lib.mdlg_get_f.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               P(C.c_int64), P(C.c_int64), C.c_void_p, P(C.c_int64)]
+    lib.mdlg_get_kinetics.restype = st
+    lib.mdlg_get_kinetics.argtypes = [C.c_void_p, C.c_void_p]
+    lib.mdlg_reset_accumulators.restype = st
+    lib.mdlg_reset_accumulators.argtypes = [C.c_void_p]
+    lib.mdlg_get_state.restype = st
+    lib.mdlg_get_state.argtypes = [C.c_void_p, P(MdlgParticles)]
+    lib.mdlg_set_state.restype = st
+    lib.mdlg_set_state.argtypes = [C.c_void_p, P(MdlgParticles)]
+    lib.mdlg_set_timing.restype = st
+    lib.mdlg_set_timing.argtypes = [C.c_void_p, C.c_int]
+    lib.mdlg_get_timing.restype = st
+    lib.mdlg_get_timing.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.mdlg_sync.restype = st
+    lib.mdlg_sync.argtypes = [C.c_void_p]
+    lib.mdlg_last_error.restype = C.c_char_p
+    lib.mdlg_last_error.argtypes = [C.c_void_p]
+    lib.mdlg_destroy.restype = None
+    lib.mdlg_destroy.argtypes = [C.c_void_p]
+    _lib = lib
+    return lib
+
+
+class MdlgError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+def _check(status, handle=None):
+    if status != MDLG_OK:
+        msg = load().mdlg_last_error(handle)
+        raise MdlgError(status, msg.decode() if msg else "")
+
+
+def make_config(dim, n_particles, lattice, lattice_dx=4.0, epsilon=1.0, sigma=1.0, mass=1.0,
+                r_cut=2.5, forces_off=False, dt=0.005, md_steps_per_lattice_step=20, vmax=3,
+                thermostat_every=0, kT=1.0, md_cell_split=0, sort_every=0, brick=(0, 0, 0)):
+    """Build an MdlgConfig.  n_particles: int or sequence per replica; lattice:
+    sites per axis, an int, a (dim,) sequence or an (n_replicas, dim) array."""
+    n = np.atleast_1d(np.asarray(n_particles, dtype=np.int32))
+    lat = np.asarray(lattice, dtype=np.int32)
+    if lat.ndim == 0:
+        lat = np.full((len(n), dim), int(lat), dtype=np.int32)
+    elif lat.ndim == 1:
+        lat = np.broadcast_to(lat, (len(n), dim)).astype(np.int32)
+    n = np.ascontiguousarray(n)
+    lat = np.ascontiguousarray(lat, dtype=np.int32)
+    cfg = MdlgConfig()
+    cfg.dim = dim
+    cfg.n_replicas = len(n)
+    cfg.n_particles = n.ctypes.data_as(C.POINTER(C.c_int32))
+    cfg.lattice = lat.ctypes.data_as(C.POINTER(C.c_int32))
+    cfg._keep = (n, lat)  # the arrays must outlive the struct
+    cfg.lattice_dx = lattice_dx
+    cfg.epsilon, cfg.sigma, cfg.mass, cfg.r_cut = epsilon, sigma, mass, r_cut
+    cfg.forces_off = int(bool(forces_off))
+    cfg.dt = dt
+    cfg.md_steps_per_lattice_step = md_steps_per_lattice_step
+    cfg.vmax = vmax
+    cfg.thermostat_every = thermostat_every
+    cfg.kT = kT
+    cfg.md_cell_split = md_cell_split
+    cfg.sort_every = sort_every
+    cfg.brick_x, cfg.brick_y, cfg.brick_z = (int(b) for b in brick)
+    return cfg
+
+
+def describe(cfg):
+    out = MdlgLayout()
+    _check(load().mdlg_describe(C.byref(cfg), C.byref(out)))
+    return {"md_cell_split": out.md_cell_split, "sort_every": out.sort_every,
+            "stencil": out.stencil, "n_velocities": out.n_velocities,
+            "n_moments": out.n_moments, "brick": tuple(out.brick), "n_total": out.n_total,
+            "n_sites": out.n_sites, "n_cells": out.n_cells, "n_bricks": out.n_bricks,
+            "cell_side": out.cell_side, "margin": out.margin}
+
+
+def workspace_bytes(cfg):
+    b = C.c_size_t(0)
+    _check(load().mdlg_workspace_bytes(C.byref(cfg), C.byref(b)))
+    return int(b.value)
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+class System:
+    """One MDLG system (one or many replicas) on the current HIP device.
+
+    pos, vel: torch float32 device tensors of shape (n_total, dim) holding the
+    initial positions in [0, box) and velocities."""
+
+    def __init__(self, cfg, pos, vel, stream=None):
+        import torch
+        lib = load()
+        self.cfg = cfg
+        self.layout = describe(cfg)
+        self.dim = cfg.dim
+        self.n_total = int(self.layout["n_total"])
+        self.n_sites = int(self.layout["n_sites"])
+        self.Q = int(self.layout["n_velocities"])
+        self.nm = int(self.layout["n_moments"])
+        if pos.dtype != torch.float32 or vel.dtype != torch.float32:
+            raise TypeError("positions and velocities must be float32")
+        if tuple(pos.shape) != (self.n_total, self.dim) or tuple(vel.shape) != (self.n_total, self.dim):
+            raise ValueError(f"expected ({self.n_total}, {self.dim}) arrays")
+        if not pos.is_cuda or not vel.is_cuda:
+            raise ValueError("positions and velocities must be device tensors")
+        self.device = pos.device
+        nbytes = workspace_bytes(cfg)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self._pos = pos.contiguous()
+        self._vel = vel.contiguous()
+        h = C.c_void_p(0)
+        st = lib.mdlg_create(C.byref(cfg), C.c_void_p(aligned), C.c_size_t(nbytes),
+                             C.c_void_p(stream.cuda_stream), C.c_void_p(self._pos.data_ptr()),
+                             C.c_void_p(self._vel.data_ptr()), C.byref(h))
+        _check(st, None)
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().mdlg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n):
+        _check(load().mdlg_step(self.handle, int(n)), self.handle)
+
+    def coarse_grain(self, n_lattice_steps):
+        _check(load().mdlg_coarse_grain(self.handle, int(n_lattice_steps)), self.handle)
+
+    def sync(self):
+        _check(load().mdlg_sync(self.handle), self.handle)
+
+    def set_timing(self, enable):
+        _check(load().mdlg_set_timing(self.handle, int(bool(enable))), self.handle)
+
+    def get_timing(self):
+        """{kernel class: (total ms, launches)} since timing was enabled."""
+        ms = np.zeros(len(KERNEL_CLASSES))
+        n = np.zeros(len(KERNEL_CLASSES), dtype=np.int64)
+        _check(load().mdlg_get_timing(self.handle, ms.ctypes.data_as(C.c_void_p),
+                                      n.ctypes.data_as(C.c_void_p)), self.handle)
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def reset_accumulators(self):
+        _check(load().mdlg_reset_accumulators(self.handle), self.handle)
+
+    def get_f(self, per_site=False):
+        f = np.zeros(self.Q)
+        counts = np.zeros(self.Q, dtype=np.uint64)
+        disp = np.zeros(2 * self.dim)
+        ns, no, nl = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+        fs = np.zeros((self.n_sites, self.Q)) if per_site else None
+        ms = np.zeros((self.n_sites, self.nm)) if per_site else None
+        _check(load().mdlg_get_f(self.handle, f.ctypes.data_as(C.c_void_p),
+                                 fs.ctypes.data_as(C.c_void_p) if per_site else None,
+                                 ms.ctypes.data_as(C.c_void_p) if per_site else None,
+                                 counts.ctypes.data_as(C.c_void_p), C.byref(ns), C.byref(no),
+                                 disp.ctypes.data_as(C.c_void_p), C.byref(nl)), self.handle)
+        out = {"f": f, "counts": counts, "n_samples": ns.value, "n_overflow": no.value,
+               "disp_sum": disp[: self.dim].copy(), "disp_sq": disp[self.dim:].copy(),
+               "n_lattice_steps": nl.value}
+        if per_site:
+            out["f_site"] = fs
+            out["mom_site"] = ms
+        return out
+
+    def kinetics(self):
+        out = np.zeros((int(self.cfg.n_replicas), self.dim + 1))
+        _check(load().mdlg_get_kinetics(self.handle, out.ctypes.data_as(C.c_void_p)), self.handle)
+        return out
+
+    def get_state(self):
+        n, d = self.n_total, self.dim
+        arrs = {"ucell": np.zeros((n, d), dtype=np.int32), "off": np.zeros((n, d), dtype=np.float32),
+                "vel": np.zeros((n, d), dtype=np.float32), "acc": np.zeros((n, d), dtype=np.float32),
+                "prev_ucell": np.zeros((n, d), dtype=np.int32),
+                "prev_off": np.zeros((n, d), dtype=np.float32)}
+        p = MdlgParticles(_ip(arrs["ucell"]), _fp(arrs["off"]), _fp(arrs["vel"]), _fp(arrs["acc"]),
+                          _ip(arrs["prev_ucell"]), _fp(arrs["prev_off"]))
+        _check(load().mdlg_get_state(self.handle, C.byref(p)), self.handle)
+        return arrs
+
+    def set_state(self, ucell, off, vel, prev_ucell=None, prev_off=None):
+        n, d = self.n_total, self.dim
+        u = np.ascontiguousarray(ucell, dtype=np.int32).reshape(n, d)
+        o = np.ascontiguousarray(off, dtype=np.float32).reshape(n, d)
+        v = np.ascontiguousarray(vel, dtype=np.float32).reshape(n, d)
+        pu = None if prev_ucell is None else np.ascontiguousarray(prev_ucell, dtype=np.int32).reshape(n, d)
+        po = None if prev_off is None else np.ascontiguousarray(prev_off, dtype=np.float32).reshape(n, d)
+        p = MdlgParticles(_ip(u), _fp(o), _fp(v), None, _ip(pu) if pu is not None else None,
+                          _fp(po) if po is not None else None)
+        _check(load().mdlg_set_state(self.handle, C.byref(p)), self.handle)

@@ -1,0 +1,112 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the header
+declares, and validates configurations on the host (no device calls)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1705_04368_amd import native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "mdlg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mdlg_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = native.load()
+    syms = declared_symbols()
+    assert len(syms) >= 13
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert sorted(native.EXPORTED) == syms
+
+
+def test_describe_config1():
+    cfg = native.make_config(2, 2048, 16, lattice_dx=4.0, dt=0.005, md_steps_per_lattice_step=20,
+                             vmax=3, kT=1.0)
+    d = native.describe(cfg)
+    assert d["n_velocities"] == 49
+    assert d["n_moments"] == 7
+    assert d["n_sites"] == 256
+    assert d["n_total"] == 2048
+    k = d["md_cell_split"]
+    assert k in (1, 2, 4, 8)
+    assert d["n_cells"] == 256 * k * k
+    assert d["cell_side"] == 4.0 / k
+    assert d["stencil"] * d["cell_side"] >= 2.5
+    assert d["margin"] > 0
+    assert 1 <= d["sort_every"] <= 20
+    assert native.workspace_bytes(cfg) > 2048 * 2 * 4 * 4
+
+
+def test_describe_3d_and_replicas():
+    cfg = native.make_config(3, 4194304, 48, lattice_dx=4.0, dt=0.004, vmax=2, kT=1.5)
+    d = native.describe(cfg)
+    assert d["n_velocities"] == 125 and d["n_moments"] == 11 and d["n_sites"] == 48 ** 3
+    cfg = native.make_config(2, [968, 2048, 66248], [[11, 11], [16, 16], [91, 91]], vmax=3)
+    d = native.describe(cfg)
+    assert d["n_total"] == 968 + 2048 + 66248
+    assert d["n_sites"] == 121 + 256 + 8281
+
+
+@pytest.mark.parametrize("change,msg", [
+    (dict(dim=4), "dim"),
+    (dict(vmax=8), "vmax"),
+    (dict(dt=0.0), "dt"),
+    (dict(md_cell_split=3), "power of two"),
+    (dict(r_cut=40.0), "box side"),
+    (dict(thermostat_every=5, kT=0.0), "kT"),
+    (dict(md_steps_per_lattice_step=0), "md_steps"),
+])
+def test_invalid_configs_rejected(change, msg):
+    kw = dict(dim=2, n_particles=100, lattice=8, lattice_dx=4.0)
+    kw.update({k: v for k, v in change.items() if k in ("dim",)})
+    extra = {k: v for k, v in change.items() if k != "dim"}
+    cfg = native.make_config(kw["dim"], kw["n_particles"], 8, lattice_dx=4.0, **extra)
+    with pytest.raises(native.MdlgError) as e:
+        native.describe(cfg)
+    assert e.value.status == -1
+    assert msg in str(e.value)
+
+
+def test_vmax_window_limit_3d():
+    cfg = native.make_config(3, 1000, 8, vmax=3)
+    with pytest.raises(native.MdlgError, match="velocity window"):
+        native.describe(cfg)
+
+
+def test_create_rejects_null_inputs_without_device():
+    lib = native.load()
+    cfg = native.make_config(2, 100, 8)
+    h = C.c_void_p(0)
+    st = lib.mdlg_create(C.byref(cfg), None, 0, None, None, None, C.byref(h))
+    assert st == -1
+    assert b"required" in lib.mdlg_last_error(None)
+    assert not h.value
+    # misaligned workspace is rejected before any device call
+    st = lib.mdlg_create(C.byref(cfg), C.c_void_p(0x1001), 1 << 20, None, C.c_void_p(0x2000),
+                         C.c_void_p(0x3000), C.byref(h))
+    assert st == -1 and b"aligned" in lib.mdlg_last_error(None)
+
+
+def test_too_small_workspace_rejected():
+    lib = native.load()
+    cfg = native.make_config(2, 100, 8)
+    h = C.c_void_p(0)
+    st = lib.mdlg_create(C.byref(cfg), C.c_void_p(0x10000), 1024, None, C.c_void_p(0x2000),
+                         C.c_void_p(0x3000), C.byref(h))
+    assert st == -3
+    assert b"too small" in lib.mdlg_last_error(None)
+
+
+def test_null_handle_calls_are_invalid():
+    lib = native.load()
+    assert lib.mdlg_step(None, 1) == -1
+    assert lib.mdlg_coarse_grain(None, 1) == -1
+    assert lib.mdlg_sync(None) == -1
+    lib.mdlg_destroy(None)

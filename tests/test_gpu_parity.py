@@ -1,0 +1,320 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars (per particle / per site):
+* binning and all integer accumulators: bit-exact on identical positions;
+* forces: |F_gpu - F_ref| <= 1e-5 max(|F_ref|, F_rms), F_ref the FP64 oracle
+  on the same float32 positions;
+* 20-step trajectories from one state: |x_gpu - x_ref| <= 1e-4 sigma
+  (unwrapped) and |v_gpu - v_ref| <= 1e-4 sqrt(kT/m);
+* ideal gas: identical counts up to particles within float rounding of a
+  cell edge, and the wedge / closed form of the paper within sampling error.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import closed_form as cf
+from tests.gpu_util import force_error, make_system, say, unwrapped, wrapped
+
+pytestmark = pytest.mark.gpu
+
+
+# ------------------------------------------------------------------ binning
+
+@pytest.mark.parametrize("dim,M,k,vmax", [(2, 8, 1, 3), (2, 6, 2, 1), (2, 5, 4, 0),
+                                         (3, 4, 1, 2), (3, 3, 2, 1)])
+def test_binning_bit_exact_edge_cases(dim, M, k, vmax):
+    from paper_1705_04368_amd import make_config
+    dx = 4.0
+    n = 3000 if dim == 2 else 4000
+    say(f"binning edge cases dim={dim} M={M} k={k} V={vmax}")
+    cfg = make_config(dim, n, M, lattice_dx=dx, dt=0.005, md_steps_per_lattice_step=1, vmax=vmax,
+                      forces_off=True, md_cell_split=k, sort_every=1)
+    pos, _ = synth.lj_initial_state(dim, n, M * dx, 1.0, seed=5, r_min=0.0)
+    sysg = make_system(cfg, pos, np.zeros_like(pos))
+    s = sysg.layout["cell_side"]
+    assert sysg.layout["md_cell_split"] == k
+    st = synth.binning_edge_state(dim, M, k, vmax, n, seed=17 + dim + k, s=s)
+    sysg.set_state(st["ucell"], st["off"], np.zeros((n, dim), np.float32),
+                   st["prev_ucell"], st["prev_off"])
+    sysg.coarse_grain(1)
+    out = sysg.get_f(per_site=True)
+    xu_now = st["ucell"].astype(np.float64) * s + st["off"].astype(np.float64)
+    xu_prev = st["prev_ucell"].astype(np.float64) * s + st["prev_off"].astype(np.float64)
+    lat = oracle.make_lattice(dim, (M,) * dim, dx, vmax)
+    ref = oracle.bin_step(lat, dim, xu_prev, xu_now)
+    got_A = np.rint(out["f_site"]).astype(np.int64)
+    got_m = np.rint(out["mom_site"]).astype(np.int64)
+    np.testing.assert_array_equal(got_A, ref["A"].astype(np.int64))
+    np.testing.assert_array_equal(got_m, ref["mom"])
+    assert out["n_overflow"] == int(ref["mom"][:, 1].sum()) > 0
+    np.testing.assert_array_equal(out["counts"], ref["A"].sum(axis=0))
+    np.testing.assert_allclose(out["disp_sum"], ref["dsum"], rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(out["disp_sq"], ref["dsq"], rtol=1e-12, atol=1e-9)
+    # the snapshot moved to the current positions
+    after = sysg.get_state()
+    np.testing.assert_array_equal(after["prev_ucell"], st["ucell"])
+    np.testing.assert_array_equal(after["ucell"], st["ucell"])
+    np.testing.assert_allclose(after["prev_off"], st["off"], rtol=0, atol=1e-37)
+
+
+# ------------------------------------------------------------------ forces
+
+def _force_case(dim, seed, k, brick=(0, 0, 0), dense=False, equil_steps=0):
+    from paper_1705_04368_amd import make_config
+    if dim == 2:
+        # dense: rho = 1.13, so a 64x3-cell brick stages more particles than one
+        # LDS chunk holds and the kernel streams its halo in several chunks
+        M, n, dx = (16, 2048, 4.0) if not dense else (40, 28877, 4.0)
+    else:
+        M, n, dx = 5, 4740, 4.0
+    box = M * dx
+    pos, vel = synth.lj_initial_state(dim, n, box, 1.0, seed=seed, r_min=0.8 if not dense else 0.82)
+    if equil_steps:
+        md = oracle.make_md(dim, n, box, dt=0.005)
+        ost = oracle.OracleState(md, pos, vel)
+        ost.run(equil_steps, thermo_every=10, kT=1.0)
+        pos = ost.x.astype(np.float32)
+        pos = np.where(pos >= np.float32(box), np.float32(0.0), pos)
+        vel = ost.v.astype(np.float32)
+    cfg = make_config(dim, n, M, lattice_dx=dx, dt=0.005, vmax=1 if dim == 3 else 3,
+                      md_cell_split=k, brick=brick, kT=1.0)
+    return cfg, pos, vel, box, n, M
+
+
+@pytest.mark.parametrize("dim,k,brick,dense,equil", [
+    (2, 1, (0, 0, 0), False, 0), (2, 2, (0, 0, 0), False, 0), (2, 4, (0, 0, 0), False, 0),
+    (2, 1, (64, 3, 1), True, 0), (2, 1, (5, 2, 1), False, 300), (3, 1, (0, 0, 0), False, 0),
+    (3, 2, (0, 0, 0), False, 0), (3, 2, (3, 2, 2), False, 0)])
+def test_forces_match_oracle(dim, k, brick, dense, equil):
+    cfg, pos, vel, box, n, M = _force_case(dim, 31 + k, k, brick, dense, equil)
+    say(f"forces dim={dim} k={k} brick={brick} dense={dense} equil={equil}")
+    sysg = make_system(cfg, pos, vel)
+    st = sysg.get_state()
+    s = sysg.layout["cell_side"]
+    mc = M * sysg.layout["md_cell_split"]
+    xw = wrapped(st, s, mc)
+    # the state the GPU holds is exactly the input (float32 -> cell + offset)
+    np.testing.assert_array_equal(xw, pos.astype(np.float64))
+    md = oracle.make_md(dim, n, box)
+    acc, _ = oracle.forces(md, xw)
+    err = force_error(st["acc"], acc)
+    say(f"  max rel force error {err.max():.3e}  median {np.median(err):.3e}")
+    assert err.max() <= 1e-5
+    np.testing.assert_array_equal(st["vel"], vel)
+
+
+# ------------------------------------------------------------------ trajectories
+
+@pytest.mark.parametrize("dim,sort_every", [(2, 0), (2, 1), (2, 7), (3, 0)])
+def test_twenty_step_trajectory(dim, sort_every):
+    # from an equilibrated state (oracle, 300 thermostatted steps)
+    cfg, pos, vel, box, n, M = _force_case(dim, 77, 2 if dim == 3 else 1, equil_steps=300)
+    cfg.sort_every = sort_every
+    say(f"trajectory dim={dim} sort_every={sort_every}")
+    sysg = make_system(cfg, pos, vel)
+    sysg.step(20)
+    st = sysg.get_state()
+    md = oracle.make_md(dim, n, box, dt=0.005)
+    ost = oracle.OracleState(md, pos, vel)
+    ost.run(20)
+    dxmax = np.abs(unwrapped(st, sysg.layout["cell_side"]) - ost.unwrapped).max()
+    dvmax = np.abs(st["vel"].astype(np.float64) - ost.v).max()
+    say(f"  max |dx| {dxmax:.3e}  max |dv| {dvmax:.3e}")
+    assert dxmax <= 1e-4
+    assert dvmax <= 1e-4
+
+
+# ------------------------------------------------------------------ ideal gas
+
+def test_ideal_gas_counts_match_oracle_and_closed_form():
+    from paper_1705_04368_amd import make_config
+    dim, n, M, dx, kT = 2, 2048, 16, 4.0, 1.0
+    box = M * dx
+    pos, vel = synth.lj_initial_state(dim, n, box, kT, seed=1)
+    steps, T = 320, 40  # Delta t = 1.6: a = 0.4
+    cfg = make_config(dim, n, M, lattice_dx=dx, dt=0.005, md_steps_per_lattice_step=steps, vmax=3,
+                      forces_off=True, kT=kT)
+    say("ideal gas f_i")
+    sysg = make_system(cfg, pos, vel)
+    sysg.coarse_grain(T)
+    g = sysg.get_f(per_site=True)
+    md = oracle.make_md(dim, n, box, dt=0.005, forces_off=True)
+    ost = oracle.OracleState(md, pos, vel, use_cells=False)
+    lat = oracle.make_lattice(dim, (M, M), dx, 3)
+    o = ost.mdlg(lat, steps, T)
+    go = g["counts"].astype(np.int64)
+    oo = o["A"].sum(axis=0).astype(np.int64)
+    # Free flight has the closed form x0 + v t.  The float32 cell offsets drift
+    # from it by eps (measured at the end); a particle can bin differently only
+    # at a lattice step where its exact position lies within eps of a cell
+    # edge, and each such event moves one count between two bins.
+    st = sysg.get_state()
+    s = sysg.layout["cell_side"]
+    x0 = pos.astype(np.float64)
+    v = vel.astype(np.float64)
+    dt_lat = steps * 0.005
+    eps = np.abs(unwrapped(st, s) - (x0 + v * dt_lat * T)).max()
+    near = 0
+    for t in range(T + 1):
+        y = (x0 + v * dt_lat * t) / dx
+        near += int((np.abs(y - np.rint(y)) * dx < eps).any(axis=1).sum())
+    say(f"  drift eps {eps:.2e}, near-edge events {near}, count mismatch {np.abs(go - oo).sum()}")
+    assert eps < 5e-3
+    assert np.abs(go - oo).sum() <= 2 * near, (go, oo)
+    f_meas = g["f"] / (n / M ** 2)
+    f_cf = cf.feq_over_rho(dim, 3, 0.4)
+    big = f_cf > 1e-3
+    np.testing.assert_allclose(f_meas[big], f_cf[big], rtol=0.08)
+    msd = g["disp_sq"] / (n * T)
+    np.testing.assert_allclose(msd, kT * 1.6 ** 2, rtol=0.08)
+
+
+# ------------------------------------------------------------------ graph / eager, replicas
+
+def _run_forces_off(env_graph, n_rep_sizes, lattices, T=6):
+    from paper_1705_04368_amd import make_config
+    old = os.environ.get("MDLG_NO_GRAPH")
+    os.environ["MDLG_NO_GRAPH"] = "0" if env_graph else "1"
+    try:
+        dim = 2
+        pos_all, vel_all = [], []
+        for r, (n, m) in enumerate(zip(n_rep_sizes, lattices)):
+            p, v = synth.lj_initial_state(dim, n, 4.0 * m, 1.0, seed=100 + r)
+            pos_all.append(p)
+            vel_all.append(v)
+        cfg = make_config(dim, n_rep_sizes, [[m, m] for m in lattices], lattice_dx=4.0, dt=0.01,
+                          md_steps_per_lattice_step=30, vmax=2, forces_off=True, kT=1.0,
+                          sort_every=4)
+        sysg = make_system(cfg, np.concatenate(pos_all), np.concatenate(vel_all))
+        sysg.coarse_grain(T)
+        return sysg.get_f(per_site=True), sysg.get_state()
+    finally:
+        if old is None:
+            os.environ.pop("MDLG_NO_GRAPH", None)
+        else:
+            os.environ["MDLG_NO_GRAPH"] = old
+
+
+def test_graph_replay_equals_eager_bitwise():
+    say("graph vs eager")
+    a, sa = _run_forces_off(True, [1500], [14])
+    b, sb = _run_forces_off(False, [1500], [14])
+    np.testing.assert_array_equal(a["f_site"], b["f_site"])
+    np.testing.assert_array_equal(a["mom_site"], b["mom_site"])
+    for key in ("ucell", "off", "vel", "prev_ucell", "prev_off"):
+        np.testing.assert_array_equal(sa[key], sb[key])
+
+
+def test_batched_replicas_equal_separate_runs():
+    sizes, lats = [968, 2048, 1500], [11, 16, 14]
+    say("batched replicas vs separate")
+    both, sboth = _run_forces_off(True, sizes, lats)
+    off_site, off_part = 0, 0
+    for r, (n, m) in enumerate(zip(sizes, lats)):
+        p, v = synth.lj_initial_state(2, n, 4.0 * m, 1.0, seed=100 + r)
+        from paper_1705_04368_amd import make_config
+        cfg = make_config(2, [n], [[m, m]], lattice_dx=4.0, dt=0.01, md_steps_per_lattice_step=30,
+                          vmax=2, forces_off=True, kT=1.0, sort_every=4)
+        single = make_system(cfg, p, v)
+        single.coarse_grain(6)
+        fs = single.get_f(per_site=True)
+        ns = m * m
+        np.testing.assert_array_equal(both["f_site"][off_site:off_site + ns], fs["f_site"])
+        np.testing.assert_array_equal(both["mom_site"][off_site:off_site + ns], fs["mom_site"])
+        ss = single.get_state()
+        np.testing.assert_array_equal(sboth["off"][off_part:off_part + n], ss["off"])
+        off_site += ns
+        off_part += n
+
+
+def test_batched_replica_forces_match_oracle():
+    from paper_1705_04368_amd import make_config
+    sizes, lats = [968, 2048, 1250], [11, 16, 10]
+    pos_all, vel_all = [], []
+    for r, (n, m) in enumerate(zip(sizes, lats)):
+        p, v = synth.lj_initial_state(2, n, 4.0 * m, 1.0, seed=300 + r)
+        pos_all.append(p)
+        vel_all.append(v)
+    say("replica forces")
+    cfg = make_config(2, sizes, [[m, m] for m in lats], lattice_dx=4.0, dt=0.005, vmax=3, kT=1.0)
+    sysg = make_system(cfg, np.concatenate(pos_all), np.concatenate(vel_all))
+    st = sysg.get_state()
+    s = sysg.layout["cell_side"]
+    k = sysg.layout["md_cell_split"]
+    off = 0
+    for r, (n, m) in enumerate(zip(sizes, lats)):
+        sl = slice(off, off + n)
+        sub = {key: val[sl] for key, val in st.items()}
+        xw = wrapped(sub, s, m * k)
+        np.testing.assert_array_equal(xw, pos_all[r].astype(np.float64))
+        acc, _ = oracle.forces(oracle.make_md(2, n, 4.0 * m), xw)
+        assert force_error(sub["acc"], acc).max() <= 1e-5
+        off += n
+
+
+# ------------------------------------------------------------------ state I/O, errors
+
+def test_state_roundtrip_and_readout_does_not_perturb():
+    cfg, pos, vel, box, n, M = _force_case(2, 5, 1)
+    say("state round trip")
+    a = make_system(cfg, pos, vel)
+    a.step(10)
+    mid = a.get_state()
+    a.step(10)
+    sa = a.get_state()
+    b = make_system(cfg, pos, vel)
+    b.step(20)
+    sb = b.get_state()
+    s = a.layout["cell_side"]
+    # the force sum order inside a cell may differ between runs (atomic slots)
+    assert np.abs(unwrapped(sa, s) - unwrapped(sb, s)).max() < 1e-5
+    assert np.abs(sa["vel"] - sb["vel"]).max() < 1e-5
+    c = make_system(cfg, pos, vel)
+    c.set_state(mid["ucell"], mid["off"], mid["vel"], mid["prev_ucell"], mid["prev_off"])
+    sc = c.get_state()
+    for key in ("ucell", "off", "vel", "prev_ucell", "prev_off"):
+        np.testing.assert_array_equal(sc[key], mid[key])
+
+
+def test_unstable_step_is_reported():
+    from paper_1705_04368_amd import MdlgError
+    cfg, pos, vel, box, n, M = _force_case(2, 9, 1)
+    cfg.sort_every = 10
+    vel = vel.copy()
+    vel[0] = [400.0, 0.0]  # crosses more than the margin within one step
+    say("unstable step")
+    sysg = make_system(cfg, pos, vel)
+    sysg.step(3)
+    with pytest.raises(MdlgError) as e:
+        sysg.sync()
+    assert e.value.status == -4
+
+
+def test_empty_lattice_steps_and_single_particle():
+    from paper_1705_04368_amd import make_config
+    say("single particle")
+    cfg = make_config(2, 1, 4, lattice_dx=4.0, dt=0.25, md_steps_per_lattice_step=4, vmax=1,
+                      forces_off=True, md_cell_split=1, sort_every=1)
+    # the worked example of the one-dimensional thought experiment, scaled to
+    # 4-sigma cells: start 1.1 cells in, move 1/3 cell per lattice time step
+    pos = np.array([[1.1 * 4.0, 1.5 * 4.0]], np.float32)
+    vel = np.array([[4.0 / 3.0, 0.0]], np.float32)
+    sysg = make_system(cfg, pos, vel)
+    sysg.coarse_grain(0)
+    hist = []
+    for t in range(6):
+        before = sysg.get_f(per_site=True)["f_site"] * max(t, 1)
+        sysg.coarse_grain(1)
+        after = sysg.get_f(per_site=True)["f_site"] * (t + 1)
+        hist.append(np.rint(after - (before if t else 0)).astype(np.int64))
+    f0, f1 = 4, 5  # bins of v = (0, 0) and v = (+1, 0) for V = 1
+    expected = [(1, f0), (1, f0), (2, f1), (2, f0), (2, f0), (3, f1)]
+    for t, (x, b) in enumerate(expected):
+        site = x + 4 * 1
+        nz = np.argwhere(hist[t] > 0)
+        assert nz.tolist() == [[site, b]], (t, nz)
