@@ -63,6 +63,12 @@ def _load():
                                  dp, P(C.c_long), C.c_int, up, lp, dp, dp, up]
     lib.orc_kinetics.restype = None
     lib.orc_kinetics.argtypes = [P(OrcMD), dp, dp, dp]
+    lib.orc_pair_terms.restype = C.c_int
+    lib.orc_pair_terms.argtypes = [P(OrcMD), dp, dp, dp, dp, dp]
+    lib.orc_adjoint.restype = C.c_int
+    lib.orc_adjoint.argtypes = [P(OrcMD), dp, dp, C.c_int, C.c_int, dp, dp, dp, dp, dp]
+    lib.orc_window_loss.restype = C.c_int
+    lib.orc_window_loss.argtypes = [P(OrcMD), dp, dp, C.c_int, C.c_int, dp]
     _lib = lib
     return lib
 
@@ -209,3 +215,40 @@ def ni_literal(lattice, dim, xu_prev, xu_now):
     _check(_load().orc_ni_literal(C.byref(lattice), dim, n, _dp(xu_prev), _dp(xu_now),
                                   _up(out)), "ni_literal")
     return out
+
+
+def pair_terms(md, x, lam=None):
+    """Accelerations, their sigma derivative and the Jacobian-vector product
+    J lam (J = d a / d x) on wrapped FP64 positions."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    acc, dacc, jl = np.zeros_like(x), np.zeros_like(x), np.zeros_like(x)
+    lp = _dp(np.ascontiguousarray(lam, dtype=np.float64)) if lam is not None else None
+    keep = lam
+    _check(_load().orc_pair_terms(C.byref(md), _dp(x), lp, _dp(acc), _dp(dacc),
+                                  _dp(jl) if lam is not None else None), "pair_terms")
+    del keep
+    return acc, dacc, (jl if lam is not None else None)
+
+
+LOSSES = {"msd": 0, "mean_x": 1}
+
+
+def adjoint(md, x0, v0, window, loss):
+    """Loss of the displacement over `window` velocity-Verlet steps and its
+    gradients with respect to eps, sigma, v0 and x0 (FP64 reverse sweep)."""
+    x0 = np.ascontiguousarray(x0, dtype=np.float64)
+    v0 = np.ascontiguousarray(v0, dtype=np.float64)
+    L, ge, gs = C.c_double(0), C.c_double(0), C.c_double(0)
+    gv, gx = np.zeros_like(v0), np.zeros_like(x0)
+    _check(_load().orc_adjoint(C.byref(md), _dp(x0), _dp(v0), int(window), LOSSES[loss],
+                               C.byref(L), C.byref(ge), C.byref(gs), _dp(gv), _dp(gx)), "adjoint")
+    return {"L": L.value, "eps": ge.value, "sigma": gs.value, "v0": gv, "x0": gx}
+
+
+def window_loss(md, x0, v0, window, loss):
+    x0 = np.ascontiguousarray(x0, dtype=np.float64)
+    v0 = np.ascontiguousarray(v0, dtype=np.float64)
+    L = C.c_double(0)
+    _check(_load().orc_window_loss(C.byref(md), _dp(x0), _dp(v0), int(window), LOSSES[loss],
+                                   C.byref(L)), "window_loss")
+    return L.value

@@ -197,6 +197,96 @@ int orc_forces_cells(const orc_md *p, const double *x, double *acc, double *epot
     return ORC_OK;
 }
 
+/* Visit every ordered pair (i, j), i != j, within r_c (minimum image),
+ * calling fn(ctx, i, j, r, r2) with r = x_i - x_j.  Uses a linked-list cell
+ * grid of side >= r_c when every axis holds at least 3 cells, else all pairs. */
+typedef void (*pair_fn)(void *ctx, int i, int j, const double *r, double r2);
+
+static int visit_pairs(const orc_md *p, const double *x, pair_fn fn, void *ctx)
+{
+    int d = p->dim, n = p->n;
+    int nc[3] = {1, 1, 1};
+    double h[3] = {1.0, 1.0, 1.0};
+    int cells = 1;
+    for (int a = 0; a < d; ++a) {
+        nc[a] = (int)floor(p->box[a] / p->rc);
+        if (nc[a] < 3)
+            cells = 0;
+        else
+            h[a] = p->box[a] / nc[a];
+    }
+    double rc2 = p->rc * p->rc;
+    if (!cells) {
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                if (j == i)
+                    continue;
+                double r[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
+                for (int a = 0; a < d; ++a) {
+                    r[a] = min_image(x[i * d + a] - x[j * d + a], p->box[a]);
+                    r2 += r[a] * r[a];
+                }
+                if (r2 < rc2)
+                    fn(ctx, i, j, r, r2);
+            }
+        return ORC_OK;
+    }
+    for (int a = d; a < 3; ++a)
+        nc[a] = 1;
+    long ncell = (long)nc[0] * nc[1] * nc[2];
+    int *head = (int *)malloc(sizeof(int) * ncell);
+    int *next = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    int *cof = (int *)malloc(sizeof(int) * 3 * (size_t)(n > 0 ? n : 1));
+    if (!head || !next || !cof) {
+        free(head); free(next); free(cof);
+        return ORC_ENOMEM;
+    }
+    for (long c = 0; c < ncell; ++c)
+        head[c] = -1;
+    for (int i = 0; i < n; ++i) {
+        int cc[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a) {
+            int q = (int)floor(x[i * d + a] / h[a]);
+            if (q < 0) q = 0;
+            if (q >= nc[a]) q = nc[a] - 1;
+            cc[a] = q;
+        }
+        for (int a = 0; a < 3; ++a)
+            cof[3 * i + a] = cc[a];
+        long c = cc[0] + (long)nc[0] * (cc[1] + (long)nc[1] * cc[2]);
+        next[i] = head[c];
+        head[c] = i;
+    }
+    int span[3] = {1, 1, 1};
+    for (int a = 0; a < d; ++a)
+        span[a] = 3;
+    for (int i = 0; i < n; ++i)
+        for (int oz = 0; oz < span[2]; ++oz)
+            for (int oy = 0; oy < span[1]; ++oy)
+                for (int ox = 0; ox < span[0]; ++ox) {
+                    int off[3] = {ox - 1, oy - 1, oz - 1};
+                    int cc[3] = {0, 0, 0};
+                    for (int a = 0; a < d; ++a)
+                        cc[a] = ((cof[3 * i + a] + off[a]) % nc[a] + nc[a]) % nc[a];
+                    long c = cc[0] + (long)nc[0] * (cc[1] + (long)nc[1] * cc[2]);
+                    for (int j = head[c]; j >= 0; j = next[j]) {
+                        if (j == i)
+                            continue;
+                        double r[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
+                        for (int a = 0; a < d; ++a) {
+                            r[a] = min_image(x[i * d + a] - x[j * d + a], p->box[a]);
+                            r2 += r[a] * r[a];
+                        }
+                        if (r2 < rc2)
+                            fn(ctx, i, j, r, r2);
+                    }
+                }
+    free(head);
+    free(next);
+    free(cof);
+    return ORC_OK;
+}
+
 static int compute_forces(const orc_md *p, const double *x, double *acc,
                           double *epot, int use_cells)
 {
@@ -471,4 +561,183 @@ void orc_kinetics(const orc_md *p, const double *v, double *ke, double *mom)
             *ke += 0.5 * p->mass * v[i * d + a] * v[i * d + a];
             mom[a] += p->mass * v[i * d + a];
         }
+}
+
+/* ------------------------------------------------------------------ */
+/* Adjoint of a velocity-Verlet window (gradients of displacement     */
+/* moments with respect to eps, sigma and the initial velocities)     */
+/* ------------------------------------------------------------------ */
+
+/* For every ordered pair (i, j) within r_c, with r = x_i - x_j (minimum image):
+ *   acceleration      a_i      += g(r) r / m,
+ *                     g(r)      = (24 eps / r^2) [2 (sigma/r)^12 - (sigma/r)^6]
+ *   sigma derivative  da_i/dsig += (dg/dsigma) r / m,
+ *                     dg/dsigma = (24 eps / (r^2 sigma)) [24 (sigma/r)^12 - 6 (sigma/r)^6]
+ *   Jacobian-vector   (J lam)_i += K (lam_i - lam_j) / m,
+ *                     K = g I + (g'(r)/r) r r^T,
+ *                     g'(r)/r   = (24 eps / r^4) [8 (sigma/r)^6 - 28 (sigma/r)^12].
+ * Any of the outputs may be NULL. */
+typedef struct {
+    const orc_md *p;
+    const double *lam;
+    double *acc, *dacc, *jlam;
+} pair_terms_ctx;
+
+static void pair_terms_fn(void *vctx, int i, int j, const double *r, double r2)
+{
+    pair_terms_ctx *c = (pair_terms_ctx *)vctx;
+    const orc_md *p = c->p;
+    int d = p->dim;
+    double eps = p->eps, sig = p->sigma, m = p->mass;
+    double rr = sqrt(r2);
+    double s6 = pow(sig / rr, 6.0), s12 = s6 * s6;
+    double g = 24.0 * eps / r2 * (2.0 * s12 - s6);
+    if (c->acc)
+        for (int a = 0; a < d; ++a)
+            c->acc[i * d + a] += g * r[a] / m;
+    if (c->dacc) {
+        double dg = 24.0 * eps / (r2 * sig) * (24.0 * s12 - 6.0 * s6);
+        for (int a = 0; a < d; ++a)
+            c->dacc[i * d + a] += dg * r[a] / m;
+    }
+    if (c->jlam) {
+        double gp = 24.0 * eps / (r2 * r2) * (8.0 * s6 - 28.0 * s12);
+        double dl[3] = {0.0, 0.0, 0.0}, rdl = 0.0;
+        for (int a = 0; a < d; ++a) {
+            dl[a] = c->lam[i * d + a] - c->lam[j * d + a];
+            rdl += r[a] * dl[a];
+        }
+        for (int a = 0; a < d; ++a)
+            c->jlam[i * d + a] += (g * dl[a] + gp * rdl * r[a]) / m;
+    }
+}
+
+int orc_pair_terms(const orc_md *p, const double *x, const double *lam, double *acc,
+                   double *dacc_dsigma, double *jlam)
+{
+    size_t nd = (size_t)p->n * p->dim;
+    if (acc) memset(acc, 0, sizeof(double) * nd);
+    if (dacc_dsigma) memset(dacc_dsigma, 0, sizeof(double) * nd);
+    if (jlam) memset(jlam, 0, sizeof(double) * nd);
+    if (p->forces_off)
+        return ORC_OK;
+    pair_terms_ctx c = {p, lam, acc, dacc_dsigma, jlam};
+    return visit_pairs(p, x, pair_terms_fn, &c);
+}
+
+/* Loss on the displacement over the window (unwrapped positions):
+ *   loss_id 0: L = (1/(N d)) sum_j |x_j(W) - x_j(0)|^2   (per-axis MSD)
+ *   loss_id 1: L = (1/N) sum_j (x_jx(W) - x_jx(0))       (mean x displacement)
+ * Writes L and dL/dx(W) into lx. */
+static double window_loss(int loss_id, int n, int d, const double *xu0, const double *xuW,
+                          double *lx)
+{
+    double L = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < d; ++a) {
+            double dd = xuW[i * d + a] - xu0[i * d + a];
+            if (loss_id == 0) {
+                L += dd * dd / ((double)n * d);
+                if (lx) lx[i * d + a] = 2.0 * dd / ((double)n * d);
+            } else {
+                if (a == 0) L += dd / n;
+                if (lx) lx[i * d + a] = (a == 0) ? 1.0 / n : 0.0;
+            }
+        }
+    return L;
+}
+
+/* Forward window of W velocity-Verlet steps from (x0 wrapped in [0, L), v0),
+ * then the reverse sweep.  With the step written as kick (h/2) a(x_n),
+ * drift h v, kick (h/2) a(x_{n+1}), the adjoints (lx, lv) of (x, v) run
+ * backwards as: lv += h lx (drift); at every position the two half kicks that
+ * use a(x_n) add c J(x_n)^T lv to lx and c lv . da(x_n)/dtheta to the
+ * parameter gradients, with c = h inside the window and h/2 at both ends
+ * (J is symmetric).  Outputs: *L, dL/deps, dL/dsigma, dL/dv0 [n][d] and,
+ * when gx0 is not NULL, dL/dx0. */
+int orc_adjoint(const orc_md *p, const double *x0, const double *v0, int W, int loss_id,
+                double *L, double *geps, double *gsig, double *gv0, double *gx0)
+{
+    int d = p->dim, n = p->n;
+    size_t nd = (size_t)n * d;
+    double h = p->dt;
+    double *xs = (double *)malloc(sizeof(double) * nd * (size_t)(W + 1)); /* wrapped */
+    double *xu = (double *)malloc(sizeof(double) * nd * 2);               /* unwrapped x0, xW */
+    double *x = (double *)malloc(sizeof(double) * nd);
+    double *v = (double *)malloc(sizeof(double) * nd);
+    double *acc = (double *)malloc(sizeof(double) * nd);
+    double *lx = (double *)malloc(sizeof(double) * nd);
+    double *lv = (double *)calloc(nd, sizeof(double));
+    double *t1 = (double *)malloc(sizeof(double) * nd);
+    double *t2 = (double *)malloc(sizeof(double) * nd);
+    int32_t *img = (int32_t *)calloc(nd, sizeof(int32_t));
+    if (!xs || !xu || !x || !v || !acc || !lx || !lv || !t1 || !t2 || !img) {
+        free(xs); free(xu); free(x); free(v); free(acc); free(lx); free(lv); free(t1);
+        free(t2); free(img);
+        return ORC_ENOMEM;
+    }
+    memcpy(x, x0, sizeof(double) * nd);
+    memcpy(v, v0, sizeof(double) * nd);
+    memcpy(xs, x0, sizeof(double) * nd);
+    memcpy(xu, x0, sizeof(double) * nd);
+    orc_pair_terms(p, x, NULL, acc, NULL, NULL);
+    long step = 0;
+    for (int s = 1; s <= W; ++s) {
+        orc_vv(p, x, img, v, acc, 1, &step, 0, 0.0, 1);
+        memcpy(xs + nd * (size_t)s, x, sizeof(double) * nd);
+    }
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < d; ++a)
+            xu[nd + i * d + a] = x[i * d + a] + img[i * d + a] * p->box[a];
+    double Lv = window_loss(loss_id, n, d, xu, xu + nd, lx);
+    double ge = 0.0, gs = 0.0;
+    for (int s = W; s >= 0; --s) {
+        double c = (s == W || s == 0) ? 0.5 * h : h;
+        const double *xn = xs + nd * (size_t)s;
+        orc_pair_terms(p, xn, lv, acc, t1, t2);
+        for (size_t k = 0; k < nd; ++k) {
+            lx[k] += c * t2[k];
+            ge += c * lv[k] * acc[k] / p->eps;
+            gs += c * lv[k] * t1[k];
+        }
+        if (s > 0)
+            for (size_t k = 0; k < nd; ++k)
+                lv[k] += h * lx[k];
+    }
+    if (L) *L = Lv;
+    if (geps) *geps = ge;
+    if (gsig) *gsig = gs;
+    if (gv0) memcpy(gv0, lv, sizeof(double) * nd);
+    if (gx0) memcpy(gx0, lx, sizeof(double) * nd);
+    free(xs); free(xu); free(x); free(v); free(acc); free(lx); free(lv); free(t1); free(t2);
+    free(img);
+    return ORC_OK;
+}
+
+/* The window loss alone (forward only), for finite differences. */
+int orc_window_loss(const orc_md *p, const double *x0, const double *v0, int W, int loss_id,
+                    double *L)
+{
+    int d = p->dim, n = p->n;
+    size_t nd = (size_t)n * d;
+    double *x = (double *)malloc(sizeof(double) * nd);
+    double *v = (double *)malloc(sizeof(double) * nd);
+    double *acc = (double *)malloc(sizeof(double) * nd);
+    double *xuW = (double *)malloc(sizeof(double) * nd);
+    int32_t *img = (int32_t *)calloc(nd, sizeof(int32_t));
+    if (!x || !v || !acc || !xuW || !img) {
+        free(x); free(v); free(acc); free(xuW); free(img);
+        return ORC_ENOMEM;
+    }
+    memcpy(x, x0, sizeof(double) * nd);
+    memcpy(v, v0, sizeof(double) * nd);
+    orc_pair_terms(p, x, NULL, acc, NULL, NULL);
+    long step = 0;
+    orc_vv(p, x, img, v, acc, W, &step, 0, 0.0, 1);
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < d; ++a)
+            xuW[i * d + a] = x[i * d + a] + img[i * d + a] * p->box[a];
+    *L = window_loss(loss_id, n, d, x0, xuW, NULL);
+    free(x); free(v); free(acc); free(xuW); free(img);
+    return ORC_OK;
 }
