@@ -37,7 +37,9 @@
  *     One handle must be used from one host thread at a time.
  *   - Lattice: a cubic lattice of spacing lattice_dx with lattice[r][a] sites
  *     along axis a of replica r; the periodic box side is lattice[r][a] *
- *     lattice_dx.  A particle belongs to site c along an axis when
+ *     lattice_dx.  Internally each lattice cell is k x k (x k) MD cells of side
+ *     s = float32(lattice_dx / k); when lattice_dx / k is not a float32 value
+ *     the box is lattice[r][a] * k * s (mdlg_describe reports s).  A particle belongs to site c along an axis when
  *     c * dx <= x < (c+1) * dx (the paper writes the interval closed above;
  *     the two readings differ on a set of measure zero).
  *   - Velocities: lattice velocities with |v_a| <= vmax on every axis are
@@ -94,6 +96,9 @@ typedef struct {
     int32_t brick_x;            /* force-kernel brick extent along x in MD cells, 0 = auto */
     int32_t brick_y;            /* along y, 0 = auto */
     int32_t brick_z;            /* along z (3D), 0 = auto */
+    int32_t adjoint_window;     /* largest adjoint window in MD steps (0 = no adjoint buffers) */
+    int32_t adjoint_every;      /* checkpoint interval the workspace is sized for (>= 1 when
+                                   adjoint_window > 0) */
 } mdlg_config;
 
 /* Particle state in particle-id order (id = index in the concatenated input).
@@ -201,6 +206,35 @@ mdlg_status mdlg_get_state(mdlg_system *sys, mdlg_particles *out);
  * required; prev_ucell and prev_off optional: when NULL the new positions become
  * the snapshot).  Offsets must lie in [0, s).  Accumulators are kept. */
 mdlg_status mdlg_set_state(mdlg_system *sys, const mdlg_particles *in);
+
+/* Losses of the adjoint window, on the continuous displacement
+ * delta x_j = x_j(t0 + W dt) - x_j(t0) over the window (the displacement whose
+ * second moment defines a^2 in eq. eqn:a):
+ *   MDLG_LOSS_MSD:    L = (1 / (N dim)) sum_j |delta x_j|^2
+ *   MDLG_LOSS_MEAN_X: L = (1 / N) sum_j delta x_jx                         */
+typedef enum { MDLG_LOSS_MSD = 0, MDLG_LOSS_MEAN_X = 1 } mdlg_loss;
+
+/* Adjoint of one MD window (not a passage of the paper: the gradients of its
+ * displacement moments with respect to the potential and the initial
+ * velocities).  From the current positions x(t0) and velocities v(t0) -- or
+ * v0_dev when not NULL (device float [n_total][dim], id order) -- runs
+ * window_steps velocity-Verlet steps with the cell list frozen (checkpoints of
+ * the state every ckpt_every steps), then the reverse sweep, recomputing each
+ * segment from its checkpoint.  Outputs (any may be NULL): *loss, dL/deps,
+ * dL/dsigma (host doubles) and dL/dv0 into g_v0_dev (device float
+ * [n_total][dim], id order).  The system is left at t0 + window_steps.
+ * Requires window_steps <= adjoint_window of the configuration, window_steps a
+ * multiple of ckpt_every, window_steps / ckpt_every + 1 checkpoints and
+ * ckpt_every + 1 segment positions within the sizes the configuration
+ * reserved.  Synchronises.  All replicas take part: N is the particle count
+ * over all replicas. */
+mdlg_status mdlg_adjoint(mdlg_system *sys, int32_t window_steps, int32_t ckpt_every, int32_t loss,
+                         const float *v0_dev, double *out_loss, double *dL_deps, double *dL_dsigma,
+                         float *g_v0_dev);
+
+/* Change the LJ parameters eps and sigma of an existing system (r_cut stays
+ * fixed in absolute units).  Asynchronous. */
+mdlg_status mdlg_set_potential(mdlg_system *sys, double epsilon, double sigma);
 
 /* Kernel classes of the hot path, for mdlg_get_timing. */
 typedef enum {

@@ -38,8 +38,10 @@ struct Layout {
   int nbricks = 0, nchunks = 0, nstrips = 0, ntiles = 0;
   std::vector<Replica> reps;
   std::vector<int4> bricks, chunks, strips;
-  double s = 0, margin = 0;
+  double s = 0, margin = 0, margin_max = 0;
   int sort_every = 1;
+  int adj_ckpts = 0;   // checkpoints the workspace holds (0 = no adjoint)
+  int adj_seg = 0;     // segment positions the workspace holds
 };
 
 // Workspace carve-out, in the order buffers are laid out.
@@ -89,6 +91,9 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   if (c->kT < 0 || !std::isfinite(c->kT)) return set_err(msg, "kT must be >= 0");
   if (c->sort_every < 0) return set_err(msg, "sort_every must be >= 0");
   if (c->brick_x < 0 || c->brick_y < 0 || c->brick_z < 0) return set_err(msg, "brick extents must be >= 0");
+  if (c->adjoint_window < 0) return set_err(msg, "adjoint_window must be >= 0");
+  if (c->adjoint_window > 0 && (c->adjoint_every < 1 || c->adjoint_every > c->adjoint_window))
+    return set_err(msg, "adjoint_every must be in 1..adjoint_window");
   L->D = D;
   int Q = 1;
   for (int a = 0; a < D; ++a) Q *= 2 * c->vmax + 1;
@@ -154,7 +159,9 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   if (D == 3 && k * k > 64) return set_err(msg, "md_cell_split too large for 3D");
   L->k = k;
   L->log2k = lk;
-  L->s = c->lattice_dx / k;
+  // the float32 cell side is the one definition of the MD cell (kernels
+  // canonicalise offsets with it); the box side is Mc * s
+  L->s = (double)(float)(c->lattice_dx / k);
   L->ns = (int)std::ceil(c->r_cut / L->s - 1e-12);
   // largest excursion outside the cell that the stencil still covers
   const double m_max = (L->ns * L->s - c->r_cut) / 2;
@@ -176,6 +183,7 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
     return set_err(msg, "sort_every > 1 needs a positive margin (stencil reach %g vs r_cut %g)",
                    L->ns * L->s, c->r_cut);
   L->sort_every = R;
+  L->margin_max = m_max;
   L->margin = (vfast > 0) ? std::min(m_max, R * vfast * c->dt) : m_max;
   if (L->margin < 0) L->margin = 0;
   // force bricks
@@ -254,6 +262,10 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
     part_off += rep.n;
     site_off += nsite;
   }
+  if (c->adjoint_window > 0) {
+    L->adj_ckpts = c->adjoint_window / c->adjoint_every + 1;
+    L->adj_seg = c->adjoint_every + 1;
+  }
   L->n_total = n_total;
   L->n_cells = cell_off;
   L->n_sites = site_off;
@@ -320,6 +332,17 @@ struct mdlg_system {
   double* fout = nullptr;
   double* dispout = nullptr;
   float* acc_sorted = nullptr;
+  // adjoint window buffers (sorted order)
+  float* adj_off0 = nullptr;
+  float* adj_ckpt_pos = nullptr;
+  float* adj_ckpt_vel = nullptr;
+  float* adj_seg_pos = nullptr;
+  float* adj_vel = nullptr;
+  float* adj_lx = nullptr;
+  float* adj_lv[2] = {nullptr, nullptr};
+  double* adj_gpart = nullptr;
+  double* adj_lpart = nullptr;
+  double* adj_out = nullptr;
   char* staging = nullptr;
   size_t staging_bytes = 0;
   // host-side state
@@ -390,6 +413,19 @@ size_t carve(mdlg_system* S, char* base) {
   S->fout = c.take<double>(base, kMaxQ);
   S->dispout = c.take<double>(base, 8);
   S->acc_sorted = c.take<float>(base, N * D);
+  if (L.adj_ckpts > 0) {
+    S->adj_off0 = c.take<float>(base, N * D);
+    S->adj_ckpt_pos = c.take<float>(base, N * D * L.adj_ckpts);
+    S->adj_ckpt_vel = c.take<float>(base, N * D * L.adj_ckpts);
+    S->adj_seg_pos = c.take<float>(base, N * D * L.adj_seg);
+    S->adj_vel = c.take<float>(base, N * D);
+    S->adj_lx = c.take<float>(base, N * D);
+    S->adj_lv[0] = c.take<float>(base, N * D);
+    S->adj_lv[1] = c.take<float>(base, N * D);
+    S->adj_gpart = c.take<double>(base, (size_t)L.nbricks * 2);
+    S->adj_lpart = c.take<double>(base, 1024);
+    S->adj_out = c.take<double>(base, 4);
+  }
   S->staging_bytes = std::max<size_t>(N * D * 4 * 4, size_t(4) << 20);
   S->staging = c.take<char>(base, S->staging_bytes);
   return c.off + 256;
@@ -411,6 +447,8 @@ Phys make_phys(const mdlg_config* c, const Layout& L) {
   const double u = L.s / std::ldexp(1.0, P.F);
   P.fscale = (float)(std::ldexp(1.0, P.F) / L.s);
   P.rcq = (int)std::ceil((c->r_cut + L.margin) / u) + 1;
+  P.rc_d = c->r_cut;
+  P.u_d = u;
   P.rc2_u = (float)((c->r_cut / u) * (c->r_cut / u));
   P.sig2_u = (float)((c->sigma / u) * (c->sigma / u));
   P.eps24m_u = (float)(24.0 * c->epsilon / (c->mass * u));
@@ -1068,6 +1106,159 @@ mdlg_status mdlg_set_state(mdlg_system* S, const mdlg_particles* in) {
   if (st != MDLG_OK) return st;
   HIPCHK(S, hipStreamSynchronize(S->stream));
   return read_err(S);
+}
+
+// Phys of an adjoint window: the cell list stays frozen for the whole window,
+// so particles may use the full stencil margin (ns s - r_cut) / 2.
+static Phys window_phys(const mdlg_system* S) {
+  Phys P = S->P;
+  const double m = S->L.margin_max;
+  P.lo = (float)(-m);
+  P.hi = (float)(S->L.s + m);
+  P.rcq = (int)std::ceil((P.rc_d + m) / P.u_d) + 1;
+  return P;
+}
+
+static void launch_force_raw(mdlg_system* S, const Phys& P, int mode, const float* pos_in,
+                             float* pos_out, float* vel) {
+  ForceArgs a{};
+  a.P = P;
+  a.reps = S->reps;
+  a.bricks = S->bricks;
+  a.cell_start = S->cell_start;
+  a.pos_in = pos_in;
+  a.pos_out = pos_out;
+  a.vel = vel;
+  a.err = S->err;
+  a.mode = mode;
+  a.nbricks = S->L.nbricks;
+  a.xcd_remap = S->xcd_remap;
+  TimedLaunch t(S, MDLG_K_FORCE);
+  launch_force(S->D, a, S->stream);
+}
+
+mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, const float* v0_dev,
+                         double* out_loss, double* dL_deps, double* dL_dsigma, float* g_v0_dev) {
+  if (!S) return MDLG_E_INVALID;
+  const Layout& L = S->L;
+  if (L.adj_ckpts == 0) {
+    S->last_error = "the configuration reserved no adjoint buffers (adjoint_window = 0)";
+    return MDLG_E_STATE;
+  }
+  if (W < 1 || k < 1 || W % k != 0 || W / k + 1 > L.adj_ckpts || k + 1 > L.adj_seg ||
+      W > S->cfg.adjoint_window) {
+    S->last_error = "adjoint window/checkpoint interval outside the reserved sizes";
+    return MDLG_E_INVALID;
+  }
+  if (loss != MDLG_LOSS_MSD && loss != MDLG_LOSS_MEAN_X) {
+    S->last_error = "unknown loss";
+    return MDLG_E_INVALID;
+  }
+  const int D = S->D;
+  const long long nd = L.n_total * D;
+  const Phys PW = window_phys(S);
+  if (S->timing) close_run(S);
+  // start of the window: canonical cells (frozen from here on), full-step v
+  if (S->since_sort != 0) enqueue_sort(S);
+  if (v0_dev) {
+    AdjIoArgs io{S->id[S->scur], S->vel[S->scur], const_cast<float*>(v0_dev), (int)L.n_total, 1};
+    launch_adj_io(D, io, S->stream);
+    S->vel_full = true;
+    S->lambda_pending = false;
+  } else if (!S->vel_full) {
+    enqueue_force(S, kModeFinish, false, nullptr, nullptr);
+    S->vel_full = true;
+  }
+  // forward window with checkpoints
+  launch_copy_f32(S->pos[S->pcur], S->adj_off0, nd, S->stream);
+  launch_copy_f32(S->pos[S->pcur], S->adj_ckpt_pos, nd, S->stream);
+  launch_copy_f32(S->vel[S->scur], S->adj_ckpt_vel, nd, S->stream);
+  for (int n = 1; n <= W; ++n) {
+    launch_force_raw(S, PW, n == 1 ? kModeStart : kModeStep, S->pos[S->pcur], S->pos[S->pcur ^ 1],
+                     S->vel[S->scur]);
+    S->pcur ^= 1;
+    if (n % k == 0 && n < W) {
+      launch_copy_f32(S->pos[S->pcur], S->adj_ckpt_pos + (size_t)(n / k) * nd, nd, S->stream);
+      launch_copy_f32(S->vel[S->scur], S->adj_ckpt_vel + (size_t)(n / k) * nd, nd, S->stream);
+    }
+  }
+  // loss and dL/dx(W); lam_v(W) = 0
+  const int nlb = (int)std::min<long long>(1024, (L.n_total + kBlock - 1) / kBlock);
+  AdjLossArgs la{S->adj_off0, S->pos[S->pcur], S->adj_lx, S->adj_lv[0], S->adj_lpart,
+                 (int)L.n_total, loss, nlb};
+  launch_adj_loss(D, la, S->stream);
+  launch_fill_u32(reinterpret_cast<unsigned*>(S->adj_gpart), 0u, (long long)L.nbricks * 4, S->stream);
+  // reverse sweep, segment by segment
+  const float h = (float)S->cfg.dt;
+  const double u = PW.u_d;
+  const double e1 = 24.0 * S->cfg.epsilon / (S->cfg.mass * u);
+  int cur = 0;
+  for (int seg = W / k - 1; seg >= 0; --seg) {
+    launch_copy_f32(S->adj_ckpt_pos + (size_t)seg * nd, S->adj_seg_pos, nd, S->stream);
+    launch_copy_f32(S->adj_ckpt_vel + (size_t)seg * nd, S->adj_vel, nd, S->stream);
+    for (int j = 1; j <= k; ++j)
+      launch_force_raw(S, PW, (seg == 0 && j == 1) ? kModeStart : kModeStep,
+                       S->adj_seg_pos + (size_t)(j - 1) * nd, S->adj_seg_pos + (size_t)j * nd,
+                       S->adj_vel);
+    for (int j = k; j >= (seg == 0 ? 0 : 1); --j) {
+      const int sg = seg * k + j;
+      AdjArgs a{};
+      a.P = PW;
+      a.reps = S->reps;
+      a.bricks = S->bricks;
+      a.cell_start = S->cell_start;
+      a.pos = S->adj_seg_pos + (size_t)j * nd;
+      a.lam_v_in = S->adj_lv[cur];
+      a.lam_v_out = S->adj_lv[cur ^ 1];
+      a.lam_x = S->adj_lx;
+      a.gpart = S->adj_gpart;
+      a.c = (sg == W || sg == 0) ? 0.5f * h : h;
+      a.drift = sg > 0 ? 1 : 0;
+      a.e1_over_sigma = (float)(e1 / S->cfg.sigma);
+      a.e2 = (float)(e1 / u);
+      a.eps = S->cfg.epsilon;
+      a.nbricks = L.nbricks;
+      launch_adjoint(D, a, S->stream);
+      cur ^= 1;
+    }
+  }
+  AdjFinalArgs fa{S->adj_lpart, S->adj_gpart, S->adj_out, nlb, L.nbricks};
+  launch_adj_final(fa, S->stream);
+  if (g_v0_dev) {
+    AdjIoArgs io{S->id[S->scur], S->adj_lv[cur], g_v0_dev, (int)L.n_total, 0};
+    launch_adj_io(D, io, S->stream);
+  }
+  // leave the system at the end of the window, cells rebuilt
+  S->vel_full = false;
+  S->since_sort = W;
+  S->md_step += W;
+  enqueue_sort(S);
+  S->snapshot_valid = false;
+  mdlg_status st = check_launch(S, "mdlg_adjoint");
+  if (st != MDLG_OK) return st;
+  double out[3] = {0, 0, 0};
+  HIPCHK(S, hipMemcpyAsync(out, S->adj_out, sizeof out, hipMemcpyDeviceToHost, S->stream));
+  st = read_err(S);
+  if (out_loss) *out_loss = out[0];
+  if (dL_deps) *dL_deps = out[1];
+  if (dL_dsigma) *dL_dsigma = out[2];
+  return st;
+}
+
+mdlg_status mdlg_set_potential(mdlg_system* S, double epsilon, double sigma) {
+  if (!S) return MDLG_E_INVALID;
+  if (!(epsilon > 0) || !(sigma > 0) || !std::isfinite(epsilon) || !std::isfinite(sigma)) {
+    S->last_error = "epsilon and sigma must be > 0";
+    return MDLG_E_INVALID;
+  }
+  S->cfg.epsilon = epsilon;
+  S->cfg.sigma = sigma;
+  S->P = make_phys(&S->cfg, S->L);
+  // captured lattice steps carry the old parameters
+  HIPCHK(S, hipStreamSynchronize(S->stream));
+  for (auto& kv : S->graphs) (void)hipGraphExecDestroy(kv.second.exec);
+  S->graphs.clear();
+  return MDLG_OK;
 }
 
 mdlg_status mdlg_set_timing(mdlg_system* S, int enable) {

@@ -149,7 +149,57 @@ struct XportArgs {
   unsigned* err;
 };
 
+struct AdjArgs {
+  Phys P;
+  const Replica* reps;
+  const int4* bricks;
+  const int* cell_start;
+  const float* pos;        // positions x_s (sorted order, cells fixed for the window)
+  const float* lam_v_in;   // adjoint velocity before this step
+  float* lam_v_out;        // adjoint velocity after this step
+  float* lam_x;            // adjoint position, updated in place
+  double* gpart;           // per-brick partials of (dL/deps, dL/dsigma), accumulated
+  float c;                 // weight of the two half kicks that use a(x_s): h or h/2
+  int drift;               // 1: apply lam_v += h lam_x (not at the first position)
+  float e1_over_sigma;     // 24 eps / (m u sigma)
+  float e2;                // 24 eps / (m u^2)
+  double eps;
+  int nbricks;
+};
+
+struct AdjLossArgs {
+  const float* off0;       // offsets at the start of the window
+  const float* offW;       // offsets at its end
+  float* lam_x;
+  float* lam_v;
+  double* lpart;           // per-block partial losses
+  int n;
+  int loss;                // 0: per-axis MSD, 1: mean x displacement
+  int nblocks;
+};
+
+struct AdjFinalArgs {
+  const double* lpart;
+  const double* gpart;
+  double* out;             // loss, dL/deps, dL/dsigma
+  int nl;
+  int nb;
+};
+
+struct AdjIoArgs {
+  const int* id;
+  float* sorted;
+  float* by_id;
+  int n;
+  int to_sorted;
+};
+
 void launch_fill_u32(unsigned* p, unsigned v, long long n, hipStream_t s);
+void launch_adjoint(int D, const AdjArgs& a, hipStream_t s);
+void launch_adj_loss(int D, const AdjLossArgs& a, hipStream_t s);
+void launch_adj_final(const AdjFinalArgs& a, hipStream_t s);
+void launch_adj_io(int D, const AdjIoArgs& a, hipStream_t s);
+void launch_copy_f32(const float* src, float* dst, long long n, hipStream_t s);
 void launch_fill_f32(float* p, float v, long long n, hipStream_t s);
 void launch_ingest(int D, int nchunks, const IngestArgs& a, hipStream_t s);
 void launch_count(int D, int nchunks, const SortArgs& a, hipStream_t s);

@@ -74,6 +74,8 @@ struct Phys {
   int n_cells;
   int n_sites;
   double s_d;       // MD cell side in double (displacement sums)
+  double rc_d;      // r_cut (host bookkeeping)
+  double u_d;       // fixed-point unit s / 2^F (host bookkeeping)
 };
 
 }  // namespace mdlg

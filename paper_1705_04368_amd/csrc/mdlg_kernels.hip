@@ -413,22 +413,159 @@ __global__ __launch_bounds__(kBlock) void k_scatter(SortArgs a) {
 // margin) can reach, reading contiguous LDS ranges row by row.  The LJ sum is
 // computed in units of u = s / 2^F; the acceleration comes out in physical
 // units because 24 eps / m was divided by u on the host.
+//
+// The same brick machinery serves the adjoint kernel, which stages the
+// adjoint velocity next to the coordinates.
 
 template <int D>
-struct ForceLds {
+using Coord = typename std::conditional<D == 2, int2, int4>::type;
+
+template <int D, bool ADJ>
+struct BrickLds {
   static constexpr int MAXH = (D == 2) ? kMaxHalo2 : kMaxHalo3;
-  static constexpr int CAP = (D == 2) ? kCap2 : kCap3;
-  using Coord = typename std::conditional<D == 2, int2, int4>::type;
+  static constexpr int CAP = ADJ ? ((D == 2) ? kCap2 / 2 : kCap3 / 2) : ((D == 2) ? kCap2 : kCap3);
   int hs[MAXH + 1];   // LDS start of every halo cell (exclusive scan of counts)
   int gs[MAXH];       // global start of every halo cell
-  Coord p[CAP];       // fixed-point coordinates of the staged particles
+  Coord<D> p[CAP];    // fixed-point coordinates of the staged particles
+  float lam[ADJ ? CAP * D : 1];  // adjoint velocity of the staged particles
   int rowpre[kMaxRows + 1];
   int tmp[kWaves + 1];
   double red[kWaves][D + 1];
 };
 
+struct BrickGeom {
+  int ns, nsz, x0, y0, z0, wx, wy, wz, HX, HY, HZ, nh, total, nrows, ntg;
+};
+
 __device__ __forceinline__ int fixed_coord(int h, float off, const Phys& P) {
   return (h << P.F) + __float2int_rn(off * P.fscale);
+}
+
+// Halo table of a brick: particle count of every halo cell, exclusive scan
+// into L.hs (LDS starts), global starts into L.gs, and the prefix of the
+// brick's rows of targets into L.rowpre.
+template <int D, class Lds>
+__device__ __forceinline__ BrickGeom brick_setup(const Phys& P, const Replica& R, const int4 br,
+                                                 const int* __restrict__ cell_start, Lds& L) {
+  BrickGeom G;
+  G.ns = P.ns;
+  G.nsz = (D == 3) ? P.ns : 0;
+  G.x0 = br.y * P.BX;
+  G.y0 = br.z * P.BY;
+  G.z0 = (D == 3) ? br.w * P.BZ : 0;
+  G.wx = min(P.BX, R.Mc[0] - G.x0);
+  G.wy = min(P.BY, R.Mc[1] - G.y0);
+  G.wz = (D == 3) ? min(P.BZ, R.Mc[2] - G.z0) : 1;
+  G.HX = G.wx + 2 * G.ns;
+  G.HY = G.wy + 2 * G.ns;
+  G.HZ = G.wz + 2 * G.nsz;
+  G.nh = G.HX * G.HY * G.HZ;
+  const int ipt = (G.nh + kBlock - 1) / kBlock;
+  const int h0 = threadIdx.x * ipt, h1 = min(G.nh, h0 + ipt);
+  int mysum = 0;
+  for (int h = h0; h < h1; ++h) {
+    const int hx = h % G.HX, r = h / G.HX, hy = r % G.HY, hz = r / G.HY;
+    const int cx = wrap_cell(G.x0 - G.ns + hx, R.Mc[0]);
+    const int cy = wrap_cell(G.y0 - G.ns + hy, R.Mc[1]);
+    const int cz = (D == 3) ? wrap_cell(G.z0 - G.nsz + hz, R.Mc[2]) : 0;
+    const int gc = R.cell_off + cx + R.Mc[0] * (cy + R.Mc[1] * cz);
+    const int st = cell_start[gc], en = cell_start[gc + 1];
+    L.gs[h] = st;
+    L.hs[h] = en - st;
+    mysum += en - st;
+  }
+  int run = block_excl_scan(mysum, L.tmp, &G.total);
+  for (int h = h0; h < h1; ++h) {
+    const int cnt = L.hs[h];
+    L.hs[h] = run;
+    run += cnt;
+  }
+  G.nrows = G.wy * G.wz;
+  if (threadIdx.x == 0) L.hs[G.nh] = G.total;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int r = 0; r < G.nrows; ++r) {
+      const int hlo = G.ns + G.HX * ((G.ns + r % G.wy) + G.HY * (G.nsz + r / G.wy));
+      L.rowpre[r] = acc;
+      acc += L.hs[hlo + G.wx] - L.hs[hlo];
+    }
+    L.rowpre[G.nrows] = acc;
+  }
+  __syncthreads();
+  G.ntg = L.rowpre[G.nrows];
+  return G;
+}
+
+// Stage halo particles [cb, ce) (LDS order) as fixed-point coordinates, and
+// their adjoint velocities when `lam` is given.
+template <int D, class Lds>
+__device__ __forceinline__ void brick_stage(const BrickGeom& G, const Phys& P,
+                                            const float* __restrict__ pos, const float* __restrict__ lam,
+                                            Lds& L, int cb, int ce) {
+  for (int v0 = cb + (int)threadIdx.x; v0 < ce; v0 += 4 * kBlock) {
+    int hh[4], g[4];
+    float p[4][D];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int v = v0 + u * kBlock;
+      int lo = 0;
+      if (v < ce) {
+        int hi = G.nh - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (L.hs[mid] <= v) lo = mid; else hi = mid - 1;
+        }
+      }
+      hh[u] = lo;
+      g[u] = L.gs[lo] + (v - L.hs[lo]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (v0 + u * kBlock < ce) ldv<D>(pos, g[u], p[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int v = v0 + u * kBlock;
+      if (v < ce) {
+        const int hx = hh[u] % G.HX, r = hh[u] / G.HX;
+        if constexpr (D == 2)
+          L.p[v - cb] = make_int2(fixed_coord(hx, p[u][0], P), fixed_coord(r, p[u][1], P));
+        else
+          L.p[v - cb] = make_int4(fixed_coord(hx, p[u][0], P), fixed_coord(r % G.HY, p[u][1], P),
+                                  fixed_coord(r / G.HY, p[u][2], P), 0);
+        if (lam) {
+          float l[D];
+          ldv<D>(lam, g[u], l);
+#pragma unroll
+          for (int k = 0; k < D; ++k) L.lam[(v - cb) * D + k] = l[k];
+        }
+      }
+    }
+  }
+}
+
+// Halo coordinates and global index of target t of the brick.
+template <int D, class Lds>
+__device__ __forceinline__ void brick_target(const BrickGeom& G, const Lds& L, int t, int& hxi,
+                                             int& hyi, int& hzi, int& gi) {
+  int lo = 0, hi = G.nrows - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (L.rowpre[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const int row = lo;
+  hyi = G.ns + row % G.wy;
+  hzi = G.nsz + row / G.wy;
+  const int hbase = G.HX * (hyi + G.HY * hzi);
+  const int vi = L.hs[hbase + G.ns] + (t - L.rowpre[row]);
+  int clo = G.ns, chi = G.ns + G.wx - 1;
+  while (clo < chi) {
+    const int mid = (clo + chi + 1) >> 1;
+    if (L.hs[hbase + mid] <= vi) clo = mid; else chi = mid - 1;
+  }
+  hxi = clo;
+  const int hc = hbase + hxi;
+  gi = L.gs[hc] + (vi - L.hs[hc]);
 }
 
 // Accumulate the LJ acceleration of one candidate on the target at (X, Y, Z).
@@ -455,10 +592,29 @@ __device__ __forceinline__ void lj_pair(const C& q, int X, int Y, int Z, const P
   if constexpr (D == 3) f[D - 1] -= gg * dz;
 }
 
+// Cell range a target at (X, Y, Z) has to visit: every cell whose particles
+// (which may sit up to the rebuild margin outside it) can lie within r_cut.
+struct Reach {
+  int cx0, cx1, cy0, cy1, cz0, cz1;
+};
+
+template <int D>
+__device__ __forceinline__ Reach target_reach(const BrickGeom& G, const Phys& P, int X, int Y, int Z) {
+  Reach r;
+  r.cx0 = max(0, (X - P.rcq) >> P.F);
+  r.cx1 = min(G.HX - 1, (X + P.rcq) >> P.F);
+  r.cy0 = max(0, (Y - P.rcq) >> P.F);
+  r.cy1 = min(G.HY - 1, (Y + P.rcq) >> P.F);
+  r.cz0 = (D == 3) ? max(0, (Z - P.rcq) >> P.F) : 0;
+  r.cz1 = (D == 3) ? min(G.HZ - 1, (Z + P.rcq) >> P.F) : 0;
+  return r;
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
-  constexpr int CAP = ForceLds<D>::CAP;
-  __shared__ ForceLds<D> L;
+  using Lds = BrickLds<D, false>;
+  constexpr int CAP = Lds::CAP;
+  __shared__ Lds L;
   int b = blockIdx.x;
   if (a.xcd_remap) {
     // blocks are dispatched round-robin over the 8 XCDs; give each XCD a
@@ -470,94 +626,11 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
   const Phys& P = a.P;
   const int4 br = a.bricks[b];
   const Replica R = a.reps[br.x];
-  const int ns = P.ns;
-  const int nsz = (D == 3) ? ns : 0;
-  const int x0 = br.y * P.BX, y0 = br.z * P.BY, z0 = (D == 3) ? br.w * P.BZ : 0;
-  const int wx = min(P.BX, R.Mc[0] - x0);
-  const int wy = min(P.BY, R.Mc[1] - y0);
-  const int wz = (D == 3) ? min(P.BZ, R.Mc[2] - z0) : 1;
-  const int HX = wx + 2 * ns, HY = wy + 2 * ns, HZ = wz + 2 * nsz;
-  const int HXY = HX * HY;
-  const int nh = HXY * HZ;
-
-  // 1) particle count of every halo cell, exclusive scan -> LDS starts
-  const int ipt = (nh + kBlock - 1) / kBlock;
-  const int h0 = threadIdx.x * ipt, h1 = min(nh, h0 + ipt);
-  int mysum = 0;
-  for (int h = h0; h < h1; ++h) {
-    const int hx = h % HX, r = h / HX, hy = r % HY, hz = r / HY;
-    const int cx = wrap_cell(x0 - ns + hx, R.Mc[0]);
-    const int cy = wrap_cell(y0 - ns + hy, R.Mc[1]);
-    const int cz = (D == 3) ? wrap_cell(z0 - nsz + hz, R.Mc[2]) : 0;
-    const int gc = R.cell_off + cx + R.Mc[0] * (cy + R.Mc[1] * cz);
-    const int st = a.cell_start[gc], en = a.cell_start[gc + 1];
-    L.gs[h] = st;
-    L.hs[h] = en - st;
-    mysum += en - st;
-  }
-  int total;
-  int run = block_excl_scan(mysum, L.tmp, &total);
-  for (int h = h0; h < h1; ++h) {
-    const int cnt = L.hs[h];
-    L.hs[h] = run;
-    run += cnt;
-  }
-  const int nrows = wy * wz;
-  if (threadIdx.x == 0) L.hs[nh] = total;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int r = 0; r < nrows; ++r) {
-      const int hlo = ns + HX * ((ns + r % wy) + HY * (nsz + r / wy));
-      L.rowpre[r] = acc;
-      acc += L.hs[hlo + wx] - L.hs[hlo];
-    }
-    L.rowpre[nrows] = acc;
-  }
-  __syncthreads();
-  const int ntg = L.rowpre[nrows];
-  const int nchunks = (total + CAP - 1) / CAP;
-
-  // 2) staging of halo particles [cb, ce) as fixed-point coordinates
-  auto stage = [&](int cb, int ce) {
-    for (int v0 = cb + (int)threadIdx.x; v0 < ce; v0 += 4 * kBlock) {
-      int hh[4], g[4];
-      float p[4][D];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int v = v0 + u * kBlock;
-        int lo = 0;
-        if (v < ce) {
-          int hi = nh - 1;
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (L.hs[mid] <= v) lo = mid; else hi = mid - 1;
-          }
-        }
-        hh[u] = lo;
-        g[u] = L.gs[lo] + (v - L.hs[lo]);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (v0 + u * kBlock < ce) ldv<D>(a.pos_in, g[u], p[u]);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int v = v0 + u * kBlock;
-        if (v < ce) {
-          const int hx = hh[u] % HX, r = hh[u] / HX;
-          if constexpr (D == 2)
-            L.p[v - cb] = make_int2(fixed_coord(hx, p[u][0], P), fixed_coord(r, p[u][1], P));
-          else
-            L.p[v - cb] = make_int4(fixed_coord(hx, p[u][0], P), fixed_coord(r % HY, p[u][1], P),
-                                    fixed_coord(r / HY, p[u][2], P), 0);
-        }
-      }
-    }
-  };
-
+  const BrickGeom G = brick_setup<D>(P, R, br, a.cell_start, L);
+  const int nchunks = (G.total + CAP - 1) / CAP;
   const bool interact = !P.forces_off;
   if (interact && nchunks == 1) {
-    stage(0, total);
+    brick_stage<D>(G, P, a.pos_in, nullptr, L, 0, G.total);
     __syncthreads();
   }
 
@@ -565,30 +638,11 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
 #pragma unroll
   for (int k = 0; k <= D; ++k) kin[k] = 0.0;
 
-  for (int tb = 0; tb < ntg; tb += kBlock) {
+  for (int tb = 0; tb < G.ntg; tb += kBlock) {
     const int t = tb + (int)threadIdx.x;
-    const bool valid = t < ntg;
-    int hxi = ns, hyi = ns, hzi = nsz, gi = 0;
-    if (valid) {
-      int lo = 0, hi = nrows - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (L.rowpre[mid] <= t) lo = mid; else hi = mid - 1;
-      }
-      const int row = lo;
-      hyi = ns + row % wy;
-      hzi = nsz + row / wy;
-      const int hbase = HX * (hyi + HY * hzi);
-      const int vi = L.hs[hbase + ns] + (t - L.rowpre[row]);
-      int clo = ns, chi = ns + wx - 1;
-      while (clo < chi) {
-        const int mid = (clo + chi + 1) >> 1;
-        if (L.hs[hbase + mid] <= vi) clo = mid; else chi = mid - 1;
-      }
-      hxi = clo;
-      const int hc = hbase + hxi;
-      gi = L.gs[hc] + (vi - L.hs[hc]);
-    }
+    const bool valid = t < G.ntg;
+    int hxi = G.ns, hyi = G.ns, hzi = G.nsz, gi = 0;
+    if (valid) brick_target<D>(G, L, t, hxi, hyi, hzi, gi);
     float o[D], f[D], v[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -604,26 +658,23 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
       const int X = fixed_coord(hxi, o[0], P);
       const int Y = fixed_coord(hyi, o[1], P);
       const int Z = (D == 3) ? fixed_coord(hzi, o[D - 1], P) : 0;
-      const int cx0 = max(0, (X - P.rcq) >> P.F), cx1 = min(HX - 1, (X + P.rcq) >> P.F);
-      const int cy0 = max(0, (Y - P.rcq) >> P.F), cy1 = min(HY - 1, (Y + P.rcq) >> P.F);
-      const int cz0 = (D == 3) ? max(0, (Z - P.rcq) >> P.F) : 0;
-      const int cz1 = (D == 3) ? min(HZ - 1, (Z + P.rcq) >> P.F) : 0;
+      const Reach rr = target_reach<D>(G, P, X, Y, Z);
       for (int ci = 0; ci < nchunks; ++ci) {
-        const int cb = ci * CAP, ce = min(total, cb + CAP);
+        const int cb = ci * CAP, ce = min(G.total, cb + CAP);
         if (nchunks > 1) {
           __syncthreads();
-          stage(cb, ce);
+          brick_stage<D>(G, P, a.pos_in, nullptr, L, cb, ce);
           __syncthreads();
         }
         if (valid) {
-          for (int cz = cz0; cz <= cz1; ++cz) {
-            for (int cy = cy0; cy <= cy1; ++cy) {
-              const int hrow = HX * (cy + HY * cz);
-              const int jlo = max(L.hs[hrow + cx0], cb) - cb;
-              const int jhi = min(L.hs[hrow + cx1 + 1], ce) - cb;
+          for (int cz = rr.cz0; cz <= rr.cz1; ++cz) {
+            for (int cy = rr.cy0; cy <= rr.cy1; ++cy) {
+              const int hrow = G.HX * (cy + G.HY * cz);
+              const int jlo = max(L.hs[hrow + rr.cx0], cb) - cb;
+              const int jhi = min(L.hs[hrow + rr.cx1 + 1], ce) - cb;
               int j = jlo;
               for (; j + 3 < jhi; j += 4) {
-                typename ForceLds<D>::Coord q[4];
+                Coord<D> q[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) q[u] = L.p[j + u];
 #pragma unroll
@@ -684,6 +735,214 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
       a.kpart[(size_t)b * (D + 1) + threadIdx.x] = s;
     }
   }
+}
+
+// ---------------------------------------------------------------- adjoint
+//
+// One reverse step of the velocity-Verlet adjoint at positions x_s: for every
+// particle i,
+//   a_i, da_i/dsigma, and (J lam_v)_i = sum_j K_ij (lam_v,i - lam_v,j) / m with
+//   K = g I + (g'(r)/r) r r^T, g(r) = (24 eps / r^2)[2 (sigma/r)^12 - (sigma/r)^6],
+// then lam_x,i += c (J lam_v)_i, the parameter gradients gain
+// c lam_v,i . a_i / eps and c lam_v,i . da_i/dsigma, and (unless this is the
+// first position of the window) lam_v,i += h lam_x,i, written to the other
+// lam_v buffer.  Coordinates are fixed point as in k_force; with d = x_j - x_i
+// in units u, r = -d and the terms read (E1 = 24 eps / (m u), E2 = E1 / u):
+//   a_i      -= E1 ir2 s6 (2 s6 - 1) d
+//   da_i/ds  -= (E1 / sigma) ir2 s6 (24 s6 - 6) d
+//   (J l)_i  += E2 [ir2 s6 (2 s6 - 1) dl + ir2^2 s6 (8 - 28 s6) (d . dl) d]
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs a) {
+  using Lds = BrickLds<D, true>;
+  constexpr int CAP = Lds::CAP;
+  __shared__ Lds L;
+  const int b = blockIdx.x;
+  if (b >= a.nbricks) return;
+  const Phys& P = a.P;
+  const int4 br = a.bricks[b];
+  const Replica R = a.reps[br.x];
+  const BrickGeom G = brick_setup<D>(P, R, br, a.cell_start, L);
+  const int nchunks = (G.total + CAP - 1) / CAP;
+  const bool interact = !P.forces_off;
+  if (interact && nchunks == 1) {
+    brick_stage<D>(G, P, a.pos, a.lam_v_in, L, 0, G.total);
+    __syncthreads();
+  }
+  double ge = 0.0, gs = 0.0;
+  for (int tb = 0; tb < G.ntg; tb += kBlock) {
+    const int t = tb + (int)threadIdx.x;
+    const bool valid = t < G.ntg;
+    int hxi = G.ns, hyi = G.ns, hzi = G.nsz, gi = 0;
+    if (valid) brick_target<D>(G, L, t, hxi, hyi, hzi, gi);
+    float o[D], li[D], acc[D], dacc[D], jl[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      o[k] = 0.f;
+      li[k] = 0.f;
+      acc[k] = 0.f;
+      dacc[k] = 0.f;
+      jl[k] = 0.f;
+    }
+    if (valid) {
+      ldv<D>(a.pos, gi, o);
+      ldv<D>(a.lam_v_in, gi, li);
+    }
+    if (interact) {
+      const int X = fixed_coord(hxi, o[0], P);
+      const int Y = fixed_coord(hyi, o[1], P);
+      const int Z = (D == 3) ? fixed_coord(hzi, o[D - 1], P) : 0;
+      const Reach rr = target_reach<D>(G, P, X, Y, Z);
+      for (int ci = 0; ci < nchunks; ++ci) {
+        const int cb = ci * CAP, ce = min(G.total, cb + CAP);
+        if (nchunks > 1) {
+          __syncthreads();
+          brick_stage<D>(G, P, a.pos, a.lam_v_in, L, cb, ce);
+          __syncthreads();
+        }
+        if (valid) {
+          for (int cz = rr.cz0; cz <= rr.cz1; ++cz) {
+            for (int cy = rr.cy0; cy <= rr.cy1; ++cy) {
+              const int hrow = G.HX * (cy + G.HY * cz);
+              const int jlo = max(L.hs[hrow + rr.cx0], cb) - cb;
+              const int jhi = min(L.hs[hrow + rr.cx1 + 1], ce) - cb;
+              for (int j = jlo; j < jhi; ++j) {
+                const Coord<D> q = L.p[j];
+                float d[D], dl[D];
+                d[0] = (float)(q.x - X);
+                d[1] = (float)(q.y - Y);
+                if constexpr (D == 3) d[2] = (float)(q.z - Z);
+                float r2 = 0.f, ddl = 0.f;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                  dl[k] = li[k] - L.lam[j * D + k];
+                  r2 += d[k] * d[k];
+                  ddl += d[k] * dl[k];
+                }
+                const bool in = (r2 < P.rc2_u) && (r2 > 0.f);
+                const float ir2 = in ? __builtin_amdgcn_rcpf(r2) : 0.f;
+                const float sr2 = P.sig2_u * ir2;
+                const float s6 = sr2 * sr2 * sr2;
+                const float t1 = ir2 * s6 * (2.f * s6 - 1.f);
+                const float ts = ir2 * s6 * (24.f * s6 - 6.f);
+                const float t2 = ir2 * ir2 * s6 * (8.f - 28.f * s6) * ddl;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                  acc[k] -= t1 * d[k];
+                  dacc[k] -= ts * d[k];
+                  jl[k] += t1 * dl[k] + t2 * d[k];
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+    if (valid) {
+      float lx[D], lv[D];
+      ldv<D>(a.lam_x, gi, lx);
+      double e = 0.0, s = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const float a_k = P.eps24m_u * acc[k];
+        const float da_k = a.e1_over_sigma * dacc[k];
+        const float jl_k = a.e2 * jl[k];
+        lx[k] = fmaf(a.c, jl_k, lx[k]);
+        e += (double)li[k] * (double)a_k;
+        s += (double)li[k] * (double)da_k;
+        lv[k] = a.drift ? fmaf(P.dt, lx[k], li[k]) : li[k];
+      }
+      ge += (double)a.c * e / a.eps;
+      gs += (double)a.c * s;
+      stv<D>(a.lam_x, gi, lx);
+      stv<D>(a.lam_v_out, gi, lv);
+    }
+  }
+  const int w = threadIdx.x >> 6;
+  const double se = wave_sum_d(ge), ss = wave_sum_d(gs);
+  if (lane_id() == 0) {
+    L.red[w][0] = se;
+    L.red[w][1] = ss;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+    for (int i = 0; i < kWaves; ++i) t += L.red[i][threadIdx.x];
+    a.gpart[(size_t)b * 2 + threadIdx.x] += t;
+  }
+}
+
+// Loss of the window and its gradient with respect to the final positions.
+// Cells are fixed during the window, so x_j(W) - x_j(0) = off_W - off_0.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_adj_loss(AdjLossArgs a) {
+  __shared__ double s_red[kWaves];
+  double L = 0.0;
+  const double inv_nd = 1.0 / ((double)a.n * D), inv_n = 1.0 / (double)a.n;
+  for (int g = blockIdx.x * kBlock + threadIdx.x; g < a.n; g += gridDim.x * kBlock) {
+    float o0[D], o1[D], lx[D], zero[D];
+    ldv<D>(a.off0, g, o0);
+    ldv<D>(a.offW, g, o1);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double dd = (double)o1[k] - (double)o0[k];
+      zero[k] = 0.f;
+      if (a.loss == 0) {
+        L += dd * dd * inv_nd;
+        lx[k] = (float)(2.0 * dd * inv_nd);
+      } else {
+        if (k == 0) L += dd * inv_n;
+        lx[k] = (k == 0) ? (float)inv_n : 0.f;
+      }
+    }
+    stv<D>(a.lam_x, g, lx);
+    stv<D>(a.lam_v, g, zero);
+  }
+  const double s = wave_sum_d(L);
+  if (lane_id() == 0) s_red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < kWaves; ++i) t += s_red[i];
+    a.lpart[blockIdx.x] = t;
+  }
+}
+
+// Sum of the per-block partials of the loss and the parameter gradients, in
+// a fixed order.
+__global__ void k_adj_final(AdjFinalArgs a) {
+  if (threadIdx.x == 0) {
+    double L = 0.0;
+    for (int i = 0; i < a.nl; ++i) L += a.lpart[i];
+    a.out[0] = L;
+  } else if (threadIdx.x <= 2) {
+    const int c = threadIdx.x - 1;
+    double t = 0.0;
+    for (int b = 0; b < a.nb; ++b) t += a.gpart[(size_t)b * 2 + c];
+    a.out[1 + c] = t;
+  }
+}
+
+// Velocities by id into the sorted state (start of an adjoint window), and
+// the adjoint of v(0) from the sorted order back to id order.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_adj_io(AdjIoArgs a) {
+  for (int g = blockIdx.x * kBlock + threadIdx.x; g < a.n; g += gridDim.x * kBlock) {
+    const int pid = a.id[g];
+    float v[D];
+    if (a.to_sorted) {
+      ldv<D>(a.by_id, pid, v);
+      stv<D>(a.sorted, g, v);
+    } else {
+      ldv<D>(a.sorted, g, v);
+      stv<D>(a.by_id, pid, v);
+    }
+  }
+}
+
+__global__ void k_copy_f32(const float* __restrict__ src, float* __restrict__ dst, long long n) {
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock)
+    dst[i] = src[i];
 }
 
 // ---------------------------------------------------------------- kinetics
@@ -1027,6 +1286,32 @@ void launch_site_avg(const SiteAvgArgs& a, hipStream_t s) {
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_site_avg, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+}
+
+void launch_adjoint(int D, const AdjArgs& a, hipStream_t s) {
+  MDLG_LAUNCH_DIM(D, k_adjoint, a.nbricks, 0, s, a);
+}
+
+static int grid_for(long long n) {
+  long long b = (n + kBlock - 1) / kBlock;
+  return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+void launch_adj_loss(int D, const AdjLossArgs& a, hipStream_t s) {
+  MDLG_LAUNCH_DIM(D, k_adj_loss, a.nblocks, 0, s, a);
+}
+
+void launch_adj_final(const AdjFinalArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_final, dim3(1), dim3(64), 0, s, a);
+}
+
+void launch_adj_io(int D, const AdjIoArgs& a, hipStream_t s) {
+  MDLG_LAUNCH_DIM(D, k_adj_io, grid_for(a.n), 0, s, a);
+}
+
+void launch_copy_f32(const float* src, float* dst, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_copy_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, src, dst, n);
 }
 
 void launch_export(int D, int nchunks, const XportArgs& a, hipStream_t s) {

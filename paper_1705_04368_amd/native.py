@@ -20,8 +20,9 @@ STATUS = {0: "MDLG_OK", -1: "MDLG_E_INVALID", -2: "MDLG_E_DEVICE", -3: "MDLG_E_N
 
 EXPORTED = ["mdlg_describe", "mdlg_workspace_bytes", "mdlg_create", "mdlg_step",
             "mdlg_coarse_grain", "mdlg_get_f", "mdlg_get_kinetics", "mdlg_reset_accumulators",
-            "mdlg_get_state", "mdlg_set_state", "mdlg_set_timing", "mdlg_get_timing", "mdlg_sync",
-            "mdlg_last_error", "mdlg_destroy"]
+            "mdlg_get_state", "mdlg_set_state", "mdlg_adjoint", "mdlg_set_potential",
+            "mdlg_set_timing", "mdlg_get_timing", "mdlg_sync", "mdlg_last_error", "mdlg_destroy"]
+LOSSES = {"msd": 0, "mean_x": 1}
 KERNEL_CLASSES = ["force", "count", "scan", "scatter", "bin"]
 
 
@@ -33,7 +34,8 @@ class MdlgConfig(C.Structure):
                 ("dt", C.c_double), ("md_steps_per_lattice_step", C.c_int32),
                 ("vmax", C.c_int32), ("thermostat_every", C.c_int32), ("kT", C.c_double),
                 ("md_cell_split", C.c_int32), ("sort_every", C.c_int32),
-                ("brick_x", C.c_int32), ("brick_y", C.c_int32), ("brick_z", C.c_int32)]
+                ("brick_x", C.c_int32), ("brick_y", C.c_int32), ("brick_z", C.c_int32),
+                ("adjoint_window", C.c_int32), ("adjoint_every", C.c_int32)]
 
 
 class MdlgParticles(C.Structure):
@@ -90,6 +92,11 @@ def load():
     lib.mdlg_get_state.argtypes = [C.c_void_p, P(MdlgParticles)]
     lib.mdlg_set_state.restype = st
     lib.mdlg_set_state.argtypes = [C.c_void_p, P(MdlgParticles)]
+    lib.mdlg_adjoint.restype = st
+    lib.mdlg_adjoint.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                 P(C.c_double), P(C.c_double), P(C.c_double), C.c_void_p]
+    lib.mdlg_set_potential.restype = st
+    lib.mdlg_set_potential.argtypes = [C.c_void_p, C.c_double, C.c_double]
     lib.mdlg_set_timing.restype = st
     lib.mdlg_set_timing.argtypes = [C.c_void_p, C.c_int]
     lib.mdlg_get_timing.restype = st
@@ -118,7 +125,8 @@ def _check(status, handle=None):
 
 def make_config(dim, n_particles, lattice, lattice_dx=4.0, epsilon=1.0, sigma=1.0, mass=1.0,
                 r_cut=2.5, forces_off=False, dt=0.005, md_steps_per_lattice_step=20, vmax=3,
-                thermostat_every=0, kT=1.0, md_cell_split=0, sort_every=0, brick=(0, 0, 0)):
+                thermostat_every=0, kT=1.0, md_cell_split=0, sort_every=0, brick=(0, 0, 0),
+                adjoint_window=0, adjoint_every=1):
     """Build an MdlgConfig.  n_particles: int or sequence per replica; lattice:
     sites per axis, an int, a (dim,) sequence or an (n_replicas, dim) array."""
     n = np.atleast_1d(np.asarray(n_particles, dtype=np.int32))
@@ -146,6 +154,8 @@ def make_config(dim, n_particles, lattice, lattice_dx=4.0, epsilon=1.0, sigma=1.
     cfg.md_cell_split = md_cell_split
     cfg.sort_every = sort_every
     cfg.brick_x, cfg.brick_y, cfg.brick_z = (int(b) for b in brick)
+    cfg.adjoint_window = adjoint_window
+    cfg.adjoint_every = adjoint_every if adjoint_window else 0
     return cfg
 
 
@@ -231,6 +241,24 @@ class System:
 
     def sync(self):
         _check(load().mdlg_sync(self.handle), self.handle)
+
+    def adjoint(self, window, ckpt_every, loss="msd", v0=None, want_v0=True):
+        """Loss of the displacement over `window` MD steps from the current
+        positions (and v0, a device tensor in id order, when given) with its
+        gradients: returns (L, dL/deps, dL/dsigma, dL/dv0 device tensor or None)."""
+        import torch
+        L, ge, gs = C.c_double(0), C.c_double(0), C.c_double(0)
+        g = torch.empty((self.n_total, self.dim), dtype=torch.float32, device=self.device) if want_v0 else None
+        if v0 is not None:
+            v0 = v0.detach().to(device=self.device, dtype=torch.float32).contiguous()
+        _check(load().mdlg_adjoint(self.handle, int(window), int(ckpt_every), LOSSES[loss],
+                                   C.c_void_p(v0.data_ptr()) if v0 is not None else None,
+                                   C.byref(L), C.byref(ge), C.byref(gs),
+                                   C.c_void_p(g.data_ptr()) if g is not None else None), self.handle)
+        return L.value, ge.value, gs.value, g
+
+    def set_potential(self, epsilon, sigma):
+        _check(load().mdlg_set_potential(self.handle, float(epsilon), float(sigma)), self.handle)
 
     def set_timing(self, enable):
         _check(load().mdlg_set_timing(self.handle, int(bool(enable))), self.handle)
