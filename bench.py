@@ -39,6 +39,12 @@ WORKLOADS = {
     "3d": dict(dim=3, n=4194304, M=48, dx=4.0, kT=1.5, dt=0.004, steps=20, vmax=2,
                desc="3D LJ N=4194304, 192 sigma cube (rho=0.593), kT=1.5, dt=0.004, "
                     "48^3 lattice of 4 sigma, Delta t=20 MD steps, V=2 (Q=125)"),
+    "batched": dict(dim=2, n=None, M=None, dx=4.0, kT=1.0, dt=0.005, steps=20, vmax=3,
+                    replicas=512,
+                    desc="512 2D LJ replicas, N_r log-uniform in [1024, 65536] (seed 4), rho=0.5, "
+                         "kT=1, dt=0.005, 4 sigma lattice per replica, Delta t=20 MD steps, V=3; "
+                         "batched (one launch per kernel for all replicas) vs plain (one system "
+                         "per replica, launched one after another)"),
 }
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector, published
@@ -111,6 +117,54 @@ def cpu_baseline(w, pos, vel, lattice_steps):
                       f"steps + binning), FP64 single thread, {t:.1f} s"}
 
 
+def plain_replicas(sysg, cfg, n_r, m_r, w, dev, lattice_steps):
+    """The same ensemble as one system per replica, launched one after the
+    other (each replica's lattice step is its own graph of launches).  The
+    replicas start from the batched system's equilibrated state."""
+    import torch
+
+    from paper_1705_04368_amd import System, make_config
+    st = sysg.get_state()
+    k = sysg.layout["md_cell_split"]
+    systems = []
+    off = 0
+    for nr, mr in zip(n_r, m_r):
+        nr, mr = int(nr), int(mr)
+        c = make_config(2, nr, mr, lattice_dx=w["dx"], dt=w["dt"], md_steps_per_lattice_step=w["steps"],
+                        vmax=w["vmax"], kT=w["kT"], md_cell_split=k, sort_every=sysg.layout["sort_every"])
+        sl = slice(off, off + nr)
+        s = sysg.layout["cell_side"]
+        x = (np.mod(st["ucell"][sl], mr * k).astype(np.float64) * s + st["off"][sl]).astype(np.float32)
+        x = np.where(x >= np.float32(mr * k * s), np.float32(0.0), x)
+        r = System(c, torch.from_numpy(x).to(dev), torch.from_numpy(st["vel"][sl].copy()).to(dev))
+        systems.append(r)
+        off += nr
+    for r in systems:  # warm-up: captures each replica's lattice-step graph
+        r.coarse_grain(1)
+    for r in systems:
+        r.sync()
+        r.reset_accumulators()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(lattice_steps):
+        for r in systems:
+            r.coarse_grain(1)
+    for r in systems:
+        r.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    n = int(np.sum(n_r))
+    counts = sum(r.get_f()["counts"] for r in systems)
+    sites = int(np.sum(m_r.astype(np.int64) ** 2))
+    q = len(counts)
+    f0 = float(counts[(q - 1) // 2]) / (lattice_steps * sites) / 8.0
+    for r in systems:
+        r.close()
+    return {"value": n * lattice_steps * w["steps"] / el, "unit": "particle-steps/s",
+            "lattice_steps": lattice_steps, "ms_per_step": el / lattice_steps * 1e3,
+            "f0_plain": f0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +176,8 @@ def main():
                     help="lattice steps of the event-timed per-kernel pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-lattice-steps", type=int, default=2)
+    ap.add_argument("--plain-steps", type=int, default=3,
+                    help="lattice steps timed for the plain (one system per replica) path")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -134,14 +190,32 @@ def main():
     from paper_1705_04368_amd import System, make_config
 
     w = WORKLOADS[args.workload]
-    dim, n, M = w["dim"], w["n"], w["M"]
-    box = M * w["dx"]
-    rho = n / box ** dim
+    dim = w["dim"]
     dev = torch.device("cuda:0")
-    pos, vel = synth.lj_initial_state(dim, n, box, w["kT"], seed=2 if dim == 2 else 3)
-    cfg = make_config(dim, n, M, lattice_dx=w["dx"], dt=w["dt"],
-                      md_steps_per_lattice_step=w["steps"], vmax=w["vmax"], thermostat_every=10,
-                      kT=w["kT"])
+    if w.get("replicas"):
+        n_r, m_r = synth.replica_sizes(w["replicas"], seed=4)
+        seeds = synth.replica_seeds(w["replicas"], seed=4)
+        parts = [synth.lj_initial_state(dim, int(nr), w["dx"] * int(mr), w["kT"], seed=sd)
+                 for nr, mr, sd in zip(n_r, m_r, seeds)]
+        pos = np.concatenate([p for p, _ in parts])
+        vel = np.concatenate([v for _, v in parts])
+        n = int(n_r.sum())
+        M = None
+        rho = 0.5
+        lattice = np.stack([m_r, m_r], axis=1)
+        n_sites = int((m_r.astype(np.int64) ** 2).sum())
+        cfg = make_config(dim, n_r, lattice, lattice_dx=w["dx"], dt=w["dt"],
+                          md_steps_per_lattice_step=w["steps"], vmax=w["vmax"], thermostat_every=10,
+                          kT=w["kT"])
+    else:
+        n, M = w["n"], w["M"]
+        box = M * w["dx"]
+        rho = n / box ** dim
+        n_sites = M ** dim
+        pos, vel = synth.lj_initial_state(dim, n, box, w["kT"], seed=2 if dim == 2 else 3)
+        cfg = make_config(dim, n, M, lattice_dx=w["dx"], dt=w["dt"],
+                          md_steps_per_lattice_step=w["steps"], vmax=w["vmax"], thermostat_every=10,
+                          kT=w["kT"])
     sysg = System(cfg, torch.from_numpy(pos).to(dev), torch.from_numpy(vel).to(dev))
     lay = sysg.layout
     print(f"# workload {args.workload}: {w['desc']}; layout {lay}", file=sys.stderr, flush=True)
@@ -170,7 +244,7 @@ def main():
     tim = sysg.get_timing()
     sysg.set_timing(False)
     q, nm = lay["n_velocities"], lay["n_moments"]
-    per_site = n / (M ** dim)
+    per_site = n / n_sites
     kernels = {}
     for k, (ms, cnt) in tim.items():
         if cnt == 0:
@@ -204,8 +278,14 @@ def main():
                 "unit": kd["unit"], "frac": kd["frac"],
                 "traffic": load_traffic(args.workload, dom)}
 
+    plain = None
+    if w.get("replicas"):
+        plain = plain_replicas(sysg, cfg, n_r, m_r, w, dev, args.plain_steps)
+        plain["batched_over_plain"] = value / plain["value"]
+        plain["f0_batched"] = float(f["f"][(q - 1) // 2]) / 8.0
+
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not w.get("replicas"):
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(w, pos, vel, args.cpu_lattice_steps)
 
@@ -220,6 +300,7 @@ def main():
                    "brick": list(lay["brick"])},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "plain": plain,
         "kernels": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
     }

@@ -40,6 +40,8 @@ struct Layout {
   std::vector<int4> bricks, chunks, strips;
   double s = 0, margin = 0, margin_max = 0;
   int sort_every = 1;
+  int halo_cells = 0;  // halo cells of the largest force brick
+  double per_cell = 0; // mean particles per MD cell
   int adj_ckpts = 0;   // checkpoints the workspace holds (0 = no adjoint)
   int adj_seg = 0;     // segment positions the workspace holds
 };
@@ -216,6 +218,8 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   while (c->brick_x == 0 && BX > 1 && halo_of(BX, BY, BZ) > maxh) BX = (BX + 1) / 2;
   while (c->brick_y == 0 && BY > 1 && halo_of(BX, BY, BZ) > maxh) BY = (BY + 1) / 2;
   const long long halo = halo_of(BX, BY, BZ);
+  L->halo_cells = (int)halo;
+  L->per_cell = per_cell;
   if (halo > maxh) return set_err(msg, "brick %dx%dx%d with stencil %d needs %lld halo cells > %d",
                                   BX, BY, BZ, L->ns, halo, maxh);
   if ((long long)BY * BZ > kMaxRows) return set_err(msg, "brick has more than %d rows", kMaxRows);
@@ -314,8 +318,8 @@ struct mdlg_system {
   int* count = nullptr;
   int* cell_start = nullptr;
   int* tile_sum = nullptr;
-  int* prev_u = nullptr;
-  float* prev_off = nullptr;
+  int* prev_u[2] = {nullptr, nullptr};    // snapshot, sorted order (set parity)
+  float* prev_off[2] = {nullptr, nullptr};
   unsigned* A = nullptr;
   long long* mom = nullptr;
   double* dpart = nullptr;
@@ -395,8 +399,10 @@ size_t carve(mdlg_system* S, char* base) {
   S->count = c.take<int>(base, (size_t)L.n_cells);
   S->cell_start = c.take<int>(base, (size_t)L.n_cells + 1);
   S->tile_sum = c.take<int>(base, (size_t)L.ntiles);
-  S->prev_u = c.take<int>(base, N * D);
-  S->prev_off = c.take<float>(base, N * D);
+  for (int i = 0; i < 2; ++i) {
+    S->prev_u[i] = c.take<int>(base, N * D);
+    S->prev_off[i] = c.take<float>(base, N * D);
+  }
   S->A = c.take<unsigned>(base, (size_t)L.n_sites * L.Q);
   S->mom = c.take<long long>(base, (size_t)L.n_sites * L.nm);
   S->dpart = c.take<double>(base, (size_t)L.nstrips * 2 * D);
@@ -426,7 +432,7 @@ size_t carve(mdlg_system* S, char* base) {
     S->adj_lpart = c.take<double>(base, 1024);
     S->adj_out = c.take<double>(base, 4);
   }
-  S->staging_bytes = std::max<size_t>(N * D * 4 * 4, size_t(4) << 20);
+  S->staging_bytes = std::max<size_t>(N * D * 4 * 6, size_t(4) << 20);
   S->staging = c.take<char>(base, S->staging_bytes);
   return c.off + 256;
 }
@@ -447,8 +453,20 @@ Phys make_phys(const mdlg_config* c, const Layout& L) {
   const double u = L.s / std::ldexp(1.0, P.F);
   P.fscale = (float)(std::ldexp(1.0, P.F) / L.s);
   P.rcq = (int)std::ceil((c->r_cut + L.margin) / u) + 1;
+  P.mq = (int)std::ceil(L.margin / u) + 4;
   P.rc_d = c->r_cut;
   P.u_d = u;
+  // dynamic LDS of the brick kernels: the halo cell table of the largest
+  // brick and room for about 1.5x the expected halo particles (a fuller halo
+  // is staged in several chunks); the adjoint also stages d floats each
+  P.lmaxh = L.halo_cells;
+  const double expect = L.halo_cells * L.per_cell;
+  const size_t head = ((size_t)(2 * P.lmaxh + 1) * sizeof(int) + 15) & ~size_t(15);
+  const size_t per = (L.D == 2 ? sizeof(int2) : sizeof(int4)) + L.D * sizeof(float);
+  long long cap = (long long)std::ceil(1.5 * expect) + 128;
+  cap = (cap + 63) / 64 * 64;
+  const long long fit = (long long)((kBrickLdsBytes - head) / per) / 64 * 64;
+  P.lcap = (int)std::max<long long>(64, std::min(cap, fit));
   P.rc2_u = (float)((c->r_cut / u) * (c->r_cut / u));
   P.sig2_u = (float)((c->sigma / u) * (c->sigma / u));
   P.eps24m_u = (float)(24.0 * c->epsilon / (c->mass * u));
@@ -564,6 +582,10 @@ SortArgs sort_args(mdlg_system* S) {
   a.img_out = S->img[S->scur ^ 1];
   a.id_out = S->id[S->scur ^ 1];
   a.cell_out = S->cell[S->scur ^ 1];
+  a.prev_u = S->prev_u[S->scur];
+  a.prev_off = S->prev_off[S->scur];
+  a.prev_u_out = S->prev_u[S->scur ^ 1];
+  a.prev_off_out = S->prev_off[S->scur ^ 1];
   a.err = S->err;
   a.ntiles = S->L.ntiles;
   return a;
@@ -659,8 +681,8 @@ void enqueue_bin(mdlg_system* S, bool snapshot_only) {
   b.img = S->img[S->scur];
   b.id = S->id[S->scur];
   b.cell = S->cell[S->scur];
-  b.prev_u = S->prev_u;
-  b.prev_off = S->prev_off;
+  b.prev_u = S->prev_u[S->scur];
+  b.prev_off = S->prev_off[S->scur];
   b.A = S->A;
   b.mom = S->mom;
   b.dpart = S->dpart;
@@ -1033,6 +1055,10 @@ mdlg_status mdlg_get_state(mdlg_system* S, mdlg_particles* out) {
   x.x_off = reinterpret_cast<float*>(S->staging) + nd;
   x.x_vel = reinterpret_cast<float*>(S->staging) + 2 * nd;
   x.x_acc = reinterpret_cast<float*>(S->staging) + 3 * nd;
+  x.prev_u = S->prev_u[S->scur];
+  x.prev_off = S->prev_off[S->scur];
+  x.x_pu = reinterpret_cast<int*>(S->staging) + 4 * nd;
+  x.x_poff = reinterpret_cast<float*>(S->staging) + 5 * nd;
   x.err = S->err;
   launch_export(D, L.nchunks, x, S->stream);
   mdlg_status st = check_launch(S, "mdlg_get_state");
@@ -1042,9 +1068,9 @@ mdlg_status mdlg_get_state(mdlg_system* S, mdlg_particles* out) {
   if (out->vel) HIPCHK(S, hipMemcpyAsync(out->vel, x.x_vel, nd * 4, hipMemcpyDeviceToHost, S->stream));
   if (out->acc) HIPCHK(S, hipMemcpyAsync(out->acc, x.x_acc, nd * 4, hipMemcpyDeviceToHost, S->stream));
   if (out->prev_ucell)
-    HIPCHK(S, hipMemcpyAsync(out->prev_ucell, S->prev_u, nd * 4, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(S, hipMemcpyAsync(out->prev_ucell, x.x_pu, nd * 4, hipMemcpyDeviceToHost, S->stream));
   if (out->prev_off)
-    HIPCHK(S, hipMemcpyAsync(out->prev_off, S->prev_off, nd * 4, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(S, hipMemcpyAsync(out->prev_off, x.x_poff, nd * 4, hipMemcpyDeviceToHost, S->stream));
   return read_err(S);
 }
 
@@ -1086,6 +1112,14 @@ mdlg_status mdlg_set_state(mdlg_system* S, const mdlg_particles* in) {
   x.x_u = reinterpret_cast<int*>(S->staging);
   x.x_off = reinterpret_cast<float*>(S->staging) + nd;
   x.x_vel = reinterpret_cast<float*>(S->staging) + 2 * nd;
+  x.prev_u = S->prev_u[S->scur];
+  x.prev_off = S->prev_off[S->scur];
+  if (in->prev_ucell) {
+    x.x_pu = reinterpret_cast<int*>(S->staging) + 4 * nd;
+    x.x_poff = reinterpret_cast<float*>(S->staging) + 5 * nd;
+    HIPCHK(S, hipMemcpyAsync(x.x_pu, in->prev_ucell, nd * 4, hipMemcpyHostToDevice, S->stream));
+    HIPCHK(S, hipMemcpyAsync(x.x_poff, in->prev_off, nd * 4, hipMemcpyHostToDevice, S->stream));
+  }
   x.err = S->err;
   HIPCHK(S, hipMemcpyAsync(x.x_u, in->ucell, nd * 4, hipMemcpyHostToDevice, S->stream));
   HIPCHK(S, hipMemcpyAsync(x.x_off, in->off, nd * 4, hipMemcpyHostToDevice, S->stream));
@@ -1093,12 +1127,7 @@ mdlg_status mdlg_set_state(mdlg_system* S, const mdlg_particles* in) {
   launch_import(D, L.nchunks, x, S->stream);
   S->since_sort = 1;  // the imported arrays are in id order: rebuild
   enqueue_sort(S);
-  if (in->prev_ucell) {
-    HIPCHK(S, hipMemcpyAsync(S->prev_u, in->prev_ucell, nd * 4, hipMemcpyHostToDevice, S->stream));
-    HIPCHK(S, hipMemcpyAsync(S->prev_off, in->prev_off, nd * 4, hipMemcpyHostToDevice, S->stream));
-  } else {
-    enqueue_bin(S, true);
-  }
+  if (!in->prev_ucell) enqueue_bin(S, true);
   S->snapshot_valid = true;
   S->vel_full = true;
   S->lambda_pending = false;
@@ -1116,6 +1145,7 @@ static Phys window_phys(const mdlg_system* S) {
   P.lo = (float)(-m);
   P.hi = (float)(S->L.s + m);
   P.rcq = (int)std::ceil((P.rc_d + m) / P.u_d) + 1;
+  P.mq = (int)std::ceil(m / P.u_d) + 4;
   return P;
 }
 

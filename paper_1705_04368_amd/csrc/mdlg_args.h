@@ -38,6 +38,10 @@ struct SortArgs {
   int* img_out;
   int* id_out;
   int* cell_out;
+  const int* prev_u;      // snapshot (sorted order), permuted with the state
+  const float* prev_off;
+  int* prev_u_out;
+  float* prev_off_out;
   unsigned* err;
   int ntiles;
 };
@@ -88,7 +92,7 @@ struct BinArgs {
   const int* img;
   const int* id;
   const int* cell;
-  int* prev_u;
+  int* prev_u;           // snapshot in the sorted order of the state
   float* prev_off;
   unsigned* A;
   long long* mom;
@@ -146,6 +150,10 @@ struct XportArgs {
   float* x_off;
   float* x_vel;
   float* x_acc;      // optional
+  int* prev_u;       // snapshot, sorted order
+  float* prev_off;
+  int* x_pu;         // snapshot, id order (import: null = none)
+  float* x_poff;
   unsigned* err;
 };
 
@@ -195,6 +203,7 @@ struct AdjIoArgs {
 };
 
 void launch_fill_u32(unsigned* p, unsigned v, long long n, hipStream_t s);
+size_t brick_lds_bytes(const Phys& P, int D, bool adj);
 void launch_adjoint(int D, const AdjArgs& a, hipStream_t s);
 void launch_adj_loss(int D, const AdjLossArgs& a, hipStream_t s);
 void launch_adj_final(const AdjFinalArgs& a, hipStream_t s);

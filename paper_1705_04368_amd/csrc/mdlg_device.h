@@ -15,10 +15,9 @@ constexpr int kMaxStripSites = 16;   // lattice sites per block of the binning k
 constexpr int kMaxQ = 225;           // largest velocity window handled (V <= 7 in 2D, V <= 2 in 3D)
 
 // LDS budgets of the force kernel
-constexpr int kMaxHalo2 = 1024;      // halo cells per brick (2D)
-constexpr int kCap2 = 2048;          // staged particles per chunk (2D)
-constexpr int kMaxHalo3 = 2048;      // halo cells per brick (3D)
-constexpr int kCap3 = 2048;          // staged particles per chunk (3D)
+constexpr int kMaxHalo2 = 1536;      // halo cells per brick (2D)
+constexpr int kMaxHalo3 = 2560;      // halo cells per brick (3D)
+constexpr int kBrickLdsBytes = 60 * 1024;  // dynamic LDS budget of a brick kernel
 constexpr int kMaxRows = 64;         // brick rows (BY * BZ)
 
 // device error word bits
@@ -55,6 +54,9 @@ struct Phys {
   float fscale;     // 2^F / s
   int rcq;          // (r_cut + margin) / u, rounded up
   float rc2_u;      // (r_cut / u)^2
+  int mq;           // rebuild margin / u, rounded up, plus a few units
+  int lmaxh;        // halo cells of the largest brick (dynamic LDS table)
+  int lcap;         // staged particles per LDS chunk
   float sig2_u;     // (sigma / u)^2
   float eps24m_u;   // 24 eps / (m u)
   float dt;

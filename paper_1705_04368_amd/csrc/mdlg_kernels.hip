@@ -267,11 +267,13 @@ __device__ __forceinline__ bool canon_particle(const SortArgs& a, const Replica&
 }
 
 // Slot of each particle inside its new cell.  A chunk of particles sorted by
-// their old cell maps into a narrow range of new cells: the block counts them
-// in an LDS histogram over that range (rank inside the block from the LDS
-// atomic), then takes one global atomic per distinct cell for its base.  A
-// chunk whose key range does not fit falls back to one global atomic per
-// particle.  Scan-tile totals are added without waiting for a result.
+// their old cell moves into a narrow window of new cells: the old cells of the
+// chunk widened by one row of cells on either side (moves along x and y).  The
+// block counts those particles in an LDS histogram over the window (rank in
+// the block from the LDS atomic) and takes one global atomic per distinct
+// cell for its base; particles outside the window (moves along z in 3D) take
+// one global atomic each.  Scan-tile totals are summed in LDS first: same-
+// address global atomics serialise across the device.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
   constexpr int kHist = 2048;
@@ -279,63 +281,37 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
   constexpr int kTiles = kHist / kScanTile + 2;
   __shared__ int s_cnt[kHist];
   __shared__ int s_tile[kTiles];
-  __shared__ int s_lo, s_hi;
   const int4 ch = a.chunks[blockIdx.x];
   const Replica R = a.reps[ch.x];
-  if (threadIdx.x == 0) {
-    s_lo = 0x7fffffff;
-    s_hi = -1;
-  }
   for (int i = threadIdx.x; i < kHist; i += kBlock) s_cnt[i] = 0;
   if (threadIdx.x < kTiles) s_tile[threadIdx.x] = 0;
+  const int lo = a.cell[ch.y] - R.Mc[0] - 1;  // window start (old cells are sorted)
   __syncthreads();
-  int key[kPer];
+  int key[kPer], rank[kPer];
+  bool inwin[kPer];
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
     const int g = ch.y + u * kBlock + (int)threadIdx.x;
     key[u] = -1;
+    inwin[u] = false;
+    rank[u] = 0;
     if (g < ch.z) {
       float o[D];
       int c[D], im[D];
       if (!canon_particle<D>(a, R, g, o, c, im)) atomicOr(a.err, kErrJump);
       key[u] = R.cell_off + cell_linear<D>(c, R);
+      inwin[u] = key[u] >= lo && key[u] < lo + kHist;
+      if (inwin[u]) {
+        rank[u] = atomicAdd(&s_cnt[key[u] - lo], 1);
+      } else {
+        a.keyslot[g] = make_int2(key[u], atomicAdd(a.count + key[u], 1));
+      }
     }
-  }
-  int kmin = 0x7fffffff, kmax = -1;
-#pragma unroll
-  for (int u = 0; u < kPer; ++u)
-    if (key[u] >= 0) {
-      kmin = min(kmin, key[u]);
-      kmax = max(kmax, key[u]);
-    }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    kmin = min(kmin, __shfl_xor(kmin, o, 64));
-    kmax = max(kmax, __shfl_xor(kmax, o, 64));
-  }
-  if (lane_id() == 0) {
-    atomicMin(&s_lo, kmin);
-    atomicMax(&s_hi, kmax);
+    wave_agg_add_i(a.tile_sum, key[u] >= 0 ? key[u] / kScanTile : 0, key[u] >= 0 && !inwin[u]);
   }
   __syncthreads();
-  const int lo = s_lo, span = s_hi - s_lo + 1;
-  if (span > kHist) {
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int g = ch.y + u * kBlock + (int)threadIdx.x;
-      if (key[u] >= 0) a.keyslot[g] = make_int2(key[u], atomicAdd(a.count + key[u], 1));
-      wave_agg_add_i(a.tile_sum, key[u] >= 0 ? key[u] / kScanTile : 0, key[u] >= 0);
-    }
-    return;
-  }
-  int rank[kPer];
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) rank[u] = key[u] >= 0 ? atomicAdd(&s_cnt[key[u] - lo], 1) : 0;
-  __syncthreads();
-  // same-address global atomics serialise across the device: sum the scan
-  // tiles of this block in LDS and add each once
-  const int tile0 = lo / kScanTile;
-  for (int i = threadIdx.x; i < span; i += kBlock) {
+  const int tile0 = lo >= 0 ? lo / kScanTile : 0;
+  for (int i = threadIdx.x; i < kHist; i += kBlock) {
     const int c = s_cnt[i];
     if (c) {
       s_cnt[i] = atomicAdd(a.count + lo + i, c);
@@ -347,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
     const int g = ch.y + u * kBlock + (int)threadIdx.x;
-    if (key[u] >= 0) a.keyslot[g] = make_int2(key[u], s_cnt[key[u] - lo] + rank[u]);
+    if (inwin[u]) a.keyslot[g] = make_int2(key[u], s_cnt[key[u] - lo] + rank[u]);
   }
 }
 
@@ -399,6 +375,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(SortArgs a) {
     sti<D>(a.img_out, dst, im);
     a.id_out[dst] = a.id[g];
     a.cell_out[dst] = ks.x;
+    int pu[D];
+    float po[D];
+    ldi<D>(a.prev_u, g, pu);
+    ldv<D>(a.prev_off, g, po);
+    sti<D>(a.prev_u_out, dst, pu);
+    stv<D>(a.prev_off_out, dst, po);
   }
 }
 
@@ -420,18 +402,37 @@ __global__ __launch_bounds__(kBlock) void k_scatter(SortArgs a) {
 template <int D>
 using Coord = typename std::conditional<D == 2, int2, int4>::type;
 
+// LDS of a brick: the halo cell table and the staged particles live in the
+// dynamic shared memory, sized by the host from the brick extent and the
+// density (lmaxh halo cells, lcap staged particles per chunk); the small
+// arrays are static.
 template <int D, bool ADJ>
 struct BrickLds {
-  static constexpr int MAXH = (D == 2) ? kMaxHalo2 : kMaxHalo3;
-  static constexpr int CAP = ADJ ? ((D == 2) ? kCap2 / 2 : kCap3 / 2) : ((D == 2) ? kCap2 : kCap3);
-  int hs[MAXH + 1];   // LDS start of every halo cell (exclusive scan of counts)
-  int gs[MAXH];       // global start of every halo cell
-  Coord<D> p[CAP];    // fixed-point coordinates of the staged particles
-  float lam[ADJ ? CAP * D : 1];  // adjoint velocity of the staged particles
-  int rowpre[kMaxRows + 1];
-  int tmp[kWaves + 1];
-  double red[kWaves][D + 1];
+  int* hs;            // LDS start of every halo cell (exclusive scan of counts)
+  int* gs;            // global start of every halo cell
+  Coord<D>* p;        // fixed-point coordinates of the staged particles
+  float* lam;         // adjoint velocity of the staged particles (ADJ)
+  int* rowpre;
+  int* tmp;
+  double (*red)[4];
+  int cap;
 };
+
+template <int D, bool ADJ>
+__device__ __forceinline__ BrickLds<D, ADJ> brick_lds(char* dyn, int* rowpre, int* tmp,
+                                                      double (*red)[4], const Phys& P) {
+  BrickLds<D, ADJ> L;
+  L.hs = reinterpret_cast<int*>(dyn);
+  L.gs = L.hs + P.lmaxh + 1;
+  const size_t off = ((size_t)(2 * P.lmaxh + 1) * sizeof(int) + 15) & ~size_t(15);
+  L.p = reinterpret_cast<Coord<D>*>(dyn + off);
+  L.lam = reinterpret_cast<float*>(dyn + off + (size_t)P.lcap * sizeof(Coord<D>));
+  L.rowpre = rowpre;
+  L.tmp = tmp;
+  L.red = red;
+  L.cap = P.lcap;
+  return L;
+}
 
 struct BrickGeom {
   int ns, nsz, x0, y0, z0, wx, wy, wz, HX, HY, HZ, nh, total, nrows, ntg;
@@ -610,11 +611,39 @@ __device__ __forceinline__ Reach target_reach(const BrickGeom& G, const Phys& P,
   return r;
 }
 
+// Columns of halo row (cy, cz) that can hold a particle within r_cut of the
+// target at (X, Y, Z): the row's particles lie within its cells widened by the
+// rebuild margin, so the smallest |dy| (and |dz|) to the row bounds the reach
+// along x by sqrt(r_cut^2 - dy^2 - dz^2).  Conservative by a few units.
+// Returns false when the row is out of reach.
+template <int D>
+__device__ __forceinline__ bool row_columns(const BrickGeom& G, const Phys& P, int X, int Y, int Z,
+                                            int cy, int cz, int& cx0, int& cx1) {
+  // distances in exact integer units; r_cut^2 is inflated by 4e-6 so that the
+  // float rounding of the squares can only widen the reach
+  const int dyi = max(0, max(((cy << P.F) - P.mq) - Y, Y - (((cy + 1) << P.F) + P.mq)));
+  const float dy = (float)dyi;
+  float r2 = fmaf(P.rc2_u, 4e-6f, P.rc2_u) - dy * dy;
+  if constexpr (D == 3) {
+    const int dzi = max(0, max(((cz << P.F) - P.mq) - Z, Z - (((cz + 1) << P.F) + P.mq)));
+    const float dz = (float)dzi;
+    r2 -= dz * dz;
+  }
+  if (r2 <= 0.f) return false;
+  const int hw = (int)sqrtf(r2) + P.mq + 64;
+  cx0 = max(0, (X - hw) >> P.F);
+  cx1 = min(G.HX - 1, (X + hw) >> P.F);
+  return true;
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
-  using Lds = BrickLds<D, false>;
-  constexpr int CAP = Lds::CAP;
-  __shared__ Lds L;
+  extern __shared__ __align__(16) char s_dyn_brick[];
+  __shared__ int s_rowpre[kMaxRows + 1];
+  __shared__ int s_tmp[kWaves + 1];
+  __shared__ double s_red[kWaves][4];
+  auto L = brick_lds<D, false>(s_dyn_brick, s_rowpre, s_tmp, s_red, a.P);
+  const int CAP = L.cap;
   int b = blockIdx.x;
   if (a.xcd_remap) {
     // blocks are dispatched round-robin over the 8 XCDs; give each XCD a
@@ -669,9 +698,11 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
         if (valid) {
           for (int cz = rr.cz0; cz <= rr.cz1; ++cz) {
             for (int cy = rr.cy0; cy <= rr.cy1; ++cy) {
+              int cx0, cx1;
+              if (!row_columns<D>(G, P, X, Y, Z, cy, cz, cx0, cx1)) continue;
               const int hrow = G.HX * (cy + G.HY * cz);
-              const int jlo = max(L.hs[hrow + rr.cx0], cb) - cb;
-              const int jhi = min(L.hs[hrow + rr.cx1 + 1], ce) - cb;
+              const int jlo = max(L.hs[hrow + cx0], cb) - cb;
+              const int jhi = min(L.hs[hrow + cx1 + 1], ce) - cb;
               int j = jlo;
               for (; j + 3 < jhi; j += 4) {
                 Coord<D> q[4];
@@ -753,9 +784,12 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
 //   (J l)_i  += E2 [ir2 s6 (2 s6 - 1) dl + ir2^2 s6 (8 - 28 s6) (d . dl) d]
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs a) {
-  using Lds = BrickLds<D, true>;
-  constexpr int CAP = Lds::CAP;
-  __shared__ Lds L;
+  extern __shared__ __align__(16) char s_dyn_brick[];
+  __shared__ int s_rowpre[kMaxRows + 1];
+  __shared__ int s_tmp[kWaves + 1];
+  __shared__ double s_red[kWaves][4];
+  auto L = brick_lds<D, true>(s_dyn_brick, s_rowpre, s_tmp, s_red, a.P);
+  const int CAP = L.cap;
   const int b = blockIdx.x;
   if (b >= a.nbricks) return;
   const Phys& P = a.P;
@@ -802,9 +836,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs a) {
         if (valid) {
           for (int cz = rr.cz0; cz <= rr.cz1; ++cz) {
             for (int cy = rr.cy0; cy <= rr.cy1; ++cy) {
+              int cx0, cx1;
+              if (!row_columns<D>(G, P, X, Y, Z, cy, cz, cx0, cx1)) continue;
               const int hrow = G.HX * (cy + G.HY * cz);
-              const int jlo = max(L.hs[hrow + rr.cx0], cb) - cb;
-              const int jhi = min(L.hs[hrow + rr.cx1 + 1], ce) - cb;
+              const int jlo = max(L.hs[hrow + cx0], cb) - cb;
+              const int jhi = min(L.hs[hrow + cx1 + 1], ce) - cb;
               for (int j = jlo; j < jhi; ++j) {
                 const Coord<D> q = L.p[j];
                 float d[D], dl[D];
@@ -1043,8 +1079,8 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs a) {
 #pragma unroll
       for (int q = 0; q < D; ++q) u[q] = c[q] + R.Mc[q] * im[q];
       if (!a.snapshot_only) {
-        ldi<D>(a.prev_u, pid, pu);
-        ldv<D>(a.prev_off, pid, po);
+        ldi<D>(a.prev_u, g, pu);
+        ldv<D>(a.prev_off, g, po);
         inside = true;
         int bin = 0, stride = 1;
 #pragma unroll
@@ -1060,8 +1096,8 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs a) {
         sitek = (c[0] >> P.log2k) - sx0;
         bink = sitek * Q + (inside ? bin : 0);
       }
-      sti<D>(a.prev_u, pid, u);
-      stv<D>(a.prev_off, pid, o);
+      sti<D>(a.prev_u, g, u);
+      stv<D>(a.prev_off, g, o);
     }
     if (!a.snapshot_only) {
       wave_agg_add(s_h, bink, valid && inside);
@@ -1191,6 +1227,12 @@ __global__ __launch_bounds__(kBlock) void k_export(XportArgs a) {
       ldv<D>(a.acc, g, f);
       stv<D>(a.x_acc, pid, f);
     }
+    int pu[D];
+    float po[D];
+    ldi<D>(a.prev_u, g, pu);
+    ldv<D>(a.prev_off, g, po);
+    sti<D>(a.x_pu, pid, pu);
+    stv<D>(a.x_poff, pid, po);
   }
 }
 
@@ -1213,6 +1255,14 @@ __global__ __launch_bounds__(kBlock) void k_import(XportArgs a) {
     sti<D>(a.img, g, im);
     a.id[g] = g;
     a.cell[g] = R.cell_off + cell_linear<D>(c, R);
+    if (a.x_pu) {
+      int pu[D];
+      float po[D];
+      ldi<D>(a.x_pu, g, pu);
+      ldv<D>(a.x_poff, g, po);
+      sti<D>(a.prev_u, g, pu);
+      stv<D>(a.prev_off, g, po);
+    }
   }
 }
 
@@ -1256,10 +1306,16 @@ void launch_scatter(int D, int nchunks, const SortArgs& a, hipStream_t s) {
   MDLG_LAUNCH_DIM(D, k_scatter, nchunks, 0, s, a);
 }
 
+size_t brick_lds_bytes(const Phys& P, int D, bool adj) {
+  const size_t head = ((size_t)(2 * P.lmaxh + 1) * sizeof(int) + 15) & ~size_t(15);
+  const size_t coord = (D == 2) ? sizeof(int2) : sizeof(int4);
+  return head + (size_t)P.lcap * (coord + (adj ? D * sizeof(float) : 0));
+}
+
 void launch_force(int D, const ForceArgs& a, hipStream_t s) {
   int grid = a.nbricks;
   if (a.xcd_remap) grid = ((a.nbricks + 7) / 8) * 8;
-  MDLG_LAUNCH_DIM(D, k_force, grid, 0, s, a);
+  MDLG_LAUNCH_DIM(D, k_force, grid, brick_lds_bytes(a.P, D, false), s, a);
 }
 
 void launch_kin(const KinArgs& a, hipStream_t s) {
@@ -1289,7 +1345,7 @@ void launch_site_avg(const SiteAvgArgs& a, hipStream_t s) {
 }
 
 void launch_adjoint(int D, const AdjArgs& a, hipStream_t s) {
-  MDLG_LAUNCH_DIM(D, k_adjoint, a.nbricks, 0, s, a);
+  MDLG_LAUNCH_DIM(D, k_adjoint, a.nbricks, brick_lds_bytes(a.P, D, true), s, a);
 }
 
 static int grid_for(long long n) {
