@@ -99,6 +99,52 @@ def load_traffic(workload, kernel):
     return None if k is None else float(k["bytes_per_launch"])
 
 
+def _counter_means(folder, counter):
+    """Mean value of one rocprofv3 counter per dispatch, by kernel name."""
+    import csv
+    import glob
+    tot = {}
+    for path in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] != counter:
+                    continue
+                name = row["Kernel_Name"]
+                name = name.split("(")[0].split("<")[0].replace("void ", "").strip()
+                name = name.split("::")[-1]
+                s, c = tot.get(name, (0.0, 0))
+                tot[name] = (s + float(row["Counter_Value"]), c + 1)
+    return {k: s / c for k, (s, c) in tot.items()}
+
+
+def summarize_traffic(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
+    """HBM bytes per launch of each kernel: FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch) scaled by what the same counters read for a plain copy of 1 GiB."""
+    copy_bytes = float(1 << 30)
+    cf = max(_counter_means(copy_fetch_dir, "FETCH_SIZE").values())
+    cw = max(_counter_means(copy_write_dir, "WRITE_SIZE").values())
+    f_fac, w_fac = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+    fetch = _counter_means(fetch_dir, "FETCH_SIZE")
+    write = _counter_means(write_dir, "WRITE_SIZE")
+    names = {"k_force": "force", "k_count": "count", "k_scan": "scan", "k_scatter": "scatter",
+             "k_bin": "bin", "k_kin": "kin", "k_ingest": "ingest"}
+    kernels = {}
+    for kname, cls in names.items():
+        if kname in fetch and kname in write:
+            kernels[cls] = {"fetch_kib": fetch[kname], "write_kib": write[kname],
+                            "bytes_per_launch": fetch[kname] * 1024.0 * f_fac
+                            + write[kname] * 1024.0 * w_fac}
+    out = {"workload": workload, "source_digest": source_digest(),
+           "copy_calibration": {"bytes": copy_bytes, "fetch_kib": cf, "write_kib": cw,
+                                "fetch_factor": f_fac, "write_factor": w_fac},
+           "kernels": kernels}
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(out, indent=1))
+
+
 def cpu_baseline(w, pos, vel, lattice_steps):
     """The FP64 oracle, single-threaded on the host, on a bounded sample: the
     full system for `lattice_steps` lattice steps from the same initial state."""
@@ -178,7 +224,28 @@ def main():
     ap.add_argument("--cpu-lattice-steps", type=int, default=2)
     ap.add_argument("--plain-steps", type=int, default=3,
                     help="lattice steps timed for the plain (one system per replica) path")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB five times (scales the HBM "
+                         "counters of a profiler to bytes)")
+    ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH",
+                                                             "COPY_WRITE"),
+                    help="write profiles/traffic_<workload>.json from four rocprofv3 --pmc "
+                         "output folders: FETCH_SIZE and WRITE_SIZE of this bench, then of "
+                         "--copy-calibration")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        summarize_traffic(args.workload, *args.summarize_traffic)
+        return
+    if args.copy_calibration:
+        import torch
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes, "copies": 5}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(replicas or domains would shard across GPUs; see DESIGN.md)", file=sys.stderr)
