@@ -127,7 +127,7 @@ def summarize_traffic(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write
     fetch = _counter_means(fetch_dir, "FETCH_SIZE")
     write = _counter_means(write_dir, "WRITE_SIZE")
     names = {"k_force": "force", "k_count": "count", "k_scan": "scan", "k_scatter": "scatter",
-             "k_bin": "bin", "k_kin": "kin", "k_ingest": "ingest"}
+             "k_bin": "bin", "k_kin": "kin", "k_ingest": "ingest", "k_nlist": "nlist"}
     kernels = {}
     for kname, cls in names.items():
         if kname in fetch and kname in write:
@@ -177,7 +177,8 @@ def plain_replicas(sysg, cfg, n_r, m_r, w, dev, lattice_steps):
     for nr, mr in zip(n_r, m_r):
         nr, mr = int(nr), int(mr)
         c = make_config(2, nr, mr, lattice_dx=w["dx"], dt=w["dt"], md_steps_per_lattice_step=w["steps"],
-                        vmax=w["vmax"], kT=w["kT"], md_cell_split=k, sort_every=sysg.layout["sort_every"])
+                        vmax=w["vmax"], kT=w["kT"], md_cell_split=k, sort_every=sysg.layout["sort_every"],
+                        pair_list=sysg.layout["pair_slots"] > 0)
         sl = slice(off, off + nr)
         s = sysg.layout["cell_side"]
         x = (np.mod(st["ucell"][sl], mr * k).astype(np.float64) * s + st["off"][sl]).astype(np.float32)
@@ -224,6 +225,11 @@ def main():
     ap.add_argument("--cpu-lattice-steps", type=int, default=2)
     ap.add_argument("--plain-steps", type=int, default=3,
                     help="lattice steps timed for the plain (one system per replica) path")
+    ap.add_argument("--sort-every", type=int, default=0, help="rebuild interval (0 = automatic)")
+    ap.add_argument("--md-cell-split", type=int, default=0, help="MD cells per lattice cell (0 = auto)")
+    ap.add_argument("--brick", type=int, nargs=3, default=(0, 0, 0), help="force brick (0 = auto)")
+    ap.add_argument("--no-pair-list", action="store_true",
+                    help="walk the neighbour cells at every MD step instead of using pair lists")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (scales the HBM "
                          "counters of a profiler to bytes)")
@@ -258,6 +264,8 @@ def main():
 
     w = WORKLOADS[args.workload]
     dim = w["dim"]
+    tuning = dict(sort_every=args.sort_every, pair_list=not args.no_pair_list,
+                  md_cell_split=args.md_cell_split, brick=tuple(args.brick))
     dev = torch.device("cuda:0")
     if w.get("replicas"):
         n_r, m_r = synth.replica_sizes(w["replicas"], seed=4)
@@ -273,7 +281,7 @@ def main():
         n_sites = int((m_r.astype(np.int64) ** 2).sum())
         cfg = make_config(dim, n_r, lattice, lattice_dx=w["dx"], dt=w["dt"],
                           md_steps_per_lattice_step=w["steps"], vmax=w["vmax"], thermostat_every=10,
-                          kT=w["kT"])
+                          kT=w["kT"], **tuning)
     else:
         n, M = w["n"], w["M"]
         box = M * w["dx"]
@@ -282,7 +290,7 @@ def main():
         pos, vel = synth.lj_initial_state(dim, n, box, w["kT"], seed=2 if dim == 2 else 3)
         cfg = make_config(dim, n, M, lattice_dx=w["dx"], dt=w["dt"],
                           md_steps_per_lattice_step=w["steps"], vmax=w["vmax"], thermostat_every=10,
-                          kT=w["kT"])
+                          kT=w["kT"], **tuning)
     sysg = System(cfg, torch.from_numpy(pos).to(dev), torch.from_numpy(vel).to(dev))
     lay = sysg.layout
     print(f"# workload {args.workload}: {w['desc']}; layout {lay}", file=sys.stderr, flush=True)
@@ -333,6 +341,16 @@ def main():
             kernels[k] = {"avg_ms": avg, "launches": cnt, "bound": "hbm", "achieved": ach,
                           "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
                           "work_per_launch": work}
+        elif k == "nlist":
+            # read the offsets, write the lists (16-bit entries within
+            # r_cut + 2 margin), the staging map and the reference offsets
+            rl = 2.5 + 2 * lay["margin"]
+            vol = math.pi * rl * rl if dim == 2 else 4.0 / 3.0 * math.pi * rl ** 3
+            work = n * (4 * dim + 2 * vol * rho + 8 + 4 * dim)
+            ach = work / (avg * 1e-3) / 1e9
+            kernels[k] = {"avg_ms": avg, "launches": cnt, "bound": "hbm", "achieved": ach,
+                          "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                          "work_per_launch": work}
         elif k == "bin":
             work = n * bin_bytes_per_particle(dim, q, nm, per_site)
             ach = work / (avg * 1e-3) / 1e9
@@ -364,7 +382,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["desc"], "lattice_steps": args.steps, "md_steps": md_steps,
                    "md_cell_split": lay["md_cell_split"], "sort_every": lay["sort_every"],
-                   "brick": list(lay["brick"])},
+                   "brick": list(lay["brick"]), "pair_slots": lay["pair_slots"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plain": plain,

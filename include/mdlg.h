@@ -25,7 +25,8 @@
  *   - All entry points return mdlg_status (0 = MDLG_OK, negative = error) and
  *     never throw.  Config errors are found synchronously on the host.
  *   - Device-side failures (a particle leaving the cell-list margin between
- *     rebuilds, non-finite coordinates, a velocity so large that a particle
+ *     rebuilds or moving farther than the margin since the pair lists were
+ *     built, non-finite coordinates, a velocity so large that a particle
  *     crosses more than one cell per step) set a device error word; it is
  *     reported as MDLG_E_UNSTABLE by the next call that synchronises
  *     (mdlg_get_f, mdlg_get_state, mdlg_sync), and mdlg_last_error() explains.
@@ -99,6 +100,10 @@ typedef struct {
     int32_t adjoint_window;     /* largest adjoint window in MD steps (0 = no adjoint buffers) */
     int32_t adjoint_every;      /* checkpoint interval the workspace is sized for (>= 1 when
                                    adjoint_window > 0) */
+    int32_t no_pair_list;       /* 1: every MD step walks the neighbour cells; 0: per-particle
+                                   pair lists of radius r_cut + 2 margin, built at each
+                                   cell-list rebuild, are used when the rebuild interval is
+                                   at least 2 (results agree to float rounding) */
 } mdlg_config;
 
 /* Particle state in particle-id order (id = index in the concatenated input).
@@ -134,7 +139,9 @@ typedef struct {
     int64_t n_cells;            /* MD cells over all replicas */
     int64_t n_bricks;           /* force-kernel work units per MD step */
     double cell_side;           /* s */
-    double margin;              /* allowed excursion outside the cell between rebuilds */
+    double margin;              /* allowed excursion outside the cell between rebuilds, and
+                                   the largest displacement between pair-list builds */
+    int32_t pair_slots;         /* pair-list entries per particle (0 = no pair lists) */
 } mdlg_layout;
 
 /* Validate cfg and report the derived layout.  Host only.  MDLG_E_INVALID on
@@ -243,7 +250,8 @@ typedef enum {
     MDLG_K_SCAN = 2,    /* cell-list rebuild: exclusive scan of the counts */
     MDLG_K_SCATTER = 3, /* cell-list rebuild: permute the particle state */
     MDLG_K_BIN = 4,     /* MDLG binning and per-site accumulation (eq. MDni) */
-    MDLG_K_NCLASS = 5
+    MDLG_K_NLIST = 5,   /* cell-list rebuild: per-particle pair lists */
+    MDLG_K_NCLASS = 6
 } mdlg_kernel_class;
 
 /* Enable (1) or disable (0) per-kernel timing with HIP events on the handle's

@@ -41,7 +41,10 @@ struct Layout {
   double s = 0, margin = 0, margin_max = 0;
   int sort_every = 1;
   int halo_cells = 0;  // halo cells of the largest force brick
+  int lcap = 0;        // staged particles per LDS chunk of a force brick
+  int lcap_adj = 0;    // the same for the adjoint (stages the adjoint velocity too)
   double per_cell = 0; // mean particles per MD cell
+  int kmax = 0;        // pair-list slots per particle (0 = cell walk every step)
   int adj_ckpts = 0;   // checkpoints the workspace holds (0 = no adjoint)
   int adj_seg = 0;     // segment positions the workspace holds
 };
@@ -104,7 +107,7 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   L->nm = 2 + D + D * (D + 1) / 2;
   long long n_total = 0;
   int min_m = 1 << 30;
-  double vol = 0;
+  double vol = 0, rho_max = 0;
   for (int r = 0; r < c->n_replicas; ++r) {
     if (c->n_particles[r] < 1) return set_err(msg, "replica %d has no particles", r);
     n_total += c->n_particles[r];
@@ -122,6 +125,7 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
     }
     (void)ns;
     vol += v;
+    rho_max = std::max(rho_max, c->n_particles[r] / v);
   }
   if (n_total > (1ll << 30)) return set_err(msg, "too many particles (%lld)", n_total);
   const double rho = n_total / vol;
@@ -172,13 +176,19 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   // rebuild interval and the margin it needs: eight standard deviations of
   // the Maxwell speed per axis times the interval (the kernel checks the bound)
   const double vfast = c->kT > 0 ? 8.0 * std::sqrt(c->kT / c->mass) : 0.0;
+  // with pair lists the margin also widens every list (radius r_cut + 2 m),
+  // so the automatic interval aims at m = r_cut / 8 instead of the largest
+  // margin the stencil allows
+  const bool want_list = !c->no_pair_list && !c->forces_off;
   int R = c->sort_every;
   if (R == 0) {
     if (m_max <= 0 || !(vfast > 0)) {
       R = 1;
     } else {
-      R = (int)std::floor(m_max / (vfast * c->dt));
-      R = std::max(1, std::min(R, c->md_steps_per_lattice_step));
+      const double m_aim = want_list ? std::min(m_max, c->r_cut / 8) : m_max;
+      R = (int)std::floor(m_aim / (vfast * c->dt));
+      R = std::max(want_list ? 2 : 1, std::min(R, c->md_steps_per_lattice_step));
+      if (R * vfast * c->dt > m_max) R = std::max(1, (int)std::floor(m_max / (vfast * c->dt)));
     }
   }
   if (R > 1 && m_max <= 0)
@@ -196,7 +206,7 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
     // in flight hide the staging latency)
     const double cells = 128.0 / std::max(per_cell, 0.05);
     if (BY == 0) BY = cells >= 32 ? 2 : 1;
-    if (BX == 0) BX = std::max(4, std::min(256, (int)std::lround(cells / BY)));
+    if (BX == 0) BX = std::max(4, std::min(128, (int)std::lround(cells / BY)));
     BZ = 1;
   } else {
     if (BX == 0 || BY == 0) {
@@ -220,12 +230,39 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   const long long halo = halo_of(BX, BY, BZ);
   L->halo_cells = (int)halo;
   L->per_cell = per_cell;
+  {
+    // dynamic LDS of the brick kernels: the halo cell table of the largest
+    // brick and room for about 1.5x the expected halo particles (a fuller
+    // halo is staged in several chunks); the adjoint also stages d floats each
+    const double expect = halo * per_cell;
+    const size_t head = ((size_t)(2 * halo + 1) * sizeof(int) + 15) & ~size_t(15);
+    long long cap = (long long)std::ceil(1.5 * expect) + 128;
+    cap = (cap + 63) / 64 * 64;
+    const size_t coord = (D == 2 ? sizeof(int2) : sizeof(int4));
+    auto fit = [&](size_t per) {
+      const long long f = (long long)((kBrickLdsBytes - head) / per) / 64 * 64;
+      return (int)std::max<long long>(64, std::min(cap, f));
+    };
+    L->lcap = fit(coord);
+    L->lcap_adj = fit(coord + D * sizeof(float));
+  }
   if (halo > maxh) return set_err(msg, "brick %dx%dx%d with stencil %d needs %lld halo cells > %d",
                                   BX, BY, BZ, L->ns, halo, maxh);
   if ((long long)BY * BZ > kMaxRows) return set_err(msg, "brick has more than %d rows", kMaxRows);
   L->BX = BX;
   L->BY = BY;
   L->BZ = BZ;
+  // pair lists: radius r_cut + 2 margin; slots for 1.5x the neighbours
+  // expected at the densest replica's mean density plus 20 (a brick with a
+  // fuller list walks its cells instead)
+  L->kmax = 0;
+  if (want_list && R >= 2 && BX + 2 * L->ns <= kMaxListHalo &&
+      BY + 2 * L->ns <= kMaxListHalo && BZ + 2 * nsz <= kMaxListHalo) {
+    const double rl = c->r_cut + 2 * L->margin;
+    const double vol_l = (D == 2) ? M_PI * rl * rl : 4.0 / 3.0 * M_PI * rl * rl * rl;
+    const int want = (int)std::ceil(1.5 * vol_l * rho_max) + 20;
+    L->kmax = std::min(kMaxPairSlots, (want + 3) / 4 * 4);
+  }
   // binning strip width (LDS budget 60 kB)
   L->BSX = std::max(1, std::min(kMaxStripSites, 60000 / ((L->Q + L->nm) * 4)));
   // tables
@@ -292,6 +329,7 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   P.n_bricks = L->nbricks;
   P.cell_side = L->s;
   P.margin = L->margin;
+  P.pair_slots = L->kmax;
   return true;
 }
 
@@ -336,6 +374,11 @@ struct mdlg_system {
   double* fout = nullptr;
   double* dispout = nullptr;
   float* acc_sorted = nullptr;
+  // pair lists
+  int2* smap = nullptr;
+  int4* binfo = nullptr;
+  unsigned long long* nl = nullptr;
+  float* off0 = nullptr;
   // adjoint window buffers (sorted order)
   float* adj_off0 = nullptr;
   float* adj_ckpt_pos = nullptr;
@@ -419,6 +462,12 @@ size_t carve(mdlg_system* S, char* base) {
   S->fout = c.take<double>(base, kMaxQ);
   S->dispout = c.take<double>(base, 8);
   S->acc_sorted = c.take<float>(base, N * D);
+  if (L.kmax > 0) {
+    S->smap = c.take<int2>(base, (size_t)L.nbricks * L.lcap);
+    S->binfo = c.take<int4>(base, (size_t)L.nbricks);
+    S->nl = c.take<unsigned long long>(base, (size_t)(L.kmax / 4) * N);
+    S->off0 = c.take<float>(base, N * D);
+  }
   if (L.adj_ckpts > 0) {
     S->adj_off0 = c.take<float>(base, N * D);
     S->adj_ckpt_pos = c.take<float>(base, N * D * L.adj_ckpts);
@@ -456,17 +505,18 @@ Phys make_phys(const mdlg_config* c, const Layout& L) {
   P.mq = (int)std::ceil(L.margin / u) + 4;
   P.rc_d = c->r_cut;
   P.u_d = u;
+  {
+    const double rl = c->r_cut + 2 * L.margin;
+    P.rlq = (int)std::ceil(rl / u) + 1;
+    P.rl2_u = (float)((rl / u) * (rl / u) * (1 + 1e-5));
+    P.kmax = L.kmax;
+    P.disp2 = (float)(L.margin * L.margin);
+  }
   // dynamic LDS of the brick kernels: the halo cell table of the largest
   // brick and room for about 1.5x the expected halo particles (a fuller halo
   // is staged in several chunks); the adjoint also stages d floats each
   P.lmaxh = L.halo_cells;
-  const double expect = L.halo_cells * L.per_cell;
-  const size_t head = ((size_t)(2 * P.lmaxh + 1) * sizeof(int) + 15) & ~size_t(15);
-  const size_t per = (L.D == 2 ? sizeof(int2) : sizeof(int4)) + L.D * sizeof(float);
-  long long cap = (long long)std::ceil(1.5 * expect) + 128;
-  cap = (cap + 63) / 64 * 64;
-  const long long fit = (long long)((kBrickLdsBytes - head) / per) / 64 * 64;
-  P.lcap = (int)std::max<long long>(64, std::min(cap, fit));
+  P.lcap = L.lcap;
   P.rc2_u = (float)((c->r_cut / u) * (c->r_cut / u));
   P.sig2_u = (float)((c->sigma / u) * (c->sigma / u));
   P.eps24m_u = (float)(24.0 * c->epsilon / (c->mass * u));
@@ -614,6 +664,22 @@ void enqueue_sort(mdlg_system* S) {
   S->pcur ^= 1;
   S->scur ^= 1;
   S->since_sort = 0;
+  if (S->L.kmax > 0) {
+    NlistArgs nl{};
+    nl.P = S->P;
+    nl.reps = S->reps;
+    nl.bricks = S->bricks;
+    nl.cell_start = S->cell_start;
+    nl.pos = S->pos[S->pcur];
+    nl.smap = S->smap;
+    nl.binfo = S->binfo;
+    nl.nl = S->nl;
+    nl.off0 = S->off0;
+    nl.nbricks = S->L.nbricks;
+    nl.xcd_remap = S->xcd_remap;
+    TimedLaunch t(S, MDLG_K_NLIST);
+    launch_nlist(S->D, nl, S->stream);
+  }
 }
 
 void enqueue_force(mdlg_system* S, int mode, bool sort_follows, float* acc_out, double* kpart) {
@@ -637,6 +703,14 @@ void enqueue_force(mdlg_system* S, int mode, bool sort_follows, float* acc_out, 
   a.mode = mode;
   a.nbricks = S->L.nbricks;
   a.xcd_remap = S->xcd_remap;
+  if (S->L.kmax > 0) {
+    a.smap = S->smap;
+    a.binfo = S->binfo;
+    a.nl = S->nl;
+    a.off0 = S->off0;
+    // the rebuild that follows makes new lists
+    a.check_disp = sort_follows ? 0 : 1;
+  }
   {
     TimedLaunch t(S, MDLG_K_FORCE);
     launch_force(S->D, a, S->stream);
@@ -715,6 +789,7 @@ mdlg_status read_err(mdlg_system* S) {
   if (e) {
     std::string m = "device error word 0x" + std::to_string(e) + ":";
     if (e & kErrMargin) m += " a particle left its cell by more than the rebuild margin (lower sort_every or dt);";
+    if (e & kErrSkin) m += " a particle moved farther than the rebuild margin since the pair lists were built (lower sort_every or dt);";
     if (e & kErrNonFinite) m += " non-finite coordinates;";
     if (e & kErrJump) m += " a particle moved more than one cell between rebuilds or started outside the box;";
     if (e & kErrImage) m += " image counter out of range;";
@@ -1146,6 +1221,8 @@ static Phys window_phys(const mdlg_system* S) {
   P.hi = (float)(S->L.s + m);
   P.rcq = (int)std::ceil((P.rc_d + m) / P.u_d) + 1;
   P.mq = (int)std::ceil(m / P.u_d) + 4;
+  P.lcap = S->L.lcap_adj;
+  P.kmax = 0;
   return P;
 }
 

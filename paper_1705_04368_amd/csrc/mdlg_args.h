@@ -69,6 +69,26 @@ struct ForceArgs {
   int mode;
   int nbricks;
   int xcd_remap;
+  // pair lists (null nl: every brick walks its cell rows)
+  const int2* smap;    // [nbricks][lcap] {particle, hx | hy << 8 | hz << 16 | len << 24}
+  const int4* binfo;   // [nbricks] {staged, targets, lists valid, -}
+  const unsigned long long* nl;  // [kmax / 4][n_total] four 16-bit halo indices per word
+  const float* off0;   // offsets when the lists were built
+  int check_disp;      // 1: flag drifts farther than sqrt(P.disp2) from off0
+};
+
+struct NlistArgs {
+  Phys P;
+  const Replica* reps;
+  const int4* bricks;
+  const int* cell_start;
+  const float* pos;
+  int2* smap;
+  int4* binfo;
+  unsigned long long* nl;
+  float* off0;
+  int nbricks;
+  int xcd_remap;
 };
 
 struct KinArgs {
@@ -215,6 +235,7 @@ void launch_count(int D, int nchunks, const SortArgs& a, hipStream_t s);
 void launch_scan(const ScanArgs& a, hipStream_t s);
 void launch_scatter(int D, int nchunks, const SortArgs& a, hipStream_t s);
 void launch_force(int D, const ForceArgs& a, hipStream_t s);
+void launch_nlist(int D, const NlistArgs& a, hipStream_t s);
 void launch_kin(const KinArgs& a, hipStream_t s);
 void launch_bin(int D, int nstrips, const BinArgs& a, hipStream_t s);
 void launch_fsum(const FsumArgs& a, hipStream_t s);

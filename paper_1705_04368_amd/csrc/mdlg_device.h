@@ -26,6 +26,12 @@ constexpr unsigned kErrNonFinite = 2u;  // non-finite position or velocity
 constexpr unsigned kErrJump = 4u;       // moved more than one cell between rebuilds / bad input
 constexpr unsigned kErrImage = 8u;      // image counter or unwrapped cell out of range
 constexpr unsigned kErrOverflow = 16u;  // more particles in one cell than a slot can index
+constexpr unsigned kErrSkin = 32u;      // moved farther than the margin since the pair lists were built
+
+// pair lists: halo-local indices of 16 bits, four per 64-bit word; the list
+// length shares a word with three 8-bit halo coordinates
+constexpr int kMaxPairSlots = 252;
+constexpr int kMaxListHalo = 255;    // halo cells per axis a packed coordinate can hold
 
 // force-kernel modes (what the velocity buffer holds on entry)
 enum StepMode : int {
@@ -55,6 +61,10 @@ struct Phys {
   int rcq;          // (r_cut + margin) / u, rounded up
   float rc2_u;      // (r_cut / u)^2
   int mq;           // rebuild margin / u, rounded up, plus a few units
+  int rlq;          // pair-list radius (r_cut + 2 margin) / u, rounded up
+  float rl2_u;      // (pair-list radius / u)^2, widened against rounding
+  int kmax;         // pair-list slots per particle (multiple of 4; 0 = no lists)
+  float disp2;      // largest squared displacement since the lists were built
   int lmaxh;        // halo cells of the largest brick (dynamic LDS table)
   int lcap;         // staged particles per LDS chunk
   float sig2_u;     // (sigma / u)^2

@@ -500,10 +500,33 @@ __device__ __forceinline__ BrickGeom brick_setup(const Phys& P, const Replica& R
 
 // Stage halo particles [cb, ce) (LDS order) as fixed-point coordinates, and
 // their adjoint velocities when `lam` is given.
+// Offset from the LDS index of a particle of halo cell h to its index in the
+// pair-list order, which puts the brick's own particles (the targets, in
+// target order) first and the rest of the halo after them, both in halo
+// order.
+template <class Lds>
+__device__ __forceinline__ int list_shift(const BrickGeom& G, const Lds& L, int hx, int hy, int hz) {
+  const int rh = hy + G.HY * hz;
+  const bool row_in = hy >= G.ns && hy < G.ns + G.wy && hz >= G.nsz && hz < G.nsz + G.wz;
+  int rb;  // brick rows that come before this halo row
+  if (hz < G.nsz) rb = 0;
+  else if (hz >= G.nsz + G.wz) rb = G.nrows;
+  else rb = (hz - G.nsz) * G.wy + min(max(hy - G.ns, 0), G.wy);
+  if (row_in) {
+    if (hx >= G.ns && hx < G.ns + G.wx) return L.rowpre[rb] - L.hs[G.HX * rh + G.ns];
+    if (hx >= G.ns + G.wx) rb += 1;
+  }
+  return G.ntg - L.rowpre[rb];
+}
+
+__device__ __forceinline__ int pack_halo(int hx, int hy, int hz) {
+  return hx | (hy << 8) | (hz << 16);
+}
+
 template <int D, class Lds>
 __device__ __forceinline__ void brick_stage(const BrickGeom& G, const Phys& P,
                                             const float* __restrict__ pos, const float* __restrict__ lam,
-                                            Lds& L, int cb, int ce) {
+                                            Lds& L, int cb, int ce, int2* __restrict__ smap = nullptr) {
   for (int v0 = cb + (int)threadIdx.x; v0 < ce; v0 += 4 * kBlock) {
     int hh[4], g[4];
     float p[4][D];
@@ -540,6 +563,14 @@ __device__ __forceinline__ void brick_stage(const BrickGeom& G, const Phys& P,
 #pragma unroll
           for (int k = 0; k < D; ++k) L.lam[(v - cb) * D + k] = l[k];
         }
+        if (smap) {
+          // halo entries of the pair-list staging map (targets are written
+          // with their list lengths by the list builder)
+          const int nv = v + list_shift(G, L, hx, r % G.HY, r / G.HY);
+          if (nv >= G.ntg)
+            smap[nv] = make_int2(g[u], (D == 2) ? pack_halo(hx, r, 0)
+                                                : pack_halo(hx, r % G.HY, r / G.HY));
+        }
       }
     }
   }
@@ -548,7 +579,7 @@ __device__ __forceinline__ void brick_stage(const BrickGeom& G, const Phys& P,
 // Halo coordinates and global index of target t of the brick.
 template <int D, class Lds>
 __device__ __forceinline__ void brick_target(const BrickGeom& G, const Lds& L, int t, int& hxi,
-                                             int& hyi, int& hzi, int& gi) {
+                                             int& hyi, int& hzi, int& gi, int& vi) {
   int lo = 0, hi = G.nrows - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -558,7 +589,7 @@ __device__ __forceinline__ void brick_target(const BrickGeom& G, const Lds& L, i
   hyi = G.ns + row % G.wy;
   hzi = G.nsz + row / G.wy;
   const int hbase = G.HX * (hyi + G.HY * hzi);
-  const int vi = L.hs[hbase + G.ns] + (t - L.rowpre[row]);
+  vi = L.hs[hbase + G.ns] + (t - L.rowpre[row]);
   int clo = G.ns, chi = G.ns + G.wx - 1;
   while (clo < chi) {
     const int mid = (clo + chi + 1) >> 1;
@@ -600,14 +631,15 @@ struct Reach {
 };
 
 template <int D>
-__device__ __forceinline__ Reach target_reach(const BrickGeom& G, const Phys& P, int X, int Y, int Z) {
+__device__ __forceinline__ Reach target_reach(const BrickGeom& G, const Phys& P, int X, int Y, int Z,
+                                              int rq) {
   Reach r;
-  r.cx0 = max(0, (X - P.rcq) >> P.F);
-  r.cx1 = min(G.HX - 1, (X + P.rcq) >> P.F);
-  r.cy0 = max(0, (Y - P.rcq) >> P.F);
-  r.cy1 = min(G.HY - 1, (Y + P.rcq) >> P.F);
-  r.cz0 = (D == 3) ? max(0, (Z - P.rcq) >> P.F) : 0;
-  r.cz1 = (D == 3) ? min(G.HZ - 1, (Z + P.rcq) >> P.F) : 0;
+  r.cx0 = max(0, (X - rq) >> P.F);
+  r.cx1 = min(G.HX - 1, (X + rq) >> P.F);
+  r.cy0 = max(0, (Y - rq) >> P.F);
+  r.cy1 = min(G.HY - 1, (Y + rq) >> P.F);
+  r.cz0 = (D == 3) ? max(0, (Z - rq) >> P.F) : 0;
+  r.cz1 = (D == 3) ? min(G.HZ - 1, (Z + rq) >> P.F) : 0;
   return r;
 }
 
@@ -618,22 +650,82 @@ __device__ __forceinline__ Reach target_reach(const BrickGeom& G, const Phys& P,
 // Returns false when the row is out of reach.
 template <int D>
 __device__ __forceinline__ bool row_columns(const BrickGeom& G, const Phys& P, int X, int Y, int Z,
-                                            int cy, int cz, int& cx0, int& cx1) {
-  // distances in exact integer units; r_cut^2 is inflated by 4e-6 so that the
-  // float rounding of the squares can only widen the reach
-  const int dyi = max(0, max(((cy << P.F) - P.mq) - Y, Y - (((cy + 1) << P.F) + P.mq)));
+                                            int cy, int cz, float rr2, int mq, int& cx0, int& cx1) {
+  // distances in exact integer units; the squared radius is inflated by 4e-6
+  // so that the float rounding of the squares can only widen the reach.  mq:
+  // how far (in units) a particle may sit outside its cell
+  const int dyi = max(0, max(((cy << P.F) - mq) - Y, Y - (((cy + 1) << P.F) + mq)));
   const float dy = (float)dyi;
-  float r2 = fmaf(P.rc2_u, 4e-6f, P.rc2_u) - dy * dy;
+  float r2 = fmaf(rr2, 4e-6f, rr2) - dy * dy;
   if constexpr (D == 3) {
-    const int dzi = max(0, max(((cz << P.F) - P.mq) - Z, Z - (((cz + 1) << P.F) + P.mq)));
+    const int dzi = max(0, max(((cz << P.F) - mq) - Z, Z - (((cz + 1) << P.F) + mq)));
     const float dz = (float)dzi;
     r2 -= dz * dz;
   }
   if (r2 <= 0.f) return false;
-  const int hw = (int)sqrtf(r2) + P.mq + 64;
+  const int hw = (int)sqrtf(r2) + mq + 64;
   cx0 = max(0, (X - hw) >> P.F);
   cx1 = min(G.HX - 1, (X + hw) >> P.F);
   return true;
+}
+
+// Velocity-Verlet update of one particle from its acceleration f, shared by
+// both force paths; accumulates the kinetic partials.
+template <int D>
+__device__ __forceinline__ void vv_update(const ForceArgs& a, const Phys& P, int rep, int gi,
+                                          const float (&o)[D], const float (&v)[D],
+                                          const float (&f)[D], double (&kin)[D + 1]) {
+  float vf[D];
+  const float lam = (a.mode == kModeStart && a.lambda) ? a.lambda[rep] : 1.f;
+  const bool drift = (a.mode == kModeStep || a.mode == kModeStart);
+  float on[D], vh[D];
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    if (a.mode == kModeStep || a.mode == kModeFinish)
+      vf[k] = fmaf(P.half_dt, f[k], v[k]);
+    else
+      vf[k] = lam * v[k];
+    vh[k] = fmaf(P.half_dt, f[k], vf[k]);
+    on[k] = fmaf(vh[k], P.dt, o[k]);
+    ok = ok && (on[k] >= P.lo) && (on[k] < P.hi);
+  }
+  if (drift) {
+    if (!ok) atomicOr(a.err, kErrMargin);
+    if (a.check_disp) {
+      float o0[D];
+      ldv<D>(a.off0, gi, o0);
+      float d2 = 0.f;
+#pragma unroll
+      for (int k = 0; k < D; ++k) d2 = fmaf(on[k] - o0[k], on[k] - o0[k], d2);
+      if (!(d2 <= P.disp2)) atomicOr(a.err, kErrSkin);
+    }
+    stv<D>(a.pos_out, gi, on);
+    stv<D>(a.vel, gi, vh);
+  } else if (a.mode == kModeFinish) {
+    stv<D>(a.vel, gi, vf);
+  }
+  if (a.acc_out) stv<D>(a.acc_out, gi, f);
+  if (a.kpart) {
+    double e = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      kin[k] += (double)P.mass * (double)vf[k];
+      e += (double)vf[k] * (double)vf[k];
+    }
+    kin[D] += 0.5 * (double)P.mass * e;
+  }
+}
+
+// Accumulate the LJ acceleration from the four halo indices packed in e.
+template <int D, class Lds>
+__device__ __forceinline__ void list_word(const Lds& L, unsigned long long e, int X, int Y, int Z,
+                                          const Phys& P, float (&f)[D]) {
+  Coord<D> q[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) q[u] = L.p[(unsigned)(e >> (16 * u)) & 0xffffu];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) lj_pair<D>(q[u], X, Y, Z, P, f);
 }
 
 template <int D>
@@ -654,102 +746,137 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
   if (b >= a.nbricks) return;
   const Phys& P = a.P;
   const int4 br = a.bricks[b];
-  const Replica R = a.reps[br.x];
-  const BrickGeom G = brick_setup<D>(P, R, br, a.cell_start, L);
-  const int nchunks = (G.total + CAP - 1) / CAP;
   const bool interact = !P.forces_off;
-  if (interact && nchunks == 1) {
-    brick_stage<D>(G, P, a.pos_in, nullptr, L, 0, G.total);
-    __syncthreads();
-  }
 
   double kin[D + 1];
 #pragma unroll
   for (int k = 0; k <= D; ++k) kin[k] = 0.0;
 
-  for (int tb = 0; tb < G.ntg; tb += kBlock) {
-    const int t = tb + (int)threadIdx.x;
-    const bool valid = t < G.ntg;
-    int hxi = G.ns, hyi = G.ns, hzi = G.nsz, gi = 0;
-    if (valid) brick_target<D>(G, L, t, hxi, hyi, hzi, gi);
-    float o[D], f[D], v[D];
+  const int4 bi = a.nl ? a.binfo[b] : make_int4(0, 0, 0, 0);
+  if (bi.z) {
+    // pair-list path: stage the halo through the map written by the list
+    // builder (targets first), then each target walks its own list
+    const int2* __restrict__ smap = a.smap + (size_t)b * CAP;
+    const int total = bi.x, ntg = bi.y;
+    for (int v0 = (int)threadIdx.x; v0 < total; v0 += 2 * kBlock) {
+      int2 e[2];
+      float p[2][D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      o[k] = 0.f;
-      f[k] = 0.f;
-      v[k] = 0.f;
+      for (int u = 0; u < 2; ++u) {
+        const int v = v0 + u * kBlock;
+        e[u] = smap[min(v, total - 1)];
+        ldv<D>(a.pos_in, e[u].x, p[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int v = v0 + u * kBlock;
+        if (v < total) {
+          const int hx = e[u].y & 255, hy = (e[u].y >> 8) & 255;
+          if constexpr (D == 2)
+            L.p[v] = make_int2(fixed_coord(hx, p[u][0], P), fixed_coord(hy, p[u][1], P));
+          else
+            L.p[v] = make_int4(fixed_coord(hx, p[u][0], P), fixed_coord(hy, p[u][1], P),
+                               fixed_coord((e[u].y >> 16) & 255, p[u][2], P), 0);
+        }
+      }
     }
-    if (valid) {
+    __syncthreads();
+    const size_t nt = (size_t)P.n_total;
+    for (int tb = 0; tb < ntg; tb += kBlock) {
+      const int t = tb + (int)threadIdx.x;
+      if (t >= ntg) break;
+      const int2 e = smap[t];
+      const int gi = e.x;
+      const int ng = ((unsigned)e.y >> 24) >> 2;
+      const Coord<D> me = L.p[t];
+      const int X = me.x, Y = me.y;
+      int Z = 0;
+      if constexpr (D == 3) Z = me.z;
+      float o[D], v[D], f[D];
       ldv<D>(a.pos_in, gi, o);
       ldv<D>(a.vel, gi, v);
+#pragma unroll
+      for (int k = 0; k < D; ++k) f[k] = 0.f;
+      // a group of words in flight ahead of the group being summed (two in
+      // 2D, four in 3D where lists are longer); words past the end of the
+      // list stand in as four copies of the target itself (zero terms)
+      constexpr int GW = (D == 2) ? 2 : 4;
+      const unsigned long long* __restrict__ lp = a.nl + gi;
+      const unsigned long long self = 0x0001000100010001ull * (unsigned)t;
+      unsigned long long w[GW];
+#pragma unroll
+      for (int u = 0; u < GW; ++u) w[u] = (u < ng) ? lp[(size_t)u * nt] : self;
+      for (int k = 0; k < ng; k += GW) {
+        unsigned long long nx[GW];
+#pragma unroll
+        for (int u = 0; u < GW; ++u)
+          nx[u] = (k + GW + u < ng) ? lp[(size_t)(k + GW + u) * nt] : self;
+#pragma unroll
+        for (int u = 0; u < GW; ++u) list_word<D>(L, w[u], X, Y, Z, P, f);
+#pragma unroll
+        for (int u = 0; u < GW; ++u) w[u] = nx[u];
+      }
+      vv_update<D>(a, P, br.x, gi, o, v, f, kin);
     }
-    if (interact) {
-      const int X = fixed_coord(hxi, o[0], P);
-      const int Y = fixed_coord(hyi, o[1], P);
-      const int Z = (D == 3) ? fixed_coord(hzi, o[D - 1], P) : 0;
-      const Reach rr = target_reach<D>(G, P, X, Y, Z);
-      for (int ci = 0; ci < nchunks; ++ci) {
-        const int cb = ci * CAP, ce = min(G.total, cb + CAP);
-        if (nchunks > 1) {
-          __syncthreads();
-          brick_stage<D>(G, P, a.pos_in, nullptr, L, cb, ce);
-          __syncthreads();
-        }
-        if (valid) {
-          for (int cz = rr.cz0; cz <= rr.cz1; ++cz) {
-            for (int cy = rr.cy0; cy <= rr.cy1; ++cy) {
-              int cx0, cx1;
-              if (!row_columns<D>(G, P, X, Y, Z, cy, cz, cx0, cx1)) continue;
-              const int hrow = G.HX * (cy + G.HY * cz);
-              const int jlo = max(L.hs[hrow + cx0], cb) - cb;
-              const int jhi = min(L.hs[hrow + cx1 + 1], ce) - cb;
-              int j = jlo;
-              for (; j + 3 < jhi; j += 4) {
-                Coord<D> q[4];
+  } else {
+    const Replica R = a.reps[br.x];
+    const BrickGeom G = brick_setup<D>(P, R, br, a.cell_start, L);
+    const int nchunks = (G.total + CAP - 1) / CAP;
+    if (interact && nchunks == 1) {
+      brick_stage<D>(G, P, a.pos_in, nullptr, L, 0, G.total);
+      __syncthreads();
+    }
+    for (int tb = 0; tb < G.ntg; tb += kBlock) {
+      const int t = tb + (int)threadIdx.x;
+      const bool valid = t < G.ntg;
+      int hxi = G.ns, hyi = G.ns, hzi = G.nsz, gi = 0, vi = 0;
+      if (valid) brick_target<D>(G, L, t, hxi, hyi, hzi, gi, vi);
+      float o[D], f[D], v[D];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) q[u] = L.p[j + u];
+      for (int k = 0; k < D; ++k) {
+        o[k] = 0.f;
+        f[k] = 0.f;
+        v[k] = 0.f;
+      }
+      if (valid) {
+        ldv<D>(a.pos_in, gi, o);
+        ldv<D>(a.vel, gi, v);
+      }
+      if (interact) {
+        const int X = fixed_coord(hxi, o[0], P);
+        const int Y = fixed_coord(hyi, o[1], P);
+        const int Z = (D == 3) ? fixed_coord(hzi, o[D - 1], P) : 0;
+        const Reach rr = target_reach<D>(G, P, X, Y, Z, P.rcq);
+        for (int ci = 0; ci < nchunks; ++ci) {
+          const int cb = ci * CAP, ce = min(G.total, cb + CAP);
+          if (nchunks > 1) {
+            __syncthreads();
+            brick_stage<D>(G, P, a.pos_in, nullptr, L, cb, ce);
+            __syncthreads();
+          }
+          if (valid) {
+            for (int cz = rr.cz0; cz <= rr.cz1; ++cz) {
+              for (int cy = rr.cy0; cy <= rr.cy1; ++cy) {
+                int cx0, cx1;
+                if (!row_columns<D>(G, P, X, Y, Z, cy, cz, P.rc2_u, P.mq, cx0, cx1)) continue;
+                const int hrow = G.HX * (cy + G.HY * cz);
+                const int jlo = max(L.hs[hrow + cx0], cb) - cb;
+                const int jhi = min(L.hs[hrow + cx1 + 1], ce) - cb;
+                int j = jlo;
+                for (; j + 3 < jhi; j += 4) {
+                  Coord<D> q[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) lj_pair<D>(q[u], X, Y, Z, P, f);
+                  for (int u = 0; u < 4; ++u) q[u] = L.p[j + u];
+#pragma unroll
+                  for (int u = 0; u < 4; ++u) lj_pair<D>(q[u], X, Y, Z, P, f);
+                }
+                for (; j < jhi; ++j) lj_pair<D>(L.p[j], X, Y, Z, P, f);
               }
-              for (; j < jhi; ++j) lj_pair<D>(L.p[j], X, Y, Z, P, f);
             }
           }
         }
       }
-    }
-    if (valid) {
-      float vf[D];
-      const float lam = (a.mode == kModeStart && a.lambda) ? a.lambda[br.x] : 1.f;
-      const bool drift = (a.mode == kModeStep || a.mode == kModeStart);
-      float on[D], vh[D];
-      bool ok = true;
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        if (a.mode == kModeStep || a.mode == kModeFinish)
-          vf[k] = fmaf(P.half_dt, f[k], v[k]);
-        else
-          vf[k] = lam * v[k];
-        vh[k] = fmaf(P.half_dt, f[k], vf[k]);
-        on[k] = fmaf(vh[k], P.dt, o[k]);
-        ok = ok && (on[k] >= P.lo) && (on[k] < P.hi);
-      }
-      if (drift) {
-        if (!ok) atomicOr(a.err, kErrMargin);
-        stv<D>(a.pos_out, gi, on);
-        stv<D>(a.vel, gi, vh);
-      } else if (a.mode == kModeFinish) {
-        stv<D>(a.vel, gi, vf);
-      }
-      if (a.acc_out) stv<D>(a.acc_out, gi, f);
-      if (a.kpart) {
-        double e = 0.0;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-          kin[k] += (double)P.mass * (double)vf[k];
-          e += (double)vf[k] * (double)vf[k];
-        }
-        kin[D] += 0.5 * (double)P.mass * e;
-      }
+      if (valid) vv_update<D>(a, P, br.x, gi, o, v, f, kin);
     }
   }
   if (a.kpart) {
@@ -766,6 +893,130 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
       a.kpart[(size_t)b * (D + 1) + threadIdx.x] = s;
     }
   }
+}
+
+// Pair lists of one brick, built right after each cell-list rebuild (all
+// particles then lie inside their cells).  For every target the list holds
+// the halo particles within r_cut + 2 m, m the rebuild margin, so that it
+// covers every pair within r_cut while no particle has moved farther than m
+// since (the force kernel checks that bound).  Entries are 16-bit indices
+// into the brick's staging order (targets first), four to a word, the last
+// word padded with the target's own index (a zero term).  A brick whose
+// halo exceeds one LDS chunk, or with a target of more than kmax neighbours,
+// is marked for the cell walk.
+template <int D, typename C>
+__device__ __forceinline__ bool list_near(const C& q, int X, int Y, int Z, float rl2) {
+  const float dx = (float)(q.x - X), dy = (float)(q.y - Y);
+  float r2 = dx * dx + dy * dy;
+  if constexpr (D == 3) {
+    const float dz = (float)(q.z - Z);
+    r2 += dz * dz;
+  }
+  return r2 < rl2;
+}
+
+// Append entry nj to a list being built four 16-bit entries per word;
+// completed words go to *wp, which then steps to the next word (stride nt).
+__device__ __forceinline__ void list_push(unsigned long long*& wp, unsigned long long& word, int& cnt,
+                                          int& seen, int nj, int kmax, size_t nt) {
+  ++seen;
+  if (cnt < kmax) {
+    word |= (unsigned long long)(unsigned)nj << ((cnt & 3) << 4);
+    if ((++cnt & 3) == 0) {
+      *wp = word;
+      wp += nt;
+      word = 0;
+    }
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_nlist(NlistArgs a) {
+  extern __shared__ __align__(16) char s_dyn_brick[];
+  __shared__ int s_rowpre[kMaxRows + 1];
+  __shared__ int s_tmp[kWaves + 1];
+  __shared__ double s_red[kWaves][4];
+  __shared__ int s_over;
+  auto L = brick_lds<D, false>(s_dyn_brick, s_rowpre, s_tmp, s_red, a.P);
+  const int CAP = L.cap;
+  int b = blockIdx.x;
+  if (a.xcd_remap) {
+    const int per = gridDim.x >> 3;
+    b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  if (b >= a.nbricks) return;
+  const Phys& P = a.P;
+  const int4 br = a.bricks[b];
+  const Replica R = a.reps[br.x];
+  if (threadIdx.x == 0) s_over = 0;
+  const BrickGeom G = brick_setup<D>(P, R, br, a.cell_start, L);
+  const bool fits = G.total <= CAP;
+  int2* __restrict__ smap = a.smap + (size_t)b * CAP;
+  if (fits) brick_stage<D>(G, P, a.pos, nullptr, L, 0, G.total, smap);
+  __syncthreads();
+  const size_t nt = (size_t)P.n_total;
+  const int kmax = P.kmax;
+  const float rl2 = P.rl2_u;
+  for (int tb = 0; tb < G.ntg; tb += kBlock) {
+    const int t = tb + (int)threadIdx.x;
+    if (t >= G.ntg) break;
+    int hxi, hyi, hzi, gi, vi;
+    brick_target<D>(G, L, t, hxi, hyi, hzi, gi, vi);
+    float o[D];
+    ldv<D>(a.pos, gi, o);
+    stv<D>(a.off0, gi, o);
+    if (!fits) continue;
+    const Coord<D> me = L.p[vi];
+    const int X = me.x, Y = me.y;
+    int Z = 0;
+    if constexpr (D == 3) Z = me.z;
+    const Reach rr = target_reach<D>(G, P, X, Y, Z, P.rlq);
+    unsigned long long* wp = a.nl + gi;  // next list word
+    unsigned long long word = 0;
+    int cnt = 0, seen = 0;
+    for (int cz = rr.cz0; cz <= rr.cz1; ++cz) {
+      for (int cy = rr.cy0; cy <= rr.cy1; ++cy) {
+        int cx0, cx1;
+        if (!row_columns<D>(G, P, X, Y, Z, cy, cz, P.rl2_u, 4, cx0, cx1)) continue;
+        const int hrow = G.HX * (cy + G.HY * cz);
+        // one contiguous LDS range per row; its list shift takes at most three
+        // values: halo columns left of the brick, the brick's own, halo to the
+        // right (one loop per row keeps the lanes of a wave in step)
+        const int ca = min(max(G.ns, cx0), cx1 + 1), cb = min(max(G.ns + G.wx, cx0), cx1 + 1);
+        const int ja = L.hs[hrow + ca], jb = L.hs[hrow + cb];
+        const int s0 = list_shift(G, L, 0, cy, cz);
+        const int s1 = list_shift(G, L, G.ns, cy, cz);
+        const int s2 = list_shift(G, L, G.ns + G.wx, cy, cz);
+        const int jhi = L.hs[hrow + cx1 + 1];
+        int j = L.hs[hrow + cx0];
+        for (; j + 3 < jhi; j += 4) {
+          // four LDS reads in flight before the tests
+          Coord<D> q[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) q[u] = L.p[j + u];
+          bool in[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) in[u] = list_near<D>(q[u], X, Y, Z, rl2) && (j + u != vi);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (in[u]) list_push(wp, word, cnt, seen, j + u + (j + u < ja ? s0 : (j + u < jb ? s1 : s2)),
+                                 kmax, nt);
+        }
+        for (; j < jhi; ++j)
+          if (list_near<D>(L.p[j], X, Y, Z, rl2) && j != vi)
+            list_push(wp, word, cnt, seen, j + (j < ja ? s0 : (j < jb ? s1 : s2)), kmax, nt);
+      }
+    }
+    if (seen > kmax) s_over = 1;
+    if (cnt & 3) {
+      for (int u = cnt & 3; u < 4; ++u) word |= (unsigned long long)(unsigned)t << (16 * u);
+      *wp = word;
+    }
+    const int words = (cnt + 3) >> 2;
+    smap[t] = make_int2(gi, pack_halo(hxi, hyi, hzi) | ((words * 4) << 24));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) a.binfo[b] = make_int4(G.total, G.ntg, (fits && !s_over) ? 1 : 0, 0);
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -806,8 +1057,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs a) {
   for (int tb = 0; tb < G.ntg; tb += kBlock) {
     const int t = tb + (int)threadIdx.x;
     const bool valid = t < G.ntg;
-    int hxi = G.ns, hyi = G.ns, hzi = G.nsz, gi = 0;
-    if (valid) brick_target<D>(G, L, t, hxi, hyi, hzi, gi);
+    int hxi = G.ns, hyi = G.ns, hzi = G.nsz, gi = 0, vi = 0;
+    if (valid) brick_target<D>(G, L, t, hxi, hyi, hzi, gi, vi);
     float o[D], li[D], acc[D], dacc[D], jl[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -825,7 +1076,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs a) {
       const int X = fixed_coord(hxi, o[0], P);
       const int Y = fixed_coord(hyi, o[1], P);
       const int Z = (D == 3) ? fixed_coord(hzi, o[D - 1], P) : 0;
-      const Reach rr = target_reach<D>(G, P, X, Y, Z);
+      const Reach rr = target_reach<D>(G, P, X, Y, Z, P.rcq);
       for (int ci = 0; ci < nchunks; ++ci) {
         const int cb = ci * CAP, ce = min(G.total, cb + CAP);
         if (nchunks > 1) {
@@ -837,7 +1088,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs a) {
           for (int cz = rr.cz0; cz <= rr.cz1; ++cz) {
             for (int cy = rr.cy0; cy <= rr.cy1; ++cy) {
               int cx0, cx1;
-              if (!row_columns<D>(G, P, X, Y, Z, cy, cz, cx0, cx1)) continue;
+              if (!row_columns<D>(G, P, X, Y, Z, cy, cz, P.rc2_u, P.mq, cx0, cx1)) continue;
               const int hrow = G.HX * (cy + G.HY * cz);
               const int jlo = max(L.hs[hrow + cx0], cb) - cb;
               const int jhi = min(L.hs[hrow + cx1 + 1], ce) - cb;
@@ -1316,6 +1567,12 @@ void launch_force(int D, const ForceArgs& a, hipStream_t s) {
   int grid = a.nbricks;
   if (a.xcd_remap) grid = ((a.nbricks + 7) / 8) * 8;
   MDLG_LAUNCH_DIM(D, k_force, grid, brick_lds_bytes(a.P, D, false), s, a);
+}
+
+void launch_nlist(int D, const NlistArgs& a, hipStream_t s) {
+  int grid = a.nbricks;
+  if (a.xcd_remap) grid = ((a.nbricks + 7) / 8) * 8;
+  MDLG_LAUNCH_DIM(D, k_nlist, grid, brick_lds_bytes(a.P, D, false), s, a);
 }
 
 void launch_kin(const KinArgs& a, hipStream_t s) {

@@ -23,7 +23,7 @@ EXPORTED = ["mdlg_describe", "mdlg_workspace_bytes", "mdlg_create", "mdlg_step",
             "mdlg_get_state", "mdlg_set_state", "mdlg_adjoint", "mdlg_set_potential",
             "mdlg_set_timing", "mdlg_get_timing", "mdlg_sync", "mdlg_last_error", "mdlg_destroy"]
 LOSSES = {"msd": 0, "mean_x": 1}
-KERNEL_CLASSES = ["force", "count", "scan", "scatter", "bin"]
+KERNEL_CLASSES = ["force", "count", "scan", "scatter", "bin", "nlist"]
 
 
 class MdlgConfig(C.Structure):
@@ -35,7 +35,8 @@ class MdlgConfig(C.Structure):
                 ("vmax", C.c_int32), ("thermostat_every", C.c_int32), ("kT", C.c_double),
                 ("md_cell_split", C.c_int32), ("sort_every", C.c_int32),
                 ("brick_x", C.c_int32), ("brick_y", C.c_int32), ("brick_z", C.c_int32),
-                ("adjoint_window", C.c_int32), ("adjoint_every", C.c_int32)]
+                ("adjoint_window", C.c_int32), ("adjoint_every", C.c_int32),
+                ("no_pair_list", C.c_int32)]
 
 
 class MdlgParticles(C.Structure):
@@ -49,7 +50,7 @@ class MdlgLayout(C.Structure):
                 ("stencil", C.c_int32), ("n_velocities", C.c_int32), ("n_moments", C.c_int32),
                 ("brick", C.c_int32 * 3), ("n_total", C.c_int64), ("n_sites", C.c_int64),
                 ("n_cells", C.c_int64), ("n_bricks", C.c_int64), ("cell_side", C.c_double),
-                ("margin", C.c_double)]
+                ("margin", C.c_double), ("pair_slots", C.c_int32)]
 
 
 _lib = None
@@ -126,7 +127,7 @@ def _check(status, handle=None):
 def make_config(dim, n_particles, lattice, lattice_dx=4.0, epsilon=1.0, sigma=1.0, mass=1.0,
                 r_cut=2.5, forces_off=False, dt=0.005, md_steps_per_lattice_step=20, vmax=3,
                 thermostat_every=0, kT=1.0, md_cell_split=0, sort_every=0, brick=(0, 0, 0),
-                adjoint_window=0, adjoint_every=1):
+                adjoint_window=0, adjoint_every=1, pair_list=True):
     """Build an MdlgConfig.  n_particles: int or sequence per replica; lattice:
     sites per axis, an int, a (dim,) sequence or an (n_replicas, dim) array."""
     n = np.atleast_1d(np.asarray(n_particles, dtype=np.int32))
@@ -156,6 +157,7 @@ def make_config(dim, n_particles, lattice, lattice_dx=4.0, epsilon=1.0, sigma=1.
     cfg.brick_x, cfg.brick_y, cfg.brick_z = (int(b) for b in brick)
     cfg.adjoint_window = adjoint_window
     cfg.adjoint_every = adjoint_every if adjoint_window else 0
+    cfg.no_pair_list = 0 if pair_list else 1
     return cfg
 
 
@@ -166,7 +168,7 @@ def describe(cfg):
             "stencil": out.stencil, "n_velocities": out.n_velocities,
             "n_moments": out.n_moments, "brick": tuple(out.brick), "n_total": out.n_total,
             "n_sites": out.n_sites, "n_cells": out.n_cells, "n_bricks": out.n_bricks,
-            "cell_side": out.cell_side, "margin": out.margin}
+            "cell_side": out.cell_side, "margin": out.margin, "pair_slots": out.pair_slots}
 
 
 def workspace_bytes(cfg):

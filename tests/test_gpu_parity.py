@@ -318,3 +318,84 @@ def test_empty_lattice_steps_and_single_particle():
         site = x + 4 * 1
         nz = np.argwhere(hist[t] > 0)
         assert nz.tolist() == [[site, b]], (t, nz)
+
+
+# ------------------------------------------------------------------ pair lists
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_pair_lists_match_cell_walk_and_oracle(dim):
+    # the same 40 MD steps with per-particle pair lists (rebuilt with the cell
+    # list every 8 steps) and with the cell walk at every step
+    cfg_l, pos, vel, box, n, M = _force_case(dim, 78, 2 if dim == 3 else 1, equil_steps=300)
+    cfg_c, *_ = _force_case(dim, 78, 2 if dim == 3 else 1)
+    cfg_c.no_pair_list = 1
+    for c in (cfg_l, cfg_c):
+        c.sort_every = 8
+    say(f"pair lists vs cell walk dim={dim}")
+    sl = make_system(cfg_l, pos, vel)
+    sc = make_system(cfg_c, pos, vel)
+    assert sl.layout["pair_slots"] > 0 and sc.layout["pair_slots"] == 0
+    s = sl.layout["cell_side"]
+    f_l, f_c = sl.get_state()["acc"], sc.get_state()["acc"]
+    md = oracle.make_md(dim, n, box, dt=0.005)
+    acc, _ = oracle.forces(md, wrapped(sl.get_state(), s, M * sl.layout["md_cell_split"]))
+    assert force_error(f_l, acc).max() <= 1e-5
+    assert force_error(f_c, acc).max() <= 1e-5
+    sl.step(40)
+    sc.step(40)
+    a, b = sl.get_state(), sc.get_state()
+    ost = oracle.OracleState(md, pos, vel)
+    ost.run(40)
+    for st in (a, b):
+        assert np.abs(unwrapped(st, s) - ost.unwrapped).max() <= 1e-4
+        assert np.abs(st["vel"].astype(np.float64) - ost.v).max() <= 1e-4
+    say(f"  list vs walk max |dx| {np.abs(unwrapped(a, s) - unwrapped(b, s)).max():.3e}")
+
+
+def test_pair_list_overflow_falls_back_to_cell_walk():
+    # all particles packed into a sixteenth of the box: lists in the packed
+    # region hold about sixteen times the neighbours the mean density
+    # predicts, more than the slots, so those bricks walk their cells (one-cell
+    # bricks, so that their halo still fits one LDS chunk)
+    from paper_1705_04368_amd import make_config
+    M, dx, n = 16, 4.0, 256
+    box = M * dx
+    pos, vel = synth.lj_initial_state(2, n, box / 4, 1.0, seed=12, r_min=0.8)
+    cfg = make_config(2, n, M, lattice_dx=dx, dt=0.005, vmax=3, md_cell_split=1, kT=1.0,
+                      brick=(1, 1, 1))
+    say("pair-list overflow")
+    sysg = make_system(cfg, pos, vel)
+    kmax = sysg.layout["pair_slots"]
+    s = sysg.layout["cell_side"]
+    st = sysg.get_state()
+    md = oracle.make_md(2, n, box)
+    xw = wrapped(st, s, M)
+    acc, _ = oracle.forces(md, xw)
+    assert force_error(st["acc"], acc).max() <= 1e-5
+    # the packed region really exceeds the slots
+    d = xw[:, None, :] - xw[None, :, :]
+    d -= box * np.rint(d / box)
+    r = np.sqrt((d ** 2).sum(-1))
+    rl = 2.5 + 2 * sysg.layout["margin"]
+    assert ((r < rl).sum(1) - 1).max() > kmax
+
+
+def test_pair_list_displacement_is_checked():
+    # two particles far apart; one moves 0.15 sigma per step, inside its cell,
+    # and passes the list margin after a few steps
+    from paper_1705_04368_amd import MdlgError, make_config
+    cfg = make_config(2, 2, 4, lattice_dx=4.0, dt=0.005, vmax=1, md_cell_split=1, kT=1.0,
+                      sort_every=18)
+    pos = np.array([[1.0, 2.0], [9.0, 10.0]], np.float32)
+    vel = np.array([[30.0, 0.0], [0.0, 0.0]], np.float32)
+    say("pair-list displacement check")
+    sysg = make_system(cfg, pos, vel)
+    m = sysg.layout["margin"]
+    assert sysg.layout["pair_slots"] > 0 and sysg.layout["sort_every"] == 18
+    steps = int(np.ceil(m / (30.0 * 0.005))) + 2
+    assert 1.0 + 30.0 * 0.005 * steps < 4.0  # still inside its cell
+    sysg.step(steps)
+    with pytest.raises(MdlgError) as e:
+        sysg.sync()
+    assert e.value.status == -4
+    assert "pair lists" in str(e.value)
