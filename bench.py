@@ -163,6 +163,22 @@ def cpu_baseline(w, pos, vel, lattice_steps):
                       f"steps + binning), FP64 single thread, {t:.1f} s"}
 
 
+def equilibrated_state(sysg, cfg):
+    """Positions in [0, box) and velocities of a system, in particle order
+    (host float32), to start another system from the same state."""
+    st = sysg.get_state()
+    s = sysg.layout["cell_side"]
+    k = sysg.layout["md_cell_split"]
+    n = np.ctypeslib.as_array(cfg.n_particles, shape=(cfg.n_replicas,))
+    lat = np.ctypeslib.as_array(cfg.lattice, shape=(cfg.n_replicas * cfg.dim,)).reshape(-1, cfg.dim)
+    mc = np.repeat(lat * k, n, axis=0)
+    x = np.mod(st["ucell"], mc).astype(np.float64) * s + st["off"].astype(np.float64)
+    x32 = x.astype(np.float32)
+    box = (mc * s).astype(np.float32)
+    x32 = np.where(x32 >= box, np.float32(0.0), x32)
+    return np.ascontiguousarray(x32), np.ascontiguousarray(st["vel"].astype(np.float32))
+
+
 def plain_replicas(sysg, cfg, n_r, m_r, w, dev, lattice_steps):
     """The same ensemble as one system per replica, launched one after the
     other (each replica's lattice step is its own graph of launches).  The
@@ -230,6 +246,9 @@ def main():
     ap.add_argument("--brick", type=int, nargs=3, default=(0, 0, 0), help="force brick (0 = auto)")
     ap.add_argument("--no-pair-list", action="store_true",
                     help="walk the neighbour cells at every MD step instead of using pair lists")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's analytic launch shapes instead of measuring candidates")
+    ap.add_argument("--autotune-steps", type=int, default=40, help="MD steps timed per candidate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (scales the HBM "
                          "counters of a profiler to bytes)")
@@ -292,11 +311,24 @@ def main():
                           md_steps_per_lattice_step=w["steps"], vmax=w["vmax"], thermostat_every=10,
                           kT=w["kT"], **tuning)
     sysg = System(cfg, torch.from_numpy(pos).to(dev), torch.from_numpy(vel).to(dev))
-    lay = sysg.layout
-    print(f"# workload {args.workload}: {w['desc']}; layout {lay}", file=sys.stderr, flush=True)
+    print(f"# workload {args.workload}: {w['desc']}; layout {sysg.layout}", file=sys.stderr, flush=True)
     sysg.step(args.equilibrate)
     sysg.sync()
     print("# equilibrated", file=sys.stderr, flush=True)
+    tuned_ms = None
+    if not args.no_autotune:
+        # launch shapes measured on the equilibrated state (untimed)
+        from paper_1705_04368_amd import autotune
+        xe, ve = equilibrated_state(sysg, cfg)
+        xe, ve = torch.from_numpy(xe).to(dev), torch.from_numpy(ve).to(dev)
+        t0 = time.perf_counter()
+        cfg, tuned_ms = autotune(cfg, xe, ve, md_steps=args.autotune_steps)
+        print(f"# autotuned in {time.perf_counter() - t0:.1f} s: {tuned_ms * 1e3:.2f} us per MD step",
+              file=sys.stderr, flush=True)
+        sysg.close()
+        sysg = System(cfg, xe, ve)
+    lay = sysg.layout
+    print(f"# timed layout {lay}", file=sys.stderr, flush=True)
     sysg.coarse_grain(args.warmup)
     sysg.sync()
     sysg.reset_accumulators()
@@ -382,7 +414,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["desc"], "lattice_steps": args.steps, "md_steps": md_steps,
                    "md_cell_split": lay["md_cell_split"], "sort_every": lay["sort_every"],
-                   "brick": list(lay["brick"]), "pair_slots": lay["pair_slots"]},
+                   "brick": list(lay["brick"]), "pair_slots": lay["pair_slots"],
+                   "autotuned": tuned_ms is not None},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plain": plain,

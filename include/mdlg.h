@@ -104,6 +104,8 @@ typedef struct {
                                    pair lists of radius r_cut + 2 margin, built at each
                                    cell-list rebuild, are used when the rebuild interval is
                                    at least 2 (results agree to float rounding) */
+    int32_t block_threads;      /* threads per block of the force and pair-list kernels:
+                                   64, 128 or 256, or 0 = choose automatically */
 } mdlg_config;
 
 /* Particle state in particle-id order (id = index in the concatenated input).
@@ -142,6 +144,7 @@ typedef struct {
     double margin;              /* allowed excursion outside the cell between rebuilds, and
                                    the largest displacement between pair-list builds */
     int32_t pair_slots;         /* pair-list entries per particle (0 = no pair lists) */
+    int32_t block_threads;      /* threads per force / pair-list block actually used */
 } mdlg_layout;
 
 /* Validate cfg and report the derived layout.  Host only.  MDLG_E_INVALID on
@@ -273,6 +276,34 @@ const char *mdlg_last_error(const mdlg_system *sys);
 
 /* Release the handle (the caller still owns the workspace). */
 void mdlg_destroy(mdlg_system *sys);
+
+/* Launch-shape autotuner for batched and single systems (the f_i^eq of
+ * eq. fieq are ensemble averages, so the same configuration is typically run
+ * for many lattice steps and its shapes are worth measuring).  Every field of
+ * cfg left automatic (0) among md_cell_split, sort_every, brick_x/y/z and
+ * block_threads is
+ * tuned by timing candidate layouts on the device: first the automatic layout
+ * with and without pair lists (unless cfg asks for none), then the other MD-cell
+ * splits, then rebuild intervals that divide a lattice step into equal parts
+ * and fit the stencil margin, then block sizes of 64, 128 and 256 threads
+ * with force-brick extents around 3/4, 1 and 3/2 targets per thread; each
+ * stage keeps the fastest so far.  A candidate runs two warm-up
+ * lattice steps and then ceil(md_steps / md_steps_per_lattice_step) timed
+ * lattice steps (HIP events on hip_stream) from pos_dev / vel_dev (device
+ * [n_total][dim], as for mdlg_create; not modified).  Candidates that do not
+ * fit the workspace, fail to create, or report a device error are skipped.
+ * *best receives a copy of *cfg with the tuned fields set (pointers still the
+ * caller's); *best_ms_per_md_step (optional) the time per MD step measured
+ * for it.  Every candidate runs in workspace_dev, one after another: the
+ * library still allocates nothing.  Synchronises the stream.
+ * MDLG_E_INVALID for bad arguments, MDLG_E_DEVICE when no candidate ran. */
+mdlg_status mdlg_autotune(const mdlg_config *cfg, void *workspace_dev, size_t workspace_bytes,
+                          void *hip_stream, const float *pos_dev, const float *vel_dev,
+                          int32_t md_steps, mdlg_config *best, double *best_ms_per_md_step);
+
+/* Workspace that holds every candidate mdlg_autotune may try for cfg.
+ * Host only. */
+mdlg_status mdlg_autotune_workspace_bytes(const mdlg_config *cfg, size_t *bytes);
 
 #ifdef __cplusplus
 }

@@ -4,5 +4,5 @@ Molecular-Dynamics lattice gas of Parsa & Wagner.
 The computation lives in ``libmdlg.so`` (HIP kernels for gfx950 behind the C
 ABI of ``include/mdlg.h``); this package only marshals arguments.
 """
-from .native import (MdlgError, System, describe, library_path, load, make_config,  # noqa: F401
-                     workspace_bytes)
+from .native import (MdlgError, System, autotune, describe, library_path, load,  # noqa: F401
+                     make_config, workspace_bytes)

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmdlg.so")
-SOURCES = ["mdlg_kernels.hip", "mdlg_api.hip"]
+SOURCES = ["mdlg_kernels.hip", "mdlg_api.hip", "mdlg_autotune.hip"]
 
 # Packed FP32 instructions are disabled: hipcc would otherwise form
 # v_pk_{add,mul,fma}_f32 from ordinary float code.

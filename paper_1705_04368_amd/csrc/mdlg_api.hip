@@ -33,6 +33,7 @@ struct Layout {
   int Q = 1;
   int nm = 0;
   int BX = 1, BY = 1, BZ = 1;
+  int bthreads = 256;
   int BSX = 1;
   long long n_total = 0, n_cells = 0, n_sites = 0;
   int nbricks = 0, nchunks = 0, nstrips = 0, ntiles = 0;
@@ -96,6 +97,9 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   if (c->kT < 0 || !std::isfinite(c->kT)) return set_err(msg, "kT must be >= 0");
   if (c->sort_every < 0) return set_err(msg, "sort_every must be >= 0");
   if (c->brick_x < 0 || c->brick_y < 0 || c->brick_z < 0) return set_err(msg, "brick extents must be >= 0");
+  if (c->block_threads != 0 && c->block_threads != 64 && c->block_threads != 128 &&
+      c->block_threads != 256)
+    return set_err(msg, "block_threads must be 0, 64, 128 or 256 (got %d)", c->block_threads);
   if (c->adjoint_window < 0) return set_err(msg, "adjoint_window must be >= 0");
   if (c->adjoint_window > 0 && (c->adjoint_every < 1 || c->adjoint_every > c->adjoint_window))
     return set_err(msg, "adjoint_every must be in 1..adjoint_window");
@@ -137,6 +141,17 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
     if (ns_out) *ns_out = ns;
     return (ns * s - c->r_cut) / 2;
   };
+  const bool want_list = !c->no_pair_list && !c->forces_off;
+  if (k == 0 && want_list) {
+    // with pair lists the MD step stages the brick halo and walks the lists;
+    // the cell walk runs only at rebuilds.  Measured best: cells of side
+    // dx (one-cell stencil) in 2D, dx / 2 in 3D, where a one-cell stencil
+    // would walk ~1000 candidates per particle at each rebuild
+    const int kk = (D == 2) ? 1 : 2;
+    int ns_k;
+    const double m = margin_of(kk, &ns_k);
+    if (m >= 0.5 * c->sigma && min_m * kk >= 2 * ns_k + 1) k = kk;
+  }
   if (k == 0) {
     // fewest candidates per target: the force kernel visits the cells that
     // overlap a cube of side 2 (r_cut + margin) around each target, i.e.
@@ -177,17 +192,20 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   // the Maxwell speed per axis times the interval (the kernel checks the bound)
   const double vfast = c->kT > 0 ? 8.0 * std::sqrt(c->kT / c->mass) : 0.0;
   // with pair lists the margin also widens every list (radius r_cut + 2 m),
-  // so the automatic interval aims at m = r_cut / 8 instead of the largest
+  // so the automatic interval aims at m <= 0.16 r_cut instead of the largest
   // margin the stencil allows
-  const bool want_list = !c->no_pair_list && !c->forces_off;
   int R = c->sort_every;
   if (R == 0) {
     if (m_max <= 0 || !(vfast > 0)) {
       R = 1;
     } else {
-      const double m_aim = want_list ? std::min(m_max, c->r_cut / 8) : m_max;
+      const double m_aim = want_list ? std::min(m_max, 0.16 * c->r_cut) : m_max;
       R = (int)std::floor(m_aim / (vfast * c->dt));
       R = std::max(want_list ? 2 : 1, std::min(R, c->md_steps_per_lattice_step));
+      // as few rebuilds per lattice step as that allows, evenly spaced
+      const int steps = c->md_steps_per_lattice_step;
+      const int nreb = (steps + R - 1) / R;
+      R = (steps + nreb - 1) / nreb;
       if (R * vfast * c->dt > m_max) R = std::max(1, (int)std::floor(m_max / (vfast * c->dt)));
     }
   }
@@ -201,13 +219,25 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   // force bricks
   int BX = c->brick_x, BY = c->brick_y, BZ = c->brick_z;
   const double per_cell = rho * std::pow(L->s, D);
+  // threads per force block (the autotuner also tries 64 and 128)
+  int NT = c->block_threads;
+  if (NT == 0) NT = 256;
+  L->bthreads = NT;
   if (D == 2) {
-    // about 128 targets per block of 256 threads measured best (more blocks
-    // in flight hide the staging latency)
-    const double cells = 128.0 / std::max(per_cell, 0.05);
-    if (BY == 0) BY = cells >= 32 ? 2 : 1;
+    // targets per block: about 3/4 of the threads with pair lists, half for
+    // the cell walk (measured best on the 2D workloads)
+    const double cells = (want_list ? 0.75 * NT : 0.5 * NT) / std::max(per_cell, 0.05);
+    if (BY == 0) BY = cells >= (want_list ? 16 : 32) ? 2 : 1;
     if (BX == 0) BX = std::max(4, std::min(128, (int)std::lround(cells / BY)));
     BZ = 1;
+  } else if (want_list) {
+    // about 3/4 target per thread in a compact brick, which keeps the halo
+    // (staged in LDS) small enough for several blocks per CU
+    const double cells = 0.75 * NT / std::max(per_cell, 0.05);
+    if (BZ == 0) BZ = cells >= 27 ? 3 : (cells >= 8 ? 2 : 1);
+    const int side = std::max(1, (int)std::lround(std::sqrt(cells / BZ)));
+    if (BX == 0) BX = std::min(16, side);
+    if (BY == 0) BY = std::min(16, std::max(1, (int)std::lround(cells / (BZ * BX))));
   } else {
     if (BX == 0 || BY == 0) {
       const double cells = 256.0 / std::max(per_cell, 0.05);
@@ -330,6 +360,7 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   P.cell_side = L->s;
   P.margin = L->margin;
   P.pair_slots = L->kmax;
+  P.block_threads = L->bthreads;
   return true;
 }
 
@@ -533,6 +564,7 @@ Phys make_phys(const mdlg_config* c, const Layout& L) {
   P.BX = L.BX;
   P.BY = L.BY;
   P.BZ = L.BZ;
+  P.bthreads = L.bthreads;
   P.forces_off = c->forces_off ? 1 : 0;
   P.n_rep = (int)L.reps.size();
   P.n_total = (int)L.n_total;

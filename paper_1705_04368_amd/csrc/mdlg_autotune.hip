@@ -1,0 +1,254 @@
+// Empirical autotuner of the launch shapes: times candidate layouts of one
+// configuration on the device (rebuild interval, force-brick extents, pair
+// lists on or off, MD cells per lattice cell) through the public C ABI and
+// keeps the fastest.  Host code only; every candidate runs in the caller's
+// workspace, one after the other.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "mdlg.h"
+
+namespace {
+
+struct Cand {
+  int k, R, bx, by, bz, nolist, nt;
+};
+
+mdlg_config with(const mdlg_config& base, const Cand& c) {
+  mdlg_config x = base;
+  x.md_cell_split = c.k;
+  x.sort_every = c.R;
+  x.brick_x = c.bx;
+  x.brick_y = c.by;
+  x.brick_z = c.bz;
+  x.no_pair_list = c.nolist;
+  x.block_threads = c.nt;
+  return x;
+}
+
+// The layout the library picks for the fields left automatic.
+bool resolve(const mdlg_config& base, const Cand& c, Cand* out, mdlg_layout* lay) {
+  mdlg_layout L{};
+  mdlg_config x = with(base, c);
+  if (mdlg_describe(&x, &L) != MDLG_OK) return false;
+  *out = {L.md_cell_split, L.sort_every, L.brick[0], L.brick[1], L.brick[2], c.nolist,
+          L.block_threads};
+  if (lay) *lay = L;
+  return true;
+}
+
+// Rebuild intervals that split a lattice step into 1..6 equal segments and
+// whose margin (R steps at the fast-speed bound) fits the stencil.
+std::vector<int> interval_candidates(const mdlg_config& base, int k) {
+  std::vector<int> out;
+  const int steps = base.md_steps_per_lattice_step;
+  const double s = (double)(float)(base.lattice_dx / k);
+  const int ns = (int)std::ceil(base.r_cut / s - 1e-12);
+  const double m_max = (ns * s - base.r_cut) / 2;
+  const double vfast = base.kT > 0 ? 8.0 * std::sqrt(base.kT / base.mass) : 0.0;
+  for (int nreb = 1; nreb <= 6; ++nreb) {
+    const int R = (steps + nreb - 1) / nreb;
+    if (R < 2) break;
+    if (vfast > 0 && R * vfast * base.dt > m_max) continue;
+    if (std::find(out.begin(), out.end(), R) == out.end()) out.push_back(R);
+  }
+  return out;
+}
+
+// Block sizes of 64, 128 and 256 threads, each with bricks of about 3/4, 1
+// and 3/2 targets per thread in a few shapes.
+std::vector<Cand> brick_candidates(const mdlg_config& base, const Cand& c, double per_cell) {
+  std::vector<Cand> out;
+  const int D = base.dim;
+  const double pc = std::max(per_cell, 0.05);
+  for (int nt : {64, 128, 256}) {
+    if (base.block_threads && nt != base.block_threads) continue;
+    for (double f : {0.75, 1.0, 1.5}) {
+      const double cells = f * nt / pc;
+      if (D == 2) {
+        for (int by : {1, 2}) {
+          const int bx = std::max(2, (int)std::lround(cells / by));
+          if (bx > 128) continue;
+          out.push_back({c.k, c.R, bx, by, 1, c.nolist, nt});
+        }
+      } else {
+        for (int bz : {1, 2, 3}) {
+          const int side = std::max(1, (int)std::lround(std::sqrt(cells / bz)));
+          const int by = std::max(1, (int)std::lround(cells / (bz * side)));
+          out.push_back({c.k, c.R, std::min(16, side), std::min(16, by), bz, c.nolist, nt});
+        }
+      }
+    }
+  }
+  return out;
+}
+
+struct Timer {
+  const mdlg_config* base;
+  void* ws;
+  size_t ws_bytes;
+  hipStream_t stream;
+  const float* pos;
+  const float* vel;
+  int lattice_steps;
+  hipEvent_t a = nullptr, b = nullptr;
+  int tried = 0;
+
+  // ms per MD step of candidate c, or a negative value when it does not run.
+  double time(const Cand& c) {
+    mdlg_config x = with(*base, c);
+    size_t need = 0;
+    if (mdlg_workspace_bytes(&x, &need) != MDLG_OK || need > ws_bytes) return -1;
+    mdlg_system* S = nullptr;
+    if (mdlg_create(&x, ws, ws_bytes, stream, pos, vel, &S) != MDLG_OK) return -1;
+    ++tried;
+    double ms = -1;
+    float el = 0.f;
+    // two lattice steps capture the step graphs and fill the caches
+    if (mdlg_coarse_grain(S, 2) == MDLG_OK && mdlg_sync(S) == MDLG_OK &&
+        hipEventRecord(a, stream) == hipSuccess && mdlg_coarse_grain(S, lattice_steps) == MDLG_OK &&
+        hipEventRecord(b, stream) == hipSuccess && mdlg_sync(S) == MDLG_OK &&
+        hipEventElapsedTime(&el, a, b) == hipSuccess)
+      ms = el / ((double)lattice_steps * base->md_steps_per_lattice_step);
+    mdlg_destroy(S);
+    return ms;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+mdlg_status mdlg_autotune_workspace_bytes(const mdlg_config* cfg, size_t* bytes) {
+  if (!cfg || !bytes) return MDLG_E_INVALID;
+  mdlg_layout L0{};
+  if (mdlg_describe(cfg, &L0) != MDLG_OK) return MDLG_E_INVALID;
+  size_t best = 0;
+  std::vector<int> ks;
+  if (cfg->md_cell_split) ks.push_back(cfg->md_cell_split);
+  else for (int k = 1; k <= 8; k *= 2) ks.push_back(k);
+  for (int k : ks) {
+    for (int nolist : {0, 1}) {
+      Cand c{k, cfg->sort_every, cfg->brick_x, cfg->brick_y, cfg->brick_z, nolist,
+             cfg->block_threads};
+      Cand r{};
+      mdlg_layout L{};
+      if (!resolve(*cfg, c, &r, &L)) continue;
+      std::vector<int> Rs = cfg->sort_every ? std::vector<int>{cfg->sort_every}
+                                            : interval_candidates(*cfg, k);
+      Rs.push_back(r.R);
+      const double per_cell = (double)L.n_total / (double)L.n_cells;
+      for (int R : Rs) {
+        Cand cr = r;
+        cr.R = R;
+        std::vector<Cand> bs = (cfg->brick_x || cfg->brick_y || cfg->brick_z)
+                                   ? std::vector<Cand>{cr}
+                                   : brick_candidates(*cfg, cr, per_cell);
+        for (int nt : {64, 128, 256}) {
+          Cand cn = cr;
+          cn.nt = nt;
+          bs.push_back(cn);
+        }
+        bs.push_back(cr);
+        for (const Cand& cb : bs) {
+          mdlg_config x = with(*cfg, cb);
+          size_t need = 0;
+          if (mdlg_workspace_bytes(&x, &need) == MDLG_OK) best = std::max(best, need);
+        }
+      }
+    }
+  }
+  if (best == 0) return MDLG_E_INVALID;
+  *bytes = best;
+  return MDLG_OK;
+}
+
+mdlg_status mdlg_autotune(const mdlg_config* cfg, void* workspace_dev, size_t workspace_bytes,
+                          void* hip_stream, const float* pos_dev, const float* vel_dev,
+                          int32_t md_steps, mdlg_config* best, double* best_ms_per_md_step) {
+  if (!cfg || !workspace_dev || !pos_dev || !vel_dev || !best || md_steps < 1) return MDLG_E_INVALID;
+  mdlg_layout L0{};
+  if (mdlg_describe(cfg, &L0) != MDLG_OK) return MDLG_E_INVALID;
+  Timer T{cfg, workspace_dev, workspace_bytes, static_cast<hipStream_t>(hip_stream), pos_dev,
+          vel_dev, std::max(1, (md_steps + cfg->md_steps_per_lattice_step - 1) /
+                                   cfg->md_steps_per_lattice_step)};
+  if (hipEventCreate(&T.a) != hipSuccess || hipEventCreate(&T.b) != hipSuccess) return MDLG_E_DEVICE;
+  const bool auto_k = cfg->md_cell_split == 0, auto_R = cfg->sort_every == 0;
+  const bool auto_brick = !cfg->brick_x && !cfg->brick_y && !cfg->brick_z;
+  const bool auto_nt = cfg->block_threads == 0;
+  const double per_cell = (double)L0.n_total / (double)L0.n_cells;
+
+  Cand cur{};
+  double cur_ms = -1;
+  auto consider = [&](const Cand& c) {
+    const double ms = T.time(c);
+    if (ms > 0 && (cur_ms < 0 || ms < cur_ms)) {
+      cur = c;
+      cur_ms = ms;
+    }
+  };
+  // the automatic layout, with and without pair lists
+  for (int nolist : {cfg->no_pair_list, 1}) {
+    Cand c{cfg->md_cell_split, cfg->sort_every, cfg->brick_x, cfg->brick_y, cfg->brick_z, nolist,
+           cfg->block_threads};
+    Cand r{};
+    if (resolve(*cfg, c, &r, nullptr)) consider(r);
+    if (cfg->no_pair_list) break;
+  }
+  if (cur_ms < 0) {
+    (void)hipEventDestroy(T.a);
+    (void)hipEventDestroy(T.b);
+    return MDLG_E_DEVICE;
+  }
+  // MD cells per lattice cell (automatic layout for each)
+  if (auto_k) {
+    const Cand base = cur;
+    for (int k = 1; k <= 8; k *= 2) {
+      if (k == base.k) continue;
+      Cand c{k, cfg->sort_every, cfg->brick_x, cfg->brick_y, cfg->brick_z, base.nolist,
+             cfg->block_threads};
+      Cand r{};
+      if (resolve(*cfg, c, &r, nullptr)) consider(r);
+    }
+  }
+  // rebuild interval, then brick extents, each around the best so far
+  if (auto_R) {
+    const Cand base = cur;
+    for (int R : interval_candidates(*cfg, base.k)) {
+      if (R == base.R) continue;
+      Cand c = base;
+      c.R = R;
+      consider(c);
+    }
+  }
+  if (auto_brick) {
+    const Cand base = cur;
+    mdlg_layout L{};
+    mdlg_config x = with(*cfg, base);
+    const double pc = (mdlg_describe(&x, &L) == MDLG_OK) ? (double)L.n_total / (double)L.n_cells
+                                                          : per_cell;
+    for (const Cand& c : brick_candidates(*cfg, base, pc)) {
+      if (c.bx == base.bx && c.by == base.by && c.bz == base.bz && c.nt == base.nt) continue;
+      consider(c);
+    }
+  } else if (auto_nt) {
+    const Cand base = cur;
+    for (int nt : {64, 128, 256}) {
+      if (nt == base.nt) continue;
+      Cand c = base;
+      c.nt = nt;
+      consider(c);
+    }
+  }
+  (void)hipEventDestroy(T.a);
+  (void)hipEventDestroy(T.b);
+  *best = with(*cfg, cur);
+  if (best_ms_per_md_step) *best_ms_per_md_step = cur_ms;
+  return MDLG_OK;
+}
+
+}  // extern "C"

@@ -80,6 +80,7 @@ struct Phys {
   int Q;
   int nm;           // per-site moments
   int BX, BY, BZ;   // brick extent
+  int bthreads;     // threads per block of the force and pair-list kernels (64, 128, 256)
   int forces_off;
   int n_rep;
   int n_total;

@@ -146,6 +146,7 @@ __device__ __forceinline__ bool canon(float& o, int& c, int& im, int mc, float s
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
 // Exclusive scan of one int per thread over the block; *total gets the sum.
+template <int NW = kWaves>
 __device__ __forceinline__ int block_excl_scan(int v, int* s_tmp, int* total) {
   const int lane = lane_id(), w = threadIdx.x >> 6;
   int incl = v;
@@ -158,16 +159,16 @@ __device__ __forceinline__ int block_excl_scan(int v, int* s_tmp, int* total) {
   __syncthreads();
   if (threadIdx.x == 0) {
     int run = 0;
-    for (int i = 0; i < kWaves; ++i) {
+    for (int i = 0; i < NW; ++i) {
       int t = s_tmp[i];
       s_tmp[i] = run;
       run += t;
     }
-    s_tmp[kWaves] = run;
+    s_tmp[NW] = run;
   }
   __syncthreads();
   const int excl = incl - v + s_tmp[w];
-  *total = s_tmp[kWaves];
+  *total = s_tmp[NW];
   __syncthreads();
   return excl;
 }
@@ -445,7 +446,7 @@ __device__ __forceinline__ int fixed_coord(int h, float off, const Phys& P) {
 // Halo table of a brick: particle count of every halo cell, exclusive scan
 // into L.hs (LDS starts), global starts into L.gs, and the prefix of the
 // brick's rows of targets into L.rowpre.
-template <int D, class Lds>
+template <int D, int NT, class Lds>
 __device__ __forceinline__ BrickGeom brick_setup(const Phys& P, const Replica& R, const int4 br,
                                                  const int* __restrict__ cell_start, Lds& L) {
   BrickGeom G;
@@ -461,7 +462,7 @@ __device__ __forceinline__ BrickGeom brick_setup(const Phys& P, const Replica& R
   G.HY = G.wy + 2 * G.ns;
   G.HZ = G.wz + 2 * G.nsz;
   G.nh = G.HX * G.HY * G.HZ;
-  const int ipt = (G.nh + kBlock - 1) / kBlock;
+  const int ipt = (G.nh + NT - 1) / NT;
   const int h0 = threadIdx.x * ipt, h1 = min(G.nh, h0 + ipt);
   int mysum = 0;
   for (int h = h0; h < h1; ++h) {
@@ -475,7 +476,7 @@ __device__ __forceinline__ BrickGeom brick_setup(const Phys& P, const Replica& R
     L.hs[h] = en - st;
     mysum += en - st;
   }
-  int run = block_excl_scan(mysum, L.tmp, &G.total);
+  int run = block_excl_scan<NT / 64>(mysum, L.tmp, &G.total);
   for (int h = h0; h < h1; ++h) {
     const int cnt = L.hs[h];
     L.hs[h] = run;
@@ -523,16 +524,16 @@ __device__ __forceinline__ int pack_halo(int hx, int hy, int hz) {
   return hx | (hy << 8) | (hz << 16);
 }
 
-template <int D, class Lds>
+template <int D, int NT, class Lds>
 __device__ __forceinline__ void brick_stage(const BrickGeom& G, const Phys& P,
                                             const float* __restrict__ pos, const float* __restrict__ lam,
                                             Lds& L, int cb, int ce, int2* __restrict__ smap = nullptr) {
-  for (int v0 = cb + (int)threadIdx.x; v0 < ce; v0 += 4 * kBlock) {
+  for (int v0 = cb + (int)threadIdx.x; v0 < ce; v0 += 4 * NT) {
     int hh[4], g[4];
     float p[4][D];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int v = v0 + u * kBlock;
+      const int v = v0 + u * NT;
       int lo = 0;
       if (v < ce) {
         int hi = G.nh - 1;
@@ -546,10 +547,10 @@ __device__ __forceinline__ void brick_stage(const BrickGeom& G, const Phys& P,
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (v0 + u * kBlock < ce) ldv<D>(pos, g[u], p[u]);
+      if (v0 + u * NT < ce) ldv<D>(pos, g[u], p[u]);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int v = v0 + u * kBlock;
+      const int v = v0 + u * NT;
       if (v < ce) {
         const int hx = hh[u] % G.HX, r = hh[u] / G.HX;
         if constexpr (D == 2)
@@ -728,12 +729,13 @@ __device__ __forceinline__ void list_word(const Lds& L, unsigned long long e, in
   for (int u = 0; u < 4; ++u) lj_pair<D>(q[u], X, Y, Z, P, f);
 }
 
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
+template <int D, int NT>
+__global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
   extern __shared__ __align__(16) char s_dyn_brick[];
   __shared__ int s_rowpre[kMaxRows + 1];
-  __shared__ int s_tmp[kWaves + 1];
-  __shared__ double s_red[kWaves][4];
+  constexpr int NW = NT / 64;
+  __shared__ int s_tmp[NW + 1];
+  __shared__ double s_red[NW][4];
   auto L = brick_lds<D, false>(s_dyn_brick, s_rowpre, s_tmp, s_red, a.P);
   const int CAP = L.cap;
   int b = blockIdx.x;
@@ -758,18 +760,18 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
     // builder (targets first), then each target walks its own list
     const int2* __restrict__ smap = a.smap + (size_t)b * CAP;
     const int total = bi.x, ntg = bi.y;
-    for (int v0 = (int)threadIdx.x; v0 < total; v0 += 2 * kBlock) {
+    for (int v0 = (int)threadIdx.x; v0 < total; v0 += 2 * NT) {
       int2 e[2];
       float p[2][D];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int v = v0 + u * kBlock;
+        const int v = v0 + u * NT;
         e[u] = smap[min(v, total - 1)];
         ldv<D>(a.pos_in, e[u].x, p[u]);
       }
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int v = v0 + u * kBlock;
+        const int v = v0 + u * NT;
         if (v < total) {
           const int hx = e[u].y & 255, hy = (e[u].y >> 8) & 255;
           if constexpr (D == 2)
@@ -782,7 +784,7 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
     }
     __syncthreads();
     const size_t nt = (size_t)P.n_total;
-    for (int tb = 0; tb < ntg; tb += kBlock) {
+    for (int tb = 0; tb < ntg; tb += NT) {
       const int t = tb + (int)threadIdx.x;
       if (t >= ntg) break;
       const int2 e = smap[t];
@@ -820,13 +822,13 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
     }
   } else {
     const Replica R = a.reps[br.x];
-    const BrickGeom G = brick_setup<D>(P, R, br, a.cell_start, L);
+    const BrickGeom G = brick_setup<D, NT>(P, R, br, a.cell_start, L);
     const int nchunks = (G.total + CAP - 1) / CAP;
     if (interact && nchunks == 1) {
-      brick_stage<D>(G, P, a.pos_in, nullptr, L, 0, G.total);
+      brick_stage<D, NT>(G, P, a.pos_in, nullptr, L, 0, G.total);
       __syncthreads();
     }
-    for (int tb = 0; tb < G.ntg; tb += kBlock) {
+    for (int tb = 0; tb < G.ntg; tb += NT) {
       const int t = tb + (int)threadIdx.x;
       const bool valid = t < G.ntg;
       int hxi = G.ns, hyi = G.ns, hzi = G.nsz, gi = 0, vi = 0;
@@ -851,7 +853,7 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
           const int cb = ci * CAP, ce = min(G.total, cb + CAP);
           if (nchunks > 1) {
             __syncthreads();
-            brick_stage<D>(G, P, a.pos_in, nullptr, L, cb, ce);
+            brick_stage<D, NT>(G, P, a.pos_in, nullptr, L, cb, ce);
             __syncthreads();
           }
           if (valid) {
@@ -889,7 +891,7 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
     __syncthreads();
     if (threadIdx.x <= D) {
       double s = 0.0;
-      for (int i = 0; i < kWaves; ++i) s += L.red[i][threadIdx.x];
+      for (int i = 0; i < NW; ++i) s += L.red[i][threadIdx.x];
       a.kpart[(size_t)b * (D + 1) + threadIdx.x] = s;
     }
   }
@@ -930,12 +932,13 @@ __device__ __forceinline__ void list_push(unsigned long long*& wp, unsigned long
   }
 }
 
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_nlist(NlistArgs a) {
+template <int D, int NT>
+__global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
   extern __shared__ __align__(16) char s_dyn_brick[];
   __shared__ int s_rowpre[kMaxRows + 1];
-  __shared__ int s_tmp[kWaves + 1];
-  __shared__ double s_red[kWaves][4];
+  constexpr int NW = NT / 64;
+  __shared__ int s_tmp[NW + 1];
+  __shared__ double s_red[NW][4];
   __shared__ int s_over;
   auto L = brick_lds<D, false>(s_dyn_brick, s_rowpre, s_tmp, s_red, a.P);
   const int CAP = L.cap;
@@ -949,15 +952,15 @@ __global__ __launch_bounds__(kBlock) void k_nlist(NlistArgs a) {
   const int4 br = a.bricks[b];
   const Replica R = a.reps[br.x];
   if (threadIdx.x == 0) s_over = 0;
-  const BrickGeom G = brick_setup<D>(P, R, br, a.cell_start, L);
+  const BrickGeom G = brick_setup<D, NT>(P, R, br, a.cell_start, L);
   const bool fits = G.total <= CAP;
   int2* __restrict__ smap = a.smap + (size_t)b * CAP;
-  if (fits) brick_stage<D>(G, P, a.pos, nullptr, L, 0, G.total, smap);
+  if (fits) brick_stage<D, NT>(G, P, a.pos, nullptr, L, 0, G.total, smap);
   __syncthreads();
   const size_t nt = (size_t)P.n_total;
   const int kmax = P.kmax;
   const float rl2 = P.rl2_u;
-  for (int tb = 0; tb < G.ntg; tb += kBlock) {
+  for (int tb = 0; tb < G.ntg; tb += NT) {
     const int t = tb + (int)threadIdx.x;
     if (t >= G.ntg) break;
     int hxi, hyi, hzi, gi, vi;
@@ -988,23 +991,29 @@ __global__ __launch_bounds__(kBlock) void k_nlist(NlistArgs a) {
         const int s1 = list_shift(G, L, G.ns, cy, cz);
         const int s2 = list_shift(G, L, G.ns + G.wx, cy, cz);
         const int jhi = L.hs[hrow + cx1 + 1];
-        int j = L.hs[hrow + cx0];
-        for (; j + 3 < jhi; j += 4) {
-          // four LDS reads in flight before the tests
-          Coord<D> q[4];
+        // test up to 32 candidates into a bit mask (four LDS reads in flight),
+        // then append the accepted ones: the appends cost per accepted entry
+        // rather than per candidate
+        for (int j0 = L.hs[hrow + cx0]; j0 < jhi; j0 += 32) {
+          const int nb = min(32, jhi - j0);
+          unsigned mask = 0;
+          int u = 0;
+          for (; u + 3 < nb; u += 4) {
+            Coord<D> q[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) q[u] = L.p[j + u];
-          bool in[4];
+            for (int e = 0; e < 4; ++e) q[e] = L.p[j0 + u + e];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) in[u] = list_near<D>(q[u], X, Y, Z, rl2) && (j + u != vi);
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (in[u]) list_push(wp, word, cnt, seen, j + u + (j + u < ja ? s0 : (j + u < jb ? s1 : s2)),
-                                 kmax, nt);
-        }
-        for (; j < jhi; ++j)
-          if (list_near<D>(L.p[j], X, Y, Z, rl2) && j != vi)
+            for (int e = 0; e < 4; ++e) mask |= (unsigned)list_near<D>(q[e], X, Y, Z, rl2) << (u + e);
+          }
+          for (; u < nb; ++u) mask |= (unsigned)list_near<D>(L.p[j0 + u], X, Y, Z, rl2) << u;
+          const unsigned self = (unsigned)(vi - j0);
+          if (self < 32u) mask &= ~(1u << self);
+          while (mask) {
+            const int j = j0 + __builtin_ctz(mask);
+            mask &= mask - 1;
             list_push(wp, word, cnt, seen, j + (j < ja ? s0 : (j < jb ? s1 : s2)), kmax, nt);
+          }
+        }
       }
     }
     if (seen > kmax) s_over = 1;
@@ -1046,11 +1055,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs a) {
   const Phys& P = a.P;
   const int4 br = a.bricks[b];
   const Replica R = a.reps[br.x];
-  const BrickGeom G = brick_setup<D>(P, R, br, a.cell_start, L);
+  const BrickGeom G = brick_setup<D, kBlock>(P, R, br, a.cell_start, L);
   const int nchunks = (G.total + CAP - 1) / CAP;
   const bool interact = !P.forces_off;
   if (interact && nchunks == 1) {
-    brick_stage<D>(G, P, a.pos, a.lam_v_in, L, 0, G.total);
+    brick_stage<D, kBlock>(G, P, a.pos, a.lam_v_in, L, 0, G.total);
     __syncthreads();
   }
   double ge = 0.0, gs = 0.0;
@@ -1081,7 +1090,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs a) {
         const int cb = ci * CAP, ce = min(G.total, cb + CAP);
         if (nchunks > 1) {
           __syncthreads();
-          brick_stage<D>(G, P, a.pos, a.lam_v_in, L, cb, ce);
+          brick_stage<D, kBlock>(G, P, a.pos, a.lam_v_in, L, cb, ce);
           __syncthreads();
         }
         if (valid) {
@@ -1326,7 +1335,6 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs a) {
       cell_coords<D>(a.cell[g] - R.cell_off, R, c);
       ldi<D>(a.img, g, im);
       ldv<D>(a.pos, g, o);
-      const int pid = a.id[g];
 #pragma unroll
       for (int q = 0; q < D; ++q) u[q] = c[q] + R.Mc[q] * im[q];
       if (!a.snapshot_only) {
@@ -1563,16 +1571,31 @@ size_t brick_lds_bytes(const Phys& P, int D, bool adj) {
   return head + (size_t)P.lcap * (coord + (adj ? D * sizeof(float) : 0));
 }
 
+// Brick kernels come in 64-, 128- and 256-thread blocks (P.bthreads).
+#define MDLG_LAUNCH_BRICK(D, NT, kern, grid, lds, stream, args)                           \
+  do {                                                                                    \
+    if ((NT) == 64) {                                                                     \
+      if ((D) == 2) hipLaunchKernelGGL((kern<2, 64>), dim3(grid), dim3(64), lds, stream, args);   \
+      else hipLaunchKernelGGL((kern<3, 64>), dim3(grid), dim3(64), lds, stream, args);            \
+    } else if ((NT) == 128) {                                                             \
+      if ((D) == 2) hipLaunchKernelGGL((kern<2, 128>), dim3(grid), dim3(128), lds, stream, args); \
+      else hipLaunchKernelGGL((kern<3, 128>), dim3(grid), dim3(128), lds, stream, args);          \
+    } else {                                                                              \
+      if ((D) == 2) hipLaunchKernelGGL((kern<2, 256>), dim3(grid), dim3(256), lds, stream, args); \
+      else hipLaunchKernelGGL((kern<3, 256>), dim3(grid), dim3(256), lds, stream, args);          \
+    }                                                                                     \
+  } while (0)
+
 void launch_force(int D, const ForceArgs& a, hipStream_t s) {
   int grid = a.nbricks;
   if (a.xcd_remap) grid = ((a.nbricks + 7) / 8) * 8;
-  MDLG_LAUNCH_DIM(D, k_force, grid, brick_lds_bytes(a.P, D, false), s, a);
+  MDLG_LAUNCH_BRICK(D, a.P.bthreads, k_force, grid, brick_lds_bytes(a.P, D, false), s, a);
 }
 
 void launch_nlist(int D, const NlistArgs& a, hipStream_t s) {
   int grid = a.nbricks;
   if (a.xcd_remap) grid = ((a.nbricks + 7) / 8) * 8;
-  MDLG_LAUNCH_DIM(D, k_nlist, grid, brick_lds_bytes(a.P, D, false), s, a);
+  MDLG_LAUNCH_BRICK(D, a.P.bthreads, k_nlist, grid, brick_lds_bytes(a.P, D, false), s, a);
 }
 
 void launch_kin(const KinArgs& a, hipStream_t s) {

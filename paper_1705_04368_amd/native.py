@@ -21,7 +21,8 @@ STATUS = {0: "MDLG_OK", -1: "MDLG_E_INVALID", -2: "MDLG_E_DEVICE", -3: "MDLG_E_N
 EXPORTED = ["mdlg_describe", "mdlg_workspace_bytes", "mdlg_create", "mdlg_step",
             "mdlg_coarse_grain", "mdlg_get_f", "mdlg_get_kinetics", "mdlg_reset_accumulators",
             "mdlg_get_state", "mdlg_set_state", "mdlg_adjoint", "mdlg_set_potential",
-            "mdlg_set_timing", "mdlg_get_timing", "mdlg_sync", "mdlg_last_error", "mdlg_destroy"]
+            "mdlg_set_timing", "mdlg_get_timing", "mdlg_sync", "mdlg_last_error", "mdlg_destroy",
+            "mdlg_autotune", "mdlg_autotune_workspace_bytes"]
 LOSSES = {"msd": 0, "mean_x": 1}
 KERNEL_CLASSES = ["force", "count", "scan", "scatter", "bin", "nlist"]
 
@@ -36,7 +37,7 @@ class MdlgConfig(C.Structure):
                 ("md_cell_split", C.c_int32), ("sort_every", C.c_int32),
                 ("brick_x", C.c_int32), ("brick_y", C.c_int32), ("brick_z", C.c_int32),
                 ("adjoint_window", C.c_int32), ("adjoint_every", C.c_int32),
-                ("no_pair_list", C.c_int32)]
+                ("no_pair_list", C.c_int32), ("block_threads", C.c_int32)]
 
 
 class MdlgParticles(C.Structure):
@@ -50,7 +51,7 @@ class MdlgLayout(C.Structure):
                 ("stencil", C.c_int32), ("n_velocities", C.c_int32), ("n_moments", C.c_int32),
                 ("brick", C.c_int32 * 3), ("n_total", C.c_int64), ("n_sites", C.c_int64),
                 ("n_cells", C.c_int64), ("n_bricks", C.c_int64), ("cell_side", C.c_double),
-                ("margin", C.c_double), ("pair_slots", C.c_int32)]
+                ("margin", C.c_double), ("pair_slots", C.c_int32), ("block_threads", C.c_int32)]
 
 
 _lib = None
@@ -108,6 +109,11 @@ def load():
     lib.mdlg_last_error.argtypes = [C.c_void_p]
     lib.mdlg_destroy.restype = None
     lib.mdlg_destroy.argtypes = [C.c_void_p]
+    lib.mdlg_autotune.restype = st
+    lib.mdlg_autotune.argtypes = [P(MdlgConfig), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_int32, P(MdlgConfig), P(C.c_double)]
+    lib.mdlg_autotune_workspace_bytes.restype = st
+    lib.mdlg_autotune_workspace_bytes.argtypes = [P(MdlgConfig), P(C.c_size_t)]
     _lib = lib
     return lib
 
@@ -127,7 +133,7 @@ def _check(status, handle=None):
 def make_config(dim, n_particles, lattice, lattice_dx=4.0, epsilon=1.0, sigma=1.0, mass=1.0,
                 r_cut=2.5, forces_off=False, dt=0.005, md_steps_per_lattice_step=20, vmax=3,
                 thermostat_every=0, kT=1.0, md_cell_split=0, sort_every=0, brick=(0, 0, 0),
-                adjoint_window=0, adjoint_every=1, pair_list=True):
+                adjoint_window=0, adjoint_every=1, pair_list=True, block_threads=0):
     """Build an MdlgConfig.  n_particles: int or sequence per replica; lattice:
     sites per axis, an int, a (dim,) sequence or an (n_replicas, dim) array."""
     n = np.atleast_1d(np.asarray(n_particles, dtype=np.int32))
@@ -158,6 +164,7 @@ def make_config(dim, n_particles, lattice, lattice_dx=4.0, epsilon=1.0, sigma=1.
     cfg.adjoint_window = adjoint_window
     cfg.adjoint_every = adjoint_every if adjoint_window else 0
     cfg.no_pair_list = 0 if pair_list else 1
+    cfg.block_threads = block_threads
     return cfg
 
 
@@ -168,13 +175,39 @@ def describe(cfg):
             "stencil": out.stencil, "n_velocities": out.n_velocities,
             "n_moments": out.n_moments, "brick": tuple(out.brick), "n_total": out.n_total,
             "n_sites": out.n_sites, "n_cells": out.n_cells, "n_bricks": out.n_bricks,
-            "cell_side": out.cell_side, "margin": out.margin, "pair_slots": out.pair_slots}
+            "cell_side": out.cell_side, "margin": out.margin, "pair_slots": out.pair_slots,
+            "block_threads": out.block_threads}
 
 
 def workspace_bytes(cfg):
     b = C.c_size_t(0)
     _check(load().mdlg_workspace_bytes(C.byref(cfg), C.byref(b)))
     return int(b.value)
+
+
+def autotune(cfg, pos, vel, md_steps=100, stream=None):
+    """Time candidate launch shapes of cfg on the device (mdlg_autotune) from
+    the state pos, vel (float32 device tensors, as for System) and return
+    (tuned config, ms per MD step).  Fields of cfg left at 0 are tuned."""
+    import torch
+    lib = load()
+    b = C.c_size_t(0)
+    _check(lib.mdlg_autotune_workspace_bytes(C.byref(cfg), C.byref(b)))
+    nbytes = int(b.value)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=pos.device)
+    aligned = (ws.data_ptr() + 255) & ~255
+    if stream is None:
+        stream = torch.cuda.current_stream(pos.device)
+    pos = pos.contiguous()
+    vel = vel.contiguous()
+    best = MdlgConfig()
+    ms = C.c_double(0.0)
+    _check(lib.mdlg_autotune(C.byref(cfg), C.c_void_p(aligned), C.c_size_t(nbytes),
+                             C.c_void_p(stream.cuda_stream), C.c_void_p(pos.data_ptr()),
+                             C.c_void_p(vel.data_ptr()), int(md_steps), C.byref(best), C.byref(ms)))
+    best._keep = getattr(cfg, "_keep", None)  # the replica arrays stay alive with the copy
+    del ws
+    return best, float(ms.value)
 
 
 def _fp(a):

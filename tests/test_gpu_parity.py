@@ -399,3 +399,26 @@ def test_pair_list_displacement_is_checked():
         sysg.sync()
     assert e.value.status == -4
     assert "pair lists" in str(e.value)
+
+
+# ------------------------------------------------------------------ autotuner
+
+def test_autotuned_layout_runs_the_same_trajectory():
+    import torch
+
+    from paper_1705_04368_amd import autotune, describe
+    cfg, pos, vel, box, n, M = _force_case(2, 79, 0, equil_steps=300)
+    say("autotune")
+    d = torch.device("cuda:0")
+    best, ms = autotune(cfg, torch.from_numpy(pos).to(d), torch.from_numpy(vel).to(d), md_steps=40)
+    lay = describe(best)
+    say(f"  tuned {lay} at {ms * 1e3:.2f} us per MD step")
+    assert ms > 0
+    sysg = make_system(best, pos, vel)
+    sysg.step(20)
+    st = sysg.get_state()
+    md = oracle.make_md(2, n, box, dt=0.005)
+    ost = oracle.OracleState(md, pos, vel)
+    ost.run(20)
+    assert np.abs(unwrapped(st, lay["cell_side"]) - ost.unwrapped).max() <= 1e-4
+    assert np.abs(st["vel"].astype(np.float64) - ost.v).max() <= 1e-4
