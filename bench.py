@@ -58,12 +58,24 @@ def pairs_per_particle(dim, rho, rc=2.5):
     return math.pi * rc * rc * rho if dim == 2 else 4.0 / 3.0 * math.pi * rc ** 3 * rho
 
 
-def sort_bytes_per_particle(dim):
-    """Algorithmic HBM bytes per particle of one cell-list rebuild: read
-    offsets, velocity, image, id, cell; write the key/slot word; read it back
-    and write the permuted offsets, velocity, image, id, cell."""
-    state = 4 * dim * 3 + 8          # off, vel, img + id, cell
-    return state + 8 + 8 + state     # read state, write key+slot, read key+slot, write state
+def count_bytes_per_particle(dim):
+    """Algorithmic HBM bytes per particle of the counting pass of a cell-list
+    rebuild: read offset, image and cell; write the key/slot word."""
+    return 4 * dim * 2 + 4 + 8
+
+
+def scatter_bytes_per_particle(dim):
+    """Algorithmic HBM bytes per particle of the permutation pass: read the
+    key/slot word, offset, image, cell, velocity, id and the lattice snapshot
+    (unwrapped cell, offset); write all of it at the new slot."""
+    reads = 8 + 4 * dim * 2 + 4 + 4 * dim + 4 + 8 * dim
+    writes = 4 * dim * 3 + 8 + 8 * dim
+    return reads + writes
+
+
+def scan_bytes_per_cell():
+    """Read and clear the count, write the cell start."""
+    return 12
 
 
 def bin_bytes_per_particle(dim, q, nm, per_site_particles):
@@ -365,10 +377,11 @@ def main():
                           "work_per_launch": work}
         elif k in ("count", "scatter", "scan"):
             if k == "scan":
-                work = 8.0 * lay["n_cells"]
+                work = scan_bytes_per_cell() * lay["n_cells"]
+            elif k == "count":
+                work = n * count_bytes_per_particle(dim)
             else:
-                half = sort_bytes_per_particle(dim) / 2
-                work = n * half
+                work = n * scatter_bytes_per_particle(dim)
             ach = work / (avg * 1e-3) / 1e9
             kernels[k] = {"avg_ms": avg, "launches": cnt, "bound": "hbm", "achieved": ach,
                           "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
@@ -389,6 +402,15 @@ def main():
             kernels[k] = {"avg_ms": avg, "launches": cnt, "bound": "hbm", "achieved": ach,
                           "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
                           "work_per_launch": work}
+    if all(k in kernels for k in ("count", "scan", "scatter")):
+        # the rebuild as one unit: its bytes over the summed kernel times
+        work = sum(kernels[k]["work_per_launch"] for k in ("count", "scan", "scatter"))
+        t = sum(kernels[k]["avg_ms"] for k in ("count", "scan", "scatter"))
+        ach = work / (t * 1e-3) / 1e9
+        sort_unit = {"avg_ms": t, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": ach / PEAK_HBM_GBS, "work_per_launch": work}
+    else:
+        sort_unit = None
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     kd = kernels[dom]
     roofline = {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
@@ -421,6 +443,8 @@ def main():
         "plain": plain,
         "kernels": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
+        "sort": None if sort_unit is None else {kk: (round(vv, 6) if isinstance(vv, float) else vv)
+                                                for kk, vv in sort_unit.items()},
     }
     print(json.dumps(out), flush=True)
 

@@ -264,17 +264,21 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
     // dynamic LDS of the brick kernels: the halo cell table of the largest
     // brick and room for about 1.5x the expected halo particles (a fuller
     // halo is staged in several chunks); the adjoint also stages d floats each
+    // (the force and list kernels size it at 1.25x + 64 so that more blocks
+    // fit a CU: the count of a halo of hundreds of cells rarely strays more
+    // than a few percent from its mean, and a brick that overflows takes the
+    // chunked cell walk)
     const double expect = halo * per_cell;
     const size_t head = ((size_t)(2 * halo + 1) * sizeof(int) + 15) & ~size_t(15);
-    long long cap = (long long)std::ceil(1.5 * expect) + 128;
-    cap = (cap + 63) / 64 * 64;
     const size_t coord = (D == 2 ? sizeof(int2) : sizeof(int4));
-    auto fit = [&](size_t per) {
+    auto fit = [&](double grow, long long extra, size_t per) {
+      long long cap = (long long)std::ceil(grow * expect) + extra;
+      cap = (cap + 63) / 64 * 64;
       const long long f = (long long)((kBrickLdsBytes - head) / per) / 64 * 64;
       return (int)std::max<long long>(64, std::min(cap, f));
     };
-    L->lcap = fit(coord);
-    L->lcap_adj = fit(coord + D * sizeof(float));
+    L->lcap = fit(1.25, 64, coord);
+    L->lcap_adj = fit(1.5, 128, coord + D * sizeof(float));
   }
   if (halo > maxh) return set_err(msg, "brick %dx%dx%d with stencil %d needs %lld halo cells > %d",
                                   BX, BY, BZ, L->ns, halo, maxh);
@@ -670,6 +674,8 @@ SortArgs sort_args(mdlg_system* S) {
   a.prev_off_out = S->prev_off[S->scur ^ 1];
   a.err = S->err;
   a.ntiles = S->L.ntiles;
+  a.nchunks = S->L.nchunks;
+  a.xcd_remap = S->xcd_remap;
   return a;
 }
 

@@ -44,6 +44,8 @@ struct SortArgs {
   float* prev_off_out;
   unsigned* err;
   int ntiles;
+  int nchunks;
+  int xcd_remap;
 };
 
 struct ScanArgs {

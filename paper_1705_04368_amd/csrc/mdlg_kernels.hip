@@ -282,11 +282,21 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
   constexpr int kTiles = kHist / kScanTile + 2;
   __shared__ int s_cnt[kHist];
   __shared__ int s_tile[kTiles];
-  const int4 ch = a.chunks[blockIdx.x];
+  // consecutive chunks on one XCD: the per-cell count atomics of neighbouring
+  // chunks then meet in one L2 instead of crossing XCDs
+  int cb = blockIdx.x;
+  if (a.xcd_remap) {
+    const int per = gridDim.x >> 3;
+    cb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  if (cb >= a.nchunks) return;
+  const int4 ch = a.chunks[cb];
   const Replica R = a.reps[ch.x];
-  for (int i = threadIdx.x; i < kHist; i += kBlock) s_cnt[i] = 0;
+  // window: the chunk's old cells (sorted) widened by one row on either side
+  const int lo = a.cell[ch.y] - R.Mc[0] - 1;
+  const int nwin = min(kHist, a.cell[ch.z - 1] + R.Mc[0] + 2 - lo);
+  for (int i = threadIdx.x; i < nwin; i += kBlock) s_cnt[i] = 0;
   if (threadIdx.x < kTiles) s_tile[threadIdx.x] = 0;
-  const int lo = a.cell[ch.y] - R.Mc[0] - 1;  // window start (old cells are sorted)
   __syncthreads();
   int key[kPer], rank[kPer];
   bool inwin[kPer];
@@ -301,7 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
       int c[D], im[D];
       if (!canon_particle<D>(a, R, g, o, c, im)) atomicOr(a.err, kErrJump);
       key[u] = R.cell_off + cell_linear<D>(c, R);
-      inwin[u] = key[u] >= lo && key[u] < lo + kHist;
+      inwin[u] = key[u] >= lo && key[u] < lo + nwin;
       if (inwin[u]) {
         rank[u] = atomicAdd(&s_cnt[key[u] - lo], 1);
       } else {
@@ -312,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
   }
   __syncthreads();
   const int tile0 = lo >= 0 ? lo / kScanTile : 0;
-  for (int i = threadIdx.x; i < kHist; i += kBlock) {
+  for (int i = threadIdx.x; i < nwin; i += kBlock) {
     const int c = s_cnt[i];
     if (c) {
       s_cnt[i] = atomicAdd(a.count + lo + i, c);
@@ -1554,7 +1564,8 @@ void launch_ingest(int D, int nchunks, const IngestArgs& a, hipStream_t s) {
 }
 
 void launch_count(int D, int nchunks, const SortArgs& a, hipStream_t s) {
-  MDLG_LAUNCH_DIM(D, k_count, nchunks, 0, s, a);
+  const int grid = a.xcd_remap ? (nchunks + 7) / 8 * 8 : nchunks;
+  MDLG_LAUNCH_DIM(D, k_count, grid, 0, s, a);
 }
 
 void launch_scan(const ScanArgs& a, hipStream_t s) {
