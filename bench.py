@@ -258,6 +258,8 @@ def main():
     ap.add_argument("--brick", type=int, nargs=3, default=(0, 0, 0), help="force brick (0 = auto)")
     ap.add_argument("--no-pair-list", action="store_true",
                     help="walk the neighbour cells at every MD step instead of using pair lists")
+    ap.add_argument("--collision-stats", action="store_true",
+                    help="also record the collision operator Xi of consecutive lattice steps")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's analytic launch shapes instead of measuring candidates")
     ap.add_argument("--autotune-steps", type=int, default=40, help="MD steps timed per candidate")
@@ -296,7 +298,8 @@ def main():
     w = WORKLOADS[args.workload]
     dim = w["dim"]
     tuning = dict(sort_every=args.sort_every, pair_list=not args.no_pair_list,
-                  md_cell_split=args.md_cell_split, brick=tuple(args.brick))
+                  md_cell_split=args.md_cell_split, brick=tuple(args.brick),
+                  collision_stats=args.collision_stats)
     dev = torch.device("cuda:0")
     if w.get("replicas"):
         n_r, m_r = synth.replica_sizes(w["replicas"], seed=4)
@@ -396,6 +399,14 @@ def main():
             kernels[k] = {"avg_ms": avg, "launches": cnt, "bound": "hbm", "achieved": ach,
                           "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
                           "work_per_launch": work}
+        elif k == "xi":
+            # per (site, bin): n_i(x, t), the shifted n_i(x + v_i, t + 1), the
+            # running sum (read and write) and the latest value
+            work = n_sites * q * (4 + 4 + 16 + 4)
+            ach = work / (avg * 1e-3) / 1e9
+            kernels[k] = {"avg_ms": avg, "launches": cnt, "bound": "hbm", "achieved": ach,
+                          "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                          "work_per_launch": work}
         elif k == "bin":
             work = n * bin_bytes_per_particle(dim, q, nm, per_site)
             ach = work / (avg * 1e-3) / 1e9
@@ -437,7 +448,7 @@ def main():
         "config": {"workload": w["desc"], "lattice_steps": args.steps, "md_steps": md_steps,
                    "md_cell_split": lay["md_cell_split"], "sort_every": lay["sort_every"],
                    "brick": list(lay["brick"]), "pair_slots": lay["pair_slots"],
-                   "autotuned": tuned_ms is not None},
+                   "autotuned": tuned_ms is not None, "collision_stats": args.collision_stats},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plain": plain,

@@ -106,6 +106,9 @@ typedef struct {
                                    at least 2 (results agree to float rounding) */
     int32_t block_threads;      /* threads per block of the force and pair-list kernels:
                                    64, 128 or 256, or 0 = choose automatically */
+    int32_t collision_stats;    /* 1: record the MDLG collision operator Xi (eq. Xi) of
+                                   every pair of consecutive lattice steps (see
+                                   mdlg_get_xi); 0: off */
 } mdlg_config;
 
 /* Particle state in particle-id order (id = index in the concatenated input).
@@ -254,7 +257,8 @@ typedef enum {
     MDLG_K_SCATTER = 3, /* cell-list rebuild: permute the particle state */
     MDLG_K_BIN = 4,     /* MDLG binning and per-site accumulation (eq. MDni) */
     MDLG_K_NLIST = 5,   /* cell-list rebuild: per-particle pair lists */
-    MDLG_K_NCLASS = 6
+    MDLG_K_XI = 6,      /* collision operator of consecutive lattice steps (eq. Xi) */
+    MDLG_K_NCLASS = 7
 } mdlg_kernel_class;
 
 /* Enable (1) or disable (0) per-kernel timing with HIP events on the handle's
@@ -276,6 +280,26 @@ const char *mdlg_last_error(const mdlg_system *sys);
 
 /* Release the handle (the caller still owns the workspace). */
 void mdlg_destroy(mdlg_system *sys);
+
+/* The MDLG collision operator (eq. Xi):
+ *   Xi_i(x, t) = n_i(x + v_i, t + Delta t) - n_i(x, t),
+ * with n_i of eq. (MDni) (arrival site x, lattice velocity v_i, periodic
+ * wrap of x + v_i inside the site's replica).  With collision_stats on, every
+ * mdlg_coarse_grain lattice step after the first of an unbroken chain (the
+ * chain restarts whenever the snapshot is retaken: after mdlg_step,
+ * mdlg_set_state or mdlg_reset_accumulators) evaluates Xi at the previous
+ * lattice time and accumulates, all in exact integers:
+ *   sums      host [5][Q]: over sites and samples, sum Xi_i, sum Xi_i^2,
+ *             sum Xi_i n_i, sum n_i, sum n_i^2 (n_i = n_i(x, t), the
+ *             populations Xi acts on); NULL to skip;
+ *   xi_site   host [n_sites][Q]: per site, sum over samples of Xi_i; or NULL;
+ *   xi_last   host [n_sites][Q]: Xi_i(x, t) of the latest sample; or NULL;
+ *   n_steps   number of samples (lattice times t).
+ * Sum_i Xi_i(x, t) = 0 (eq. Mom0) holds exactly when no particle leaves or
+ * enters x with a displacement outside the velocity window.  Synchronises.
+ * MDLG_E_STATE when collision_stats is off. */
+mdlg_status mdlg_get_xi(mdlg_system *sys, int64_t *sums, int64_t *xi_site, int32_t *xi_last,
+                        int64_t *n_steps);
 
 /* Launch-shape autotuner for batched and single systems (the f_i^eq of
  * eq. fieq are ensemble averages, so the same configuration is typically run

@@ -252,3 +252,32 @@ def window_loss(md, x0, v0, window, loss):
     _check(_load().orc_window_loss(C.byref(md), _dp(x0), _dp(v0), int(window), LOSSES[loss],
                                    C.byref(L)), "window_loss")
     return L.value
+
+
+def bin_velocity(dim, vmax, i):
+    """Lattice velocity of bin i (i = sum_a (v_a + V) (2V + 1)^a, x fastest)."""
+    w = 2 * vmax + 1
+    return tuple((i // w ** a) % w - vmax for a in range(dim))
+
+
+def collision_operator(lattice, dim, n_t, n_next):
+    """The MDLG collision operator of eq. (Xi),
+        Xi_i(x, t) = n_i(x + v_i, t + 1) - n_i(x, t),
+    from the occupation numbers of eq. (MDni) at two consecutive lattice times
+    (arrays [n_sites][Q], site index x fastest) on the periodic lattice.
+    Returns int64 [n_sites][Q]."""
+    M = [int(lattice.M[a]) for a in range(dim)]
+    V = int(lattice.V)
+    Q = (2 * V + 1) ** dim
+    grid = tuple(reversed(M))  # numpy axes (z,) y, x
+    now = np.asarray(n_t, dtype=np.int64).reshape(grid + (Q,))
+    nxt = np.asarray(n_next, dtype=np.int64).reshape(grid + (Q,))
+    xi = np.zeros_like(now)
+    for i in range(Q):
+        v = bin_velocity(dim, V, i)
+        # shifted[x] = n_i(x + v_i, t + 1): roll by -v along every axis
+        shifted = nxt[..., i]
+        for a in range(dim):
+            shifted = np.roll(shifted, -v[a], axis=dim - 1 - a)
+        xi[..., i] = shifted - now[..., i]
+    return xi.reshape(-1, Q)

@@ -46,6 +46,7 @@ struct Layout {
   int lcap_adj = 0;    // the same for the adjoint (stages the adjoint velocity too)
   double per_cell = 0; // mean particles per MD cell
   int kmax = 0;        // pair-list slots per particle (0 = cell walk every step)
+  bool xi = false;     // collision-operator statistics buffers
   int adj_ckpts = 0;   // checkpoints the workspace holds (0 = no adjoint)
   int adj_seg = 0;     // segment positions the workspace holds
 };
@@ -337,6 +338,7 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
     part_off += rep.n;
     site_off += nsite;
   }
+  L->xi = c->collision_stats != 0;
   if (c->adjoint_window > 0) {
     L->adj_ckpts = c->adjoint_window / c->adjoint_every + 1;
     L->adj_seg = c->adjoint_every + 1;
@@ -409,6 +411,15 @@ struct mdlg_system {
   double* fout = nullptr;
   double* dispout = nullptr;
   float* acc_sorted = nullptr;
+  // collision operator (eq. Xi)
+  unsigned* nstep[2] = {nullptr, nullptr};
+  long long* xi_site = nullptr;
+  int* xi_last = nullptr;
+  unsigned long long* xi_sums = nullptr;
+  long long* xi_part = nullptr;
+  int xi_par = 0;         // nstep[xi_par] receives the next lattice step
+  bool xi_have = false;   // nstep[xi_par ^ 1] holds the previous lattice step
+  long long xi_steps = 0;
   // pair lists
   int2* smap = nullptr;
   int4* binfo = nullptr;
@@ -442,8 +453,9 @@ struct mdlg_system {
     hipGraphExec_t exec;
     int pcur, scur, since_sort;
     bool vel_full;
+    int xi_par;
   };
-  std::map<std::tuple<int, int, int, bool, bool>, GraphEntry> graphs;
+  std::map<std::tuple<int, int, int, bool, bool, int, bool>, GraphEntry> graphs;
   // per-kernel event timing (measurement aid)
   bool timing = false;
   struct Timed {
@@ -460,6 +472,10 @@ struct mdlg_system {
 };
 
 namespace {
+
+// Sites per block of the collision-operator kernel, and its block count.
+constexpr int kXiSites = 64;
+int xi_blocks(const Layout& L) { return (int)((L.n_sites + kXiSites - 1) / kXiSites); }
 
 size_t carve(mdlg_system* S, char* base) {
   const Layout& L = S->L;
@@ -497,6 +513,15 @@ size_t carve(mdlg_system* S, char* base) {
   S->fout = c.take<double>(base, kMaxQ);
   S->dispout = c.take<double>(base, 8);
   S->acc_sorted = c.take<float>(base, N * D);
+  if (L.xi) {
+    const size_t sq = (size_t)L.n_sites * L.Q;
+    S->nstep[0] = c.take<unsigned>(base, sq);
+    S->nstep[1] = c.take<unsigned>(base, sq);
+    S->xi_site = c.take<long long>(base, sq);
+    S->xi_last = c.take<int>(base, sq);
+    S->xi_sums = c.take<unsigned long long>(base, (size_t)5 * L.Q);
+    S->xi_part = c.take<long long>(base, (size_t)xi_blocks(L) * 5 * L.Q);
+  }
   if (L.kmax > 0) {
     S->smap = c.take<int2>(base, (size_t)L.nbricks * L.lcap);
     S->binfo = c.take<int4>(base, (size_t)L.nbricks);
@@ -801,6 +826,7 @@ void enqueue_bin(mdlg_system* S, bool snapshot_only) {
   b.err = S->err;
   b.snapshot_only = snapshot_only ? 1 : 0;
   b.BSX = S->L.BSX;
+  b.nstep = (S->L.xi && !snapshot_only) ? S->nstep[S->xi_par] : nullptr;
   {
     TimedLaunch t(S, MDLG_K_BIN);
     launch_bin(S->D, S->L.nstrips, b, S->stream);
@@ -811,12 +837,41 @@ void enqueue_snapshot(mdlg_system* S) {
   if (S->since_sort != 0) enqueue_sort(S);
   enqueue_bin(S, true);
   S->snapshot_valid = true;
+  S->xi_have = false;  // a new chain of lattice steps starts here
+}
+
+// Xi of the previous lattice step from its arrivals and this step's.
+void enqueue_xi(mdlg_system* S) {
+  XiArgs x{};
+  x.reps = S->reps;
+  x.ncur = S->nstep[S->xi_par];
+  x.nprev = S->nstep[S->xi_par ^ 1];
+  x.xi_site = S->xi_site;
+  x.xi_last = S->xi_last;
+  x.sums = S->xi_sums;
+  x.part = S->xi_part;
+  x.n_sites = (int)S->L.n_sites;
+  x.sites_per_block = kXiSites;
+  x.nblocks = xi_blocks(S->L);
+  x.n_rep = (int)S->L.reps.size();
+  x.Q = S->L.Q;
+  x.vmax = S->cfg.vmax;
+  TimedLaunch t(S, MDLG_K_XI);
+  launch_xi(S->D, x, S->stream);
 }
 
 void enqueue_lattice_step(mdlg_system* S) {
   const int steps = S->cfg.md_steps_per_lattice_step;
   for (int s = 1; s <= steps; ++s) enqueue_md_step(S, s == steps);
   enqueue_bin(S, false);
+  if (S->L.xi) {
+    if (S->xi_have) {
+      enqueue_xi(S);
+      S->xi_steps += 1;
+    }
+    S->xi_par ^= 1;
+    S->xi_have = true;
+  }
   S->n_lattice += 1;
 }
 
@@ -844,6 +899,14 @@ void zero_accumulators(mdlg_system* S) {
   launch_fill_u32(reinterpret_cast<unsigned*>(S->mom), 0u, (long long)L.n_sites * L.nm * 2, S->stream);
   launch_fill_u32(reinterpret_cast<unsigned*>(S->dpart), 0u, (long long)L.nstrips * 2 * L.D * 2,
                   S->stream);
+  if (L.xi) {
+    launch_fill_u32(reinterpret_cast<unsigned*>(S->xi_site), 0u, (long long)L.n_sites * L.Q * 2,
+                    S->stream);
+    launch_fill_u32(reinterpret_cast<unsigned*>(S->xi_last), 0u, (long long)L.n_sites * L.Q,
+                    S->stream);
+    launch_fill_u32(reinterpret_cast<unsigned*>(S->xi_sums), 0u, (long long)5 * L.Q * 2, S->stream);
+    S->xi_steps = 0;
+  }
   S->n_lattice = 0;
 }
 
@@ -1006,14 +1069,16 @@ mdlg_status mdlg_coarse_grain(mdlg_system* S, int64_t T) {
       enqueue_lattice_step(S);
       continue;
     }
-    auto key = std::make_tuple(S->pcur, S->scur, S->since_sort, S->vel_full, S->lambda_pending);
+    auto key = std::make_tuple(S->pcur, S->scur, S->since_sort, S->vel_full, S->lambda_pending,
+                               S->xi_par, S->xi_have);
     auto it = S->graphs.find(key);
     if (it == S->graphs.end()) {
       if (!S->cap_stream) HIPCHK(S, hipStreamCreateWithFlags(&S->cap_stream, hipStreamNonBlocking));
       hipStream_t user = S->stream;
       const long long md0 = S->md_step, nl0 = S->n_lattice;
-      const int p0 = S->pcur, s0 = S->scur, ss0 = S->since_sort;
-      const bool v0 = S->vel_full, l0 = S->lambda_pending;
+      const int p0 = S->pcur, s0 = S->scur, ss0 = S->since_sort, x0 = S->xi_par;
+      const bool v0 = S->vel_full, l0 = S->lambda_pending, h0 = S->xi_have;
+      const long long xs0 = S->xi_steps;
       S->stream = S->cap_stream;
       HIPCHK(S, hipStreamBeginCapture(S->cap_stream, hipStreamCaptureModeThreadLocal));
       enqueue_lattice_step(S);
@@ -1029,7 +1094,11 @@ mdlg_status mdlg_coarse_grain(mdlg_system* S, int64_t T) {
       ent.scur = S->scur;
       ent.since_sort = S->since_sort;
       ent.vel_full = S->vel_full;
+      ent.xi_par = S->xi_par;
       // the capture only recorded work; restore the state it started from
+      S->xi_par = x0;
+      S->xi_have = h0;
+      S->xi_steps = xs0;
       S->md_step = md0;
       S->n_lattice = nl0;
       S->pcur = p0;
@@ -1045,6 +1114,11 @@ mdlg_status mdlg_coarse_grain(mdlg_system* S, int64_t T) {
     S->since_sort = it->second.since_sort;
     S->vel_full = it->second.vel_full;
     S->lambda_pending = false;
+    if (S->L.xi) {
+      if (S->xi_have) S->xi_steps += 1;
+      S->xi_par = it->second.xi_par;
+      S->xi_have = true;
+    }
     S->md_step += S->cfg.md_steps_per_lattice_step;
     S->n_lattice += 1;
   }
@@ -1137,6 +1211,29 @@ mdlg_status mdlg_get_kinetics(mdlg_system* S, double* out) {
   if (st != MDLG_OK) return st;
   const size_t n = S->L.reps.size() * (S->D + 1);
   HIPCHK(S, hipMemcpyAsync(out, S->kin, n * sizeof(double), hipMemcpyDeviceToHost, S->stream));
+  return read_err(S);
+}
+
+mdlg_status mdlg_get_xi(mdlg_system* S, int64_t* sums, int64_t* xi_site, int32_t* xi_last,
+                        int64_t* n_steps) {
+  if (!S) return MDLG_E_INVALID;
+  const Layout& L = S->L;
+  if (!L.xi) {
+    S->last_error = "collision_stats was not enabled in the configuration";
+    return MDLG_E_STATE;
+  }
+  if (S->timing) close_run(S);
+  const size_t sq = (size_t)L.n_sites * L.Q;
+  if (sums)
+    HIPCHK(S, hipMemcpyAsync(sums, S->xi_sums, sizeof(int64_t) * 5 * L.Q, hipMemcpyDeviceToHost,
+                             S->stream));
+  if (xi_site)
+    HIPCHK(S, hipMemcpyAsync(xi_site, S->xi_site, sizeof(int64_t) * sq, hipMemcpyDeviceToHost,
+                             S->stream));
+  if (xi_last)
+    HIPCHK(S, hipMemcpyAsync(xi_last, S->xi_last, sizeof(int32_t) * sq, hipMemcpyDeviceToHost,
+                             S->stream));
+  if (n_steps) *n_steps = S->xi_steps;
   return read_err(S);
 }
 
@@ -1242,6 +1339,7 @@ mdlg_status mdlg_set_state(mdlg_system* S, const mdlg_particles* in) {
   enqueue_sort(S);
   if (!in->prev_ucell) enqueue_bin(S, true);
   S->snapshot_valid = true;
+  S->xi_have = false;
   S->vel_full = true;
   S->lambda_pending = false;
   mdlg_status st = check_launch(S, "mdlg_set_state");

@@ -122,6 +122,23 @@ struct BinArgs {
   unsigned* err;
   int snapshot_only;
   int BSX;
+  unsigned* nstep;     // optional: this step's n_i(x,t) [sites][Q], overwritten
+};
+
+struct XiArgs {
+  const Replica* reps;
+  const unsigned* ncur;        // n_i(x, t + dt_L) [sites][Q]
+  const unsigned* nprev;       // n_i(x, t) [sites][Q]
+  long long* xi_site;          // [sites][Q] running sum over t of Xi_i(x, t)
+  int* xi_last;                // [sites][Q] Xi_i(x, t) of this step
+  unsigned long long* sums;    // [5][Q] sums of Xi, Xi^2, Xi n, n, n^2 (two's complement)
+  long long* part;             // [nblocks][5][Q] per-block sums of this step
+  int n_sites;
+  int sites_per_block;
+  int nblocks;
+  int n_rep;
+  int Q;
+  int vmax;
 };
 
 struct FsumArgs {
@@ -240,6 +257,7 @@ void launch_force(int D, const ForceArgs& a, hipStream_t s);
 void launch_nlist(int D, const NlistArgs& a, hipStream_t s);
 void launch_kin(const KinArgs& a, hipStream_t s);
 void launch_bin(int D, int nstrips, const BinArgs& a, hipStream_t s);
+void launch_xi(int D, const XiArgs& a, hipStream_t s);
 void launch_fsum(const FsumArgs& a, hipStream_t s);
 void launch_ffinal(const FfinalArgs& a, hipStream_t s);
 void launch_site_avg(const SiteAvgArgs& a, hipStream_t s);

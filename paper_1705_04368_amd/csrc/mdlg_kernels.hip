@@ -1397,6 +1397,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs a) {
   for (int e = threadIdx.x; e < wsx * Q; e += kBlock) {
     const unsigned c = s_h[e];
     if (c) atomicAdd(a.A + site0 * Q + e, c);
+    if (a.nstep) a.nstep[site0 * Q + e] = c;
   }
   for (int e = threadIdx.x; e < wsx * nm; e += kBlock) {
     const int c = s_m[e];
@@ -1535,6 +1536,91 @@ __global__ __launch_bounds__(kBlock) void k_import(XportArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- collision operator
+//
+// Xi_i(x, t) = n_i(x + v_i, t + dt_L) - n_i(x, t) (eq. Xi), from the arrival
+// histograms of two consecutive lattice steps: n_i(x + v_i, t + dt_L) counts
+// the particles that sat in x at t and moved by v_i.  A block takes a run of
+// sites; thread t owns bin t % Q for every (256 / Q)-th site of the run, so
+// the reads of n_i(x, t) are coalesced and each thread keeps its bin's sums
+// of Xi, Xi^2, Xi n, n and n^2 (n = n_i(x, t), the populations Xi acts on)
+// in registers.  x + v_i wraps periodically inside the site's replica.  The
+// block's per-bin sums go to its own row of partials; k_xi_reduce adds the
+// rows into the running totals.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_xi(XiArgs a) {
+  __shared__ long long s_acc[5][kMaxQ];
+  const int Q = a.Q;
+  const int lanes = kBlock / Q;
+  const int tid = threadIdx.x;
+  const bool act = tid < lanes * Q;
+  const int i = tid % Q, ls = tid / Q;
+  for (int e = tid; e < 5 * Q; e += kBlock) s_acc[e / Q][e % Q] = 0;
+  __syncthreads();
+  const int W = 2 * a.vmax + 1;
+  int v[3] = {i % W - a.vmax, (i / W) % W - a.vmax, 0};
+  if constexpr (D == 3) v[2] = i / (W * W) - a.vmax;
+  long long acc[5] = {0, 0, 0, 0, 0};
+  const int s0 = blockIdx.x * a.sites_per_block;
+  const int s1 = min(a.n_sites, s0 + a.sites_per_block);
+  if (act) {
+    for (int site = s0 + ls; site < s1; site += lanes) {
+      int lo = 0, hi = a.n_rep - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.reps[mid].site_off <= site) lo = mid; else hi = mid - 1;
+      }
+      const Replica& R = a.reps[lo];
+      const int local = site - R.site_off;
+      int c[3] = {local % R.M[0], (local / R.M[0]) % R.M[1], 0};
+      if constexpr (D == 3) c[2] = local / (R.M[0] * R.M[1]);
+      int dst = 0, stride = 1;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        int y = c[q] + v[q];
+        while (y < 0) y += R.M[q];
+        while (y >= R.M[q]) y -= R.M[q];
+        dst += y * stride;
+        stride *= R.M[q];
+      }
+      const size_t idx = (size_t)site * Q + i;
+      const long long n0 = a.nprev[idx];
+      const long long xi = (long long)a.ncur[((size_t)R.site_off + dst) * Q + i] - n0;
+      a.xi_site[idx] += xi;
+      a.xi_last[idx] = (int)xi;
+      acc[0] += xi;
+      acc[1] += xi * xi;
+      acc[2] += xi * n0;
+      acc[3] += n0;
+      acc[4] += n0 * n0;
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+      if (acc[k]) atomicAdd(reinterpret_cast<unsigned long long*>(&s_acc[k][i]),
+                            (unsigned long long)acc[k]);
+  }
+  __syncthreads();
+  for (int e = tid; e < 5 * Q; e += kBlock)
+    a.part[(size_t)blockIdx.x * 5 * Q + e] = s_acc[e / Q][e % Q];
+}
+
+// One block per (sum, bin): its threads stride over the per-block rows.
+__global__ __launch_bounds__(kBlock) void k_xi_reduce(XiArgs a) {
+  __shared__ long long s_red[kWaves];
+  const int e = blockIdx.x;
+  long long s = 0;
+  for (int b = threadIdx.x; b < a.nblocks; b += kBlock) s += a.part[(size_t)b * 5 * a.Q + e];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane_id() == 0) s_red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long t = 0;
+    for (int w = 0; w < kWaves; ++w) t += s_red[w];
+    a.sums[e] += (unsigned long long)t;
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 
 #define MDLG_LAUNCH_DIM(D, kern, grid, lds, stream, args)                        \
@@ -1616,6 +1702,12 @@ void launch_kin(const KinArgs& a, hipStream_t s) {
 void launch_bin(int D, int nstrips, const BinArgs& a, hipStream_t s) {
   const size_t lds = (size_t)a.BSX * (a.P.Q + a.P.nm) * sizeof(int);
   MDLG_LAUNCH_DIM(D, k_bin, nstrips, lds, s, a);
+}
+
+void launch_xi(int D, const XiArgs& a, hipStream_t s) {
+  if (a.nblocks <= 0) return;
+  MDLG_LAUNCH_DIM(D, k_xi, a.nblocks, 0, s, a);
+  hipLaunchKernelGGL(k_xi_reduce, dim3(5 * a.Q), dim3(kBlock), 0, s, a);
 }
 
 void launch_fsum(const FsumArgs& a, hipStream_t s) {

@@ -22,9 +22,9 @@ EXPORTED = ["mdlg_describe", "mdlg_workspace_bytes", "mdlg_create", "mdlg_step",
             "mdlg_coarse_grain", "mdlg_get_f", "mdlg_get_kinetics", "mdlg_reset_accumulators",
             "mdlg_get_state", "mdlg_set_state", "mdlg_adjoint", "mdlg_set_potential",
             "mdlg_set_timing", "mdlg_get_timing", "mdlg_sync", "mdlg_last_error", "mdlg_destroy",
-            "mdlg_autotune", "mdlg_autotune_workspace_bytes"]
+            "mdlg_autotune", "mdlg_autotune_workspace_bytes", "mdlg_get_xi"]
 LOSSES = {"msd": 0, "mean_x": 1}
-KERNEL_CLASSES = ["force", "count", "scan", "scatter", "bin", "nlist"]
+KERNEL_CLASSES = ["force", "count", "scan", "scatter", "bin", "nlist", "xi"]
 
 
 class MdlgConfig(C.Structure):
@@ -37,7 +37,8 @@ class MdlgConfig(C.Structure):
                 ("md_cell_split", C.c_int32), ("sort_every", C.c_int32),
                 ("brick_x", C.c_int32), ("brick_y", C.c_int32), ("brick_z", C.c_int32),
                 ("adjoint_window", C.c_int32), ("adjoint_every", C.c_int32),
-                ("no_pair_list", C.c_int32), ("block_threads", C.c_int32)]
+                ("no_pair_list", C.c_int32), ("block_threads", C.c_int32),
+                ("collision_stats", C.c_int32)]
 
 
 class MdlgParticles(C.Structure):
@@ -112,6 +113,8 @@ def load():
     lib.mdlg_autotune.restype = st
     lib.mdlg_autotune.argtypes = [P(MdlgConfig), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_int32, P(MdlgConfig), P(C.c_double)]
+    lib.mdlg_get_xi.restype = st
+    lib.mdlg_get_xi.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, P(C.c_int64)]
     lib.mdlg_autotune_workspace_bytes.restype = st
     lib.mdlg_autotune_workspace_bytes.argtypes = [P(MdlgConfig), P(C.c_size_t)]
     _lib = lib
@@ -133,7 +136,8 @@ def _check(status, handle=None):
 def make_config(dim, n_particles, lattice, lattice_dx=4.0, epsilon=1.0, sigma=1.0, mass=1.0,
                 r_cut=2.5, forces_off=False, dt=0.005, md_steps_per_lattice_step=20, vmax=3,
                 thermostat_every=0, kT=1.0, md_cell_split=0, sort_every=0, brick=(0, 0, 0),
-                adjoint_window=0, adjoint_every=1, pair_list=True, block_threads=0):
+                adjoint_window=0, adjoint_every=1, pair_list=True, block_threads=0,
+                collision_stats=False):
     """Build an MdlgConfig.  n_particles: int or sequence per replica; lattice:
     sites per axis, an int, a (dim,) sequence or an (n_replicas, dim) array."""
     n = np.atleast_1d(np.asarray(n_particles, dtype=np.int32))
@@ -165,6 +169,7 @@ def make_config(dim, n_particles, lattice, lattice_dx=4.0, epsilon=1.0, sigma=1.
     cfg.adjoint_every = adjoint_every if adjoint_window else 0
     cfg.no_pair_list = 0 if pair_list else 1
     cfg.block_threads = block_threads
+    cfg.collision_stats = int(bool(collision_stats))
     return cfg
 
 
@@ -267,6 +272,26 @@ class System:
             self.close()
         except Exception:
             pass
+
+    def get_xi(self, per_site=False, last=False):
+        """Collision-operator statistics (mdlg_get_xi): dict with the number of
+        samples, per-bin sums of Xi, Xi^2, Xi n, n, n^2 (int64 [Q] each), and
+        optionally the per-site sums and the latest field ([n_sites, Q])."""
+        sums = np.zeros((5, self.Q), dtype=np.int64)
+        site = np.zeros((self.n_sites, self.Q), dtype=np.int64) if per_site else None
+        lastf = np.zeros((self.n_sites, self.Q), dtype=np.int32) if last else None
+        n = C.c_int64(0)
+        _check(load().mdlg_get_xi(self.handle, sums.ctypes.data_as(C.c_void_p),
+                                  None if site is None else site.ctypes.data_as(C.c_void_p),
+                                  None if lastf is None else lastf.ctypes.data_as(C.c_void_p),
+                                  C.byref(n)), self.handle)
+        out = {"n_steps": int(n.value), "xi": sums[0], "xi2": sums[1], "xi_n": sums[2],
+               "n": sums[3], "n2": sums[4]}
+        if per_site:
+            out["xi_site"] = site
+        if last:
+            out["xi_last"] = lastf
+        return out
 
     def step(self, n):
         _check(load().mdlg_step(self.handle, int(n)), self.handle)

@@ -10,6 +10,9 @@
 * the ideal-gas equilibrium f_i against the wedge form of eq. (fieqW) and the
   Gaussian closed form eq. (feqfull).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -32,7 +35,9 @@ def test_worked_example_one_particle_table():
     st = oracle.OracleState(md, np.array([[1.1, 1.5]]), np.array([[1.0 / 3.0, 0.0]]),
                             use_cells=False)
     f0, f1 = _bin_index((0, 0), vmax), _bin_index((1, 0), vmax)
-    expected = {1: (1, f0), 2: (1, f0), 3: (2, f1), 4: (2, f0), 5: (2, f0), 6: (3, f1)}
+    table = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                        "one_particle_table.json")))
+    expected = {r["t"]: (r["x"], f0 if r["i"] == 0 else f1) for r in table["rows"]}
     mom_total = 0
     for t in range(1, 7):
         out = st.mdlg(lat, md_per_lattice=4, n_lattice=1)
