@@ -250,7 +250,8 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=10,
                     help="lattice steps of the event-timed per-kernel pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-lattice-steps", type=int, default=2)
+    ap.add_argument("--cpu-lattice-steps", type=int, default=4,
+                    help="lattice steps of the oracle timed on the host (about 12 s at 2d_scale)")
     ap.add_argument("--plain-steps", type=int, default=3,
                     help="lattice steps timed for the plain (one system per replica) path")
     ap.add_argument("--sort-every", type=int, default=0, help="rebuild interval (0 = automatic)")
