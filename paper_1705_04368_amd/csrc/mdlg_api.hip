@@ -291,7 +291,8 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   // expected at the densest replica's mean density plus 20 (a brick with a
   // fuller list walks its cells instead)
   L->kmax = 0;
-  if (want_list && R >= 2 && BX + 2 * L->ns <= kMaxListHalo &&
+  // (list entries are LDS byte offsets of 16 bits: lcap * coordinate size < 64 KiB)
+  if (want_list && R >= 2 && L->lcap * (D == 2 ? 8 : 16) < 65536 && BX + 2 * L->ns <= kMaxListHalo &&
       BY + 2 * L->ns <= kMaxListHalo && BZ + 2 * nsz <= kMaxListHalo) {
     const double rl = c->r_cut + 2 * L->margin;
     const double vol_l = (D == 2) ? M_PI * rl * rl : 4.0 / 3.0 * M_PI * rl * rl * rl;
@@ -425,6 +426,7 @@ struct mdlg_system {
   int4* binfo = nullptr;
   unsigned long long* nl = nullptr;
   float* off0 = nullptr;
+  int2* trec = nullptr;
   // adjoint window buffers (sorted order)
   float* adj_off0 = nullptr;
   float* adj_ckpt_pos = nullptr;
@@ -527,6 +529,7 @@ size_t carve(mdlg_system* S, char* base) {
     S->binfo = c.take<int4>(base, (size_t)L.nbricks);
     S->nl = c.take<unsigned long long>(base, (size_t)(L.kmax / 4) * N);
     S->off0 = c.take<float>(base, N * D);
+    S->trec = c.take<int2>(base, (size_t)L.nbricks * L.lcap);
   }
   if (L.adj_ckpts > 0) {
     S->adj_off0 = c.take<float>(base, N * D);
@@ -738,6 +741,7 @@ void enqueue_sort(mdlg_system* S) {
     nl.binfo = S->binfo;
     nl.nl = S->nl;
     nl.off0 = S->off0;
+    nl.trec = S->trec;
     nl.nbricks = S->L.nbricks;
     nl.xcd_remap = S->xcd_remap;
     TimedLaunch t(S, MDLG_K_NLIST);
@@ -771,6 +775,7 @@ void enqueue_force(mdlg_system* S, int mode, bool sort_follows, float* acc_out, 
     a.binfo = S->binfo;
     a.nl = S->nl;
     a.off0 = S->off0;
+    a.trec = S->trec;
     // the rebuild that follows makes new lists
     a.check_disp = sort_follows ? 0 : 1;
   }

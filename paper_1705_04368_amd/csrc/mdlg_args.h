@@ -76,6 +76,7 @@ struct ForceArgs {
   const int4* binfo;   // [nbricks] {staged, targets, lists valid, -}
   const unsigned long long* nl;  // [kmax / 4][n_total] four 16-bit halo indices per word
   const float* off0;   // offsets when the lists were built
+  const int2* trec;    // [nbricks][lcap] targets in processing order {particle, slot | words << 16}
   int check_disp;      // 1: flag drifts farther than sqrt(P.disp2) from off0
 };
 
@@ -89,6 +90,7 @@ struct NlistArgs {
   int4* binfo;
   unsigned long long* nl;
   float* off0;
+  int2* trec;
   int nbricks;
   int xcd_remap;
 };

@@ -429,15 +429,24 @@ struct BrickLds {
   int cap;
 };
 
+template <int D>
+__device__ __forceinline__ size_t brick_lds_bytes_dev(const Phys& P) {
+  const size_t tables = ((size_t)(2 * P.lmaxh + 1) * sizeof(int) + 15) & ~size_t(15);
+  return tables + (size_t)P.lcap * sizeof(Coord<D>);
+}
+
 template <int D, bool ADJ>
 __device__ __forceinline__ BrickLds<D, ADJ> brick_lds(char* dyn, int* rowpre, int* tmp,
                                                       double (*red)[4], const Phys& P) {
+  // the staged coordinates come first, at the fixed start of the dynamic LDS,
+  // so that a list entry (a byte offset) addresses them without arithmetic
   BrickLds<D, ADJ> L;
-  L.hs = reinterpret_cast<int*>(dyn);
+  L.p = reinterpret_cast<Coord<D>*>(dyn);
+  size_t off = (size_t)P.lcap * sizeof(Coord<D>);
+  L.lam = reinterpret_cast<float*>(dyn + off);
+  if (ADJ) off += (size_t)P.lcap * D * sizeof(float);
+  L.hs = reinterpret_cast<int*>(dyn + off);
   L.gs = L.hs + P.lmaxh + 1;
-  const size_t off = ((size_t)(2 * P.lmaxh + 1) * sizeof(int) + 15) & ~size_t(15);
-  L.p = reinterpret_cast<Coord<D>*>(dyn + off);
-  L.lam = reinterpret_cast<float*>(dyn + off + (size_t)P.lcap * sizeof(Coord<D>));
   L.rowpre = rowpre;
   L.tmp = tmp;
   L.red = red;
@@ -635,6 +644,34 @@ __device__ __forceinline__ void lj_pair(const C& q, int X, int Y, int Z, const P
   if constexpr (D == 3) f[D - 1] -= gg * dz;
 }
 
+// The same term for a list entry: the list never holds the target itself, and
+// its padding points at a sentinel far outside the cutoff, so only the cutoff
+// is tested.
+template <int D, typename C>
+__device__ __forceinline__ void lj_pair_listed(const C& q, int X, int Y, int Z, const Phys& P,
+                                               float (&f)[D]) {
+  const float dx = (float)(q.x - X);
+  const float dy = (float)(q.y - Y);
+  float r2 = dx * dx + dy * dy;
+  float dz = 0.f;
+  if constexpr (D == 3) {
+    dz = (float)(q.z - Z);
+    r2 += dz * dz;
+  }
+  const float ir2 = (r2 < P.rc2_u) ? __builtin_amdgcn_rcpf(r2) : 0.f;
+  const float sr2 = P.sig2_u * ir2;
+  const float sr6 = sr2 * sr2 * sr2;
+  // 24 eps / (m r^2) (sigma/r)^6 [2 (sigma/r)^6 - 1], one product fewer
+  const float gg = (ir2 * sr6) * fmaf(2.f * P.eps24m_u, sr6, -P.eps24m_u);
+  f[0] -= gg * dx;
+  f[1] -= gg * dy;
+  if constexpr (D == 3) f[D - 1] -= gg * dz;
+}
+
+// Fixed-point coordinate of the padding sentinel: 2^30 units from any staged
+// particle (whose coordinates lie in [-2^27, 2^31)), far beyond the cutoff.
+constexpr int kSentinel = 1 << 30;
+
 // Cell range a target at (X, Y, Z) has to visit: every cell whose particles
 // (which may sit up to the rebuild margin outside it) can lie within r_cut.
 struct Reach {
@@ -733,10 +770,12 @@ template <int D, class Lds>
 __device__ __forceinline__ void list_word(const Lds& L, unsigned long long e, int X, int Y, int Z,
                                           const Phys& P, float (&f)[D]) {
   Coord<D> q[4];
+  const char* base = reinterpret_cast<const char*>(L.p);
 #pragma unroll
-  for (int u = 0; u < 4; ++u) q[u] = L.p[(unsigned)(e >> (16 * u)) & 0xffffu];
+  for (int u = 0; u < 4; ++u)
+    q[u] = *reinterpret_cast<const Coord<D>*>(base + ((unsigned)(e >> (16 * u)) & 0xffffu));
 #pragma unroll
-  for (int u = 0; u < 4; ++u) lj_pair<D>(q[u], X, Y, Z, P, f);
+  for (int u = 0; u < 4; ++u) lj_pair_listed<D>(q[u], X, Y, Z, P, f);
 }
 
 template <int D, int NT>
@@ -767,62 +806,81 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
   const int4 bi = a.nl ? a.binfo[b] : make_int4(0, 0, 0, 0);
   if (bi.z) {
     // pair-list path: stage the halo through the map written by the list
-    // builder (targets first), then each target walks its own list
+    // builder (targets first), then each target walks its own list.  The
+    // targets come in the builder's order (decreasing list length, so that
+    // the lanes of a wave walk lists of similar length) as records
+    // {particle, LDS slot | words << 16}; the first pass's records, state and
+    // first list words are requested before the staging so that their
+    // latency overlaps it.
     const int2* __restrict__ smap = a.smap + (size_t)b * CAP;
+    const int2* __restrict__ trec = a.trec + (size_t)b * CAP;
     const int total = bi.x, ntg = bi.y;
+    const size_t nt = (size_t)P.n_total;
+    constexpr int GW = (D == 2) ? 2 : 4;
+    const unsigned long long pad = 0x0001000100010001ull * (unsigned)(total * sizeof(Coord<D>));
+    int gi = 0, t = 0, ng = 0;
+    float o[D], v[D];
+    unsigned long long w[GW];
+    auto fetch = [&](int k) {
+      const bool has = k < ntg;
+      const int2 r = has ? trec[k] : make_int2(0, 0);
+      gi = r.x;
+      t = r.y & 0xffff;
+      ng = has ? ((unsigned)r.y >> 16) : 0;
+      if (has) {
+        ldv<D>(a.pos_in, gi, o);
+        ldv<D>(a.vel, gi, v);
+      }
+#pragma unroll
+      for (int u = 0; u < GW; ++u) w[u] = (u < ng) ? a.nl[(size_t)u * nt + gi] : pad;
+    };
+    fetch((int)threadIdx.x);
+    if (threadIdx.x == 0) {
+      if constexpr (D == 2) L.p[total] = make_int2(kSentinel, kSentinel);
+      else L.p[total] = make_int4(kSentinel, kSentinel, kSentinel, 0);
+    }
     for (int v0 = (int)threadIdx.x; v0 < total; v0 += 2 * NT) {
       int2 e[2];
       float p[2][D];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int v = v0 + u * NT;
-        e[u] = smap[min(v, total - 1)];
+        const int vv = v0 + u * NT;
+        e[u] = smap[min(vv, total - 1)];
         ldv<D>(a.pos_in, e[u].x, p[u]);
       }
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int v = v0 + u * NT;
-        if (v < total) {
+        const int vv = v0 + u * NT;
+        if (vv < total) {
           const int hx = e[u].y & 255, hy = (e[u].y >> 8) & 255;
           if constexpr (D == 2)
-            L.p[v] = make_int2(fixed_coord(hx, p[u][0], P), fixed_coord(hy, p[u][1], P));
+            L.p[vv] = make_int2(fixed_coord(hx, p[u][0], P), fixed_coord(hy, p[u][1], P));
           else
-            L.p[v] = make_int4(fixed_coord(hx, p[u][0], P), fixed_coord(hy, p[u][1], P),
-                               fixed_coord((e[u].y >> 16) & 255, p[u][2], P), 0);
+            L.p[vv] = make_int4(fixed_coord(hx, p[u][0], P), fixed_coord(hy, p[u][1], P),
+                                fixed_coord((e[u].y >> 16) & 255, p[u][2], P), 0);
         }
       }
     }
     __syncthreads();
-    const size_t nt = (size_t)P.n_total;
     for (int tb = 0; tb < ntg; tb += NT) {
-      const int t = tb + (int)threadIdx.x;
-      if (t >= ntg) break;
-      const int2 e = smap[t];
-      const int gi = e.x;
-      const int ng = ((unsigned)e.y >> 24) >> 2;
+      if (tb + (int)threadIdx.x >= ntg) break;
+      if (tb > 0) fetch(tb + (int)threadIdx.x);
       const Coord<D> me = L.p[t];
       const int X = me.x, Y = me.y;
       int Z = 0;
       if constexpr (D == 3) Z = me.z;
-      float o[D], v[D], f[D];
-      ldv<D>(a.pos_in, gi, o);
-      ldv<D>(a.vel, gi, v);
+      float f[D];
 #pragma unroll
       for (int k = 0; k < D; ++k) f[k] = 0.f;
-      // a group of words in flight ahead of the group being summed (two in
-      // 2D, four in 3D where lists are longer); words past the end of the
-      // list stand in as four copies of the target itself (zero terms)
-      constexpr int GW = (D == 2) ? 2 : 4;
+      // one group of words in flight ahead of the group being summed (two
+      // words in 2D, four in 3D where lists are longer); words past the end
+      // of the list stand in as four copies of the sentinel (zero terms)
       const unsigned long long* __restrict__ lp = a.nl + gi;
-      const unsigned long long self = 0x0001000100010001ull * (unsigned)t;
-      unsigned long long w[GW];
-#pragma unroll
-      for (int u = 0; u < GW; ++u) w[u] = (u < ng) ? lp[(size_t)u * nt] : self;
       for (int k = 0; k < ng; k += GW) {
         unsigned long long nx[GW];
 #pragma unroll
         for (int u = 0; u < GW; ++u)
-          nx[u] = (k + GW + u < ng) ? lp[(size_t)(k + GW + u) * nt] : self;
+          nx[u] = (k + GW + u < ng) ? lp[(size_t)(k + GW + u) * nt] : pad;
 #pragma unroll
         for (int u = 0; u < GW; ++u) list_word<D>(L, w[u], X, Y, Z, P, f);
 #pragma unroll
@@ -950,7 +1008,11 @@ __global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
   __shared__ int s_tmp[NW + 1];
   __shared__ double s_red[NW][4];
   __shared__ int s_over;
+  __shared__ int s_cnt[64];
   auto L = brick_lds<D, false>(s_dyn_brick, s_rowpre, s_tmp, s_red, a.P);
+  // word count of every target's list (dynamic LDS behind the brick's own)
+  unsigned char* s_words =
+      reinterpret_cast<unsigned char*>(s_dyn_brick) + brick_lds_bytes_dev<D>(a.P);
   const int CAP = L.cap;
   int b = blockIdx.x;
   if (a.xcd_remap) {
@@ -963,7 +1025,7 @@ __global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
   const Replica R = a.reps[br.x];
   if (threadIdx.x == 0) s_over = 0;
   const BrickGeom G = brick_setup<D, NT>(P, R, br, a.cell_start, L);
-  const bool fits = G.total <= CAP;
+  const bool fits = G.total < CAP;  // one slot stays free for the padding sentinel
   int2* __restrict__ smap = a.smap + (size_t)b * CAP;
   if (fits) brick_stage<D, NT>(G, P, a.pos, nullptr, L, 0, G.total, smap);
   __syncthreads();
@@ -1021,20 +1083,43 @@ __global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
           while (mask) {
             const int j = j0 + __builtin_ctz(mask);
             mask &= mask - 1;
-            list_push(wp, word, cnt, seen, j + (j < ja ? s0 : (j < jb ? s1 : s2)), kmax, nt);
+            list_push(wp, word, cnt, seen,
+                      (j + (j < ja ? s0 : (j < jb ? s1 : s2))) * (int)sizeof(Coord<D>), kmax, nt);
           }
         }
       }
     }
     if (seen > kmax) s_over = 1;
     if (cnt & 3) {
-      for (int u = cnt & 3; u < 4; ++u) word |= (unsigned long long)(unsigned)t << (16 * u);
+      for (int u = cnt & 3; u < 4; ++u)
+        word |= (unsigned long long)(unsigned)(G.total * (int)sizeof(Coord<D>)) << (16 * u);
       *wp = word;
     }
     const int words = (cnt + 3) >> 2;
     smap[t] = make_int2(gi, pack_halo(hxi, hyi, hzi) | ((words * 4) << 24));
+    s_words[t] = (unsigned char)words;
   }
   __syncthreads();
+  // processing order of the targets: decreasing word count (counting sort)
+  if (fits) {
+    int2* __restrict__ trec = a.trec + (size_t)b * CAP;
+    for (int i = threadIdx.x; i < 64; i += NT) s_cnt[i] = 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < G.ntg; t += NT) atomicAdd(&s_cnt[63 - s_words[t]], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int acc = 0;
+      for (int i = 0; i < 64; ++i) {
+        const int c = s_cnt[i];
+        s_cnt[i] = acc;
+        acc += c;
+      }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < G.ntg; t += NT)
+      trec[atomicAdd(&s_cnt[63 - s_words[t]], 1)] =
+          make_int2(smap[t].x, t | ((int)s_words[t] << 16));
+  }
   if (threadIdx.x == 0) a.binfo[b] = make_int4(G.total, G.ntg, (fits && !s_over) ? 1 : 0, 0);
 }
 
@@ -1663,9 +1748,9 @@ void launch_scatter(int D, int nchunks, const SortArgs& a, hipStream_t s) {
 }
 
 size_t brick_lds_bytes(const Phys& P, int D, bool adj) {
-  const size_t head = ((size_t)(2 * P.lmaxh + 1) * sizeof(int) + 15) & ~size_t(15);
+  const size_t tables = ((size_t)(2 * P.lmaxh + 1) * sizeof(int) + 15) & ~size_t(15);
   const size_t coord = (D == 2) ? sizeof(int2) : sizeof(int4);
-  return head + (size_t)P.lcap * (coord + (adj ? D * sizeof(float) : 0));
+  return tables + (size_t)P.lcap * (coord + (adj ? D * sizeof(float) : 0));
 }
 
 // Brick kernels come in 64-, 128- and 256-thread blocks (P.bthreads).
@@ -1692,7 +1777,9 @@ void launch_force(int D, const ForceArgs& a, hipStream_t s) {
 void launch_nlist(int D, const NlistArgs& a, hipStream_t s) {
   int grid = a.nbricks;
   if (a.xcd_remap) grid = ((a.nbricks + 7) / 8) * 8;
-  MDLG_LAUNCH_BRICK(D, a.P.bthreads, k_nlist, grid, brick_lds_bytes(a.P, D, false), s, a);
+  // the brick's LDS plus one byte per target for the list word counts
+  const size_t lds = brick_lds_bytes(a.P, D, false) + (size_t)a.P.lcap;
+  MDLG_LAUNCH_BRICK(D, a.P.bthreads, k_nlist, grid, lds, s, a);
 }
 
 void launch_kin(const KinArgs& a, hipStream_t s) {
