@@ -261,6 +261,8 @@ def main():
                     help="walk the neighbour cells at every MD step instead of using pair lists")
     ap.add_argument("--collision-stats", action="store_true",
                     help="also record the collision operator Xi of consecutive lattice steps")
+    ap.add_argument("--galilean", type=int, default=0,
+                    help="also bin on this many lattices drifting with u_x in [0, 0.5]")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's analytic launch shapes instead of measuring candidates")
     ap.add_argument("--autotune-steps", type=int, default=40, help="MD steps timed per candidate")
@@ -301,6 +303,12 @@ def main():
     tuning = dict(sort_every=args.sort_every, pair_list=not args.no_pair_list,
                   md_cell_split=args.md_cell_split, brick=tuple(args.brick),
                   collision_stats=args.collision_stats)
+    if args.galilean:
+        # drifting lattices u_x = 0 .. 0.5 (the sweep of the figure on the second moment)
+        us = np.linspace(0.0, 0.5, args.galilean)
+        sh = np.zeros((args.galilean, 2, dim))
+        sh[:, 1, 0] = us
+        tuning["shifts"] = sh
     dev = torch.device("cuda:0")
     if w.get("replicas"):
         n_r, m_r = synth.replica_sizes(w["replicas"], seed=4)
@@ -400,6 +408,13 @@ def main():
             kernels[k] = {"avg_ms": avg, "launches": cnt, "bound": "hbm", "achieved": ach,
                           "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
                           "work_per_launch": work}
+        elif k == "shift":
+            # per particle: cell, image, offset and the snapshot (cell, offset)
+            work = n * (4 + 16 * dim)
+            ach = work / (avg * 1e-3) / 1e9
+            kernels[k] = {"avg_ms": avg, "launches": cnt, "bound": "hbm", "achieved": ach,
+                          "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                          "work_per_launch": work}
         elif k == "xi":
             # per (site, bin): n_i(x, t), the shifted n_i(x + v_i, t + 1), the
             # running sum (read and write) and the latest value
@@ -449,7 +464,8 @@ def main():
         "config": {"workload": w["desc"], "lattice_steps": args.steps, "md_steps": md_steps,
                    "md_cell_split": lay["md_cell_split"], "sort_every": lay["sort_every"],
                    "brick": list(lay["brick"]), "pair_slots": lay["pair_slots"],
-                   "autotuned": tuned_ms is not None, "collision_stats": args.collision_stats},
+                   "autotuned": tuned_ms is not None, "collision_stats": args.collision_stats,
+                   "galilean_lattices": args.galilean},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plain": plain,

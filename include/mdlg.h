@@ -109,6 +109,11 @@ typedef struct {
     int32_t collision_stats;    /* 1: record the MDLG collision operator Xi (eq. Xi) of
                                    every pair of consecutive lattice steps (see
                                    mdlg_get_xi); 0: off */
+    int32_t n_shifts;           /* extra lattices binned every lattice step (0..32), see
+                                   mdlg_get_shifts */
+    const double *shifts;       /* host [n_shifts][2][dim], copied at creation: per extra
+                                   lattice an offset a (lattice spacings) and a drift b
+                                   (lattice spacings per lattice step) along every axis */
 } mdlg_config;
 
 /* Particle state in particle-id order (id = index in the concatenated input).
@@ -258,7 +263,8 @@ typedef enum {
     MDLG_K_BIN = 4,     /* MDLG binning and per-site accumulation (eq. MDni) */
     MDLG_K_NLIST = 5,   /* cell-list rebuild: per-particle pair lists */
     MDLG_K_XI = 6,      /* collision operator of consecutive lattice steps (eq. Xi) */
-    MDLG_K_NCLASS = 7
+    MDLG_K_SHIFT = 7,   /* binning on displaced and moving lattices */
+    MDLG_K_NCLASS = 8
 } mdlg_kernel_class;
 
 /* Enable (1) or disable (0) per-kernel timing with HIP events on the handle's
@@ -300,6 +306,25 @@ void mdlg_destroy(mdlg_system *sys);
  * MDLG_E_STATE when collision_stats is off. */
 mdlg_status mdlg_get_xi(mdlg_system *sys, int64_t *sums, int64_t *xi_site, int32_t *xi_last,
                         int64_t *n_steps);
+
+/* Binning on displaced and moving lattices.  Extra lattice j places the cell
+ * boundaries so that a particle at x lies in cell floor(x / dx + a_j + b_j k)
+ * along each axis at lattice time k (cfg.shifts).  A drift b_j = u is the
+ * Galilean transform x + u t of the positions, which the paper uses to obtain
+ * the equilibrium distribution at mean velocity u from one trajectory
+ * (section on the velocity dependence of f_i^eq, eq. fialpha); static
+ * offsets a_j = m / K, m = 0..K-1, average over K lattice placements, which
+ * the paper names as the way to make the lattice momentum exact (remarks
+ * after the one-particle table).  Every mdlg_coarse_grain lattice step
+ * accumulates, per extra lattice and summed over all sites, exact integers:
+ *   counts   host [n_shifts][Q + 1]: window bins as in eq. (MDni) (same
+ *            numbering), then the particles whose displacement left the
+ *            window;
+ *   moments  host [n_shifts][d + d(d+1)/2]: sum over all particles of the
+ *            lattice displacement v_a, then v_a v_b for a <= b;
+ *   n_steps  lattice steps accumulated since the last reset.
+ * NULL skips an output.  Synchronises.  MDLG_E_STATE when n_shifts is 0. */
+mdlg_status mdlg_get_shifts(mdlg_system *sys, uint64_t *counts, int64_t *moments, int64_t *n_steps);
 
 /* Launch-shape autotuner for batched and single systems (the f_i^eq of
  * eq. fieq are ensemble averages, so the same configuration is typically run

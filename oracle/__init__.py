@@ -281,3 +281,34 @@ def collision_operator(lattice, dim, n_t, n_next):
             shifted = np.roll(shifted, -v[a], axis=dim - 1 - a)
         xi[..., i] = shifted - now[..., i]
     return xi.reshape(-1, Q)
+
+
+def bin_shifted(lattice, dim, xu_prev, xu_now, a, b, k):
+    """eq. (MDni) on a displaced, moving lattice, summed over sites: at lattice
+    time k a particle at x is in cell floor(x / dx + a + b k) per axis (a, b
+    in lattice spacings; b = u bins the Galilean-transformed positions
+    x + u t).  Returns (counts [Q + 1]: window bins then the overflow,
+    moments [d + d(d+1)/2]: sum of v_a over all particles, then v_a v_b)."""
+    dx = float(lattice.dx)
+    V = int(lattice.V)
+    W = 2 * V + 1
+    Q = W ** dim
+    a = np.asarray(a, dtype=np.float64).reshape(dim)
+    b = np.asarray(b, dtype=np.float64).reshape(dim)
+    y_now = np.asarray(xu_now, dtype=np.float64) / dx
+    y_prev = np.asarray(xu_prev, dtype=np.float64) / dx
+    now = a + b * float(k)
+    before = a + b * (float(k) - 1.0)
+    v = (np.floor(y_now + now) - np.floor(y_prev + before)).astype(np.int64)
+    inside = np.all(np.abs(v) <= V, axis=1)
+    bins = np.zeros(len(v), dtype=np.int64)
+    for ax in range(dim):
+        bins += (v[:, ax] + V) * W ** ax
+    counts = np.zeros(Q + 1, dtype=np.int64)
+    counts[:Q] = np.bincount(bins[inside], minlength=Q)
+    counts[Q] = int((~inside).sum())
+    mom = [int(v[:, ax].sum()) for ax in range(dim)]
+    for p in range(dim):
+        for q in range(p, dim):
+            mom.append(int((v[:, p] * v[:, q]).sum()))
+    return counts, np.array(mom, dtype=np.int64)

@@ -47,6 +47,7 @@ struct Layout {
   double per_cell = 0; // mean particles per MD cell
   int kmax = 0;        // pair-list slots per particle (0 = cell walk every step)
   bool xi = false;     // collision-operator statistics buffers
+  int n_shifts = 0;    // displaced / moving lattices
   int adj_ckpts = 0;   // checkpoints the workspace holds (0 = no adjoint)
   int adj_seg = 0;     // segment positions the workspace holds
 };
@@ -102,6 +103,14 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
       c->block_threads != 256)
     return set_err(msg, "block_threads must be 0, 64, 128 or 256 (got %d)", c->block_threads);
   if (c->adjoint_window < 0) return set_err(msg, "adjoint_window must be >= 0");
+  if (c->n_shifts < 0 || c->n_shifts > kMaxShifts)
+    return set_err(msg, "n_shifts must be in 0..%d", kMaxShifts);
+  if (c->n_shifts > 0) {
+    if (!c->shifts) return set_err(msg, "shifts is NULL");
+    for (int i = 0; i < c->n_shifts * 2 * c->dim; ++i)
+      if (!std::isfinite(c->shifts[i]) || std::fabs(c->shifts[i]) > 1e6)
+        return set_err(msg, "shift values must be finite and below 1e6 lattice spacings");
+  }
   if (c->adjoint_window > 0 && (c->adjoint_every < 1 || c->adjoint_every > c->adjoint_window))
     return set_err(msg, "adjoint_every must be in 1..adjoint_window");
   L->D = D;
@@ -340,6 +349,7 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
     site_off += nsite;
   }
   L->xi = c->collision_stats != 0;
+  L->n_shifts = c->n_shifts;
   if (c->adjoint_window > 0) {
     L->adj_ckpts = c->adjoint_window / c->adjoint_every + 1;
     L->adj_seg = c->adjoint_every + 1;
@@ -412,6 +422,11 @@ struct mdlg_system {
   double* fout = nullptr;
   double* dispout = nullptr;
   float* acc_sorted = nullptr;
+  // displaced / moving lattices
+  std::vector<double> shifts_host;
+  double* shifts = nullptr;
+  long long* shift_k = nullptr;
+  unsigned long long* shift_acc = nullptr;
   // collision operator (eq. Xi)
   unsigned* nstep[2] = {nullptr, nullptr};
   long long* xi_site = nullptr;
@@ -475,6 +490,9 @@ struct mdlg_system {
 
 namespace {
 
+// Accumulators per displaced lattice: Q + 1 counts and d + d(d+1)/2 sums.
+int shift_per(const Layout& L) { return L.Q + 1 + L.D + L.D * (L.D + 1) / 2; }
+
 // Sites per block of the collision-operator kernel, and its block count.
 constexpr int kXiSites = 64;
 int xi_blocks(const Layout& L) { return (int)((L.n_sites + kXiSites - 1) / kXiSites); }
@@ -515,6 +533,11 @@ size_t carve(mdlg_system* S, char* base) {
   S->fout = c.take<double>(base, kMaxQ);
   S->dispout = c.take<double>(base, 8);
   S->acc_sorted = c.take<float>(base, N * D);
+  if (L.n_shifts > 0) {
+    S->shifts = c.take<double>(base, (size_t)L.n_shifts * 2 * D);
+    S->shift_k = c.take<long long>(base, 1);
+    S->shift_acc = c.take<unsigned long long>(base, (size_t)L.n_shifts * shift_per(L));
+  }
   if (L.xi) {
     const size_t sq = (size_t)L.n_sites * L.Q;
     S->nstep[0] = c.take<unsigned>(base, sq);
@@ -832,6 +855,7 @@ void enqueue_bin(mdlg_system* S, bool snapshot_only) {
   b.snapshot_only = snapshot_only ? 1 : 0;
   b.BSX = S->L.BSX;
   b.nstep = (S->L.xi && !snapshot_only) ? S->nstep[S->xi_par] : nullptr;
+  b.shift_k = (S->L.n_shifts > 0 && !snapshot_only) ? S->shift_k : nullptr;
   {
     TimedLaunch t(S, MDLG_K_BIN);
     launch_bin(S->D, S->L.nstrips, b, S->stream);
@@ -868,6 +892,26 @@ void enqueue_xi(mdlg_system* S) {
 void enqueue_lattice_step(mdlg_system* S) {
   const int steps = S->cfg.md_steps_per_lattice_step;
   for (int s = 1; s <= steps; ++s) enqueue_md_step(S, s == steps);
+  if (S->L.n_shifts > 0) {
+    // before the binning, which moves the snapshot forward
+    ShiftArgs h{};
+    h.P = S->P;
+    h.reps = S->reps;
+    h.chunks = S->chunks;
+    h.pos = S->pos[S->pcur];
+    h.img = S->img[S->scur];
+    h.cell = S->cell[S->scur];
+    h.prev_u = S->prev_u[S->scur];
+    h.prev_off = S->prev_off[S->scur];
+    h.shifts = S->shifts;
+    h.shift_k = S->shift_k;
+    h.acc = S->shift_acc;
+    h.dx = S->cfg.lattice_dx;
+    h.n_shifts = S->L.n_shifts;
+    h.nchunks = S->L.nchunks;
+    TimedLaunch t(S, MDLG_K_SHIFT);
+    launch_shift(S->D, h, S->stream);
+  }
   enqueue_bin(S, false);
   if (S->L.xi) {
     if (S->xi_have) {
@@ -904,6 +948,13 @@ void zero_accumulators(mdlg_system* S) {
   launch_fill_u32(reinterpret_cast<unsigned*>(S->mom), 0u, (long long)L.n_sites * L.nm * 2, S->stream);
   launch_fill_u32(reinterpret_cast<unsigned*>(S->dpart), 0u, (long long)L.nstrips * 2 * L.D * 2,
                   S->stream);
+  if (L.n_shifts > 0) {
+    launch_fill_u32(reinterpret_cast<unsigned*>(S->shift_acc), 0u,
+                    (long long)L.n_shifts * shift_per(L) * 2, S->stream);
+    // lattice time of the next arrival: 1 (the snapshot is time 0)
+    launch_fill_u32(reinterpret_cast<unsigned*>(S->shift_k), 1u, 1, S->stream);
+    launch_fill_u32(reinterpret_cast<unsigned*>(S->shift_k) + 1, 0u, 1, S->stream);
+  }
   if (L.xi) {
     launch_fill_u32(reinterpret_cast<unsigned*>(S->xi_site), 0u, (long long)L.n_sites * L.Q * 2,
                     S->stream);
@@ -1008,6 +1059,13 @@ mdlg_status mdlg_create(const mdlg_config* cfg, void* workspace_dev, size_t work
                             hipMemcpyHostToDevice, S->stream));
   CREATE_HIP(hipMemcpyAsync(S->strips, L.strips.data(), L.strips.size() * sizeof(int4),
                             hipMemcpyHostToDevice, S->stream));
+  if (L.n_shifts > 0) {
+    S->shifts_host.assign(cfg->shifts, cfg->shifts + (size_t)L.n_shifts * 2 * L.D);
+    S->cfg.shifts = S->shifts_host.data();
+    CREATE_HIP(hipMemcpyAsync(S->shifts, S->shifts_host.data(),
+                              S->shifts_host.size() * sizeof(double), hipMemcpyHostToDevice,
+                              S->stream));
+  }
   launch_fill_u32(reinterpret_cast<unsigned*>(S->count), 0u, L.n_cells, S->stream);
   launch_fill_u32(reinterpret_cast<unsigned*>(S->tile_sum), 0u, L.ntiles, S->stream);
   launch_fill_u32(S->err, 0u, 64, S->stream);
@@ -1217,6 +1275,30 @@ mdlg_status mdlg_get_kinetics(mdlg_system* S, double* out) {
   const size_t n = S->L.reps.size() * (S->D + 1);
   HIPCHK(S, hipMemcpyAsync(out, S->kin, n * sizeof(double), hipMemcpyDeviceToHost, S->stream));
   return read_err(S);
+}
+
+mdlg_status mdlg_get_shifts(mdlg_system* S, uint64_t* counts, int64_t* moments, int64_t* n_steps) {
+  if (!S) return MDLG_E_INVALID;
+  const Layout& L = S->L;
+  if (L.n_shifts == 0) {
+    S->last_error = "no shifted lattices were configured (n_shifts = 0)";
+    return MDLG_E_STATE;
+  }
+  if (S->timing) close_run(S);
+  const int per = shift_per(L), nmo = per - L.Q - 1;
+  std::vector<unsigned long long> h((size_t)L.n_shifts * per);
+  HIPCHK(S, hipMemcpyAsync(h.data(), S->shift_acc, h.size() * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, S->stream));
+  mdlg_status st = read_err(S);
+  for (int j = 0; j < L.n_shifts; ++j) {
+    if (counts)
+      for (int i = 0; i <= L.Q; ++i) counts[(size_t)j * (L.Q + 1) + i] = h[(size_t)j * per + i];
+    if (moments)
+      for (int i = 0; i < nmo; ++i)
+        moments[(size_t)j * nmo + i] = (int64_t)h[(size_t)j * per + L.Q + 1 + i];
+  }
+  if (n_steps) *n_steps = S->n_lattice;
+  return st;
 }
 
 mdlg_status mdlg_get_xi(mdlg_system* S, int64_t* sums, int64_t* xi_site, int32_t* xi_last,

@@ -125,6 +125,24 @@ struct BinArgs {
   int snapshot_only;
   int BSX;
   unsigned* nstep;     // optional: this step's n_i(x,t) [sites][Q], overwritten
+  long long* shift_k;  // optional: lattice-time counter of the shifted lattices, advanced here
+};
+
+struct ShiftArgs {
+  Phys P;
+  const Replica* reps;
+  const int4* chunks;          // {replica, g0, g1, -}
+  const float* pos;            // sorted state at t
+  const int* img;
+  const int* cell;
+  const int* prev_u;           // snapshot at t - Delta t (sorted order)
+  const float* prev_off;
+  const double* shifts;        // [n_shifts][2][D]: offset a, drift b (lattice units)
+  const long long* shift_k;    // lattice time index k of t
+  unsigned long long* acc;     // [n_shifts][Q + 1 + D + D(D+1)/2]
+  double dx;                   // lattice spacing
+  int n_shifts;
+  int nchunks;
 };
 
 struct XiArgs {
@@ -260,6 +278,7 @@ void launch_nlist(int D, const NlistArgs& a, hipStream_t s);
 void launch_kin(const KinArgs& a, hipStream_t s);
 void launch_bin(int D, int nstrips, const BinArgs& a, hipStream_t s);
 void launch_xi(int D, const XiArgs& a, hipStream_t s);
+void launch_shift(int D, const ShiftArgs& a, hipStream_t s);
 void launch_fsum(const FsumArgs& a, hipStream_t s);
 void launch_ffinal(const FfinalArgs& a, hipStream_t s);
 void launch_site_avg(const SiteAvgArgs& a, hipStream_t s);

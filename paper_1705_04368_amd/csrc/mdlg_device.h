@@ -13,6 +13,7 @@ constexpr int kScanItems = kScanTile / kBlock;
 constexpr int kPartChunkMax = 512;   // particles per block of the per-particle kernels
 constexpr int kMaxStripSites = 16;   // lattice sites per block of the binning kernel
 constexpr int kMaxQ = 225;           // largest velocity window handled (V <= 7 in 2D, V <= 2 in 3D)
+constexpr int kMaxShifts = 32;       // displaced / moving lattices binned beside the main one
 
 // LDS budgets of the force kernel
 constexpr int kMaxHalo2 = 1536;      // halo cells per brick (2D)

@@ -1474,6 +1474,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs a) {
     }
   }
   if (a.snapshot_only) return;
+  if (a.shift_k && blockIdx.x == 0 && threadIdx.x == 0) *a.shift_k += 1;
   __syncthreads();
   const int sy_lin = (D == 2) ? R.M[0] * sy : R.M[0] * (sy + R.M[1] * sz);
   const size_t site0 = (size_t)R.site_off + sy_lin + sx0;
@@ -1618,6 +1619,98 @@ __global__ __launch_bounds__(kBlock) void k_import(XportArgs a) {
       sti<D>(a.prev_u, g, pu);
       stv<D>(a.prev_off, g, po);
     }
+  }
+}
+
+// ---------------------------------------------------------------- shifted lattices
+//
+// eq. (MDni) on lattices displaced by a_j + b_j k lattice spacings at lattice
+// time k: a particle's cell is floor(x / dx + a_j + b_j k) per axis.  A drift
+// b_j = u bins the Galilean-transformed positions x + u t (the section on the
+// velocity dependence of the equilibrium), so the histogram is f_i for mean
+// velocity u from one trajectory; static offsets a_j = m / K average over
+// lattice placements (the remark on exact momentum after the one-particle
+// table).  Per lattice j the block counts the window bins and the overflow
+// (wave-aggregated LDS atomics) and sums the lattice displacement and its
+// products over all particles; one atomic per non-zero counter and block.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_shift(ShiftArgs a) {
+  constexpr int NM = D + D * (D + 1) / 2;
+  const int Q = a.P.Q;
+  const int per = Q + 1 + NM;
+  __shared__ unsigned s_cnt[kMaxShifts * (kMaxQ + 1)];
+  __shared__ int s_mom[kMaxShifts][NM];
+  for (int e = threadIdx.x; e < a.n_shifts * (Q + 1); e += kBlock) s_cnt[e] = 0;
+  for (int e = threadIdx.x; e < a.n_shifts * NM; e += kBlock) s_mom[e / NM][e % NM] = 0;
+  __syncthreads();
+  const double kk = (double)*a.shift_k;
+  const int W = 2 * a.P.vmax + 1;
+  for (int c = blockIdx.x; c < a.nchunks; c += gridDim.x) {
+    const int4 ch = a.chunks[c];
+    const Replica R = a.reps[ch.x];
+    for (int g0 = ch.y; g0 < ch.z; g0 += kBlock) {
+      const int g = g0 + (int)threadIdx.x;
+      const bool valid = g < ch.z;
+      double y[D], yp[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        y[q] = 0.0;
+        yp[q] = 0.0;
+      }
+      if (valid) {
+        int cc[D], im[D], pu[D];
+        float o[D], po[D];
+        cell_coords<D>(a.cell[g] - R.cell_off, R, cc);
+        ldi<D>(a.img, g, im);
+        ldv<D>(a.pos, g, o);
+        ldi<D>(a.prev_u, g, pu);
+        ldv<D>(a.prev_off, g, po);
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+          const int u = cc[q] + R.Mc[q] * im[q];
+          y[q] = ((double)u * a.P.s_d + (double)o[q]) / a.dx;
+          yp[q] = ((double)pu[q] * a.P.s_d + (double)po[q]) / a.dx;
+        }
+      }
+      for (int j = 0; j < a.n_shifts; ++j) {
+        const double* sh = a.shifts + (size_t)j * 2 * D;
+        int v[D];
+        bool inside = true;
+        int bin = 0, stride = 1;
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+          const double now = sh[q] + sh[D + q] * kk;
+          const double before = sh[q] + sh[D + q] * (kk - 1.0);
+          v[q] = (int)floor(y[q] + now) - (int)floor(yp[q] + before);
+          inside = inside && v[q] >= -a.P.vmax && v[q] <= a.P.vmax;
+          bin += (v[q] + a.P.vmax) * stride;
+          stride *= W;
+        }
+        wave_agg_add(s_cnt + j * (Q + 1), inside ? bin : Q, valid);
+        if (valid) {
+          int kq = D;
+#pragma unroll
+          for (int p = 0; p < D; ++p) {
+            if (v[p] != 0) atomicAdd(&s_mom[j][p], v[p]);
+#pragma unroll
+            for (int q = p; q < D; ++q) {
+              if (v[p] * v[q] != 0) atomicAdd(&s_mom[j][kq], v[p] * v[q]);
+              ++kq;
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < a.n_shifts * (Q + 1); e += kBlock) {
+    const unsigned c = s_cnt[e];
+    if (c) atomicAdd(a.acc + (size_t)(e / (Q + 1)) * per + e % (Q + 1), (unsigned long long)c);
+  }
+  for (int e = threadIdx.x; e < a.n_shifts * NM; e += kBlock) {
+    const int m = s_mom[e / NM][e % NM];
+    if (m) atomicAdd(a.acc + (size_t)(e / NM) * per + Q + 1 + e % NM,
+                     (unsigned long long)(long long)m);
   }
 }
 
@@ -1789,6 +1882,12 @@ void launch_kin(const KinArgs& a, hipStream_t s) {
 void launch_bin(int D, int nstrips, const BinArgs& a, hipStream_t s) {
   const size_t lds = (size_t)a.BSX * (a.P.Q + a.P.nm) * sizeof(int);
   MDLG_LAUNCH_DIM(D, k_bin, nstrips, lds, s, a);
+}
+
+void launch_shift(int D, const ShiftArgs& a, hipStream_t s) {
+  const int grid = a.nchunks < 1024 ? a.nchunks : 1024;
+  if (grid <= 0 || a.n_shifts <= 0) return;
+  MDLG_LAUNCH_DIM(D, k_shift, grid, 0, s, a);
 }
 
 void launch_xi(int D, const XiArgs& a, hipStream_t s) {

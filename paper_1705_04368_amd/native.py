@@ -22,9 +22,9 @@ EXPORTED = ["mdlg_describe", "mdlg_workspace_bytes", "mdlg_create", "mdlg_step",
             "mdlg_coarse_grain", "mdlg_get_f", "mdlg_get_kinetics", "mdlg_reset_accumulators",
             "mdlg_get_state", "mdlg_set_state", "mdlg_adjoint", "mdlg_set_potential",
             "mdlg_set_timing", "mdlg_get_timing", "mdlg_sync", "mdlg_last_error", "mdlg_destroy",
-            "mdlg_autotune", "mdlg_autotune_workspace_bytes", "mdlg_get_xi"]
+            "mdlg_autotune", "mdlg_autotune_workspace_bytes", "mdlg_get_xi", "mdlg_get_shifts"]
 LOSSES = {"msd": 0, "mean_x": 1}
-KERNEL_CLASSES = ["force", "count", "scan", "scatter", "bin", "nlist", "xi"]
+KERNEL_CLASSES = ["force", "count", "scan", "scatter", "bin", "nlist", "xi", "shift"]
 
 
 class MdlgConfig(C.Structure):
@@ -38,7 +38,8 @@ class MdlgConfig(C.Structure):
                 ("brick_x", C.c_int32), ("brick_y", C.c_int32), ("brick_z", C.c_int32),
                 ("adjoint_window", C.c_int32), ("adjoint_every", C.c_int32),
                 ("no_pair_list", C.c_int32), ("block_threads", C.c_int32),
-                ("collision_stats", C.c_int32)]
+                ("collision_stats", C.c_int32), ("n_shifts", C.c_int32),
+                ("shifts", C.POINTER(C.c_double))]
 
 
 class MdlgParticles(C.Structure):
@@ -113,6 +114,8 @@ def load():
     lib.mdlg_autotune.restype = st
     lib.mdlg_autotune.argtypes = [P(MdlgConfig), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_int32, P(MdlgConfig), P(C.c_double)]
+    lib.mdlg_get_shifts.restype = st
+    lib.mdlg_get_shifts.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, P(C.c_int64)]
     lib.mdlg_get_xi.restype = st
     lib.mdlg_get_xi.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, P(C.c_int64)]
     lib.mdlg_autotune_workspace_bytes.restype = st
@@ -137,7 +140,7 @@ def make_config(dim, n_particles, lattice, lattice_dx=4.0, epsilon=1.0, sigma=1.
                 r_cut=2.5, forces_off=False, dt=0.005, md_steps_per_lattice_step=20, vmax=3,
                 thermostat_every=0, kT=1.0, md_cell_split=0, sort_every=0, brick=(0, 0, 0),
                 adjoint_window=0, adjoint_every=1, pair_list=True, block_threads=0,
-                collision_stats=False):
+                collision_stats=False, shifts=None):
     """Build an MdlgConfig.  n_particles: int or sequence per replica; lattice:
     sites per axis, an int, a (dim,) sequence or an (n_replicas, dim) array."""
     n = np.atleast_1d(np.asarray(n_particles, dtype=np.int32))
@@ -170,6 +173,14 @@ def make_config(dim, n_particles, lattice, lattice_dx=4.0, epsilon=1.0, sigma=1.
     cfg.no_pair_list = 0 if pair_list else 1
     cfg.block_threads = block_threads
     cfg.collision_stats = int(bool(collision_stats))
+    keep = [n, lat]
+    if shifts is not None:
+        # [n_shifts][2][dim]: offset a and drift b per axis, in lattice spacings
+        sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64).reshape(-1, 2, dim))
+        cfg.n_shifts = sh.shape[0]
+        cfg.shifts = sh.ctypes.data_as(C.POINTER(C.c_double))
+        keep.append(sh)
+    cfg._keep = tuple(keep)
     return cfg
 
 
@@ -272,6 +283,18 @@ class System:
             self.close()
         except Exception:
             pass
+
+    def get_shifts(self):
+        """Histograms of the displaced / moving lattices (mdlg_get_shifts):
+        counts [n_shifts, Q + 1] (window bins, then overflow), moments
+        [n_shifts, d + d(d+1)/2] (sum of v_a, then v_a v_b) and n_steps."""
+        ns = int(self.cfg.n_shifts)
+        counts = np.zeros((ns, self.Q + 1), dtype=np.uint64)
+        mom = np.zeros((ns, self.dim + self.dim * (self.dim + 1) // 2), dtype=np.int64)
+        n = C.c_int64(0)
+        _check(load().mdlg_get_shifts(self.handle, counts.ctypes.data_as(C.c_void_p),
+                                      mom.ctypes.data_as(C.c_void_p), C.byref(n)), self.handle)
+        return {"counts": counts, "moments": mom, "n_steps": int(n.value)}
 
     def get_xi(self, per_site=False, last=False):
         """Collision-operator statistics (mdlg_get_xi): dict with the number of
