@@ -722,7 +722,8 @@ __device__ __forceinline__ bool row_columns(const BrickGeom& G, const Phys& P, i
 template <int D>
 __device__ __forceinline__ void vv_update(const ForceArgs& a, const Phys& P, int rep, int gi,
                                           const float (&o)[D], const float (&v)[D],
-                                          const float (&f)[D], double (&kin)[D + 1]) {
+                                          const float (&f)[D], double (&kin)[D + 1],
+                                          const float (&o0_pre)[D], bool have_o0) {
   float vf[D];
   const float lam = (a.mode == kModeStart && a.lambda) ? a.lambda[rep] : 1.f;
   const bool drift = (a.mode == kModeStep || a.mode == kModeStart);
@@ -742,7 +743,12 @@ __device__ __forceinline__ void vv_update(const ForceArgs& a, const Phys& P, int
     if (!ok) atomicOr(a.err, kErrMargin);
     if (a.check_disp) {
       float o0[D];
-      ldv<D>(a.off0, gi, o0);
+      if (have_o0) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) o0[k] = o0_pre[k];
+      } else {
+        ldv<D>(a.off0, gi, o0);
+      }
       float d2 = 0.f;
 #pragma unroll
       for (int k = 0; k < D; ++k) d2 = fmaf(on[k] - o0[k], on[k] - o0[k], d2);
@@ -778,6 +784,25 @@ __device__ __forceinline__ void list_word(const Lds& L, unsigned long long e, in
   for (int u = 0; u < 4; ++u) lj_pair_listed<D>(q[u], X, Y, Z, P, f);
 }
 
+// Target record {particle, LDS slot | words << 16} of the list path, with the
+// particle's offset, velocity, reference offset and first list words.
+template <int D, int GW>
+__device__ __forceinline__ void list_fetch(const ForceArgs& a, int2 r, bool has, size_t nt,
+                                           unsigned long long pad, int& gi, int& t, int& ng,
+                                           float (&o)[D], float (&v)[D], float (&o0)[D],
+                                           unsigned long long (&w)[GW]) {
+  gi = r.x;
+  t = r.y & 0xffff;
+  ng = has ? ((unsigned)r.y >> 16) : 0;
+  if (has) {
+    ldv<D>(a.pos_in, gi, o);
+    ldv<D>(a.vel, gi, v);
+    if (a.check_disp) ldv<D>(a.off0, gi, o0);
+  }
+#pragma unroll
+  for (int u = 0; u < GW; ++u) w[u] = (u < ng) ? a.nl[(size_t)u * nt + gi] : pad;
+}
+
 template <int D, int NT>
 __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
   extern __shared__ __align__(16) char s_dyn_brick[];
@@ -803,6 +828,16 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
 #pragma unroll
   for (int k = 0; k <= D; ++k) kin[k] = 0.0;
 
+  // the list path's first staging-map entries and target record are
+  // requested together with the brick's header (their addresses do not
+  // depend on it; entries past the brick's counts are ignored)
+  int2 pre_e0 = make_int2(0, 0), pre_e1 = make_int2(0, 0), pre_r = make_int2(0, 0);
+  if (a.nl) {
+    const int2* __restrict__ sm = a.smap + (size_t)b * CAP;
+    pre_e0 = sm[min((int)threadIdx.x, CAP - 1)];
+    pre_e1 = sm[min((int)threadIdx.x + NT, CAP - 1)];
+    pre_r = a.trec[(size_t)b * CAP + min((int)threadIdx.x, CAP - 1)];
+  }
   const int4 bi = a.nl ? a.binfo[b] : make_int4(0, 0, 0, 0);
   if (bi.z) {
     // pair-list path: stage the halo through the map written by the list
@@ -819,22 +854,11 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
     constexpr int GW = (D == 2) ? 2 : 4;
     const unsigned long long pad = 0x0001000100010001ull * (unsigned)(total * sizeof(Coord<D>));
     int gi = 0, t = 0, ng = 0;
-    float o[D], v[D];
-    unsigned long long w[GW];
-    auto fetch = [&](int k) {
-      const bool has = k < ntg;
-      const int2 r = has ? trec[k] : make_int2(0, 0);
-      gi = r.x;
-      t = r.y & 0xffff;
-      ng = has ? ((unsigned)r.y >> 16) : 0;
-      if (has) {
-        ldv<D>(a.pos_in, gi, o);
-        ldv<D>(a.vel, gi, v);
-      }
+    float o[D], v[D], o0[D];
 #pragma unroll
-      for (int u = 0; u < GW; ++u) w[u] = (u < ng) ? a.nl[(size_t)u * nt + gi] : pad;
-    };
-    fetch((int)threadIdx.x);
+    for (int k = 0; k < D; ++k) o0[k] = 0.f;
+    unsigned long long w[GW];
+    list_fetch<D, GW>(a, pre_r, (int)threadIdx.x < ntg, nt, pad, gi, t, ng, o, v, o0, w);
     if (threadIdx.x == 0) {
       if constexpr (D == 2) L.p[total] = make_int2(kSentinel, kSentinel);
       else L.p[total] = make_int4(kSentinel, kSentinel, kSentinel, 0);
@@ -845,7 +869,8 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int vv = v0 + u * NT;
-        e[u] = smap[min(vv, total - 1)];
+        e[u] = (v0 == (int)threadIdx.x && vv < total) ? (u == 0 ? pre_e0 : pre_e1)
+                                                       : smap[min(vv, total - 1)];
         ldv<D>(a.pos_in, e[u].x, p[u]);
       }
 #pragma unroll
@@ -864,7 +889,8 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
     __syncthreads();
     for (int tb = 0; tb < ntg; tb += NT) {
       if (tb + (int)threadIdx.x >= ntg) break;
-      if (tb > 0) fetch(tb + (int)threadIdx.x);
+      if (tb > 0)
+        list_fetch<D, GW>(a, trec[tb + threadIdx.x], true, nt, pad, gi, t, ng, o, v, o0, w);
       const Coord<D> me = L.p[t];
       const int X = me.x, Y = me.y;
       int Z = 0;
@@ -886,7 +912,7 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
 #pragma unroll
         for (int u = 0; u < GW; ++u) w[u] = nx[u];
       }
-      vv_update<D>(a, P, br.x, gi, o, v, f, kin);
+      vv_update<D>(a, P, br.x, gi, o, v, f, kin, o0, true);
     }
   } else {
     const Replica R = a.reps[br.x];
@@ -946,7 +972,7 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
           }
         }
       }
-      if (valid) vv_update<D>(a, P, br.x, gi, o, v, f, kin);
+      if (valid) vv_update<D>(a, P, br.x, gi, o, v, f, kin, o, false);
     }
   }
   if (a.kpart) {
