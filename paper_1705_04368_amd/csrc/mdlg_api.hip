@@ -226,6 +226,9 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   L->margin_max = m_max;
   L->margin = (vfast > 0) ? std::min(m_max, R * vfast * c->dt) : m_max;
   if (L->margin < 0) L->margin = 0;
+  // a particle then sits less than one cell outside its own (the pair-list
+  // builder's coordinate range relies on it)
+  if (L->margin >= L->s) return set_err(msg, "rebuild margin %g reaches the cell side %g", L->margin, L->s);
   // force bricks
   int BX = c->brick_x, BY = c->brick_y, BZ = c->brick_z;
   const double per_cell = rho * std::pow(L->s, D);
@@ -595,6 +598,19 @@ Phys make_phys(const mdlg_config* c, const Layout& L) {
     const double rl = c->r_cut + 2 * L.margin;
     P.rlq = (int)std::ceil(rl / u) + 1;
     P.rl2_u = (float)((rl / u) * (rl / u) * (1 + 1e-5));
+    // The list builder compares coarser copies of the coordinates: the halo of
+    // the widest brick, widened by two cells on either side (a particle sits
+    // less than one cell outside its own), in 14-bit units, so that a squared
+    // distance over three axes cannot overflow 31 bits.  Each axis of a
+    // difference is off by less than one unit, so its length by less than
+    // sqrt(D) units: the threshold widened by that keeps every pair within
+    // the list radius (a few pairs just beyond it enter the list too).
+    const int hx16 = std::max(std::max(L.BX, L.BY), L.D == 3 ? L.BZ : 1) + 2 * L.ns + 4;
+    int lg16 = 0;
+    while ((1 << lg16) < hx16) ++lg16;
+    P.sh16 = std::max(0, P.F - (14 - lg16));
+    const double r16 = rl / (u * std::ldexp(1.0, P.sh16)) + std::sqrt((double)L.D);
+    P.rl16 = (int)std::ceil(r16 * r16) + 1;
     P.kmax = L.kmax;
     P.disp2 = (float)(L.margin * L.margin);
   }

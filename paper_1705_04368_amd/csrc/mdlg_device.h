@@ -64,6 +64,8 @@ struct Phys {
   int mq;           // rebuild margin / u, rounded up, plus a few units
   int rlq;          // pair-list radius (r_cut + 2 margin) / u, rounded up
   float rl2_u;      // (pair-list radius / u)^2, widened against rounding
+  int sh16;         // list builder: 14-bit coordinate = (fixed + 2 cells) >> sh16
+  int rl16;         // list builder: accept a candidate when |d|^2 < rl16 in 14-bit units
   int kmax;         // pair-list slots per particle (multiple of 4; 0 = no lists)
   float disp2;      // largest squared displacement since the lists were built
   int lmaxh;        // halo cells of the largest brick (dynamic LDS table)

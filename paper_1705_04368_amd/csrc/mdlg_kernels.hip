@@ -413,15 +413,24 @@ __global__ __launch_bounds__(kBlock) void k_scatter(SortArgs a) {
 template <int D>
 using Coord = typename std::conditional<D == 2, int2, int4>::type;
 
+// The pair-list builder's coarser copy of a staged coordinate: 14-bit values,
+// x and y packed in one word (z in a second word in 3D).
+template <int D>
+using Coord14 = typename std::conditional<D == 2, unsigned, uint2>::type;
+
+// Candidates the pair-list builder tests per step (read past the end of a row
+// into a padding of as many slots behind the staged particles).
+constexpr int kNlGroup = 16;
+
 // LDS of a brick: the halo cell table and the staged particles live in the
 // dynamic shared memory, sized by the host from the brick extent and the
 // density (lmaxh halo cells, lcap staged particles per chunk); the small
 // arrays are static.
-template <int D, bool ADJ>
+template <int D, bool ADJ, class CT = Coord<D>>
 struct BrickLds {
   int* hs;            // LDS start of every halo cell (exclusive scan of counts)
   int* gs;            // global start of every halo cell
-  Coord<D>* p;        // fixed-point coordinates of the staged particles
+  CT* p;              // fixed-point coordinates of the staged particles
   float* lam;         // adjoint velocity of the staged particles (ADJ)
   int* rowpre;
   int* tmp;
@@ -429,20 +438,23 @@ struct BrickLds {
   int cap;
 };
 
+// Dynamic LDS of the pair-list builder: the 14-bit coordinates with their
+// padding, then the halo tables.
 template <int D>
-__device__ __forceinline__ size_t brick_lds_bytes_dev(const Phys& P) {
+__device__ __forceinline__ size_t nlist_lds_bytes_dev(const Phys& P) {
   const size_t tables = ((size_t)(2 * P.lmaxh + 1) * sizeof(int) + 15) & ~size_t(15);
-  return tables + (size_t)P.lcap * sizeof(Coord<D>);
+  return tables + (((size_t)(P.lcap + kNlGroup) * sizeof(Coord14<D>) + 15) & ~size_t(15));
 }
 
-template <int D, bool ADJ>
-__device__ __forceinline__ BrickLds<D, ADJ> brick_lds(char* dyn, int* rowpre, int* tmp,
-                                                      double (*red)[4], const Phys& P) {
+template <int D, bool ADJ, class CT = Coord<D>>
+__device__ __forceinline__ BrickLds<D, ADJ, CT> brick_lds(char* dyn, int* rowpre, int* tmp,
+                                                          double (*red)[4], const Phys& P,
+                                                          int pad = 0) {
   // the staged coordinates come first, at the fixed start of the dynamic LDS,
   // so that a list entry (a byte offset) addresses them without arithmetic
-  BrickLds<D, ADJ> L;
-  L.p = reinterpret_cast<Coord<D>*>(dyn);
-  size_t off = (size_t)P.lcap * sizeof(Coord<D>);
+  BrickLds<D, ADJ, CT> L;
+  L.p = reinterpret_cast<CT*>(dyn);
+  size_t off = ((size_t)(P.lcap + pad) * sizeof(CT) + 15) & ~size_t(15);
   L.lam = reinterpret_cast<float*>(dyn + off);
   if (ADJ) off += (size_t)P.lcap * D * sizeof(float);
   L.hs = reinterpret_cast<int*>(dyn + off);
@@ -460,6 +472,25 @@ struct BrickGeom {
 
 __device__ __forceinline__ int fixed_coord(int h, float off, const Phys& P) {
   return (h << P.F) + __float2int_rn(off * P.fscale);
+}
+
+// 14-bit copy of a fixed-point coordinate (which lies above minus one cell):
+// shifted up by two cells and truncated to the list builder's coarser unit.
+__device__ __forceinline__ unsigned coord14(int x, const Phys& P) {
+  return ((unsigned)x + (2u << P.F)) >> P.sh16;
+}
+
+__device__ __forceinline__ void put_coord(int2* p, int i, int x, int y, int, const Phys&) {
+  p[i] = make_int2(x, y);
+}
+__device__ __forceinline__ void put_coord(int4* p, int i, int x, int y, int z, const Phys&) {
+  p[i] = make_int4(x, y, z, 0);
+}
+__device__ __forceinline__ void put_coord(unsigned* p, int i, int x, int y, int, const Phys& P) {
+  p[i] = coord14(x, P) | (coord14(y, P) << 16);
+}
+__device__ __forceinline__ void put_coord(uint2* p, int i, int x, int y, int z, const Phys& P) {
+  p[i] = make_uint2(coord14(x, P) | (coord14(y, P) << 16), coord14(z, P));
 }
 
 // Halo table of a brick: particle count of every halo cell, exclusive scan
@@ -573,10 +604,10 @@ __device__ __forceinline__ void brick_stage(const BrickGeom& G, const Phys& P,
       if (v < ce) {
         const int hx = hh[u] % G.HX, r = hh[u] / G.HX;
         if constexpr (D == 2)
-          L.p[v - cb] = make_int2(fixed_coord(hx, p[u][0], P), fixed_coord(r, p[u][1], P));
+          put_coord(L.p, v - cb, fixed_coord(hx, p[u][0], P), fixed_coord(r, p[u][1], P), 0, P);
         else
-          L.p[v - cb] = make_int4(fixed_coord(hx, p[u][0], P), fixed_coord(r % G.HY, p[u][1], P),
-                                  fixed_coord(r / G.HY, p[u][2], P), 0);
+          put_coord(L.p, v - cb, fixed_coord(hx, p[u][0], P), fixed_coord(r % G.HY, p[u][1], P),
+                    fixed_coord(r / G.HY, p[u][2], P), P);
         if (lam) {
           float l[D];
           ldv<D>(lam, g[u], l);
@@ -1000,15 +1031,26 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
 // word padded with the target's own index (a zero term).  A brick whose
 // halo exceeds one LDS chunk, or with a target of more than kmax neighbours,
 // is marked for the cell walk.
-template <int D, typename C>
-__device__ __forceinline__ bool list_near(const C& q, int X, int Y, int Z, float rl2) {
-  const float dx = (float)(q.x - X), dy = (float)(q.y - Y);
-  float r2 = dx * dx + dy * dy;
-  if constexpr (D == 3) {
-    const float dz = (float)(q.z - Z);
-    r2 += dz * dz;
+typedef short Short2 __attribute__((ext_vector_type(2)));
+
+// List-radius test of candidate q against the target (Txy, Tz) in 14-bit
+// units: |d|^2 - rl16, negative when q is near.  The x and y differences are
+// taken as a packed 16-bit pair and squared and summed by a dot product onto
+// dz^2 - rl16 (a 24-bit multiply-add); no term can overflow, as each
+// coordinate stays below 2^14.
+template <int D>
+__device__ __forceinline__ int list_test14(Coord14<D> q, unsigned Txy, int Tz, int thr) {
+  unsigned qxy;
+  int acc = -thr;
+  if constexpr (D == 2) {
+    qxy = q;
+  } else {
+    qxy = q.x;
+    const int dz = (int)q.y - Tz;
+    acc = __mul24(dz, dz) - thr;
   }
-  return r2 < rl2;
+  const Short2 d = __builtin_bit_cast(Short2, qxy) - __builtin_bit_cast(Short2, Txy);
+  return __builtin_amdgcn_sdot2(d, d, acc, false);
 }
 
 // Append entry nj to a list being built four 16-bit entries per word;
@@ -1035,10 +1077,10 @@ __global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
   __shared__ double s_red[NW][4];
   __shared__ int s_over;
   __shared__ int s_cnt[64];
-  auto L = brick_lds<D, false>(s_dyn_brick, s_rowpre, s_tmp, s_red, a.P);
+  auto L = brick_lds<D, false, Coord14<D>>(s_dyn_brick, s_rowpre, s_tmp, s_red, a.P, kNlGroup);
   // word count of every target's list (dynamic LDS behind the brick's own)
   unsigned char* s_words =
-      reinterpret_cast<unsigned char*>(s_dyn_brick) + brick_lds_bytes_dev<D>(a.P);
+      reinterpret_cast<unsigned char*>(s_dyn_brick) + nlist_lds_bytes_dev<D>(a.P);
   const int CAP = L.cap;
   int b = blockIdx.x;
   if (a.xcd_remap) {
@@ -1057,7 +1099,7 @@ __global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
   __syncthreads();
   const size_t nt = (size_t)P.n_total;
   const int kmax = P.kmax;
-  const float rl2 = P.rl2_u;
+  const int thr = P.rl16;
   for (int tb = 0; tb < G.ntg; tb += NT) {
     const int t = tb + (int)threadIdx.x;
     if (t >= G.ntg) break;
@@ -1067,10 +1109,12 @@ __global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
     ldv<D>(a.pos, gi, o);
     stv<D>(a.off0, gi, o);
     if (!fits) continue;
-    const Coord<D> me = L.p[vi];
-    const int X = me.x, Y = me.y;
+    // the target's fixed-point coordinates, as the force kernel stages them
+    const int X = fixed_coord(hxi, o[0], P), Y = fixed_coord(hyi, o[1], P);
     int Z = 0;
-    if constexpr (D == 3) Z = me.z;
+    if constexpr (D == 3) Z = fixed_coord(hzi, o[D - 1], P);
+    const unsigned Txy = coord14(X, P) | (coord14(Y, P) << 16);
+    const int Tz = (D == 3) ? (int)coord14(Z, P) : 0;
     const Reach rr = target_reach<D>(G, P, X, Y, Z, P.rlq);
     unsigned long long* wp = a.nl + gi;  // next list word
     unsigned long long word = 0;
@@ -1089,23 +1133,24 @@ __global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
         const int s1 = list_shift(G, L, G.ns, cy, cz);
         const int s2 = list_shift(G, L, G.ns + G.wx, cy, cz);
         const int jhi = L.hs[hrow + cx1 + 1];
-        // test up to 32 candidates into a bit mask (four LDS reads in flight),
-        // then append the accepted ones: the appends cost per accepted entry
-        // rather than per candidate
-        for (int j0 = L.hs[hrow + cx0]; j0 < jhi; j0 += 32) {
-          const int nb = min(32, jhi - j0);
-          unsigned mask = 0;
-          int u = 0;
-          for (; u + 3 < nb; u += 4) {
-            Coord<D> q[4];
+        // test kNlGroup candidates into a bit mask (the last group of a row
+        // reads into the next row or the padding and is masked), then append
+        // the accepted ones: the appends cost per accepted entry rather than
+        // per candidate
+        for (int j0 = L.hs[hrow + cx0]; j0 < jhi; j0 += kNlGroup) {
+          int r[kNlGroup];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) q[e] = L.p[j0 + u + e];
+          for (int e = 0; e < kNlGroup; ++e) r[e] = list_test14<D>(L.p[j0 + e], Txy, Tz, thr);
+          // sign bits into a mask (m << 1 | sign); candidate e then sits at
+          // bit kNlGroup - 1 - e: reverse
+          unsigned m = 0;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) mask |= (unsigned)list_near<D>(q[e], X, Y, Z, rl2) << (u + e);
-          }
-          for (; u < nb; ++u) mask |= (unsigned)list_near<D>(L.p[j0 + u], X, Y, Z, rl2) << u;
+          for (int e = 0; e < kNlGroup; ++e) m = __builtin_amdgcn_alignbit(m, (unsigned)r[e], 31);
+          unsigned mask = __builtin_bitreverse32(m) >> (32 - kNlGroup);
+          const int nb = jhi - j0;
+          if (nb < kNlGroup) mask &= (1u << nb) - 1u;
           const unsigned self = (unsigned)(vi - j0);
-          if (self < 32u) mask &= ~(1u << self);
+          if (self < (unsigned)kNlGroup) mask &= ~(1u << self);
           while (mask) {
             const int j = j0 + __builtin_ctz(mask);
             mask &= mask - 1;
@@ -1896,8 +1941,12 @@ void launch_force(int D, const ForceArgs& a, hipStream_t s) {
 void launch_nlist(int D, const NlistArgs& a, hipStream_t s) {
   int grid = a.nbricks;
   if (a.xcd_remap) grid = ((a.nbricks + 7) / 8) * 8;
-  // the brick's LDS plus one byte per target for the list word counts
-  const size_t lds = brick_lds_bytes(a.P, D, false) + (size_t)a.P.lcap;
+  // the brick's LDS (14-bit coordinates) plus one byte per target for the
+  // list word counts
+  const size_t tables = ((size_t)(2 * a.P.lmaxh + 1) * sizeof(int) + 15) & ~size_t(15);
+  const size_t coord = (D == 2) ? sizeof(unsigned) : sizeof(uint2);
+  const size_t lds = tables + (((size_t)(a.P.lcap + kNlGroup) * coord + 15) & ~size_t(15)) +
+                     (size_t)a.P.lcap;
   MDLG_LAUNCH_BRICK(D, a.P.bthreads, k_nlist, grid, lds, s, a);
 }
 
