@@ -418,9 +418,11 @@ using Coord = typename std::conditional<D == 2, int2, int4>::type;
 template <int D>
 using Coord14 = typename std::conditional<D == 2, unsigned, uint2>::type;
 
-// Candidates the pair-list builder tests per step (read past the end of a row
-// into a padding of as many slots behind the staged particles).
-constexpr int kNlGroup = 16;
+// Candidates the pair-list builder tests per step, and the padding of as
+// many slots behind the staged particles that the last step of a row may read.
+template <int D>
+constexpr int nl_group() { return D == 2 ? 16 : 32; }
+constexpr int kNlPad = 32;
 
 // LDS of a brick: the halo cell table and the staged particles live in the
 // dynamic shared memory, sized by the host from the brick extent and the
@@ -443,7 +445,7 @@ struct BrickLds {
 template <int D>
 __device__ __forceinline__ size_t nlist_lds_bytes_dev(const Phys& P) {
   const size_t tables = ((size_t)(2 * P.lmaxh + 1) * sizeof(int) + 15) & ~size_t(15);
-  return tables + (((size_t)(P.lcap + kNlGroup) * sizeof(Coord14<D>) + 15) & ~size_t(15));
+  return tables + (((size_t)(P.lcap + kNlPad) * sizeof(Coord14<D>) + 15) & ~size_t(15));
 }
 
 template <int D, bool ADJ, class CT = Coord<D>>
@@ -1053,18 +1055,17 @@ __device__ __forceinline__ int list_test14(Coord14<D> q, unsigned Txy, int Tz, i
   return __builtin_amdgcn_sdot2(d, d, acc, false);
 }
 
-// Append entry nj to a list being built four 16-bit entries per word;
-// completed words go to *wp, which then steps to the next word (stride nt).
-__device__ __forceinline__ void list_push(unsigned long long*& wp, unsigned long long& word, int& cnt,
-                                          int& seen, int nj, int kmax, size_t nt) {
-  ++seen;
-  if (cnt < kmax) {
-    word |= (unsigned long long)(unsigned)nj << ((cnt & 3) << 4);
-    if ((++cnt & 3) == 0) {
-      *wp = word;
-      wp += nt;
-      word = 0;
-    }
+// Append entry e to a list being built four 16-bit entries per word: the
+// word (hi, lo) shifts down by one entry and e enters at the top, so that the
+// first of four entries ends in the lowest bits; completed words go to *wp,
+// which then steps to the next word (stride nt).
+__device__ __forceinline__ void list_push(unsigned long long*& wp, unsigned& hi, unsigned& lo, int& cnt,
+                                          unsigned e, size_t nt) {
+  lo = __builtin_amdgcn_alignbit(hi, lo, 16);
+  hi = __builtin_amdgcn_alignbit(e, hi, 16);
+  if ((++cnt & 3) == 0) {
+    *wp = ((unsigned long long)hi << 32) | lo;
+    wp += nt;
   }
 }
 
@@ -1077,7 +1078,7 @@ __global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
   __shared__ double s_red[NW][4];
   __shared__ int s_over;
   __shared__ int s_cnt[64];
-  auto L = brick_lds<D, false, Coord14<D>>(s_dyn_brick, s_rowpre, s_tmp, s_red, a.P, kNlGroup);
+  auto L = brick_lds<D, false, Coord14<D>>(s_dyn_brick, s_rowpre, s_tmp, s_red, a.P, kNlPad);
   // word count of every target's list (dynamic LDS behind the brick's own)
   unsigned char* s_words =
       reinterpret_cast<unsigned char*>(s_dyn_brick) + nlist_lds_bytes_dev<D>(a.P);
@@ -1117,8 +1118,9 @@ __global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
     const int Tz = (D == 3) ? (int)coord14(Z, P) : 0;
     const Reach rr = target_reach<D>(G, P, X, Y, Z, P.rlq);
     unsigned long long* wp = a.nl + gi;  // next list word
-    unsigned long long word = 0;
+    unsigned whi = 0, wlo = 0;
     int cnt = 0, seen = 0;
+    constexpr int GR = nl_group<D>();
     for (int cz = rr.cz0; cz <= rr.cz1; ++cz) {
       for (int cy = rr.cy0; cy <= rr.cy1; ++cy) {
         int cx0, cx1;
@@ -1133,39 +1135,42 @@ __global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
         const int s1 = list_shift(G, L, G.ns, cy, cz);
         const int s2 = list_shift(G, L, G.ns + G.wx, cy, cz);
         const int jhi = L.hs[hrow + cx1 + 1];
-        // test kNlGroup candidates into a bit mask (the last group of a row
-        // reads into the next row or the padding and is masked), then append
-        // the accepted ones: the appends cost per accepted entry rather than
-        // per candidate
-        for (int j0 = L.hs[hrow + cx0]; j0 < jhi; j0 += kNlGroup) {
-          int r[kNlGroup];
+        // test GR candidates into a bit mask (the last group of a row reads
+        // into the next row or the padding and is masked), then append the
+        // accepted ones: the appends cost per accepted entry rather than per
+        // candidate
+        for (int j0 = L.hs[hrow + cx0]; j0 < jhi; j0 += GR) {
+          int r[GR];
 #pragma unroll
-          for (int e = 0; e < kNlGroup; ++e) r[e] = list_test14<D>(L.p[j0 + e], Txy, Tz, thr);
+          for (int e = 0; e < GR; ++e) r[e] = list_test14<D>(L.p[j0 + e], Txy, Tz, thr);
           // sign bits into a mask (m << 1 | sign); candidate e then sits at
-          // bit kNlGroup - 1 - e: reverse
+          // bit GR - 1 - e: reverse
           unsigned m = 0;
 #pragma unroll
-          for (int e = 0; e < kNlGroup; ++e) m = __builtin_amdgcn_alignbit(m, (unsigned)r[e], 31);
-          unsigned mask = __builtin_bitreverse32(m) >> (32 - kNlGroup);
+          for (int e = 0; e < GR; ++e) m = __builtin_amdgcn_alignbit(m, (unsigned)r[e], 31);
+          unsigned mask = __builtin_bitreverse32(m);
+          if constexpr (GR < 32) mask >>= 32 - GR;
           const int nb = jhi - j0;
-          if (nb < kNlGroup) mask &= (1u << nb) - 1u;
+          if (nb < GR) mask &= (1u << nb) - 1u;
           const unsigned self = (unsigned)(vi - j0);
-          if (self < (unsigned)kNlGroup) mask &= ~(1u << self);
+          if (self < (unsigned)GR) mask &= ~(1u << self);
+          const int add = __popc(mask);
+          seen += add;
+          // a list longer than kmax sends the brick to the cell walk: its
+          // entries need not be complete, only kept within the slots
+          if (cnt + add > kmax) mask = 0;
           while (mask) {
             const int j = j0 + __builtin_ctz(mask);
             mask &= mask - 1;
-            list_push(wp, word, cnt, seen,
-                      (j + (j < ja ? s0 : (j < jb ? s1 : s2))) * (int)sizeof(Coord<D>), kmax, nt);
+            list_push(wp, whi, wlo, cnt,
+                      (unsigned)((j + (j < ja ? s0 : (j < jb ? s1 : s2))) * (int)sizeof(Coord<D>)), nt);
           }
         }
       }
     }
     if (seen > kmax) s_over = 1;
-    if (cnt & 3) {
-      for (int u = cnt & 3; u < 4; ++u)
-        word |= (unsigned long long)(unsigned)(G.total * (int)sizeof(Coord<D>)) << (16 * u);
-      *wp = word;
-    }
+    // pad the last word with the sentinel (far outside the cutoff)
+    while (cnt & 3) list_push(wp, whi, wlo, cnt, (unsigned)(G.total * (int)sizeof(Coord<D>)), nt);
     const int words = (cnt + 3) >> 2;
     smap[t] = make_int2(gi, pack_halo(hxi, hyi, hzi) | ((words * 4) << 24));
     s_words[t] = (unsigned char)words;
@@ -1945,7 +1950,7 @@ void launch_nlist(int D, const NlistArgs& a, hipStream_t s) {
   // list word counts
   const size_t tables = ((size_t)(2 * a.P.lmaxh + 1) * sizeof(int) + 15) & ~size_t(15);
   const size_t coord = (D == 2) ? sizeof(unsigned) : sizeof(uint2);
-  const size_t lds = tables + (((size_t)(a.P.lcap + kNlGroup) * coord + 15) & ~size_t(15)) +
+  const size_t lds = tables + (((size_t)(a.P.lcap + kNlPad) * coord + 15) & ~size_t(15)) +
                      (size_t)a.P.lcap;
   MDLG_LAUNCH_BRICK(D, a.P.bthreads, k_nlist, grid, lds, s, a);
 }
