@@ -611,6 +611,9 @@ Phys make_phys(const mdlg_config* c, const Layout& L) {
     P.sh16 = std::max(0, P.F - (14 - lg16));
     const double r16 = rl / (u * std::ldexp(1.0, P.sh16)) + std::sqrt((double)L.D);
     P.rl16 = (int)std::ceil(r16 * r16) + 1;
+    // candidates of the row through the target: its reach plus one cell
+    const double row = (2 * rl + L.s) * std::pow(L.s, L.D - 1) * L.per_cell / std::pow(L.s, L.D);
+    P.nl_wide = row >= 48 ? 1 : 0;
     P.kmax = L.kmax;
     P.disp2 = (float)(L.margin * L.margin);
   }

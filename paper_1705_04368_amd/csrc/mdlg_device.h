@@ -66,6 +66,7 @@ struct Phys {
   float rl2_u;      // (pair-list radius / u)^2, widened against rounding
   int sh16;         // list builder: 14-bit coordinate = (fixed + 2 cells) >> sh16
   int rl16;         // list builder: accept a candidate when |d|^2 < rl16 in 14-bit units
+  int nl_wide;      // list builder: test 32 candidates per step (long rows) instead of 16
   int kmax;         // pair-list slots per particle (multiple of 4; 0 = no lists)
   float disp2;      // largest squared displacement since the lists were built
   int lmaxh;        // halo cells of the largest brick (dynamic LDS table)

@@ -418,10 +418,8 @@ using Coord = typename std::conditional<D == 2, int2, int4>::type;
 template <int D>
 using Coord14 = typename std::conditional<D == 2, unsigned, uint2>::type;
 
-// Candidates the pair-list builder tests per step, and the padding of as
-// many slots behind the staged particles that the last step of a row may read.
-template <int D>
-constexpr int nl_group() { return D == 2 ? 16 : 32; }
+// Padding behind the pair-list builder's staged particles: the last test step
+// of a row (16 or 32 candidates) may read that far past its end.
 constexpr int kNlPad = 32;
 
 // LDS of a brick: the halo cell table and the staged particles live in the
@@ -1069,6 +1067,46 @@ __device__ __forceinline__ void list_push(unsigned long long*& wp, unsigned& hi,
   }
 }
 
+// One row of a target's candidates, LDS range [jlo, jhi): test GR candidates
+// at a time into a bit mask (the last step reads into the next row or the
+// padding and is masked), then append the accepted ones, so that appends cost
+// per accepted entry rather than per candidate.  Entries are force-kernel LDS
+// byte offsets: the row's LDS index plus its list shift (s0 left of ja, s1
+// below jb, s2 beyond).
+template <int D, int GR>
+__device__ __forceinline__ void nl_row(const Coord14<D>* __restrict__ p, int jlo, int jhi, int ja,
+                                       int jb, int s0, int s1, int s2, int vi, unsigned Txy, int Tz,
+                                       int thr, int kmax, size_t nt, unsigned long long*& wp,
+                                       unsigned& whi, unsigned& wlo, int& cnt, int& seen) {
+  for (int j0 = jlo; j0 < jhi; j0 += GR) {
+    int r[GR];
+#pragma unroll
+    for (int e = 0; e < GR; ++e) r[e] = list_test14<D>(p[j0 + e], Txy, Tz, thr);
+    // sign bits into a mask (m << 1 | sign); candidate e then sits at bit
+    // GR - 1 - e: reverse
+    unsigned m = 0;
+#pragma unroll
+    for (int e = 0; e < GR; ++e) m = __builtin_amdgcn_alignbit(m, (unsigned)r[e], 31);
+    unsigned mask = __builtin_bitreverse32(m);
+    if constexpr (GR < 32) mask >>= 32 - GR;
+    const int nb = jhi - j0;
+    if (nb < GR) mask &= (1u << nb) - 1u;
+    const unsigned self = (unsigned)(vi - j0);
+    if (self < (unsigned)GR) mask &= ~(1u << self);
+    const int add = __popc(mask);
+    seen += add;
+    // a list longer than kmax sends the brick to the cell walk: its entries
+    // need not be complete, only kept within the slots
+    if (cnt + add > kmax) mask = 0;
+    while (mask) {
+      const int j = j0 + __builtin_ctz(mask);
+      mask &= mask - 1;
+      list_push(wp, whi, wlo, cnt,
+                (unsigned)((j + (j < ja ? s0 : (j < jb ? s1 : s2))) * (int)sizeof(Coord<D>)), nt);
+    }
+  }
+}
+
 template <int D, int NT>
 __global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
   extern __shared__ __align__(16) char s_dyn_brick[];
@@ -1120,7 +1158,6 @@ __global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
     unsigned long long* wp = a.nl + gi;  // next list word
     unsigned whi = 0, wlo = 0;
     int cnt = 0, seen = 0;
-    constexpr int GR = nl_group<D>();
     for (int cz = rr.cz0; cz <= rr.cz1; ++cz) {
       for (int cy = rr.cy0; cy <= rr.cy1; ++cy) {
         int cx0, cx1;
@@ -1135,37 +1172,11 @@ __global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
         const int s1 = list_shift(G, L, G.ns, cy, cz);
         const int s2 = list_shift(G, L, G.ns + G.wx, cy, cz);
         const int jhi = L.hs[hrow + cx1 + 1];
-        // test GR candidates into a bit mask (the last group of a row reads
-        // into the next row or the padding and is masked), then append the
-        // accepted ones: the appends cost per accepted entry rather than per
-        // candidate
-        for (int j0 = L.hs[hrow + cx0]; j0 < jhi; j0 += GR) {
-          int r[GR];
-#pragma unroll
-          for (int e = 0; e < GR; ++e) r[e] = list_test14<D>(L.p[j0 + e], Txy, Tz, thr);
-          // sign bits into a mask (m << 1 | sign); candidate e then sits at
-          // bit GR - 1 - e: reverse
-          unsigned m = 0;
-#pragma unroll
-          for (int e = 0; e < GR; ++e) m = __builtin_amdgcn_alignbit(m, (unsigned)r[e], 31);
-          unsigned mask = __builtin_bitreverse32(m);
-          if constexpr (GR < 32) mask >>= 32 - GR;
-          const int nb = jhi - j0;
-          if (nb < GR) mask &= (1u << nb) - 1u;
-          const unsigned self = (unsigned)(vi - j0);
-          if (self < (unsigned)GR) mask &= ~(1u << self);
-          const int add = __popc(mask);
-          seen += add;
-          // a list longer than kmax sends the brick to the cell walk: its
-          // entries need not be complete, only kept within the slots
-          if (cnt + add > kmax) mask = 0;
-          while (mask) {
-            const int j = j0 + __builtin_ctz(mask);
-            mask &= mask - 1;
-            list_push(wp, whi, wlo, cnt,
-                      (unsigned)((j + (j < ja ? s0 : (j < jb ? s1 : s2))) * (int)sizeof(Coord<D>)), nt);
-          }
-        }
+        const int j0r = L.hs[hrow + cx0];
+        if (P.nl_wide)
+          nl_row<D, 32>(L.p, j0r, jhi, ja, jb, s0, s1, s2, vi, Txy, Tz, thr, kmax, nt, wp, whi, wlo, cnt, seen);
+        else
+          nl_row<D, 16>(L.p, j0r, jhi, ja, jb, s0, s1, s2, vi, Txy, Tz, thr, kmax, nt, wp, whi, wlo, cnt, seen);
       }
     }
     if (seen > kmax) s_over = 1;
