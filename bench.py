@@ -139,7 +139,8 @@ def summarize_traffic(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write
     fetch = _counter_means(fetch_dir, "FETCH_SIZE")
     write = _counter_means(write_dir, "WRITE_SIZE")
     names = {"k_force": "force", "k_count": "count", "k_scan": "scan", "k_scatter": "scatter",
-             "k_bin": "bin", "k_kin": "kin", "k_ingest": "ingest", "k_nlist": "nlist"}
+             "k_bin": "bin", "k_kin": "kin", "k_ingest": "ingest", "k_nlist_narrow": "nlist",
+             "k_nlist_wide": "nlist"}
     kernels = {}
     for kname, cls in names.items():
         if kname in fetch and kname in write:

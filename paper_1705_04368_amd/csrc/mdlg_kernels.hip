@@ -535,14 +535,27 @@ __device__ __forceinline__ BrickGeom brick_setup(const Phys& P, const Replica& R
   G.nrows = G.wy * G.wz;
   if (threadIdx.x == 0) L.hs[G.nh] = G.total;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int r = 0; r < G.nrows; ++r) {
-      const int hlo = G.ns + G.HX * ((G.ns + r % G.wy) + G.HY * (G.nsz + r / G.wy));
-      L.rowpre[r] = acc;
-      acc += L.hs[hlo + G.wx] - L.hs[hlo];
+  // exclusive scan of the target counts of the brick's rows, 64 rows per
+  // step of the first wave
+  if (threadIdx.x < 64) {
+    int carry = 0;
+    for (int r0 = 0; r0 < G.nrows; r0 += 64) {
+      const int r = r0 + (int)threadIdx.x;
+      int c = 0;
+      if (r < G.nrows) {
+        const int hlo = G.ns + G.HX * ((G.ns + r % G.wy) + G.HY * (G.nsz + r / G.wy));
+        c = L.hs[hlo + G.wx] - L.hs[hlo];
+      }
+      int x = c;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if ((int)threadIdx.x >= o) x += y;
+      }
+      if (r < G.nrows) L.rowpre[r] = carry + x - c;
+      carry += __shfl(x, 63, 64);
     }
-    L.rowpre[G.nrows] = acc;
+    if (threadIdx.x == 0) L.rowpre[G.nrows] = carry;
   }
   __syncthreads();
   G.ntg = L.rowpre[G.nrows];
@@ -577,7 +590,8 @@ __device__ __forceinline__ int pack_halo(int hx, int hy, int hz) {
 template <int D, int NT, class Lds>
 __device__ __forceinline__ void brick_stage(const BrickGeom& G, const Phys& P,
                                             const float* __restrict__ pos, const float* __restrict__ lam,
-                                            Lds& L, int cb, int ce, int2* __restrict__ smap = nullptr) {
+                                            Lds& L, int cb, int ce, int2* __restrict__ smap = nullptr,
+                                            float* __restrict__ off0 = nullptr) {
   for (int v0 = cb + (int)threadIdx.x; v0 < ce; v0 += 4 * NT) {
     int hh[4], g[4];
     float p[4][D];
@@ -621,6 +635,8 @@ __device__ __forceinline__ void brick_stage(const BrickGeom& G, const Phys& P,
           if (nv >= G.ntg)
             smap[nv] = make_int2(g[u], (D == 2) ? pack_halo(hx, r, 0)
                                                 : pack_halo(hx, r % G.HY, r / G.HY));
+          else if (off0)
+            stv<D>(off0, g[u], p[u]);  // a target: its reference offset
         }
       }
     }
@@ -1107,8 +1123,8 @@ __device__ __forceinline__ void nl_row(const Coord14<D>* __restrict__ p, int jlo
   }
 }
 
-template <int D, int NT>
-__global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
+template <int D, int NT, int GR>
+__device__ __forceinline__ void nlist_brick(const NlistArgs& a) {
   extern __shared__ __align__(16) char s_dyn_brick[];
   __shared__ int s_rowpre[kMaxRows + 1];
   constexpr int NW = NT / 64;
@@ -1134,7 +1150,7 @@ __global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
   const BrickGeom G = brick_setup<D, NT>(P, R, br, a.cell_start, L);
   const bool fits = G.total < CAP;  // one slot stays free for the padding sentinel
   int2* __restrict__ smap = a.smap + (size_t)b * CAP;
-  if (fits) brick_stage<D, NT>(G, P, a.pos, nullptr, L, 0, G.total, smap);
+  if (fits) brick_stage<D, NT>(G, P, a.pos, nullptr, L, 0, G.total, smap, a.off0);
   __syncthreads();
   const size_t nt = (size_t)P.n_total;
   const int kmax = P.kmax;
@@ -1144,24 +1160,38 @@ __global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
     if (t >= G.ntg) break;
     int hxi, hyi, hzi, gi, vi;
     brick_target<D>(G, L, t, hxi, hyi, hzi, gi, vi);
-    float o[D];
-    ldv<D>(a.pos, gi, o);
-    stv<D>(a.off0, gi, o);
-    if (!fits) continue;
-    // the target's fixed-point coordinates, as the force kernel stages them
-    const int X = fixed_coord(hxi, o[0], P), Y = fixed_coord(hyi, o[1], P);
-    int Z = 0;
-    if constexpr (D == 3) Z = fixed_coord(hzi, o[D - 1], P);
-    const unsigned Txy = coord14(X, P) | (coord14(Y, P) << 16);
-    const int Tz = (D == 3) ? (int)coord14(Z, P) : 0;
-    const Reach rr = target_reach<D>(G, P, X, Y, Z, P.rlq);
+    if (!fits) {
+      // the cell walk's displacement check still reads the reference offsets
+      float o[D];
+      ldv<D>(a.pos, gi, o);
+      stv<D>(a.off0, gi, o);
+      continue;
+    }
+    // the target's own 14-bit coordinates (its reference offset was stored
+    // by the staging) and the fixed-point coordinates they stand for, within
+    // half a 14-bit unit, which widens the reach and the row bounds
+    const Coord14<D> me = L.p[vi];
+    unsigned Txy;
+    int Tz = 0;
+    if constexpr (D == 2) {
+      Txy = me;
+    } else {
+      Txy = me.x;
+      Tz = (int)me.y;
+    }
+    const int eh = P.sh16 > 0 ? 1 << (P.sh16 - 1) : 0;
+    const unsigned lift = 2u << P.F;
+    const int X = (int)(((Txy & 0xffffu) << P.sh16) - lift) + eh;
+    const int Y = (int)(((Txy >> 16) << P.sh16) - lift) + eh;
+    const int Z = (D == 3) ? (int)(((unsigned)Tz << P.sh16) - lift) + eh : 0;
+    const Reach rr = target_reach<D>(G, P, X, Y, Z, P.rlq + eh);
     unsigned long long* wp = a.nl + gi;  // next list word
     unsigned whi = 0, wlo = 0;
     int cnt = 0, seen = 0;
     for (int cz = rr.cz0; cz <= rr.cz1; ++cz) {
       for (int cy = rr.cy0; cy <= rr.cy1; ++cy) {
         int cx0, cx1;
-        if (!row_columns<D>(G, P, X, Y, Z, cy, cz, P.rl2_u, 4, cx0, cx1)) continue;
+        if (!row_columns<D>(G, P, X, Y, Z, cy, cz, P.rl2_u, 4 + eh, cx0, cx1)) continue;
         const int hrow = G.HX * (cy + G.HY * cz);
         // one contiguous LDS range per row; its list shift takes at most three
         // values: halo columns left of the brick, the brick's own, halo to the
@@ -1173,10 +1203,7 @@ __global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
         const int s2 = list_shift(G, L, G.ns + G.wx, cy, cz);
         const int jhi = L.hs[hrow + cx1 + 1];
         const int j0r = L.hs[hrow + cx0];
-        if (P.nl_wide)
-          nl_row<D, 32>(L.p, j0r, jhi, ja, jb, s0, s1, s2, vi, Txy, Tz, thr, kmax, nt, wp, whi, wlo, cnt, seen);
-        else
-          nl_row<D, 16>(L.p, j0r, jhi, ja, jb, s0, s1, s2, vi, Txy, Tz, thr, kmax, nt, wp, whi, wlo, cnt, seen);
+        nl_row<D, GR>(L.p, j0r, jhi, ja, jb, s0, s1, s2, vi, Txy, Tz, thr, kmax, nt, wp, whi, wlo, cnt, seen);
       }
     }
     if (seen > kmax) s_over = 1;
@@ -1194,13 +1221,16 @@ __global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
     __syncthreads();
     for (int t = threadIdx.x; t < G.ntg; t += NT) atomicAdd(&s_cnt[63 - s_words[t]], 1);
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int acc = 0;
-      for (int i = 0; i < 64; ++i) {
-        const int c = s_cnt[i];
-        s_cnt[i] = acc;
-        acc += c;
+    if (threadIdx.x < 64) {
+      // exclusive scan of the 64 bins across the first wave
+      const int c = s_cnt[threadIdx.x];
+      int x = c;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if ((int)threadIdx.x >= o) x += y;
       }
+      s_cnt[threadIdx.x] = x - c;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < G.ntg; t += NT)
@@ -1208,6 +1238,18 @@ __global__ __launch_bounds__(NT) void k_nlist(NlistArgs a) {
           make_int2(smap[t].x, t | ((int)s_words[t] << 16));
   }
   if (threadIdx.x == 0) a.binfo[b] = make_int4(G.total, G.ntg, (fits && !s_over) ? 1 : 0, 0);
+}
+
+// The list builder with 16 candidates per test step (short rows) and with 32
+// (long rows).
+template <int D, int NT>
+__global__ __launch_bounds__(NT) void k_nlist_narrow(NlistArgs a) {
+  nlist_brick<D, NT, 16>(a);
+}
+
+template <int D, int NT>
+__global__ __launch_bounds__(NT) void k_nlist_wide(NlistArgs a) {
+  nlist_brick<D, NT, 32>(a);
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -1963,7 +2005,10 @@ void launch_nlist(int D, const NlistArgs& a, hipStream_t s) {
   const size_t coord = (D == 2) ? sizeof(unsigned) : sizeof(uint2);
   const size_t lds = tables + (((size_t)(a.P.lcap + kNlPad) * coord + 15) & ~size_t(15)) +
                      (size_t)a.P.lcap;
-  MDLG_LAUNCH_BRICK(D, a.P.bthreads, k_nlist, grid, lds, s, a);
+  // 16 or 32 candidates per test step: separate instantiations, so that
+  // neither carries the other's registers
+  if (a.P.nl_wide) MDLG_LAUNCH_BRICK(D, a.P.bthreads, k_nlist_wide, grid, lds, s, a);
+  else MDLG_LAUNCH_BRICK(D, a.P.bthreads, k_nlist_narrow, grid, lds, s, a);
 }
 
 void launch_kin(const KinArgs& a, hipStream_t s) {
