@@ -36,9 +36,9 @@ struct Layout {
   int bthreads = 256;
   int BSX = 1;
   long long n_total = 0, n_cells = 0, n_sites = 0;
-  int nbricks = 0, nchunks = 0, nstrips = 0, ntiles = 0;
+  int nbricks = 0, nchunks = 0, ncchunks = 0, nstrips = 0, ntiles = 0;
   std::vector<Replica> reps;
-  std::vector<int4> bricks, chunks, strips;
+  std::vector<int4> bricks, chunks, cchunks, strips;
   double s = 0, margin = 0, margin_max = 0;
   int sort_every = 1;
   int halo_cells = 0;  // halo cells of the largest force brick
@@ -317,7 +317,13 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   L->reps.clear();
   L->bricks.clear();
   L->chunks.clear();
+  L->cchunks.clear();
   L->strips.clear();
+  // the counting pass takes larger chunks on large systems (about 1024
+  // blocks): its per-block chain of dependent memory operations then serves
+  // more particles
+  int cchunk = (int)std::min<long long>(kCountChunkMax, (n_total / 1024 + kBlock - 1) / kBlock * kBlock);
+  cchunk = std::max(cchunk, kPartChunk);
   long long cell_off = 0, part_off = 0, site_off = 0;
   for (int r = 0; r < c->n_replicas; ++r) {
     Replica rep{};
@@ -342,6 +348,8 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
     rep.nbricks = (int)L->bricks.size() - rep.brick_off;
     for (long long g = part_off; g < part_off + rep.n; g += kPartChunk)
       L->chunks.push_back(make_int4(r, (int)g, (int)std::min(part_off + rep.n, g + kPartChunk), 0));
+    for (long long g = part_off; g < part_off + rep.n; g += cchunk)
+      L->cchunks.push_back(make_int4(r, (int)g, (int)std::min(part_off + rep.n, g + cchunk), 0));
     const int nsz_rows = (D == 3) ? rep.M[2] : 1;
     for (int sz = 0; sz < nsz_rows; ++sz)
       for (int sy = 0; sy < rep.M[1]; ++sy)
@@ -362,6 +370,7 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   L->n_sites = site_off;
   L->nbricks = (int)L->bricks.size();
   L->nchunks = (int)L->chunks.size();
+  L->ncchunks = (int)L->cchunks.size();
   L->nstrips = (int)L->strips.size();
   L->ntiles = (int)((L->n_cells + kScanTile - 1) / kScanTile);
   mdlg_layout& P = L->pub;
@@ -419,6 +428,7 @@ struct mdlg_system {
   Replica* reps = nullptr;
   int4* bricks = nullptr;
   int4* chunks = nullptr;
+  int4* cchunks = nullptr;
   int4* strips = nullptr;
   unsigned long long* fcount = nullptr;
   long long* momsum = nullptr;
@@ -530,6 +540,7 @@ size_t carve(mdlg_system* S, char* base) {
   S->reps = c.take<Replica>(base, L.reps.size());
   S->bricks = c.take<int4>(base, L.bricks.size());
   S->chunks = c.take<int4>(base, L.chunks.size());
+  S->cchunks = c.take<int4>(base, L.cchunks.size());
   S->strips = c.take<int4>(base, L.strips.size());
   S->fcount = c.take<unsigned long long>(base, kMaxQ);
   S->momsum = c.take<long long>(base, 16);
@@ -724,6 +735,7 @@ SortArgs sort_args(mdlg_system* S) {
   a.P = S->P;
   a.reps = S->reps;
   a.chunks = S->chunks;
+  a.cchunks = S->cchunks;
   a.cell_start = S->cell_start;
   a.pos = S->pos[S->pcur];
   a.vel = S->vel[S->scur];
@@ -745,6 +757,7 @@ SortArgs sort_args(mdlg_system* S) {
   a.err = S->err;
   a.ntiles = S->L.ntiles;
   a.nchunks = S->L.nchunks;
+  a.ncchunks = S->L.ncchunks;
   a.xcd_remap = S->xcd_remap;
   return a;
 }
@@ -753,7 +766,7 @@ void enqueue_sort(mdlg_system* S) {
   SortArgs a = sort_args(S);
   {
     TimedLaunch t(S, MDLG_K_COUNT);
-    launch_count(S->D, S->L.nchunks, a, S->stream);
+    launch_count(S->D, S->L.ncchunks, a, S->stream);
   }
   ScanArgs sc{};
   sc.count = S->count;
@@ -1075,6 +1088,8 @@ mdlg_status mdlg_create(const mdlg_config* cfg, void* workspace_dev, size_t work
   CREATE_HIP(hipMemcpyAsync(S->bricks, L.bricks.data(), L.bricks.size() * sizeof(int4),
                             hipMemcpyHostToDevice, S->stream));
   CREATE_HIP(hipMemcpyAsync(S->chunks, L.chunks.data(), L.chunks.size() * sizeof(int4),
+                            hipMemcpyHostToDevice, S->stream));
+  CREATE_HIP(hipMemcpyAsync(S->cchunks, L.cchunks.data(), L.cchunks.size() * sizeof(int4),
                             hipMemcpyHostToDevice, S->stream));
   CREATE_HIP(hipMemcpyAsync(S->strips, L.strips.data(), L.strips.size() * sizeof(int4),
                             hipMemcpyHostToDevice, S->stream));

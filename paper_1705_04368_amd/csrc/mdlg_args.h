@@ -24,6 +24,7 @@ struct SortArgs {
   Phys P;
   const Replica* reps;
   const int4* chunks;
+  const int4* cchunks;    // the counting pass's chunks (larger)
   const int* cell_start;
   const float* pos;
   const float* vel;
@@ -45,6 +46,7 @@ struct SortArgs {
   unsigned* err;
   int ntiles;
   int nchunks;
+  int ncchunks;
   int xcd_remap;
 };
 

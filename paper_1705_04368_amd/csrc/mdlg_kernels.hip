@@ -278,7 +278,7 @@ __device__ __forceinline__ bool canon_particle(const SortArgs& a, const Replica&
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
   constexpr int kHist = 2048;
-  constexpr int kPer = kPartChunkMax / kBlock;
+  constexpr int kPer = kCountChunkMax / kBlock;
   constexpr int kTiles = kHist / kScanTile + 2;
   __shared__ int s_cnt[kHist];
   __shared__ int s_tile[kTiles];
@@ -289,8 +289,8 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
     const int per = gridDim.x >> 3;
     cb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   }
-  if (cb >= a.nchunks) return;
-  const int4 ch = a.chunks[cb];
+  if (cb >= a.ncchunks) return;
+  const int4 ch = a.cchunks[cb];
   const Replica R = a.reps[ch.x];
   // window: the chunk's old cells (sorted) widened by one row on either side
   const int lo = a.cell[ch.y] - R.Mc[0] - 1;
@@ -306,6 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
     key[u] = -1;
     inwin[u] = false;
     rank[u] = 0;
+    if (ch.y + u * kBlock >= ch.z) continue;  // the chunk is shorter (uniform)
     if (g < ch.z) {
       float o[D];
       int c[D], im[D];
