@@ -47,6 +47,8 @@ def _load():
         f = getattr(lib, name)
         f.restype = C.c_int
         f.argtypes = [P(OrcMD), dp, dp, dp]
+    lib.orc_forces_subset.restype = C.c_int
+    lib.orc_forces_subset.argtypes = [P(OrcMD), dp, ip, C.c_int, dp]
     lib.orc_vv.restype = C.c_int
     lib.orc_vv.argtypes = [P(OrcMD), dp, ip, dp, dp, C.c_long, P(C.c_long), C.c_int,
                            C.c_double, C.c_int]
@@ -136,6 +138,18 @@ def forces(md, x, brute=False):
     f = _load().orc_forces_brute if brute else _load().orc_forces_cells
     _check(f(C.byref(md), _dp(x), _dp(acc), C.byref(ep)), "forces")
     return acc, ep.value
+
+
+def forces_subset(md, x, idx):
+    """Accelerations of the particles idx only (rows in the order of idx),
+    each summed over all its partners as in forces(): for sampled checks of
+    systems too large for a full evaluation."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    acc = np.zeros((idx.shape[0], x.shape[1]))
+    _check(_load().orc_forces_subset(C.byref(md), _dp(x), _ip(idx), int(idx.shape[0]), _dp(acc)),
+           "forces_subset")
+    return acc
 
 
 class OracleState:

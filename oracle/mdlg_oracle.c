@@ -132,68 +132,144 @@ int orc_forces_brute(const orc_md *p, const double *x, double *acc, double *epot
     return ORC_OK;
 }
 
-/* Same accelerations through a plain linked-list cell grid of side >= r_c.
- * Falls back to the brute-force sum when an axis holds fewer than 3 cells. */
-int orc_forces_cells(const orc_md *p, const double *x, double *acc, double *epot)
+/* Plain linked-list cell grid of side >= r_c over all particles. */
+typedef struct {
+    int nc[3];
+    int *head, *next, *cof;
+} cell_grid;
+
+static void free_grid(cell_grid *g)
+{
+    free(g->head);
+    free(g->next);
+    free(g->cof);
+}
+
+/* Returns 1 when an axis holds fewer than 3 cells (no grid), ORC_ENOMEM on
+ * allocation failure, 0 with the grid built. */
+static int build_grid(const orc_md *p, const double *x, cell_grid *g)
 {
     int d = p->dim, n = p->n;
-    int nc[3] = {1, 1, 1};
     double h[3] = {1.0, 1.0, 1.0};
+    g->nc[0] = g->nc[1] = g->nc[2] = 1;
+    g->head = g->next = g->cof = NULL;
     for (int a = 0; a < d; ++a) {
-        nc[a] = (int)floor(p->box[a] / p->rc);
-        if (nc[a] < 3)
-            return orc_forces_brute(p, x, acc, epot);
-        h[a] = p->box[a] / nc[a];
+        g->nc[a] = (int)floor(p->box[a] / p->rc);
+        if (g->nc[a] < 3)
+            return 1;
+        h[a] = p->box[a] / g->nc[a];
     }
-    memset(acc, 0, sizeof(double) * (size_t)n * d);
-    if (epot)
-        *epot = 0.0;
-    if (p->forces_off)
-        return ORC_OK;
-    long ncell = (long)nc[0] * nc[1] * nc[2];
-    int *head = (int *)malloc(sizeof(int) * ncell);
-    int *next = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
-    int *cof = (int *)malloc(sizeof(int) * 3 * (size_t)(n > 0 ? n : 1));
-    if (!head || !next || !cof) {
-        free(head); free(next); free(cof);
+    long ncell = (long)g->nc[0] * g->nc[1] * g->nc[2];
+    g->head = (int *)malloc(sizeof(int) * ncell);
+    g->next = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    g->cof = (int *)malloc(sizeof(int) * 3 * (size_t)(n > 0 ? n : 1));
+    if (!g->head || !g->next || !g->cof) {
+        free_grid(g);
         return ORC_ENOMEM;
     }
     for (long c = 0; c < ncell; ++c)
-        head[c] = -1;
+        g->head[c] = -1;
     for (int i = 0; i < n; ++i) {
         int cc[3] = {0, 0, 0};
         for (int a = 0; a < d; ++a) {
             int q = (int)floor(x[i * d + a] / h[a]);
             if (q < 0) q = 0;
-            if (q >= nc[a]) q = nc[a] - 1;
+            if (q >= g->nc[a]) q = g->nc[a] - 1;
             cc[a] = q;
-            cof[3 * i + a] = q;
+            g->cof[3 * i + a] = q;
         }
-        long c = cc[0] + (long)nc[0] * (cc[1] + (long)nc[1] * cc[2]);
-        next[i] = head[c];
-        head[c] = i;
+        long c = cc[0] + (long)g->nc[0] * (cc[1] + (long)g->nc[1] * cc[2]);
+        g->next[i] = g->head[c];
+        g->head[c] = i;
     }
-    double vshift = orc_lj_potential(p->rc, p->eps, p->sigma);
+    return 0;
+}
+
+/* Force on particle i from every j != i in its own and the neighbouring cells. */
+static void cell_walk(const orc_md *p, const double *x, const cell_grid *g, int i, double *acc,
+                      double *epot, double vshift)
+{
+    int d = p->dim;
     int span[3] = {1, 1, 1};
     for (int a = 0; a < d; ++a)
         span[a] = 3;
-    for (int i = 0; i < n; ++i) {
-        for (int oz = 0; oz < span[2]; ++oz)
-            for (int oy = 0; oy < span[1]; ++oy)
-                for (int ox = 0; ox < span[0]; ++ox) {
-                    int off[3] = {ox - 1, oy - 1, oz - 1};
-                    int cc[3] = {0, 0, 0};
-                    for (int a = 0; a < d; ++a)
-                        cc[a] = ((cof[3 * i + a] + off[a]) % nc[a] + nc[a]) % nc[a];
-                    long c = cc[0] + (long)nc[0] * (cc[1] + (long)nc[1] * cc[2]);
-                    for (int j = head[c]; j >= 0; j = next[j])
-                        if (j != i)
-                            pair_accumulate(p, x, i, j, acc, epot, vshift);
-                }
+    for (int oz = 0; oz < span[2]; ++oz)
+        for (int oy = 0; oy < span[1]; ++oy)
+            for (int ox = 0; ox < span[0]; ++ox) {
+                int off[3] = {ox - 1, oy - 1, oz - 1};
+                int cc[3] = {0, 0, 0};
+                for (int a = 0; a < d; ++a)
+                    cc[a] = ((g->cof[3 * i + a] + off[a]) % g->nc[a] + g->nc[a]) % g->nc[a];
+                long c = cc[0] + (long)g->nc[0] * (cc[1] + (long)g->nc[1] * cc[2]);
+                for (int j = g->head[c]; j >= 0; j = g->next[j])
+                    if (j != i)
+                        pair_accumulate(p, x, i, j, acc, epot, vshift);
+            }
+}
+
+/* Same accelerations through a plain linked-list cell grid of side >= r_c.
+ * Falls back to the brute-force sum when an axis holds fewer than 3 cells. */
+int orc_forces_cells(const orc_md *p, const double *x, double *acc, double *epot)
+{
+    int d = p->dim, n = p->n;
+    cell_grid g;
+    int rc = build_grid(p, x, &g);
+    if (rc == 1)
+        return orc_forces_brute(p, x, acc, epot);
+    if (rc != 0)
+        return rc;
+    memset(acc, 0, sizeof(double) * (size_t)n * d);
+    if (epot)
+        *epot = 0.0;
+    if (!p->forces_off) {
+        double vshift = orc_lj_potential(p->rc, p->eps, p->sigma);
+        for (int i = 0; i < n; ++i)
+            cell_walk(p, x, &g, i, acc, epot, vshift);
     }
-    free(head);
-    free(next);
-    free(cof);
+    free_grid(&g);
+    return ORC_OK;
+}
+
+/* Accelerations of the m particles idx[0..m) only (row k of acc_out for
+ * particle idx[k]), each summed over all its partners exactly as above. */
+int orc_forces_subset(const orc_md *p, const double *x, const int *idx, int m, double *acc_out)
+{
+    int d = p->dim, n = p->n;
+    double *acc = (double *)calloc((size_t)(n > 0 ? n : 1) * d, sizeof(double));
+    if (!acc)
+        return ORC_ENOMEM;
+    for (int k = 0; k < m; ++k)
+        if (idx[k] < 0 || idx[k] >= n) {
+            free(acc);
+            return ORC_EINVAL;
+        }
+    if (!p->forces_off) {
+        double vshift = orc_lj_potential(p->rc, p->eps, p->sigma);
+        cell_grid g;
+        int rc = build_grid(p, x, &g);
+        if (rc == ORC_ENOMEM) {
+            free(acc);
+            return rc;
+        }
+        for (int k = 0; k < m; ++k) {
+            int i = idx[k];
+            for (int a = 0; a < d; ++a)
+                acc[i * d + a] = 0.0;
+            if (rc == 1) {
+                for (int j = 0; j < n; ++j)
+                    if (j != i)
+                        pair_accumulate(p, x, i, j, acc, NULL, vshift);
+            } else {
+                cell_walk(p, x, &g, i, acc, NULL, vshift);
+            }
+        }
+        if (rc == 0)
+            free_grid(&g);
+    }
+    for (int k = 0; k < m; ++k)
+        for (int a = 0; a < d; ++a)
+            acc_out[k * d + a] = acc[idx[k] * d + a];
+    free(acc);
     return ORC_OK;
 }
 

@@ -73,6 +73,20 @@ def test_cells_equal_brute_force_and_newton3(dim):
     np.testing.assert_allclose(ab.sum(axis=0), 0.0, atol=1e-9)
 
 
+@pytest.mark.parametrize("dim,n,box", [(2, 300, 20.0), (3, 500, 10.0), (2, 20, 6.0)])
+def test_sampled_forces_equal_brute_force(dim, n, box):
+    # the sampled evaluation (used at sizes too large for a full one) against
+    # the brute-force sum over all partners; the last case has fewer than 3
+    # cells per axis and takes the all-pairs branch
+    pos, _ = synth.lj_initial_state(dim, n, box, 1.0, seed=9, r_min=0.8)
+    x = pos.astype(np.float64)
+    md = oracle.make_md(dim, n, box, rc=2.5)
+    ab, _ = oracle.forces(md, x, brute=True)
+    idx = np.random.default_rng(4).choice(n, size=n // 3, replace=False)
+    np.testing.assert_allclose(oracle.forces_subset(md, x, idx), ab[idx], rtol=1e-12, atol=1e-10)
+    assert np.abs(ab[idx]).max() > 0.1  # nonzero forces were compared
+
+
 def test_minimum_image_pair_across_boundary():
     # two particles 1.1 sigma apart across the periodic boundary
     md = oracle.make_md(2, 2, 10.0, rc=2.5)
