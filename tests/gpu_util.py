@@ -1,4 +1,5 @@
-"""Helpers shared by the GPU parity tests (marshalling only, no method arithmetic)."""
+"""Helpers shared by the GPU parity tests: marshalling, and a force check
+that accounts for pairs at the cutoff through the oracle's pair force."""
 import sys
 
 import numpy as np
@@ -39,3 +40,42 @@ def force_error(acc_gpu, acc_ref):
     frms = np.sqrt(np.mean(np.sum(acc_ref ** 2, axis=1)))
     den = np.maximum(np.linalg.norm(acc_ref, axis=1), frms)
     return np.linalg.norm(acc_gpu.astype(np.float64) - acc_ref, axis=1) / den
+
+
+def check_forces_at_cutoff(got, ref, x_targets, x_all, box, rc, mass=1.0, tol=1e-5, shell=1e-6,
+                           max_events=None):
+    """got/ref: accelerations of the targets (positions x_targets) summed over
+    all particles x_all (FP64, minimum image over box).
+
+    The LJ force jumps by |F(r_c)| at r_c, and a pair within float rounding of
+    r_c is inside the cutoff for one side of the comparison and outside for
+    the other.  Every target whose error exceeds tol must have partners with
+    |r - r_c| < shell r_c, and toggling some of those pairs in the reference
+    (removing one inside r_c, adding one outside) must bring it within tol.
+    Returns (number of such targets, largest raw error)."""
+    import itertools
+
+    import oracle
+    frms = np.sqrt(np.mean(np.sum(ref ** 2, axis=1)))
+    den = np.maximum(np.linalg.norm(ref, axis=1), frms)
+    err = np.linalg.norm(got.astype(np.float64) - ref, axis=1) / den
+    bad = np.nonzero(err > tol)[0]
+    box = np.broadcast_to(np.asarray(box, dtype=np.float64), (x_all.shape[1],))
+    for i in bad:
+        d = x_targets[i] - x_all
+        d -= box * np.round(d / box)
+        r = np.sqrt(np.sum(d * d, axis=1))
+        near = np.nonzero((np.abs(r - rc) < shell * rc) & (r > 0))[0]
+        assert 0 < len(near) <= 4, f"force error {err[i]:.3e} with {len(near)} pairs at the cutoff"
+        best = np.inf
+        for k in range(1, len(near) + 1):
+            for sub in itertools.combinations(near, k):
+                alt = ref[i].copy()
+                for j in sub:
+                    term = oracle.lj_force_over_r(r[j]) * d[j] / mass
+                    alt = alt - term if r[j] < rc else alt + term
+                best = min(best, float(np.linalg.norm(got[i].astype(np.float64) - alt) / den[i]))
+        assert best <= tol, f"force error {err[i]:.3e} not explained by the cutoff pairs ({best:.3e})"
+    if max_events is not None:
+        assert len(bad) <= max_events
+    return len(bad), float(np.max(err)) if err.size else 0.0

@@ -1,0 +1,184 @@
+"""Parity at the benchmarked sizes, in the launch configuration the benchmark
+times (the autotuner's choice of MD cell split, brick, rebuild interval and
+threads per block, pair lists on):
+
+* 2D at scale: N = 262144 in a 724 sigma box, 181 x 181 lattice, V = 3;
+* 3D: N = 4194304 in a 192 sigma cube, 48^3 lattice, V = 2;
+* the batched ensemble: 512 2D replicas of log-uniform N in [1024, 65536].
+
+For every workload: the accelerations of all particles (a seeded sample of
+16384 in 3D) at the start and after one lattice step (20 MD steps, two
+rebuilds of the cell and pair lists, the second force evaluation on lists 10
+steps old) against the FP64 oracle on the same positions (1e-5 relative, as
+for the small cases), and the lattice step's occupation numbers and moments
+per site bit-exact against the oracle's binning of the GPU's own unwrapped
+positions (eq. MDni).  The 2D system also runs a 20-step trajectory against
+the oracle (1e-4).
+
+At these sizes a few pairs sit within float rounding of the cutoff, where the
+LJ force jumps by |F(r_c)|: such a pair is inside r_c on one side of the
+comparison and outside on the other.  Force errors above 1e-5 are accepted
+only where toggling such a pair in the reference explains them, and the
+trajectory may carry the resulting velocity jumps on a few particles.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import check_forces_at_cutoff, make_system, say, unwrapped
+
+pytestmark = pytest.mark.gpu
+
+# the benchmark's workloads (bench.py WORKLOADS)
+# (the FP64 oracle takes minutes for all forces of the 3D system: there a
+# seeded sample of 16384 particles is compared)
+RC = 2.5
+W2 = dict(dim=2, n=262144, M=181, dx=4.0, kT=1.0, dt=0.005, steps=20, vmax=3, seed=2, sample=None)
+W3 = dict(dim=3, n=4194304, M=48, dx=4.0, kT=1.5, dt=0.004, steps=20, vmax=2, seed=3, sample=16384)
+
+
+def _tuned_system(cfg, pos, vel):
+    import torch
+
+    from paper_1705_04368_amd import autotune
+    from tests.gpu_util import device
+    d = device()
+    tcfg, ms = autotune(cfg, torch.from_numpy(pos).to(d), torch.from_numpy(vel).to(d), md_steps=40)
+    sysg = make_system(tcfg, pos, vel)
+    say(f"  autotuned layout {sysg.layout} ({ms * 1e3:.1f} us per MD step)")
+    return sysg
+
+
+def _wrapped_per_particle(st, s, mc):
+    return np.mod(st["ucell"], mc).astype(np.float64) * s + st["off"].astype(np.float64)
+
+
+def _check_forces(st, s, mc, parts, what, sample=None):
+    """parts: (first particle, count, box) per replica.  With sample, only
+    that many particles drawn at random (seeded) are compared, each against
+    the oracle's sum over all its partners; the error's scale F_rms is then
+    the sample's.  Errors above 1e-5 must come from pairs within float
+    rounding of r_c (at most one such particle per 10^5 compared, plus 4)."""
+    xw = _wrapped_per_particle(st, s, mc)
+    events, worst, total = 0, 0.0, 0
+    for p0, n, box in parts:
+        md = oracle.make_md(st["ucell"].shape[1], n, box)
+        x = xw[p0:p0 + n]
+        if sample is None:
+            idx = np.arange(n)
+            acc, _ = oracle.forces(md, x)
+        else:
+            idx = np.sort(np.random.default_rng(11).choice(n, size=sample, replace=False))
+            acc = oracle.forces_subset(md, x, idx)
+        got = st["acc"][p0 + idx]
+        e, w = check_forces_at_cutoff(got, acc, x[idx], x, box, RC)
+        events += e
+        worst = max(worst, w)
+        total += len(idx)
+    say(f"  {what}: {total} particles, {events} at a cutoff pair; largest other error within 1e-5 "
+        f"(largest raw {worst:.3e})")
+    assert events <= total // 100000 + 4
+
+
+def _check_binning(sysg, xu0, xu1, reps, dim, dx, vmax):
+    """reps: (first particle, count, lattice side, first site) per replica."""
+    out = sysg.get_f(per_site=True)
+    got_A = np.rint(out["f_site"]).astype(np.int64)
+    got_m = np.rint(out["mom_site"]).astype(np.int64)
+    tot = np.zeros(got_A.shape[1], np.int64)
+    for p0, n, M, s0 in reps:
+        lat = oracle.make_lattice(dim, (M,) * dim, dx, vmax)
+        ref = oracle.bin_step(lat, dim, xu0[p0:p0 + n], xu1[p0:p0 + n])
+        ns = M ** dim
+        np.testing.assert_array_equal(got_A[s0:s0 + ns], ref["A"].astype(np.int64))
+        np.testing.assert_array_equal(got_m[s0:s0 + ns], ref["mom"])
+        tot += ref["A"].astype(np.int64).sum(axis=0)
+    np.testing.assert_array_equal(out["counts"].astype(np.int64), tot)
+    # mass: every particle is counted once, in a bin or as overflow
+    assert int(tot.sum()) + out["n_overflow"] == xu1.shape[0]
+
+
+def _single(w, thermostat_every=10):
+    from paper_1705_04368_amd import make_config
+    dim, n, M = w["dim"], w["n"], w["M"]
+    box = M * w["dx"]
+    pos, vel = synth.lj_initial_state(dim, n, box, w["kT"], seed=w["seed"])
+    cfg = make_config(dim, n, M, lattice_dx=w["dx"], dt=w["dt"], md_steps_per_lattice_step=w["steps"],
+                      vmax=w["vmax"], thermostat_every=thermostat_every, kT=w["kT"])
+    return cfg, pos, vel, box
+
+
+@pytest.mark.parametrize("w", [W2, W3], ids=["2d_scale", "3d"])
+def test_full_size_forces_and_binning(w):
+    dim = w["dim"]
+    say(f"full size dim={dim} N={w['n']}: autotune, forces, one lattice step")
+    cfg, pos, vel, box = _single(w)
+    sysg = _tuned_system(cfg, pos, vel)
+    s = sysg.layout["cell_side"]
+    mc = w["M"] * sysg.layout["md_cell_split"]
+    st0 = sysg.get_state()
+    np.testing.assert_array_equal(_wrapped_per_particle(st0, s, mc), pos.astype(np.float64))
+    _check_forces(st0, s, mc, [(0, w["n"], box)], "start", w["sample"])
+    sysg.coarse_grain(1)
+    st1 = sysg.get_state()
+    _check_binning(sysg, unwrapped(st0, s), unwrapped(st1, s), [(0, w["n"], w["M"], 0)], dim,
+                   w["dx"], w["vmax"])
+    _check_forces(st1, s, mc, [(0, w["n"], box)], "after one lattice step", w["sample"])
+    sysg.close()
+
+
+def test_full_size_2d_trajectory():
+    w = W2
+    say("full size 2D: 20-step trajectory against the oracle")
+    cfg, pos, vel, box = _single(w, thermostat_every=0)
+    sysg = _tuned_system(cfg, pos, vel)
+    sysg.step(20)
+    st = sysg.get_state()
+    md = oracle.make_md(2, w["n"], box, dt=w["dt"])
+    ost = oracle.OracleState(md, pos, vel)
+    ost.run(20)
+    dx = np.abs(unwrapped(st, sysg.layout["cell_side"]) - ost.unwrapped).max(axis=1)
+    dv = np.abs(st["vel"].astype(np.float64) - ost.v).max(axis=1)
+    # a pair within float rounding of r_c at one step gives its two particles
+    # velocities that differ by up to |F(r_c)| dt / m; allow a few such
+    # particles up to three such jumps beyond the 1e-4 bar
+    jump = abs(oracle.lj_force_over_r(RC) * RC) * w["dt"]
+    out = np.nonzero(dv > 1e-4)[0]
+    say(f"  max |dx| {dx.max():.3e}  max |dv| {dv.max():.3e}; {len(out)} particles above 1e-4 "
+        f"(cutoff jump {jump:.2e})")
+    assert dx.max() <= 1e-4
+    assert len(out) <= 8
+    assert dv.max() <= 1e-4 + 3 * jump
+    sysg.close()
+
+
+def test_full_size_batched_ensemble():
+    from paper_1705_04368_amd import make_config
+    say("full size batched ensemble: 512 replicas, autotune, forces, one lattice step")
+    dim, dx, kT, vmax = 2, 4.0, 1.0, 3
+    n_r, m_r = synth.replica_sizes(512, seed=4)
+    seeds = synth.replica_seeds(512, seed=4)
+    parts = [synth.lj_initial_state(dim, int(nr), dx * int(mr), kT, seed=sd)
+             for nr, mr, sd in zip(n_r, m_r, seeds)]
+    pos = np.concatenate([p for p, _ in parts])
+    vel = np.concatenate([v for _, v in parts])
+    lattice = np.stack([m_r, m_r], axis=1)
+    cfg = make_config(dim, n_r, lattice, lattice_dx=dx, dt=0.005, md_steps_per_lattice_step=20,
+                      vmax=vmax, thermostat_every=10, kT=kT)
+    sysg = _tuned_system(cfg, pos, vel)
+    s = sysg.layout["cell_side"]
+    k = sysg.layout["md_cell_split"]
+    mc = np.repeat(lattice * k, n_r, axis=0)
+    p0 = np.concatenate([[0], np.cumsum(n_r)[:-1]]).astype(np.int64)
+    s0 = np.concatenate([[0], np.cumsum(m_r.astype(np.int64) ** 2)[:-1]]).astype(np.int64)
+    boxes = [dx * int(m) for m in m_r]
+    st0 = sysg.get_state()
+    np.testing.assert_array_equal(_wrapped_per_particle(st0, s, mc), pos.astype(np.float64))
+    _check_forces(st0, s, mc, list(zip(p0, n_r, boxes)), "start")
+    sysg.coarse_grain(1)
+    st1 = sysg.get_state()
+    _check_binning(sysg, unwrapped(st0, s), unwrapped(st1, s), list(zip(p0, n_r, m_r, s0)), dim, dx,
+                   vmax)
+    _check_forces(st1, s, mc, list(zip(p0, n_r, boxes)), "after one lattice step")
+    sysg.close()
