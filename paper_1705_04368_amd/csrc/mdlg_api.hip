@@ -23,6 +23,10 @@ namespace {
 thread_local std::string g_create_error = "no error";
 
 constexpr int kPartChunk = kPartChunkMax;  // particles per block of the per-particle kernels
+// lattice steps of up to kGraphMaxSteps MD steps replay as one graph; longer
+// ones as graphs of about kGraphBlockSteps MD steps (whole rebuild intervals)
+constexpr int kGraphMaxSteps = 400;
+constexpr int kGraphBlockSteps = 200;
 
 struct Layout {
   mdlg_layout pub;
@@ -479,13 +483,22 @@ struct mdlg_system {
   int xcd_remap = 1;
   bool use_graph = true;
   hipStream_t cap_stream = nullptr;
+  // host-side sequencing state a captured graph starts from and leaves
+  struct SeqState {
+    int pcur, scur, since_sort;
+    bool vel_full, lambda_pending;
+    int xi_par;
+    bool xi_have;
+    long long md_step, n_lattice, xi_steps;
+  };
   struct GraphEntry {
     hipGraphExec_t exec;
-    int pcur, scur, since_sort;
-    bool vel_full;
-    int xi_par;
+    SeqState after;  // counters as advanced by one replay from the key's state
   };
-  std::map<std::tuple<int, int, int, bool, bool, int, bool>, GraphEntry> graphs;
+  // key: (kind, pcur, scur, since_sort, vel_full, lambda_pending, xi_par,
+  // xi_have); kind 0 = a whole lattice step, B > 0 = a block of B MD steps,
+  // -n = the last n MD steps of a lattice step with its binning
+  std::map<std::tuple<int, int, int, int, bool, bool, int, bool>, GraphEntry> graphs;
   // per-kernel event timing (measurement aid)
   bool timing = false;
   struct Timed {
@@ -921,8 +934,9 @@ void enqueue_xi(mdlg_system* S) {
   launch_xi(S->D, x, S->stream);
 }
 
-void enqueue_lattice_step(mdlg_system* S) {
-  const int steps = S->cfg.md_steps_per_lattice_step;
+// The last `steps` MD steps of a lattice step (the last one followed by a
+// cell-list rebuild), then the lattice step's binning.
+void enqueue_lattice_tail(mdlg_system* S, int steps) {
   for (int s = 1; s <= steps; ++s) enqueue_md_step(S, s == steps);
   if (S->L.n_shifts > 0) {
     // before the binning, which moves the snapshot forward
@@ -955,6 +969,8 @@ void enqueue_lattice_step(mdlg_system* S) {
   }
   S->n_lattice += 1;
 }
+
+void enqueue_lattice_step(mdlg_system* S) { enqueue_lattice_tail(S, S->cfg.md_steps_per_lattice_step); }
 
 mdlg_status read_err(mdlg_system* S) {
   unsigned e = 0;
@@ -1153,6 +1169,70 @@ mdlg_status mdlg_step(mdlg_system* S, int64_t n) {
   return check_launch(S, "mdlg_step");
 }
 
+extern "C++" {
+
+static mdlg_system::SeqState seq_state(const mdlg_system* S) {
+  return {S->pcur, S->scur, S->since_sort, S->vel_full, S->lambda_pending, S->xi_par, S->xi_have,
+          S->md_step, S->n_lattice, S->xi_steps};
+}
+
+static void set_seq_state(mdlg_system* S, const mdlg_system::SeqState& q) {
+  S->pcur = q.pcur;
+  S->scur = q.scur;
+  S->since_sort = q.since_sort;
+  S->vel_full = q.vel_full;
+  S->lambda_pending = q.lambda_pending;
+  S->xi_par = q.xi_par;
+  S->xi_have = q.xi_have;
+  S->md_step = q.md_step;
+  S->n_lattice = q.n_lattice;
+  S->xi_steps = q.xi_steps;
+}
+
+// Launch the work `body` enqueues as a HIP graph: captured (on a capture
+// stream, recording only) the first time it is asked for from this
+// sequencing state, replayed on the user's stream every time.  The host
+// state then advances as the body would have advanced it.
+template <class F>
+mdlg_status replay_graph(mdlg_system* S, int kind, F body) {
+  auto key = std::make_tuple(kind, S->pcur, S->scur, S->since_sort, S->vel_full, S->lambda_pending,
+                             S->xi_par, S->xi_have);
+  auto it = S->graphs.find(key);
+  const mdlg_system::SeqState before = seq_state(S);
+  if (it == S->graphs.end()) {
+    if (!S->cap_stream) HIPCHK(S, hipStreamCreateWithFlags(&S->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = S->stream;
+    S->stream = S->cap_stream;
+    HIPCHK(S, hipStreamBeginCapture(S->cap_stream, hipStreamCaptureModeThreadLocal));
+    body();
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(S->cap_stream, &g);
+    S->stream = user;
+    mdlg_system::GraphEntry ent{};
+    ent.after = seq_state(S);
+    // the capture only recorded work: back to the state it started from
+    set_seq_state(S, before);
+    if (e != hipSuccess) return hip_fail(S, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(S, e, "hipGraphInstantiate");
+    // counters advance by the replay's increments from wherever they stand
+    ent.after.md_step -= before.md_step;
+    ent.after.n_lattice -= before.n_lattice;
+    ent.after.xi_steps -= before.xi_steps;
+    it = S->graphs.emplace(key, ent).first;
+  }
+  HIPCHK(S, hipGraphLaunch(it->second.exec, S->stream));
+  mdlg_system::SeqState q = it->second.after;
+  q.md_step += before.md_step;
+  q.n_lattice += before.n_lattice;
+  q.xi_steps += before.xi_steps;
+  set_seq_state(S, q);
+  return MDLG_OK;
+}
+
+}  // extern "C++"
+
 mdlg_status mdlg_coarse_grain(mdlg_system* S, int64_t T) {
   if (!S) return MDLG_E_INVALID;
   if (T < 0) {
@@ -1161,63 +1241,32 @@ mdlg_status mdlg_coarse_grain(mdlg_system* S, int64_t T) {
   }
   if (T == 0) return MDLG_OK;
   if (!S->snapshot_valid) enqueue_snapshot(S);
+  const int steps = S->cfg.md_steps_per_lattice_step;
+  // lattice steps of many MD steps are replayed in blocks (a graph of a whole
+  // lattice step would hold every launch of it): blocks of whole rebuild
+  // intervals, then the rest of the lattice step with its binning
+  const int R = std::max(1, S->L.sort_every);
+  const int block = R * std::max(1, kGraphBlockSteps / R);
   for (int64_t t = 0; t < T; ++t) {
     if (!S->use_graph || S->timing) {
       enqueue_lattice_step(S);
       continue;
     }
-    auto key = std::make_tuple(S->pcur, S->scur, S->since_sort, S->vel_full, S->lambda_pending,
-                               S->xi_par, S->xi_have);
-    auto it = S->graphs.find(key);
-    if (it == S->graphs.end()) {
-      if (!S->cap_stream) HIPCHK(S, hipStreamCreateWithFlags(&S->cap_stream, hipStreamNonBlocking));
-      hipStream_t user = S->stream;
-      const long long md0 = S->md_step, nl0 = S->n_lattice;
-      const int p0 = S->pcur, s0 = S->scur, ss0 = S->since_sort, x0 = S->xi_par;
-      const bool v0 = S->vel_full, l0 = S->lambda_pending, h0 = S->xi_have;
-      const long long xs0 = S->xi_steps;
-      S->stream = S->cap_stream;
-      HIPCHK(S, hipStreamBeginCapture(S->cap_stream, hipStreamCaptureModeThreadLocal));
-      enqueue_lattice_step(S);
-      hipGraph_t g = nullptr;
-      hipError_t e = hipStreamEndCapture(S->cap_stream, &g);
-      S->stream = user;
-      if (e != hipSuccess) return hip_fail(S, e, "hipStreamEndCapture");
-      mdlg_system::GraphEntry ent{};
-      e = hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (e != hipSuccess) return hip_fail(S, e, "hipGraphInstantiate");
-      ent.pcur = S->pcur;
-      ent.scur = S->scur;
-      ent.since_sort = S->since_sort;
-      ent.vel_full = S->vel_full;
-      ent.xi_par = S->xi_par;
-      // the capture only recorded work; restore the state it started from
-      S->xi_par = x0;
-      S->xi_have = h0;
-      S->xi_steps = xs0;
-      S->md_step = md0;
-      S->n_lattice = nl0;
-      S->pcur = p0;
-      S->scur = s0;
-      S->since_sort = ss0;
-      S->vel_full = v0;
-      S->lambda_pending = l0;
-      it = S->graphs.emplace(key, ent).first;
+    mdlg_status st;
+    if (steps <= kGraphMaxSteps) {
+      st = replay_graph(S, 0, [S] { enqueue_lattice_step(S); });
+    } else {
+      int left = steps;
+      st = MDLG_OK;
+      while (st == MDLG_OK && left > block) {
+        st = replay_graph(S, block, [S, block] {
+          for (int i = 0; i < block; ++i) enqueue_md_step(S, false);
+        });
+        left -= block;
+      }
+      if (st == MDLG_OK) st = replay_graph(S, -left, [S, left] { enqueue_lattice_tail(S, left); });
     }
-    HIPCHK(S, hipGraphLaunch(it->second.exec, S->stream));
-    S->pcur = it->second.pcur;
-    S->scur = it->second.scur;
-    S->since_sort = it->second.since_sort;
-    S->vel_full = it->second.vel_full;
-    S->lambda_pending = false;
-    if (S->L.xi) {
-      if (S->xi_have) S->xi_steps += 1;
-      S->xi_par = it->second.xi_par;
-      S->xi_have = true;
-    }
-    S->md_step += S->cfg.md_steps_per_lattice_step;
-    S->n_lattice += 1;
+    if (st != MDLG_OK) return st;
   }
   return check_launch(S, "mdlg_coarse_grain");
 }

@@ -210,6 +210,52 @@ def test_graph_replay_equals_eager_bitwise():
         np.testing.assert_array_equal(sa[key], sb[key])
 
 
+def _run_long_steps(env_graph, steps, T=3):
+    from paper_1705_04368_amd import make_config
+    old = os.environ.get("MDLG_NO_GRAPH")
+    os.environ["MDLG_NO_GRAPH"] = "0" if env_graph else "1"
+    try:
+        n, M = 2048, 16
+        pos, vel = synth.lj_initial_state(2, n, 4.0 * M, 1.0, seed=61)
+        sh = np.zeros((2, 2, 2))
+        sh[1, 1, 0] = 0.25
+        # forces off: the order of particles inside a cell after a counting
+        # sort depends on the order of atomics, and with forces on the
+        # summation order would then make two runs differ in the last bits
+        cfg = make_config(2, n, M, lattice_dx=4.0, dt=0.004, md_steps_per_lattice_step=steps, vmax=3,
+                          kT=1.0, sort_every=7, collision_stats=True, shifts=sh, forces_off=True)
+        sysg = make_system(cfg, pos, vel)
+        sysg.coarse_grain(T)
+        return (sysg.get_f(per_site=True), sysg.get_state(), sysg.get_xi(per_site=True, last=True),
+                sysg.get_shifts())
+    finally:
+        if old is None:
+            os.environ.pop("MDLG_NO_GRAPH", None)
+        else:
+            os.environ["MDLG_NO_GRAPH"] = old
+
+
+def test_long_lattice_steps_replay_in_blocks():
+    # 450 MD steps per lattice step: replayed as graphs of whole rebuild
+    # intervals (196 steps) and a tail with the binning; bitwise the same as
+    # eager launches, with the collision operator and a drifting lattice on
+    # (free flight: the sequencing is under test, not the forces)
+    say("long lattice steps: block graphs vs eager")
+    a = _run_long_steps(True, 450)
+    b = _run_long_steps(False, 450)
+    np.testing.assert_array_equal(a[0]["f_site"], b[0]["f_site"])
+    np.testing.assert_array_equal(a[0]["mom_site"], b[0]["mom_site"])
+    assert a[0]["n_lattice_steps"] == b[0]["n_lattice_steps"] == 3
+    for key in ("ucell", "off", "vel", "prev_ucell", "prev_off"):
+        np.testing.assert_array_equal(a[1][key], b[1][key])
+    for key in ("xi", "xi2", "xi_n", "xi_site", "xi_last"):
+        np.testing.assert_array_equal(a[2][key], b[2][key])
+    assert a[2]["n_steps"] == b[2]["n_steps"] == 2
+    for key in ("counts", "moments", "n_steps"):
+        np.testing.assert_array_equal(np.asarray(a[3][key]), np.asarray(b[3][key]))
+    assert a[3]["n_steps"] == 3
+
+
 def test_batched_replicas_equal_separate_runs():
     sizes, lats = [968, 2048, 1500], [11, 16, 14]
     say("batched replicas vs separate")
