@@ -81,7 +81,8 @@ def msd_exponential_vacf(kT, tau_v, t):
     """eq. (vca): per-axis MSD for an exponentially decaying velocity
     autocorrelation k_B T exp(-t/tau_v), 2 k_B T tau_v^2 (e^{-t/tau_v} + t/tau_v - 1)."""
     x = t / tau_v
-    return 2.0 * kT * tau_v * tau_v * (math.exp(-x) + x - 1.0)
+    # e^{-x} - 1 + x through expm1: no cancellation for t << tau_v
+    return 2.0 * kT * tau_v * tau_v * (math.expm1(-x) + x)
 
 
 def wedge(y):
@@ -117,3 +118,130 @@ def m2_discrete(a, kmax=None):
 D2Q9_WEIGHTS = (4.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0)
 """D2Q9 lattice Boltzmann weights w_0, w_{1-4}, w_{5-8} (section "Relation of
 MDLG equilibrium functions to lattice Boltzmann equilibria")."""
+
+
+# ---------------------------------------------------------------------------
+# Moments of a lattice distribution and consistent discretisations
+# (sections "Moments of the equilibrium distribution" and "Consistent
+# discretizations").  f is indexed like velocity_grid(dim, vmax).
+
+def lattice_velocities_of(f, dim):
+    """velocity_grid for a distribution array f of length (2V+1)^dim."""
+    q = len(f)
+    vmax = int(round(q ** (1.0 / dim))) // 2
+    assert (2 * vmax + 1) ** dim == q
+    return velocity_grid(dim, vmax)
+
+
+def second_moment_psi(f, dim, a, u=None):
+    """eq. (eqn:Psi): Psi_ab = sum_i f_i (v_ia - u_a)(v_ib - u_b) / (rho a^2),
+    rho = sum_i f_i.  Returns the dim x dim matrix."""
+    f = np.asarray(f, dtype=np.float64)
+    v = lattice_velocities_of(f, dim).astype(np.float64)
+    uu = np.zeros(dim) if u is None else np.asarray(u, dtype=np.float64)
+    rho = f.sum()
+    out = np.zeros((dim, dim))
+    for i in range(len(f)):
+        c = v[i] - uu
+        out += f[i] * np.outer(c, c)
+    return out / (rho * a * a)
+
+
+def third_moment_phi_xxx(f, dim, a, u=None):
+    """eq. (eqn:Phi) for alpha = beta = gamma = x:
+    sum_i f_i (v_ix - u_x)^3 / (rho a^3)."""
+    f = np.asarray(f, dtype=np.float64)
+    v = lattice_velocities_of(f, dim).astype(np.float64)
+    ux = 0.0 if u is None else float(np.asarray(u, dtype=np.float64)[0])
+    total = 0.0
+    for i in range(len(f)):
+        total += f[i] * (v[i, 0] - ux) ** 3
+    return total / (f.sum() * a ** 3)
+
+
+def one_shell(f, dim):
+    """f restricted to the velocities with every |v_a| <= 1 (9 in 2D, 27 in
+    3D), the others set to zero."""
+    f = np.array(f, dtype=np.float64)
+    v = lattice_velocities_of(f, dim)
+    f[np.any(np.abs(v) > 1, axis=1)] = 0.0
+    return f
+
+
+def theta2(f, dim, a, u=None):
+    """eq. (tet2): theta_2 = a^2 Psi_xx."""
+    return a * a * second_moment_psi(f, dim, a, u)[0, 0]
+
+
+def theta3_from(f_minus, f_plus, du, dim):
+    """eq. (tet3): theta_3 = (1 / (3 rho)) d/du_x sum_i f_i v_ix^3, the
+    derivative taken as the central difference of two distributions measured
+    at u_x -+ du (rho from their mean)."""
+    fm = np.asarray(f_minus, dtype=np.float64)
+    fp = np.asarray(f_plus, dtype=np.float64)
+    v = lattice_velocities_of(fm, dim).astype(np.float64)
+    sm = float(np.sum(fm * v[:, 0] ** 3))
+    sp = float(np.sum(fp * v[:, 0] ** 3))
+    rho = 0.5 * (fm.sum() + fp.sum())
+    return (sp - sm) / (2.0 * du) / (3.0 * rho)
+
+
+def a2_matching_weight(vel, w, dim=2, lo=1e-4, hi=4.0):
+    """Smallest a^2 at which the closed-form f_i^eq / rho of one velocity
+    equals the lattice Boltzmann weight w, eq. (wif0eqn): the first sign
+    change on a logarithmic scan of a^2 from lo, refined by bisection (the
+    closed form of a moving velocity first rises from 0, then falls)."""
+    vel = np.asarray(vel, dtype=np.float64)
+
+    def g(a2):
+        a = math.sqrt(a2)
+        return float(np.prod([f_alpha(vel[ax], a) for ax in range(dim)])) - w
+
+    grid = np.geomspace(lo, hi, 2001)
+    vals = [g(x) for x in grid]
+    k = next(i for i in range(len(grid) - 1) if (vals[i] < 0) != (vals[i + 1] < 0))
+    a, b, ga = grid[k], grid[k + 1], vals[k]
+    for _ in range(200):
+        mid = 0.5 * (a + b)
+        gm = g(mid)
+        if (gm < 0) == (ga < 0):
+            a, ga = mid, gm
+        else:
+            b = mid
+    return 0.5 * (a + b)
+
+
+def dt_for_dx(dx, a2, kT, tau_v, mass=1.0):
+    """Lattice time step Delta t at which the per-axis mean squared
+    displacement of eq. (vca) equals a^2 (Delta x)^2 (the consistent
+    discretisation for a given Delta x), by bisection (eq. (vca) increases
+    monotonically in t)."""
+    target = a2 * dx * dx
+
+    def msd(t):
+        return msd_exponential_vacf(kT / mass, tau_v, t)
+
+    lo, hi = 0.0, 1.0
+    while msd(hi) < target:
+        hi *= 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if msd(mid) < target:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def vacf_exponential(kT, tau_v, t, mass=1.0):
+    """The exponential velocity autocorrelation of the hot dilute gas,
+    <v_a(t) v_a(0)> = (k_B T / m) exp(-t / tau_v)."""
+    return kT / mass * np.exp(-np.asarray(t, dtype=np.float64) / tau_v)
+
+
+def fit_tau(t, vacf, kT, mass=1.0):
+    """tau_v of the exponential fit: least squares of log(vacf m / k_B T) =
+    -t / tau_v through the origin."""
+    t = np.asarray(t, dtype=np.float64)
+    y = np.log(np.asarray(vacf, dtype=np.float64) * mass / kT)
+    return -float(np.sum(t * t) / np.sum(t * y))
