@@ -39,6 +39,10 @@ WORKLOADS = {
     "3d": dict(dim=3, n=4194304, M=48, dx=4.0, kT=1.5, dt=0.004, steps=20, vmax=2,
                desc="3D LJ N=4194304, 192 sigma cube (rho=0.593), kT=1.5, dt=0.004, "
                     "48^3 lattice of 4 sigma, Delta t=20 MD steps, V=2 (Q=125)"),
+    "e1": dict(dim=2, n=100000, M=10, dx=100.0, kT=50.0, dt=1e-4, steps=341600, vmax=3,
+               desc="2D hot dilute LJ gas N=100000, 1000 sigma box (rho=0.1), kT=50, dt=1e-4, "
+                    "10x10 lattice of 100 sigma, Delta t=341600 MD steps (34.16 tau), V=3 (Q=49), "
+                    "plus lattices drifting at u_x = -/+0.01 for theta_3"),
     "batched": dict(dim=2, n=None, M=None, dx=4.0, kT=1.0, dt=0.005, steps=20, vmax=3,
                     replicas=512,
                     desc="512 2D LJ replicas, N_r log-uniform in [1024, 65536] (seed 4), rho=0.5, "
@@ -156,6 +160,51 @@ def summarize_traffic(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write
         json.dump(out, fh, indent=1)
         fh.write("\n")
     print(json.dumps(out, indent=1))
+
+
+E1_DU = 0.01  # drift of the two extra lattices of the e1 workload (lattice units per step)
+
+
+def e1_analysis(sysg, w):
+    """The paper-regime analysis of the hot dilute gas from the timed run's
+    readouts: a^2 from the measured per-axis mean squared displacement,
+    eq. (eqn:Psi), eq. (eqn:Phi), eq. (tet2), eq. (tet3) (lattices drifting at
+    u_x = -/+E1_DU), the discrete m_2, all on the full and the one-shell
+    velocity set; then the velocity autocorrelation over 1 tau of plain MD
+    steps, its exponential fit, eq. (vca) against the measured displacement,
+    the a^2 matching the D2Q9 weights and the Delta t(Delta x) of eq. (vca)."""
+    from paper_1705_04368_amd import analysis as an
+    dim, n = w["dim"], w["n"]
+    f = sysg.get_f()
+    T = f["n_lattice_steps"]
+    msd = f["disp_sq"] / (n * T)
+    a2 = float(np.mean(msd)) / w["dx"] ** 2
+    fi = f["f"]
+    sh = sysg.get_shifts()
+    q = len(fi)
+    fm, fp = sh["counts"][0][:q].astype(np.float64), sh["counts"][1][:q].astype(np.float64)
+    out = {"lattice_steps": T, "a2": a2, "msd_axis": [float(x) for x in msd],
+           "mean_velocity": [float(x) for x in (an.lattice_velocities(q, dim).T @ fi) / fi.sum()]}
+    for name, g, gm, gp in (("full", fi, fm, fp),
+                            ("one_shell", an.one_shell(fi, dim), an.one_shell(fm, dim),
+                             an.one_shell(fp, dim))):
+        out[name] = {"psi": an.psi(g, dim, a2).tolist(), "phi_xxx": an.phi_xxx(g, dim, a2),
+                     "theta2": an.theta2(g, dim, a2), "theta3": an.theta3(gm, gp, E1_DU, dim),
+                     "m2_minus_a2": an.m2(g, dim) - a2}
+    out["m2_closed_form_minus_a2"] = an.m2(an.equilibrium(dim, 12, a2), dim) - a2
+    out["f_minus_closed_form_max"] = float(np.max(np.abs(fi / fi.sum() - an.equilibrium(dim, w["vmax"], a2))))
+    # velocity autocorrelation over 1 tau of plain MD steps after the run
+    every = 250
+    t_steps, c = an.vacf_series(sysg, 40, every)
+    t = t_steps * w["dt"]
+    early = (t > 0) & (t <= 0.5)
+    tau = an.fit_tau(t[early], c[early], w["kT"])
+    out["vacf"] = {"t": t.tolist(), "c": c.tolist(), "tau_fit": tau}
+    dt_lat = w["steps"] * w["dt"]
+    out["msd_eq_vca"] = float(an.msd_exponential(w["kT"], tau, dt_lat))
+    out["d2q9_a2"] = {k: an.a2_for_weight(v, wt) for k, (v, wt) in an.D2Q9_WEIGHTS.items()}
+    out["dt_for_dx_100_a2_1_6"] = an.dt_for_dx(w["dx"], 1.0 / 6.0, w["kT"], tau)
+    return out
 
 
 def cpu_baseline(w, pos, vel, lattice_steps):
@@ -304,6 +353,10 @@ def main():
     tuning = dict(sort_every=args.sort_every, pair_list=not args.no_pair_list,
                   md_cell_split=args.md_cell_split, brick=tuple(args.brick),
                   collision_stats=args.collision_stats)
+    if args.workload == "e1":
+        sh = np.zeros((2, 2, dim))
+        sh[0, 1, 0], sh[1, 1, 0] = -E1_DU, E1_DU
+        tuning["shifts"] = sh
     if args.galilean:
         # drifting lattices u_x = 0 .. 0.5 (the sweep of the figure on the second moment)
         us = np.linspace(0.0, 0.5, args.galilean)
@@ -357,6 +410,7 @@ def main():
     sysg.coarse_grain(args.warmup)
     sysg.sync()
     sysg.reset_accumulators()
+    print(f"# warmed up ({args.warmup} lattice steps)", file=sys.stderr, flush=True)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -375,6 +429,7 @@ def main():
     sysg.coarse_grain(args.timing_steps)
     tim = sysg.get_timing()
     sysg.set_timing(False)
+    print(f"# event-timed {args.timing_steps} lattice steps", file=sys.stderr, flush=True)
     q, nm = lay["n_velocities"], lay["n_moments"]
     per_site = n / n_sites
     kernels = {}
@@ -452,7 +507,7 @@ def main():
         plain["f0_batched"] = float(f["f"][(q - 1) // 2]) / 8.0
 
     cpu = None
-    if not args.no_cpu_baseline and not w.get("replicas"):
+    if not args.no_cpu_baseline and not w.get("replicas") and args.workload != "e1":
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(w, pos, vel, args.cpu_lattice_steps)
 
@@ -475,6 +530,9 @@ def main():
         "sort": None if sort_unit is None else {kk: (round(vv, 6) if isinstance(vv, float) else vv)
                                                 for kk, vv in sort_unit.items()},
     }
+    if args.workload == "e1":
+        print("# e1 analysis", file=sys.stderr, flush=True)
+        out["analysis"] = e1_analysis(sysg, w)
     print(json.dumps(out), flush=True)
 
 

@@ -158,10 +158,14 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   const bool want_list = !c->no_pair_list && !c->forces_off;
   if (k == 0 && want_list) {
     // with pair lists the MD step stages the brick halo and walks the lists;
-    // the cell walk runs only at rebuilds.  Measured best: cells of side
-    // dx (one-cell stencil) in 2D, dx / 2 in 3D, where a one-cell stencil
-    // would walk ~1000 candidates per particle at each rebuild
-    const int kk = (D == 2) ? 1 : 2;
+    // the cell walk runs only at rebuilds.  Measured best on 4 sigma
+    // lattices: the smallest cells that keep a one-cell stencil (r_cut +
+    // sigma) in 2D, and a two-cell stencil ((r_cut + sigma) / 2) in 3D, where
+    // a one-cell stencil would walk ~1000 candidates per particle at each
+    // rebuild; coarser lattices split further (up to 8 cells per side)
+    const double smin = (D == 2) ? (c->r_cut + c->sigma) : 0.5 * (c->r_cut + c->sigma);
+    int kk = 1;
+    while (kk < 8 && c->lattice_dx / (2 * kk) >= smin) kk *= 2;
     int ns_k;
     const double m = margin_of(kk, &ns_k);
     if (m >= 0.5 * c->sigma && min_m * kk >= 2 * ns_k + 1) k = kk;

@@ -12,6 +12,9 @@
 
 #include "mdlg.h"
 
+// lattice steps longer than this are timed with this many MD steps each
+constexpr int kProxyLatticeSteps = 400;
+
 namespace {
 
 struct Cand {
@@ -101,6 +104,9 @@ struct Timer {
   // ms per MD step of candidate c, or a negative value when it does not run.
   double time(const Cand& c) {
     mdlg_config x = with(*base, c);
+    // a lattice step of very many MD steps is timed on a shorter one: the
+    // rate per MD step is what candidates are ranked by
+    if (x.md_steps_per_lattice_step > kProxyLatticeSteps) x.md_steps_per_lattice_step = kProxyLatticeSteps;
     size_t need = 0;
     if (mdlg_workspace_bytes(&x, &need) != MDLG_OK || need > ws_bytes) return -1;
     mdlg_system* S = nullptr;
@@ -113,7 +119,7 @@ struct Timer {
         hipEventRecord(a, stream) == hipSuccess && mdlg_coarse_grain(S, lattice_steps) == MDLG_OK &&
         hipEventRecord(b, stream) == hipSuccess && mdlg_sync(S) == MDLG_OK &&
         hipEventElapsedTime(&el, a, b) == hipSuccess)
-      ms = el / ((double)lattice_steps * base->md_steps_per_lattice_step);
+      ms = el / ((double)lattice_steps * x.md_steps_per_lattice_step);
     mdlg_destroy(S);
     return ms;
   }
@@ -173,9 +179,9 @@ mdlg_status mdlg_autotune(const mdlg_config* cfg, void* workspace_dev, size_t wo
   if (!cfg || !workspace_dev || !pos_dev || !vel_dev || !best || md_steps < 1) return MDLG_E_INVALID;
   mdlg_layout L0{};
   if (mdlg_describe(cfg, &L0) != MDLG_OK) return MDLG_E_INVALID;
+  const int timed_len = std::min(cfg->md_steps_per_lattice_step, kProxyLatticeSteps);
   Timer T{cfg, workspace_dev, workspace_bytes, static_cast<hipStream_t>(hip_stream), pos_dev,
-          vel_dev, std::max(1, (md_steps + cfg->md_steps_per_lattice_step - 1) /
-                                   cfg->md_steps_per_lattice_step)};
+          vel_dev, std::max(1, (md_steps + timed_len - 1) / timed_len)};
   if (hipEventCreate(&T.a) != hipSuccess || hipEventCreate(&T.b) != hipSuccess) return MDLG_E_DEVICE;
   const bool auto_k = cfg->md_cell_split == 0, auto_R = cfg->sort_every == 0;
   const bool auto_brick = !cfg->brick_x && !cfg->brick_y && !cfg->brick_z;
