@@ -311,8 +311,8 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   // expected at the densest replica's mean density plus 20 (a brick with a
   // fuller list walks its cells instead)
   L->kmax = 0;
-  // (list entries are LDS byte offsets of 16 bits: lcap * coordinate size < 64 KiB)
-  if (want_list && R >= 2 && L->lcap * (D == 2 ? 8 : 16) < 65536 && BX + 2 * L->ns <= kMaxListHalo &&
+  // (list entries are 16-bit staging indices: lcap < 2^16)
+  if (want_list && R >= 2 && L->lcap < 65536 && BX + 2 * L->ns <= kMaxListHalo &&
       BY + 2 * L->ns <= kMaxListHalo && BZ + 2 * nsz <= kMaxListHalo) {
     const double rl = c->r_cut + 2 * L->margin;
     const double vol_l = (D == 2) ? M_PI * rl * rl : 4.0 / 3.0 * M_PI * rl * rl * rl;

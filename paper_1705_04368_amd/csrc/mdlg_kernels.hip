@@ -452,7 +452,7 @@ __device__ __forceinline__ BrickLds<D, ADJ, CT> brick_lds(char* dyn, int* rowpre
                                                           double (*red)[4], const Phys& P,
                                                           int pad = 0) {
   // the staged coordinates come first, at the fixed start of the dynamic LDS,
-  // so that a list entry (a byte offset) addresses them without arithmetic
+  // so that a list entry (a staging index) addresses them with one shift
   BrickLds<D, ADJ, CT> L;
   L.p = reinterpret_cast<CT*>(dyn);
   size_t off = ((size_t)(P.lcap + pad) * sizeof(CT) + 15) & ~size_t(15);
@@ -593,11 +593,14 @@ __device__ __forceinline__ void brick_stage(const BrickGeom& G, const Phys& P,
                                             const float* __restrict__ pos, const float* __restrict__ lam,
                                             Lds& L, int cb, int ce, int2* __restrict__ smap = nullptr,
                                             float* __restrict__ off0 = nullptr) {
-  for (int v0 = cb + (int)threadIdx.x; v0 < ce; v0 += 4 * NT) {
-    int hh[4], g[4];
-    float p[4][D];
+  // SU particles per thread in flight (their halo-cell searches, then their
+  // position reads)
+  constexpr int SU = 4;
+  for (int v0 = cb + (int)threadIdx.x; v0 < ce; v0 += SU * NT) {
+    int hh[SU], g[SU];
+    float p[SU][D];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < SU; ++u) {
       const int v = v0 + u * NT;
       int lo = 0;
       if (v < ce) {
@@ -611,10 +614,10 @@ __device__ __forceinline__ void brick_stage(const BrickGeom& G, const Phys& P,
       g[u] = L.gs[lo] + (v - L.hs[lo]);
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < SU; ++u)
       if (v0 + u * NT < ce) ldv<D>(pos, g[u], p[u]);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < SU; ++u) {
       const int v = v0 + u * NT;
       if (v < ce) {
         const int hx = hh[u] % G.HX, r = hh[u] / G.HX;
@@ -819,15 +822,13 @@ __device__ __forceinline__ void vv_update(const ForceArgs& a, const Phys& P, int
   }
 }
 
-// Accumulate the LJ acceleration from the four halo indices packed in e.
+// Accumulate the LJ acceleration from the four staging indices packed in e.
 template <int D, class Lds>
 __device__ __forceinline__ void list_word(const Lds& L, unsigned long long e, int X, int Y, int Z,
                                           const Phys& P, float (&f)[D]) {
   Coord<D> q[4];
-  const char* base = reinterpret_cast<const char*>(L.p);
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-    q[u] = *reinterpret_cast<const Coord<D>*>(base + ((unsigned)(e >> (16 * u)) & 0xffffu));
+  for (int u = 0; u < 4; ++u) q[u] = L.p[(unsigned)(e >> (16 * u)) & 0xffffu];
 #pragma unroll
   for (int u = 0; u < 4; ++u) lj_pair_listed<D>(q[u], X, Y, Z, P, f);
 }
@@ -900,7 +901,7 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
     const int total = bi.x, ntg = bi.y;
     const size_t nt = (size_t)P.n_total;
     constexpr int GW = (D == 2) ? 2 : 4;
-    const unsigned long long pad = 0x0001000100010001ull * (unsigned)(total * sizeof(Coord<D>));
+    const unsigned long long pad = 0x0001000100010001ull * (unsigned)total;
     int gi = 0, t = 0, ng = 0;
     float o[D], v[D], o0[D];
 #pragma unroll
@@ -911,18 +912,25 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
       if constexpr (D == 2) L.p[total] = make_int2(kSentinel, kSentinel);
       else L.p[total] = make_int4(kSentinel, kSentinel, kSentinel, 0);
     }
-    for (int v0 = (int)threadIdx.x; v0 < total; v0 += 2 * NT) {
-      int2 e[2];
-      float p[2][D];
+    // SU map entries per thread in flight, then their positions: the map
+    // read and the position read it feeds are two dependent round trips, so
+    // a halo of total particles takes about 2 total / (SU NT) of them (2D
+    // halos of a few hundred particles take one pass either way; more
+    // registers there only cost occupancy)
+    constexpr int SU = (D == 2) ? 2 : 8;
+    for (int v0 = (int)threadIdx.x; v0 < total; v0 += SU * NT) {
+      int2 e[SU];
+      float p[SU][D];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < SU; ++u) {
         const int vv = v0 + u * NT;
-        e[u] = (v0 == (int)threadIdx.x && vv < total) ? (u == 0 ? pre_e0 : pre_e1)
-                                                       : smap[min(vv, total - 1)];
-        ldv<D>(a.pos_in, e[u].x, p[u]);
+        e[u] = (v0 == (int)threadIdx.x && u < 2 && vv < total) ? (u == 0 ? pre_e0 : pre_e1)
+                                                                : smap[min(vv, total - 1)];
       }
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < SU; ++u) ldv<D>(a.pos_in, e[u].x, p[u]);
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
         const int vv = v0 + u * NT;
         if (vv < total) {
           const int hx = e[u].y & 255, hy = (e[u].y >> 8) & 255;
@@ -1087,8 +1095,8 @@ __device__ __forceinline__ void list_push(unsigned long long*& wp, unsigned& hi,
 // One row of a target's candidates, LDS range [jlo, jhi): test GR candidates
 // at a time into a bit mask (the last step reads into the next row or the
 // padding and is masked), then append the accepted ones, so that appends cost
-// per accepted entry rather than per candidate.  Entries are force-kernel LDS
-// byte offsets: the row's LDS index plus its list shift (s0 left of ja, s1
+// per accepted entry rather than per candidate.  Entries are force-kernel
+// staging indices: the row's LDS index plus its list shift (s0 left of ja, s1
 // below jb, s2 beyond).
 template <int D, int GR>
 __device__ __forceinline__ void nl_row(const Coord14<D>* __restrict__ p, int jlo, int jhi, int ja,
@@ -1119,7 +1127,7 @@ __device__ __forceinline__ void nl_row(const Coord14<D>* __restrict__ p, int jlo
       const int j = j0 + __builtin_ctz(mask);
       mask &= mask - 1;
       list_push(wp, whi, wlo, cnt,
-                (unsigned)((j + (j < ja ? s0 : (j < jb ? s1 : s2))) * (int)sizeof(Coord<D>)), nt);
+                (unsigned)(j + (j < ja ? s0 : (j < jb ? s1 : s2))), nt);
     }
   }
 }
@@ -1209,7 +1217,7 @@ __device__ __forceinline__ void nlist_brick(const NlistArgs& a) {
     }
     if (seen > kmax) s_over = 1;
     // pad the last word with the sentinel (far outside the cutoff)
-    while (cnt & 3) list_push(wp, whi, wlo, cnt, (unsigned)(G.total * (int)sizeof(Coord<D>)), nt);
+    while (cnt & 3) list_push(wp, whi, wlo, cnt, (unsigned)G.total, nt);
     const int words = (cnt + 3) >> 2;
     smap[t] = make_int2(gi, pack_halo(hxi, hyi, hzi) | ((words * 4) << 24));
     s_words[t] = (unsigned char)words;
