@@ -984,6 +984,7 @@ mdlg_status read_err(mdlg_system* S) {
     std::string m = "device error word 0x" + std::to_string(e) + ":";
     if (e & kErrMargin) m += " a particle left its cell by more than the rebuild margin (lower sort_every or dt);";
     if (e & kErrSkin) m += " a particle moved farther than the rebuild margin since the pair lists were built (lower sort_every or dt);";
+    if (e & kErrRecord) m += " internal: a pair-list target record named no particle;";
     if (e & kErrNonFinite) m += " non-finite coordinates;";
     if (e & kErrJump) m += " a particle moved more than one cell between rebuilds or started outside the box;";
     if (e & kErrImage) m += " image counter out of range;";

@@ -29,6 +29,7 @@ constexpr unsigned kErrJump = 4u;       // moved more than one cell between rebu
 constexpr unsigned kErrImage = 8u;      // image counter or unwrapped cell out of range
 constexpr unsigned kErrOverflow = 16u;  // more particles in one cell than a slot can index
 constexpr unsigned kErrSkin = 32u;      // moved farther than the margin since the pair lists were built
+constexpr unsigned kErrRecord = 64u;    // a pair-list target record names no particle (internal)
 
 // pair lists: halo-local indices of 16 bits, four per 64-bit word; the list
 // length shares a word with three 8-bit halo coordinates

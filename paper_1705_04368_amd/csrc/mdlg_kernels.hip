@@ -842,6 +842,12 @@ __device__ __forceinline__ void list_fetch(const ForceArgs& a, int2 r, bool has,
                                            unsigned long long (&w)[GW]) {
   gi = r.x;
   t = r.y & 0xffff;
+  if (has && (size_t)(unsigned)gi >= nt) {
+    // records come from the list builder; one that names no particle is
+    // reported and read as particle 0 rather than followed out of bounds
+    atomicOr(a.err, kErrRecord);
+    gi = 0;
+  }
   ng = has ? ((unsigned)r.y >> 16) : 0;
   if (has) {
     ldv<D>(a.pos_in, gi, o);
