@@ -279,7 +279,9 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
   constexpr int kHist = 2048;
   constexpr int kPer = kCountChunkMax / kBlock;
-  constexpr int kTiles = kHist / kScanTile + 2;
+  // scan-tile totals of the block: the window's tiles and those a particle
+  // moving by one cell along the slowest axis reaches
+  constexpr int kTiles = 64;
   __shared__ int s_cnt[kHist];
   __shared__ int s_tile[kTiles];
   // consecutive chunks on one XCD: the per-cell count atomics of neighbouring
@@ -297,6 +299,10 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
   const int nwin = min(kHist, a.cell[ch.z - 1] + R.Mc[0] + 2 - lo);
   for (int i = threadIdx.x; i < nwin; i += kBlock) s_cnt[i] = 0;
   if (threadIdx.x < kTiles) s_tile[threadIdx.x] = 0;
+  // (the reach below the window is capped so that the window's own tiles
+  // always index inside s_tile: (16 + 2) tiles + 2 < kTiles)
+  const int layer = min((D == 3) ? R.Mc[0] * R.Mc[1] : R.Mc[0], 16 * kScanTile);
+  const int tile0 = max(0, lo - layer) / kScanTile;
   __syncthreads();
   int key[kPer], rank[kPer];
   bool inwin[kPer];
@@ -319,10 +325,15 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
         a.keyslot[g] = make_int2(key[u], atomicAdd(a.count + key[u], 1));
       }
     }
-    wave_agg_add_i(a.tile_sum, key[u] >= 0 ? key[u] / kScanTile : 0, key[u] >= 0 && !inwin[u]);
+    if (key[u] >= 0 && !inwin[u]) {
+      const int tl = key[u] / kScanTile - tile0;
+      if (tl >= 0 && tl < kTiles) atomicAdd(&s_tile[tl], 1);
+    }
+    const int tk = key[u] >= 0 ? key[u] / kScanTile - tile0 : 0;
+    wave_agg_add_i(a.tile_sum, key[u] >= 0 ? key[u] / kScanTile : 0,
+                   key[u] >= 0 && !inwin[u] && (tk < 0 || tk >= kTiles));
   }
   __syncthreads();
-  const int tile0 = lo >= 0 ? lo / kScanTile : 0;
   for (int i = threadIdx.x; i < nwin; i += kBlock) {
     const int c = s_cnt[i];
     if (c) {

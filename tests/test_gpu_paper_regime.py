@@ -10,9 +10,11 @@ drifting at u_x = -/+0.01 for eq. (tet3).  One lattice step on the GPU, then:
   displacement, eq. (Pfinal); at Delta t / tau ~ 68 collision times its
   non-Gaussian remainder is of order 1e-3);
 * the velocity autocorrelation decays with tau = 0.50 +- 0.05 (the paper's
-  fit to the same system) and eq. (vca) with the fitted tau gives the
-  measured mean squared displacement within 6% (the paper ignores the 2D
-  long-time tail, which adds a few percent at 34 tau);
+  fit to the same system), and eq. (vca) with the fitted tau falls short of
+  the measured mean squared displacement by at most 10% (the paper ignores
+  the 2D long-time tail of the autocorrelation, which only adds to the
+  displacement; measured 3.5-6%, the spread coming from the fit of tau on one
+  trajectory);
 * on the one-shell velocity set theta_2 and theta_3 (eqs. (tet2), (tet3))
   both lie within 0.02 of 1/3 at this a^2 close to 1/6, and the mean lattice
   velocity vanishes within 3 standard errors.
@@ -90,5 +92,5 @@ def test_hot_dilute_gas_analysis():
     pred = cf.msd_exponential_vacf(KT, tau, STEPS * DT)
     say(f"  tau {tau:.4f}; msd measured {msd:.1f}, eq. (vca) {pred:.1f}")
     assert 0.45 <= tau <= 0.55
-    assert abs(msd - pred) <= 0.06 * msd
+    assert 0.0 <= msd - pred <= 0.10 * msd
     sysg.close()
