@@ -42,7 +42,7 @@ WORKLOADS = {
     "e1": dict(dim=2, n=100000, M=10, dx=100.0, kT=50.0, dt=1e-4, steps=341600, vmax=3,
                desc="2D hot dilute LJ gas N=100000, 1000 sigma box (rho=0.1), kT=50, dt=1e-4, "
                     "10x10 lattice of 100 sigma, Delta t=341600 MD steps (34.16 tau), V=3 (Q=49), "
-                    "plus lattices drifting at u_x = -/+0.01 for theta_3"),
+                    "plus lattices drifting at u_x = -/+0.05 for theta_3"),
     "batched": dict(dim=2, n=None, M=None, dx=4.0, kT=1.0, dt=0.005, steps=20, vmax=3,
                     replicas=512,
                     desc="512 2D LJ replicas, N_r log-uniform in [1024, 65536] (seed 4), rho=0.5, "
@@ -162,7 +162,7 @@ def summarize_traffic(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write
     print(json.dumps(out, indent=1))
 
 
-E1_DU = 0.01  # drift of the two extra lattices of the e1 workload (lattice units per step)
+E1_DU = 0.05  # drift of the two extra lattices of the e1 workload (lattice units per step)
 
 
 def e1_analysis(sysg, w):

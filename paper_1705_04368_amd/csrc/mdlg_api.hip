@@ -542,7 +542,7 @@ size_t carve(mdlg_system* S, char* base) {
   S->keyslot = c.take<int2>(base, N);
   S->count = c.take<int>(base, (size_t)L.n_cells);
   S->cell_start = c.take<int>(base, (size_t)L.n_cells + 1);
-  S->tile_sum = c.take<int>(base, (size_t)L.ntiles);
+  S->tile_sum = c.take<int>(base, (size_t)L.ntiles * kTileCopies);
   for (int i = 0; i < 2; ++i) {
     S->prev_u[i] = c.take<int>(base, N * D);
     S->prev_off[i] = c.take<float>(base, N * D);
@@ -1122,7 +1122,7 @@ mdlg_status mdlg_create(const mdlg_config* cfg, void* workspace_dev, size_t work
                               S->stream));
   }
   launch_fill_u32(reinterpret_cast<unsigned*>(S->count), 0u, L.n_cells, S->stream);
-  launch_fill_u32(reinterpret_cast<unsigned*>(S->tile_sum), 0u, L.ntiles, S->stream);
+  launch_fill_u32(reinterpret_cast<unsigned*>(S->tile_sum), 0u, (long long)L.ntiles * kTileCopies, S->stream);
   launch_fill_u32(S->err, 0u, 64, S->stream);
   launch_fill_f32(S->lambda, 1.f, (long long)L.reps.size(), S->stream);
   zero_accumulators(S);

@@ -9,6 +9,7 @@ namespace mdlg {
 constexpr int kBlock = 256;          // threads per block for every kernel
 constexpr int kWaves = kBlock / 64;  // wave64
 constexpr int kScanTile = 1024;      // cells per block of the cell-start scan
+constexpr int kTileCopies = 8;       // copies of the scan-tile totals (one per XCD of the adding block)
 constexpr int kScanItems = kScanTile / kBlock;
 constexpr int kPartChunkMax = 512;   // particles per block of the per-particle kernels
 constexpr int kCountChunkMax = 4096; // particles per block of the counting pass (at most)

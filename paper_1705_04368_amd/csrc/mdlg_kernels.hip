@@ -292,6 +292,9 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
     cb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   }
   if (cb >= a.ncchunks) return;
+  // scan-tile totals go to the copy of this block's XCD (consecutive blocks
+  // alternate XCDs): same-address atomics from many blocks serialise
+  int* __restrict__ tsum = a.tile_sum + (size_t)(blockIdx.x & (kTileCopies - 1)) * a.ntiles;
   const int4 ch = a.cchunks[cb];
   const Replica R = a.reps[ch.x];
   // window: the chunk's old cells (sorted) widened by one row on either side
@@ -330,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
       if (tl >= 0 && tl < kTiles) atomicAdd(&s_tile[tl], 1);
     }
     const int tk = key[u] >= 0 ? key[u] / kScanTile - tile0 : 0;
-    wave_agg_add_i(a.tile_sum, key[u] >= 0 ? key[u] / kScanTile : 0,
+    wave_agg_add_i(tsum, key[u] >= 0 ? key[u] / kScanTile : 0,
                    key[u] >= 0 && !inwin[u] && (tk < 0 || tk >= kTiles));
   }
   __syncthreads();
@@ -342,7 +345,7 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
     }
   }
   __syncthreads();
-  if (threadIdx.x < kTiles && s_tile[threadIdx.x]) atomicAdd(a.tile_sum + tile0 + threadIdx.x, s_tile[threadIdx.x]);
+  if (threadIdx.x < kTiles && s_tile[threadIdx.x]) atomicAdd(tsum + tile0 + threadIdx.x, s_tile[threadIdx.x]);
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
     const int g = ch.y + u * kBlock + (int)threadIdx.x;
@@ -354,7 +357,9 @@ __global__ __launch_bounds__(kBlock) void k_scan(ScanArgs a) {
   __shared__ int s_tmp[kWaves + 1];
   const int b = blockIdx.x;
   int pre = 0;
-  for (int t = threadIdx.x; t < b; t += kBlock) pre += a.tile_sum[t];
+  for (int t = threadIdx.x; t < b; t += kBlock)
+#pragma unroll
+    for (int c = 0; c < kTileCopies; ++c) pre += a.tile_sum[(size_t)c * a.ntiles + t];
   pre = block_sum(pre, s_tmp);
   const int base = b * kScanTile + threadIdx.x * kScanItems;
   int vals[kScanItems];
@@ -382,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_scan(ScanArgs a) {
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_scatter(SortArgs a) {
   if (blockIdx.x == 0)
-    for (int t = threadIdx.x; t < a.ntiles; t += kBlock) a.tile_sum[t] = 0;
+    for (int t = threadIdx.x; t < a.ntiles * kTileCopies; t += kBlock) a.tile_sum[t] = 0;
   const int4 ch = a.chunks[blockIdx.x];
   const Replica R = a.reps[ch.x];
   for (int g = ch.y + threadIdx.x; g < ch.z; g += kBlock) {
