@@ -567,7 +567,7 @@ size_t carve(mdlg_system* S, char* base) {
   if (L.n_shifts > 0) {
     S->shifts = c.take<double>(base, (size_t)L.n_shifts * 2 * D);
     S->shift_k = c.take<long long>(base, 1);
-    S->shift_acc = c.take<unsigned long long>(base, (size_t)L.n_shifts * shift_per(L));
+    S->shift_acc = c.take<unsigned long long>(base, (size_t)L.n_shifts * shift_per(L) * kTileCopies);
   }
   if (L.xi) {
     const size_t sq = (size_t)L.n_sites * L.Q;
@@ -1003,7 +1003,7 @@ void zero_accumulators(mdlg_system* S) {
                   S->stream);
   if (L.n_shifts > 0) {
     launch_fill_u32(reinterpret_cast<unsigned*>(S->shift_acc), 0u,
-                    (long long)L.n_shifts * shift_per(L) * 2, S->stream);
+                    (long long)L.n_shifts * shift_per(L) * 2 * kTileCopies, S->stream);
     // lattice time of the next arrival: 1 (the snapshot is time 0)
     launch_fill_u32(reinterpret_cast<unsigned*>(S->shift_k), 1u, 1, S->stream);
     launch_fill_u32(reinterpret_cast<unsigned*>(S->shift_k) + 1, 0u, 1, S->stream);
@@ -1374,10 +1374,15 @@ mdlg_status mdlg_get_shifts(mdlg_system* S, uint64_t* counts, int64_t* moments, 
   }
   if (S->timing) close_run(S);
   const int per = shift_per(L), nmo = per - L.Q - 1;
-  std::vector<unsigned long long> h((size_t)L.n_shifts * per);
-  HIPCHK(S, hipMemcpyAsync(h.data(), S->shift_acc, h.size() * sizeof(unsigned long long),
+  // the kernel's per-XCD copies of the accumulators, summed here (modulo
+  // 2^64: the moments are two's-complement)
+  const size_t one = (size_t)L.n_shifts * per;
+  std::vector<unsigned long long> hc(one * kTileCopies), h(one, 0ull);
+  HIPCHK(S, hipMemcpyAsync(hc.data(), S->shift_acc, hc.size() * sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, S->stream));
   mdlg_status st = read_err(S);
+  for (int c = 0; c < kTileCopies; ++c)
+    for (size_t i = 0; i < one; ++i) h[i] += hc[(size_t)c * one + i];
   for (int j = 0; j < L.n_shifts; ++j) {
     if (counts)
       for (int i = 0; i <= L.Q; ++i) counts[(size_t)j * (L.Q + 1) + i] = h[(size_t)j * per + i];

@@ -179,6 +179,12 @@ __device__ __forceinline__ int block_sum(int v, int* s_tmp) {
   return total;
 }
 
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -1847,14 +1853,18 @@ __global__ __launch_bounds__(kBlock) void k_shift(ShiftArgs a) {
           stride *= W;
         }
         wave_agg_add(s_cnt + j * (Q + 1), inside ? bin : Q, valid);
-        if (valid) {
+        // moments summed across the wave first: every lane adds to the same
+        // few LDS words, which would serialise
+        {
           int kq = D;
 #pragma unroll
           for (int p = 0; p < D; ++p) {
-            if (v[p] != 0) atomicAdd(&s_mom[j][p], v[p]);
+            const int sp = wave_sum_i(valid ? v[p] : 0);
+            if (lane_id() == 0 && sp != 0) atomicAdd(&s_mom[j][p], sp);
 #pragma unroll
             for (int q = p; q < D; ++q) {
-              if (v[p] * v[q] != 0) atomicAdd(&s_mom[j][kq], v[p] * v[q]);
+              const int sq = wave_sum_i(valid ? v[p] * v[q] : 0);
+              if (lane_id() == 0 && sq != 0) atomicAdd(&s_mom[j][kq], sq);
               ++kq;
             }
           }
@@ -1863,14 +1873,17 @@ __global__ __launch_bounds__(kBlock) void k_shift(ShiftArgs a) {
     }
   }
   __syncthreads();
+  // into the copy of this block's XCD (every block adds to the same few
+  // counters; same-address atomics from many blocks serialise)
+  unsigned long long* __restrict__ acc =
+      a.acc + (size_t)(blockIdx.x & (kTileCopies - 1)) * a.n_shifts * per;
   for (int e = threadIdx.x; e < a.n_shifts * (Q + 1); e += kBlock) {
     const unsigned c = s_cnt[e];
-    if (c) atomicAdd(a.acc + (size_t)(e / (Q + 1)) * per + e % (Q + 1), (unsigned long long)c);
+    if (c) atomicAdd(acc + (size_t)(e / (Q + 1)) * per + e % (Q + 1), (unsigned long long)c);
   }
   for (int e = threadIdx.x; e < a.n_shifts * NM; e += kBlock) {
     const int m = s_mom[e / NM][e % NM];
-    if (m) atomicAdd(a.acc + (size_t)(e / NM) * per + Q + 1 + e % NM,
-                     (unsigned long long)(long long)m);
+    if (m) atomicAdd(acc + (size_t)(e / NM) * per + Q + 1 + e % NM, (unsigned long long)(long long)m);
   }
 }
 
