@@ -93,10 +93,16 @@ def bin_bytes_per_particle(dim, q, nm, per_site_particles):
 
 
 def source_digest():
+    """Digest of the kernel sources with comments and blank space removed, so
+    that a stored counter summary stays valid across comment edits."""
+    import re
     h = hashlib.sha256()
     for f in ("mdlg_kernels.hip", "mdlg_args.h", "mdlg_device.h"):
-        with open(os.path.join(ROOT, "paper_1705_04368_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1705_04368_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -16,11 +16,18 @@
 //   k_count    canonicalise (cell, offset, image) and count particles per cell
 //   k_scan     exclusive scan of the counts into cell_start
 //   k_scatter  stable-by-slot permutation of the state into cell order
-//   k_force    LJ forces with the neighbour cells of a brick staged in LDS, fused
-//              with the velocity-Verlet half kicks and the drift
+//   k_nlist_narrow / k_nlist_wide    pair lists of radius r_cut + 2 margin
+//              per brick at each rebuild (14-bit candidate tests), with the
+//              staging map and target order the force kernel follows
+//   k_force    LJ forces with the neighbour cells of a brick staged in LDS
+//              (pair lists, or the cell walk), fused with the velocity-Verlet
+//              half kicks and the drift
+//   k_shift    binning on displaced and moving lattices
 //   k_bin      MDLG binning (eq. MDni): lattice velocity from the unwrapped
 //              lattice cells at t and at the previous snapshot, LDS histogram
 //              per site strip with wave-aggregated atomics, flush to HBM
+//   k_xi / k_xi_reduce               collision operator (eq. Xi)
+//   k_adjoint / k_adj_loss / k_adj_final / k_adj_io   reverse velocity Verlet
 //   k_fsum / k_ffinal / k_site_avg   f_i^eq readout (eq. fieq)
 //   k_kin      FP64 momentum / kinetic energy per replica, thermostat factor
 //   k_export / k_import              state in id order
