@@ -484,7 +484,7 @@ def main():
                           "work_per_launch": work}
         elif k == "nlist":
             # read the offsets, write the lists (16-bit entries within
-            # r_cut + 2 margin), the staging map and the reference offsets
+            # r_cut + 2 margin), the target records and the reference offsets
             rl = 2.5 + 2 * lay["margin"]
             vol = math.pi * rl * rl if dim == 2 else 4.0 / 3.0 * math.pi * rl ** 3
             work = n * (4 * dim + 2 * vol * rho + 8 + 4 * dim)

@@ -74,7 +74,7 @@ struct ForceArgs {
   int nbricks;
   int xcd_remap;
   // pair lists (null nl: every brick walks its cell rows)
-  const int2* smap;    // [nbricks][lcap] {particle, hx | hy << 8 | hz << 16 | len << 24}
+  const int2* smap;    // [nbricks][lcap] staged halo in LDS order {particle, hx | hy << 8 | hz << 16}
   const int4* binfo;   // [nbricks] {staged, targets, lists valid, -}
   const unsigned long long* nl;  // [kmax / 4][n_total] four 16-bit halo indices per word
   const float* off0;   // offsets when the lists were built

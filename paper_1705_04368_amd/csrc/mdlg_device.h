@@ -32,8 +32,9 @@ constexpr unsigned kErrOverflow = 16u;  // more particles in one cell than a slo
 constexpr unsigned kErrSkin = 32u;      // moved farther than the margin since the pair lists were built
 constexpr unsigned kErrRecord = 64u;    // a pair-list target record names no particle (internal)
 
-// pair lists: halo-local indices of 16 bits, four per 64-bit word; the list
-// length shares a word with three 8-bit halo coordinates
+// pair lists: halo-local indices of 16 bits, four per 64-bit word; at most
+// 63 words per list (the builder orders a brick's targets by word count in 64
+// bins); the staging map packs a halo cell's coordinates in 8 bits per axis
 constexpr int kMaxPairSlots = 252;
 constexpr int kMaxListHalo = 255;    // halo cells per axis a packed coordinate can hold
 

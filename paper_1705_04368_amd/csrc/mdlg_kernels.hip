@@ -592,31 +592,16 @@ __device__ __forceinline__ BrickGeom brick_setup(const Phys& P, const Replica& R
   return G;
 }
 
-// Stage halo particles [cb, ce) (LDS order) as fixed-point coordinates, and
-// their adjoint velocities when `lam` is given.
-// Offset from the LDS index of a particle of halo cell h to its index in the
-// pair-list order, which puts the brick's own particles (the targets, in
-// target order) first and the rest of the halo after them, both in halo
-// order.
-template <class Lds>
-__device__ __forceinline__ int list_shift(const BrickGeom& G, const Lds& L, int hx, int hy, int hz) {
-  const int rh = hy + G.HY * hz;
-  const bool row_in = hy >= G.ns && hy < G.ns + G.wy && hz >= G.nsz && hz < G.nsz + G.wz;
-  int rb;  // brick rows that come before this halo row
-  if (hz < G.nsz) rb = 0;
-  else if (hz >= G.nsz + G.wz) rb = G.nrows;
-  else rb = (hz - G.nsz) * G.wy + min(max(hy - G.ns, 0), G.wy);
-  if (row_in) {
-    if (hx >= G.ns && hx < G.ns + G.wx) return L.rowpre[rb] - L.hs[G.HX * rh + G.ns];
-    if (hx >= G.ns + G.wx) rb += 1;
-  }
-  return G.ntg - L.rowpre[rb];
-}
-
 __device__ __forceinline__ int pack_halo(int hx, int hy, int hz) {
   return hx | (hy << 8) | (hz << 16);
 }
 
+// Stage halo particles [cb, ce) (LDS order) as fixed-point coordinates, and
+// their adjoint velocities when `lam` is given.  For the pair lists, `smap`
+// receives every staged particle's {index, packed halo cell} in LDS order
+// (the force kernel's staging map) and `off0` the positions of the brick's
+// own particles (the targets), the reference offsets of the displacement
+// check.
 template <int D, int NT, class Lds>
 __device__ __forceinline__ void brick_stage(const BrickGeom& G, const Phys& P,
                                             const float* __restrict__ pos, const float* __restrict__ lam,
@@ -662,14 +647,11 @@ __device__ __forceinline__ void brick_stage(const BrickGeom& G, const Phys& P,
           for (int k = 0; k < D; ++k) L.lam[(v - cb) * D + k] = l[k];
         }
         if (smap) {
-          // halo entries of the pair-list staging map (targets are written
-          // with their list lengths by the list builder)
-          const int nv = v + list_shift(G, L, hx, r % G.HY, r / G.HY);
-          if (nv >= G.ntg)
-            smap[nv] = make_int2(g[u], (D == 2) ? pack_halo(hx, r, 0)
-                                                : pack_halo(hx, r % G.HY, r / G.HY));
-          else if (off0)
-            stv<D>(off0, g[u], p[u]);  // a target: its reference offset
+          const int hy = (D == 2) ? r : r % G.HY, hz = (D == 2) ? 0 : r / G.HY;
+          smap[v - cb] = make_int2(g[u], pack_halo(hx, hy, hz));
+          if (off0 && hx >= G.ns && hx < G.ns + G.wx && hy >= G.ns && hy < G.ns + G.wy &&
+              hz >= G.nsz && hz < G.nsz + G.wz)
+            stv<D>(off0, g[u], p[u]);
         }
       }
     }
@@ -925,7 +907,7 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
   const int4 bi = a.nl ? a.binfo[b] : make_int4(0, 0, 0, 0);
   if (bi.z) {
     // pair-list path: stage the halo through the map written by the list
-    // builder (targets first), then each target walks its own list.  The
+    // builder (halo cells in order), then each target walks its own list.  The
     // targets come in the builder's order (decreasing list length, so that
     // the lanes of a wave walk lists of similar length) as records
     // {particle, LDS slot | words << 16}; the first pass's records, state and
@@ -1087,10 +1069,11 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
 // the halo particles within r_cut + 2 m, m the rebuild margin, so that it
 // covers every pair within r_cut while no particle has moved farther than m
 // since (the force kernel checks that bound).  Entries are 16-bit indices
-// into the brick's staging order (targets first), four to a word, the last
-// word padded with the target's own index (a zero term).  A brick whose
-// halo exceeds one LDS chunk, or with a target of more than kmax neighbours,
-// is marked for the cell walk.
+// into the brick's LDS staging of its halo (halo cells in order, from the
+// cell table, which stays fixed until the next rebuild), four to a word, the
+// last word padded with the index of a sentinel slot beyond the halo (a zero
+// term).  A brick whose halo exceeds one LDS chunk, or with a target of more
+// than kmax neighbours, is marked for the cell walk.
 typedef short Short2 __attribute__((ext_vector_type(2)));
 
 // List-radius test of candidate q against the target (Txy, Tz) in 14-bit
@@ -1130,14 +1113,13 @@ __device__ __forceinline__ void list_push(unsigned long long*& wp, unsigned& hi,
 // One row of a target's candidates, LDS range [jlo, jhi): test GR candidates
 // at a time into a bit mask (the last step reads into the next row or the
 // padding and is masked), then append the accepted ones, so that appends cost
-// per accepted entry rather than per candidate.  Entries are force-kernel
-// staging indices: the row's LDS index plus its list shift (s0 left of ja, s1
-// below jb, s2 beyond).
+// per accepted entry rather than per candidate.  Entries are the candidates'
+// LDS indices, which the force kernel's staging reproduces.
 template <int D, int GR>
-__device__ __forceinline__ void nl_row(const Coord14<D>* __restrict__ p, int jlo, int jhi, int ja,
-                                       int jb, int s0, int s1, int s2, int vi, unsigned Txy, int Tz,
-                                       int thr, int kmax, size_t nt, unsigned long long*& wp,
-                                       unsigned& whi, unsigned& wlo, int& cnt, int& seen) {
+__device__ __forceinline__ void nl_row(const Coord14<D>* __restrict__ p, int jlo, int jhi, int vi,
+                                       unsigned Txy, int Tz, int thr, int kmax, size_t nt,
+                                       unsigned long long*& wp, unsigned& whi, unsigned& wlo, int& cnt,
+                                       int& seen) {
   for (int j0 = jlo; j0 < jhi; j0 += GR) {
     int r[GR];
 #pragma unroll
@@ -1161,8 +1143,7 @@ __device__ __forceinline__ void nl_row(const Coord14<D>* __restrict__ p, int jlo
     while (mask) {
       const int j = j0 + __builtin_ctz(mask);
       mask &= mask - 1;
-      list_push(wp, whi, wlo, cnt,
-                (unsigned)(j + (j < ja ? s0 : (j < jb ? s1 : s2))), nt);
+      list_push(wp, whi, wlo, cnt, (unsigned)j, nt);
     }
   }
 }
@@ -1236,25 +1217,16 @@ __device__ __forceinline__ void nlist_brick(const NlistArgs& a) {
       for (int cy = rr.cy0; cy <= rr.cy1; ++cy) {
         int cx0, cx1;
         if (!row_columns<D>(G, P, X, Y, Z, cy, cz, P.rl2_u, 4 + eh, cx0, cx1)) continue;
+        // one contiguous LDS range per row
         const int hrow = G.HX * (cy + G.HY * cz);
-        // one contiguous LDS range per row; its list shift takes at most three
-        // values: halo columns left of the brick, the brick's own, halo to the
-        // right (one loop per row keeps the lanes of a wave in step)
-        const int ca = min(max(G.ns, cx0), cx1 + 1), cb = min(max(G.ns + G.wx, cx0), cx1 + 1);
-        const int ja = L.hs[hrow + ca], jb = L.hs[hrow + cb];
-        const int s0 = list_shift(G, L, 0, cy, cz);
-        const int s1 = list_shift(G, L, G.ns, cy, cz);
-        const int s2 = list_shift(G, L, G.ns + G.wx, cy, cz);
-        const int jhi = L.hs[hrow + cx1 + 1];
-        const int j0r = L.hs[hrow + cx0];
-        nl_row<D, GR>(L.p, j0r, jhi, ja, jb, s0, s1, s2, vi, Txy, Tz, thr, kmax, nt, wp, whi, wlo, cnt, seen);
+        nl_row<D, GR>(L.p, L.hs[hrow + cx0], L.hs[hrow + cx1 + 1], vi, Txy, Tz, thr, kmax, nt, wp,
+                      whi, wlo, cnt, seen);
       }
     }
     if (seen > kmax) s_over = 1;
     // pad the last word with the sentinel (far outside the cutoff)
     while (cnt & 3) list_push(wp, whi, wlo, cnt, (unsigned)G.total, nt);
     const int words = (cnt + 3) >> 2;
-    smap[t] = make_int2(gi, pack_halo(hxi, hyi, hzi) | ((words * 4) << 24));
     s_words[t] = (unsigned char)words;
   }
   __syncthreads();
@@ -1277,9 +1249,11 @@ __device__ __forceinline__ void nlist_brick(const NlistArgs& a) {
       s_cnt[threadIdx.x] = x - c;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < G.ntg; t += NT)
-      trec[atomicAdd(&s_cnt[63 - s_words[t]], 1)] =
-          make_int2(smap[t].x, t | ((int)s_words[t] << 16));
+    for (int t = threadIdx.x; t < G.ntg; t += NT) {
+      int hxi, hyi, hzi, gi, vi;
+      brick_target<D>(G, L, t, hxi, hyi, hzi, gi, vi);
+      trec[atomicAdd(&s_cnt[63 - s_words[t]], 1)] = make_int2(gi, vi | ((int)s_words[t] << 16));
+    }
   }
   if (threadIdx.x == 0) a.binfo[b] = make_int4(G.total, G.ntg, (fits && !s_over) ? 1 : 0, 0);
 }
