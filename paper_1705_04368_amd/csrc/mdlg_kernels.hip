@@ -933,19 +933,19 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
     // read and the position read it feeds are two dependent round trips, so
     // a halo of total particles takes about 2 total / (SU NT) of them (2D
     // halos of a few hundred particles take one pass either way; more
-    // registers there only cost occupancy)
+    // registers there only cost occupancy).  The first pass starts from the
+    // two entries requested with the brick's header.
     constexpr int SU = (D == 2) ? 2 : 8;
+    int2 e[SU];
+    e[0] = pre_e0;
+    e[1] = pre_e1;
+#pragma unroll
+    for (int u = 2; u < SU; ++u) e[u] = smap[min((int)threadIdx.x + u * NT, total - 1)];
     for (int v0 = (int)threadIdx.x; v0 < total; v0 += SU * NT) {
-      int2 e[SU];
       float p[SU][D];
 #pragma unroll
-      for (int u = 0; u < SU; ++u) {
-        const int vv = v0 + u * NT;
-        e[u] = (v0 == (int)threadIdx.x && u < 2 && vv < total) ? (u == 0 ? pre_e0 : pre_e1)
-                                                                : smap[min(vv, total - 1)];
-      }
-#pragma unroll
-      for (int u = 0; u < SU; ++u) ldv<D>(a.pos_in, e[u].x, p[u]);
+      for (int u = 0; u < SU; ++u)
+        if (v0 + u * NT < total) ldv<D>(a.pos_in, e[u].x, p[u]);
 #pragma unroll
       for (int u = 0; u < SU; ++u) {
         const int vv = v0 + u * NT;
@@ -957,6 +957,11 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
             L.p[vv] = make_int4(fixed_coord(hx, p[u][0], P), fixed_coord(hy, p[u][1], P),
                                 fixed_coord((e[u].y >> 16) & 255, p[u][2], P), 0);
         }
+      }
+      const int vn = v0 + SU * NT;
+      if (vn < total) {
+#pragma unroll
+        for (int u = 0; u < SU; ++u) e[u] = smap[min(vn + u * NT, total - 1)];
       }
     }
     __syncthreads();

@@ -447,6 +447,44 @@ def test_pair_list_displacement_is_checked():
     assert "pair lists" in str(e.value)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_forces_at_every_step_between_rebuilds(dim):
+    # Forces at each MD step of one rebuild interval (the pair lists, built
+    # at its start, age by one step each time) against the oracle on the
+    # GPU's own positions, with a few particles sent off at 7 (kT/m)^(1/2) so
+    # that the largest displacement since the build grows past half the
+    # rebuild margin inside the interval.
+    from tests.gpu_util import check_forces_at_cutoff
+    cfg, pos, vel, box, n, M = _force_case(dim, 91, 2 if dim == 3 else 1, equil_steps=300)
+    cfg.sort_every = 12
+    rng = np.random.default_rng(5)
+    hot = rng.choice(n, size=8, replace=False)
+    d = rng.normal(size=(8, dim))
+    vel = vel.copy()
+    vel[hot] = (7.0 * d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    say(f"forces between rebuilds dim={dim}")
+    sysg = make_system(cfg, pos, vel)
+    m = sysg.layout["margin"]
+    s = sysg.layout["cell_side"]
+    mc = M * sysg.layout["md_cell_split"]
+    assert sysg.layout["pair_slots"] > 0 and sysg.layout["sort_every"] == 12
+    md = oracle.make_md(dim, n, box)
+    x0 = unwrapped(sysg.get_state(), s)
+    deltas = []
+    for k in range(1, 12):
+        sysg.step(1)
+        st = sysg.get_state()
+        xw = wrapped(st, s, mc)
+        acc, _ = oracle.forces(md, xw)
+        events, worst = check_forces_at_cutoff(st["acc"], acc, xw, xw, box, 2.5)
+        deltas.append(np.sqrt(((unwrapped(st, s) - x0) ** 2).sum(1)).max())
+        say(f"  step {k}: largest displacement since the build {deltas[-1]:.4f} (margin {m:.4f}); "
+            f"raw error {worst:.2e}, {events} at a cutoff pair")
+        # (a pair within float rounding of r_c counts for both its particles)
+        assert events <= 4
+    assert max(deltas) > m / 2
+
+
 # ------------------------------------------------------------------ autotuner
 
 def test_autotuned_layout_runs_the_same_trajectory():
