@@ -1086,19 +1086,27 @@ typedef short Short2 __attribute__((ext_vector_type(2)));
 // taken as a packed 16-bit pair and squared and summed by a dot product onto
 // dz^2 - rl16 (a 24-bit multiply-add); no term can overflow, as each
 // coordinate stays below 2^14.
+// The three-operand forms are written out: the compiler otherwise emits the
+// two-operand accumulating dot product (v_dot2c) after a copy of the addend,
+// and a separate multiply and subtract for dz^2 - rl16, one instruction more
+// per candidate either way.  (Arithmetic only: no memory access here.)
 template <int D>
 __device__ __forceinline__ int list_test14(Coord14<D> q, unsigned Txy, int Tz, int thr) {
   unsigned qxy;
-  int acc = -thr;
+  if constexpr (D == 2) qxy = q;
+  else qxy = q.x;
+  const unsigned d = __builtin_bit_cast(
+      unsigned, __builtin_bit_cast(Short2, qxy) - __builtin_bit_cast(Short2, Txy));
+  int r;
   if constexpr (D == 2) {
-    qxy = q;
+    asm("v_dot2_i32_i16 %0, %1, %1, %2" : "=v"(r) : "v"(d), "s"(-thr));
   } else {
-    qxy = q.x;
     const int dz = (int)q.y - Tz;
-    acc = __mul24(dz, dz) - thr;
+    int acc;
+    asm("v_mad_i32_i24 %0, %1, %1, %2" : "=v"(acc) : "v"(dz), "s"(-thr));
+    asm("v_dot2_i32_i16 %0, %1, %1, %2" : "=v"(r) : "v"(d), "v"(acc));
   }
-  const Short2 d = __builtin_bit_cast(Short2, qxy) - __builtin_bit_cast(Short2, Txy);
-  return __builtin_amdgcn_sdot2(d, d, acc, false);
+  return r;
 }
 
 // Append entry e to a list being built four 16-bit entries per word: the
