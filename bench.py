@@ -335,7 +335,7 @@ def main():
                     help="also bin on this many lattices drifting with u_x in [0, 0.5]")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's analytic launch shapes instead of measuring candidates")
-    ap.add_argument("--autotune-steps", type=int, default=40, help="MD steps timed per candidate")
+    ap.add_argument("--autotune-steps", type=int, default=100, help="MD steps timed per candidate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (scales the HBM "
                          "counters of a profiler to bytes)")

@@ -113,13 +113,19 @@ struct Timer {
     if (mdlg_create(&x, ws, ws_bytes, stream, pos, vel, &S) != MDLG_OK) return -1;
     ++tried;
     double ms = -1;
-    float el = 0.f;
-    // two lattice steps capture the step graphs and fill the caches
-    if (mdlg_coarse_grain(S, 2) == MDLG_OK && mdlg_sync(S) == MDLG_OK &&
-        hipEventRecord(a, stream) == hipSuccess && mdlg_coarse_grain(S, lattice_steps) == MDLG_OK &&
-        hipEventRecord(b, stream) == hipSuccess && mdlg_sync(S) == MDLG_OK &&
-        hipEventElapsedTime(&el, a, b) == hipSuccess)
-      ms = el / ((double)lattice_steps * x.md_steps_per_lattice_step);
+    // two lattice steps capture the step graphs and fill the caches; the
+    // better of two timed runs then ranks the candidate (the first candidate
+    // timed otherwise carries the start-up of the timing itself)
+    bool ok = mdlg_coarse_grain(S, 2) == MDLG_OK && mdlg_sync(S) == MDLG_OK;
+    for (int rep = 0; ok && rep < 2; ++rep) {
+      float el = 0.f;
+      ok = hipEventRecord(a, stream) == hipSuccess && mdlg_coarse_grain(S, lattice_steps) == MDLG_OK &&
+           hipEventRecord(b, stream) == hipSuccess && mdlg_sync(S) == MDLG_OK &&
+           hipEventElapsedTime(&el, a, b) == hipSuccess;
+      const double m = el / ((double)lattice_steps * x.md_steps_per_lattice_step);
+      if (ok && (ms < 0 || m < ms)) ms = m;
+    }
+    if (!ok) ms = -1;
     mdlg_destroy(S);
     return ms;
   }

@@ -917,7 +917,10 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
     const int2* __restrict__ trec = a.trec + (size_t)b * CAP;
     const int total = bi.x, ntg = bi.y;
     const size_t nt = (size_t)P.n_total;
-    constexpr int GW = (D == 2) ? 2 : 4;
+    // list words requested with the target's record: in 2D all of a list
+    // up to 32 entries (the rare longer list reads the rest word by word);
+    // in 3D four, the rest streamed a group ahead
+    constexpr int GW = (D == 2) ? 8 : 4;
     const unsigned long long pad = 0x0001000100010001ull * (unsigned)total;
     int gi = 0, t = 0, ng = 0;
     float o[D], v[D], o0[D];
@@ -976,19 +979,27 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
       float f[D];
 #pragma unroll
       for (int k = 0; k < D; ++k) f[k] = 0.f;
-      // one group of words in flight ahead of the group being summed (two
-      // words in 2D, four in 3D where lists are longer); words past the end
-      // of the list stand in as four copies of the sentinel (zero terms)
       const unsigned long long* __restrict__ lp = a.nl + gi;
-      for (int k = 0; k < ng; k += GW) {
-        unsigned long long nx[GW];
+      if constexpr (D == 2) {
+        // (a word is skipped by a wave none of whose lanes' lists reach it)
 #pragma unroll
         for (int u = 0; u < GW; ++u)
-          nx[u] = (k + GW + u < ng) ? lp[(size_t)(k + GW + u) * nt] : pad;
+          if (u < ng) list_word<D>(L, w[u], X, Y, Z, P, f);
+        for (int k = GW; k < ng; ++k) list_word<D>(L, lp[(size_t)k * nt], X, Y, Z, P, f);
+      } else {
+        // one group of words in flight ahead of the group being summed;
+        // words past the end of the list stand in as four copies of the
+        // sentinel (zero terms)
+        for (int k = 0; k < ng; k += GW) {
+          unsigned long long nx[GW];
 #pragma unroll
-        for (int u = 0; u < GW; ++u) list_word<D>(L, w[u], X, Y, Z, P, f);
+          for (int u = 0; u < GW; ++u)
+            nx[u] = (k + GW + u < ng) ? lp[(size_t)(k + GW + u) * nt] : pad;
 #pragma unroll
-        for (int u = 0; u < GW; ++u) w[u] = nx[u];
+          for (int u = 0; u < GW; ++u) list_word<D>(L, w[u], X, Y, Z, P, f);
+#pragma unroll
+          for (int u = 0; u < GW; ++u) w[u] = nx[u];
+        }
       }
       vv_update<D>(a, P, br.x, gi, o, v, f, kin, o0, true);
     }
