@@ -51,6 +51,13 @@ WORKLOADS = {
                          "per replica, launched one after another)"),
 }
 
+# the adjoint of one MD window (gradients of the displacement moments): not a
+# lattice-step workload; bench_adjoint times it against the forward window
+ADJOINT = dict(dim=2, n=65536, M=90, dx=362.04 / 90, kT=1.0, dt=0.005, vmax=3, window=20, ckpt=5,
+               seed=5, desc="2D LJ N=65536, 362.04 sigma box (rho=0.5), kT=1, dt=0.005: adjoint of "
+                            "one window of W=20 velocity-Verlet steps, checkpoints every 5 steps, "
+                            "loss = per-axis mean squared displacement")
+
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector, published
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E, published
 FLOP_PER_PAIR = {2: 18, 3: 23}  # interacting pair: differences, r^2, rcp, LJ factor, accumulate
@@ -74,6 +81,19 @@ def force_bytes_per_particle(dim, rho, rl=None):
         return base
     vol = math.pi * rl * rl if dim == 2 else 4.0 / 3.0 * math.pi * rl ** 3
     return base + 4 * dim + 2 * vol * rho
+
+
+# FLOPs per interacting pair of the adjoint's reverse step: the force term
+# (as FLOP_PER_PAIR), its sigma derivative and the Hessian-vector product
+# K (lam_i - lam_j) of the pair
+ADJ_FLOP_PER_PAIR = {2: 44, 3: 59}
+
+
+def adjoint_bytes_per_particle(dim):
+    """Algorithmic HBM bytes per particle of one reverse step: read the
+    position and the adjoint velocity, read and write the adjoint position,
+    write the new adjoint velocity."""
+    return 4 * dim * 5
 
 
 def count_bytes_per_particle(dim):
@@ -310,12 +330,115 @@ def plain_replicas(sysg, cfg, n_r, m_r, w, dev, lattice_steps):
             "f0_plain": f0}
 
 
+def bench_adjoint(args):
+    """The adjoint of one MD window (mdlg_adjoint: forward window with
+    checkpoints, then the reverse sweep recomputing each segment) against the
+    forward window alone (W plain MD steps), on an equilibrated 2D system."""
+    import torch
+
+    import synth
+    from paper_1705_04368_amd import System, describe, make_config
+    w = ADJOINT
+    dim, n, M, W, K = w["dim"], w["n"], w["M"], w["window"], w["ckpt"]
+    dev = torch.device("cuda:0")
+    cfg = make_config(dim, n, M, lattice_dx=w["dx"], dt=w["dt"], vmax=w["vmax"], thermostat_every=10,
+                      kT=w["kT"], adjoint_window=W, adjoint_every=K)
+    lay = describe(cfg)
+    box = M * lay["md_cell_split"] * lay["cell_side"]
+    pos, vel = synth.lj_initial_state(dim, n, box, w["kT"], seed=w["seed"])
+    sysg = System(cfg, torch.from_numpy(pos).to(dev), torch.from_numpy(vel).to(dev))
+    print(f"# workload adjoint: {w['desc']}; layout {sysg.layout}", file=sys.stderr, flush=True)
+    sysg.step(args.equilibrate)
+    sysg.sync()
+    for _ in range(args.warmup):
+        sysg.adjoint(W, K, "msd", want_v0=True)
+        sysg.step(W)
+    sysg.sync()
+    torch.cuda.synchronize()
+    print("# equilibrated and warmed up", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sysg.step(W)
+    sysg.sync()
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sysg.adjoint(W, K, "msd", want_v0=True)
+    torch.cuda.synchronize()
+    adj = (time.perf_counter() - t0) / args.steps
+    print(f"# timed {args.steps} windows: forward {fwd * 1e3:.3f} ms, gradient {adj * 1e3:.3f} ms",
+          file=sys.stderr, flush=True)
+    sysg.set_timing(True)
+    sysg.adjoint(W, K, "msd", want_v0=True)
+    tim = sysg.get_timing()
+    sysg.set_timing(False)
+    rho = n / box ** dim
+    kernels = {}
+    for k, (ms, cnt) in tim.items():
+        if cnt == 0:
+            continue
+        avg = ms / cnt
+        if k == "adjoint":
+            work = n * adjoint_bytes_per_particle(dim)
+            flops = n * pairs_per_particle(dim, rho) * ADJ_FLOP_PER_PAIR[dim]
+        elif k == "force":
+            # forward and recomputed steps of the window: cell walk, no lists
+            work = n * force_bytes_per_particle(dim, rho, None)
+            flops = n * pairs_per_particle(dim, rho) * FLOP_PER_PAIR[dim]
+        else:
+            continue
+        ach = work / (avg * 1e-3) / 1e9
+        tf = flops / (avg * 1e-3) / 1e12
+        kernels[k] = {"avg_ms": round(avg, 6), "launches": cnt, "bound": "hbm",
+                      "achieved": round(ach, 6), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                      "frac": round(ach / PEAK_HBM_GBS, 6), "work_per_launch": work,
+                      "flop_per_launch": flops, "flop_achieved": round(tf, 6),
+                      "flop_peak": PEAK_FP32_TFLOPS, "flop_frac": round(tf / PEAK_FP32_TFLOPS, 6),
+                      "flop_unit": "TFLOP/s"}
+    kd = kernels["adjoint"]
+    roofline = {"kernel": "adjoint", "bound": kd["bound"], "achieved": kd["achieved"],
+                "peak": kd["peak"], "unit": kd["unit"], "frac": kd["frac"],
+                "traffic": load_traffic("adjoint", "adjoint")}
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's FP64 adjoint of the same window on the same state
+        import oracle
+        print("# cpu baseline (oracle adjoint)", file=sys.stderr, flush=True)
+        st = sysg.get_state()
+        s = sysg.layout["cell_side"]
+        x = np.mod(st["ucell"], M * sysg.layout["md_cell_split"]).astype(np.float64) * s + st["off"]
+        md = oracle.make_md(dim, n, box, dt=w["dt"])
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            oracle.adjoint(md, x, st["vel"].astype(np.float64), W, "msd")
+        tc = time.perf_counter() - t0
+        cpu = {"value": n * W * reps / tc, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"full system, {reps} windows of W={W} (forward + reverse), FP64 single "
+                         f"thread, {tc:.1f} s"}
+    out = {
+        "metric": "particle-steps/s (adjoint window: forward, recompute and reverse sweep)",
+        "value": n * W / adj, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": adj * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w["desc"], "windows": args.steps, "window": W, "ckpt_every": K,
+                   "md_cell_split": sysg.layout["md_cell_split"], "brick": list(sysg.layout["brick"])},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "adjoint": {"ms_per_window": adj * 1e3, "forward_ms_per_window": fwd * 1e3,
+                    "gradient_over_forward": adj / fwd},
+        "kernels": kernels,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50, help="timed lattice steps")
     ap.add_argument("--warmup", type=int, default=5, help="untimed lattice steps")
-    ap.add_argument("--workload", default="2d_scale", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="2d_scale", choices=sorted(WORKLOADS) + ["adjoint"])
     ap.add_argument("--equilibrate", type=int, default=2000, help="thermostatted MD steps")
     ap.add_argument("--timing-steps", type=int, default=10,
                     help="lattice steps of the event-timed per-kernel pass")
@@ -362,6 +485,10 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(replicas or domains would shard across GPUs; see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "adjoint":
+        bench_adjoint(args)
+        return
 
     import torch
 

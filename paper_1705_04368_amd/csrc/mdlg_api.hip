@@ -513,8 +513,8 @@ struct mdlg_system {
   std::vector<Timed> timed;
   Timed open_run{-1, 0, nullptr, nullptr};  // consecutive launches of one class
   std::vector<hipEvent_t> event_pool;
-  double timed_ms[MDLG_K_NCLASS] = {0, 0, 0, 0, 0};
-  int64_t timed_n[MDLG_K_NCLASS] = {0, 0, 0, 0, 0};
+  double timed_ms[MDLG_K_NCLASS] = {};
+  int64_t timed_n[MDLG_K_NCLASS] = {};
   std::string last_error = "no error";
 };
 
@@ -1601,6 +1601,7 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
                      S->vel[S->scur]);
     S->pcur ^= 1;
     if (n % k == 0 && n < W) {
+      if (S->timing) close_run(S);  // (the checkpoint copies are not force launches)
       launch_copy_f32(S->pos[S->pcur], S->adj_ckpt_pos + (size_t)(n / k) * nd, nd, S->stream);
       launch_copy_f32(S->vel[S->scur], S->adj_ckpt_vel + (size_t)(n / k) * nd, nd, S->stream);
     }
@@ -1617,6 +1618,7 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
   const double e1 = 24.0 * S->cfg.epsilon / (S->cfg.mass * u);
   int cur = 0;
   for (int seg = W / k - 1; seg >= 0; --seg) {
+    if (S->timing) close_run(S);  // (the segment copies are not timed launches)
     launch_copy_f32(S->adj_ckpt_pos + (size_t)seg * nd, S->adj_seg_pos, nd, S->stream);
     launch_copy_f32(S->adj_ckpt_vel + (size_t)seg * nd, S->adj_vel, nd, S->stream);
     for (int j = 1; j <= k; ++j)
@@ -1641,6 +1643,7 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
       a.e2 = (float)(e1 / u);
       a.eps = S->cfg.epsilon;
       a.nbricks = L.nbricks;
+      TimedLaunch t(S, MDLG_K_ADJOINT);
       launch_adjoint(D, a, S->stream);
       cur ^= 1;
     }

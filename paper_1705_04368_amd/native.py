@@ -24,7 +24,7 @@ EXPORTED = ["mdlg_describe", "mdlg_workspace_bytes", "mdlg_create", "mdlg_step",
             "mdlg_set_timing", "mdlg_get_timing", "mdlg_sync", "mdlg_last_error", "mdlg_destroy",
             "mdlg_autotune", "mdlg_autotune_workspace_bytes", "mdlg_get_xi", "mdlg_get_shifts"]
 LOSSES = {"msd": 0, "mean_x": 1}
-KERNEL_CLASSES = ["force", "count", "scan", "scatter", "bin", "nlist", "xi", "shift"]
+KERNEL_CLASSES = ["force", "count", "scan", "scatter", "bin", "nlist", "xi", "shift", "adjoint"]
 
 
 class MdlgConfig(C.Structure):
