@@ -347,9 +347,19 @@ def bench_adjoint(args):
     box = M * lay["md_cell_split"] * lay["cell_side"]
     pos, vel = synth.lj_initial_state(dim, n, box, w["kT"], seed=w["seed"])
     sysg = System(cfg, torch.from_numpy(pos).to(dev), torch.from_numpy(vel).to(dev))
-    print(f"# workload adjoint: {w['desc']}; layout {sysg.layout}", file=sys.stderr, flush=True)
     sysg.step(args.equilibrate)
     sysg.sync()
+    if not args.no_autotune:
+        # brick, block size and rebuild interval measured on the equilibrated
+        # state; the MD-cell split stays (the box is M k s with s = float32(dx / k))
+        from paper_1705_04368_amd import autotune
+        cfg.md_cell_split = lay["md_cell_split"]
+        xe, ve = equilibrated_state(sysg, cfg)
+        cfg, _ = autotune(cfg, torch.from_numpy(xe).to(dev), torch.from_numpy(ve).to(dev),
+                          md_steps=args.autotune_steps)
+        sysg.close()
+        sysg = System(cfg, torch.from_numpy(xe).to(dev), torch.from_numpy(ve).to(dev))
+    print(f"# workload adjoint: {w['desc']}; layout {sysg.layout}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         sysg.adjoint(W, K, "msd", want_v0=True)
         sysg.step(W)
@@ -423,7 +433,8 @@ def bench_adjoint(args):
         "warmup": args.warmup, "ms_per_step": adj * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w["desc"], "windows": args.steps, "window": W, "ckpt_every": K,
-                   "md_cell_split": sysg.layout["md_cell_split"], "brick": list(sysg.layout["brick"])},
+                   "md_cell_split": sysg.layout["md_cell_split"], "brick": list(sysg.layout["brick"]),
+                   "block_threads": sysg.layout["block_threads"], "autotuned": not args.no_autotune},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "adjoint": {"ms_per_window": adj * 1e3, "forward_ms_per_window": fwd * 1e3,

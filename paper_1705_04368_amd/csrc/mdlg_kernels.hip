@@ -1308,12 +1308,13 @@ __global__ __launch_bounds__(NT) void k_nlist_wide(NlistArgs a) {
 //   a_i      -= E1 ir2 s6 (2 s6 - 1) d
 //   da_i/ds  -= (E1 / sigma) ir2 s6 (24 s6 - 6) d
 //   (J l)_i  += E2 [ir2 s6 (2 s6 - 1) dl + ir2^2 s6 (8 - 28 s6) (d . dl) d]
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs a) {
+template <int D, int NT>
+__global__ __launch_bounds__(NT) void k_adjoint(AdjArgs a) {
+  constexpr int NW = NT / 64;
   extern __shared__ __align__(16) char s_dyn_brick[];
   __shared__ int s_rowpre[kMaxRows + 1];
-  __shared__ int s_tmp[kWaves + 1];
-  __shared__ double s_red[kWaves][4];
+  __shared__ int s_tmp[NW + 1];
+  __shared__ double s_red[NW][4];
   auto L = brick_lds<D, true>(s_dyn_brick, s_rowpre, s_tmp, s_red, a.P);
   const int CAP = L.cap;
   const int b = blockIdx.x;
@@ -1321,15 +1322,15 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs a) {
   const Phys& P = a.P;
   const int4 br = a.bricks[b];
   const Replica R = a.reps[br.x];
-  const BrickGeom G = brick_setup<D, kBlock>(P, R, br, a.cell_start, L);
+  const BrickGeom G = brick_setup<D, NT>(P, R, br, a.cell_start, L);
   const int nchunks = (G.total + CAP - 1) / CAP;
   const bool interact = !P.forces_off;
   if (interact && nchunks == 1) {
-    brick_stage<D, kBlock>(G, P, a.pos, a.lam_v_in, L, 0, G.total);
+    brick_stage<D, NT>(G, P, a.pos, a.lam_v_in, L, 0, G.total);
     __syncthreads();
   }
   double ge = 0.0, gs = 0.0;
-  for (int tb = 0; tb < G.ntg; tb += kBlock) {
+  for (int tb = 0; tb < G.ntg; tb += NT) {
     const int t = tb + (int)threadIdx.x;
     const bool valid = t < G.ntg;
     int hxi = G.ns, hyi = G.ns, hzi = G.nsz, gi = 0, vi = 0;
@@ -1356,7 +1357,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs a) {
         const int cb = ci * CAP, ce = min(G.total, cb + CAP);
         if (nchunks > 1) {
           __syncthreads();
-          brick_stage<D, kBlock>(G, P, a.pos, a.lam_v_in, L, cb, ce);
+          brick_stage<D, NT>(G, P, a.pos, a.lam_v_in, L, cb, ce);
           __syncthreads();
         }
         if (valid) {
@@ -1428,7 +1429,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs a) {
   __syncthreads();
   if (threadIdx.x < 2) {
     double t = 0.0;
-    for (int i = 0; i < kWaves; ++i) t += L.red[i][threadIdx.x];
+    for (int i = 0; i < NW; ++i) t += L.red[i][threadIdx.x];
     a.gpart[(size_t)b * 2 + threadIdx.x] += t;
   }
 }
@@ -2099,7 +2100,8 @@ void launch_site_avg(const SiteAvgArgs& a, hipStream_t s) {
 }
 
 void launch_adjoint(int D, const AdjArgs& a, hipStream_t s) {
-  MDLG_LAUNCH_DIM(D, k_adjoint, a.nbricks, brick_lds_bytes(a.P, D, true), s, a);
+  // the layout's block size, as for the force kernel
+  MDLG_LAUNCH_BRICK(D, a.P.bthreads, k_adjoint, a.nbricks, brick_lds_bytes(a.P, D, true), s, a);
 }
 
 static int grid_for(long long n) {
