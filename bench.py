@@ -173,9 +173,10 @@ def _counter_means(folder, counter):
     return {k: s / c for k, (s, c) in tot.items()}
 
 
-def summarize_traffic(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
+def summarize_traffic(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out_dir=None):
     """HBM bytes per launch of each kernel: FETCH_SIZE and WRITE_SIZE (KiB per
-    dispatch) scaled by what the same counters read for a plain copy of 1 GiB."""
+    dispatch) scaled by what the same counters read for a plain copy of 1 GiB.
+    Written to <out_dir>/traffic_<workload>.json (default: profiles/)."""
     copy_bytes = float(1 << 30)
     cf = max(_counter_means(copy_fetch_dir, "FETCH_SIZE").values())
     cw = max(_counter_means(copy_write_dir, "WRITE_SIZE").values())
@@ -195,11 +196,12 @@ def summarize_traffic(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write
            "copy_calibration": {"bytes": copy_bytes, "fetch_kib": cf, "write_kib": cw,
                                 "fetch_factor": f_fac, "write_factor": w_fac},
            "kernels": kernels}
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    path = os.path.join(out_dir or os.path.join(ROOT, "profiles"), f"traffic_{workload}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
         fh.write("\n")
     print(json.dumps(out, indent=1))
+    return out
 
 
 E1_DU = 0.05  # drift of the two extra lattices of the e1 workload (lattice units per step)
