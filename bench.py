@@ -572,14 +572,28 @@ def main():
     sysg.reset_accumulators()
     print(f"# warmed up ({args.warmup} lattice steps)", file=sys.stderr, flush=True)
 
+    # the K timed lattice steps run as five consecutive chunks with HIP events
+    # between them on the system's stream (no host synchronisation inside the
+    # timed region): the chunks give repeat rates, whose median is reported
+    # beside the whole-run value
+    nch = min(5, args.steps)
+    sizes = [args.steps // nch + (1 if i < args.steps % nch else 0) for i in range(nch)]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nch + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sysg.coarse_grain(args.steps)
+    evs[0].record()
+    for i, k in enumerate(sizes):
+        sysg.coarse_grain(k)
+        evs[i + 1].record()
     sysg.sync()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     md_steps = args.steps * w["steps"]
     value = n * md_steps / elapsed
+    chunk_values = [n * k * w["steps"] / (evs[i].elapsed_time(evs[i + 1]) * 1e-3)
+                    for i, k in enumerate(sizes)]
+    repeats = {"chunks": nch, "lattice_steps": sizes, "values": chunk_values,
+               "median": float(np.median(chunk_values))}
     print(f"# timed {args.steps} lattice steps in {elapsed:.4f} s", file=sys.stderr, flush=True)
     f = sysg.get_f()
     assert f["counts"].sum() + f["n_overflow"] == n * f["n_lattice_steps"]
@@ -692,6 +706,7 @@ def main():
                    "galilean_lattices": args.galilean},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "repeats": repeats,
         "plain": plain,
         "kernels": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
