@@ -53,6 +53,7 @@ struct Layout {
   bool xi = false;     // collision-operator statistics buffers
   int n_shifts = 0;    // displaced / moving lattices
   int adj_ckpts = 0;   // checkpoints the workspace holds (0 = no adjoint)
+  int kmax_adj = 0;    // pair-list slots of the adjoint window (radius r_cut + 2 margin_max; 0 = none)
   int adj_seg = 0;     // segment positions the workspace holds
 };
 
@@ -372,6 +373,15 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   if (c->adjoint_window > 0) {
     L->adj_ckpts = c->adjoint_window / c->adjoint_every + 1;
     L->adj_seg = c->adjoint_every + 1;
+    // the window's force launches walk pair lists of radius r_cut + 2
+    // margin_max, built once at its start (cells stay frozen for the window,
+    // so no particle moves farther than margin_max from its build position)
+    if (want_list && L->lcap < 65536 && L->margin_max > 0) {
+      const double rl = c->r_cut + 2 * L->margin_max;
+      const double vol_l = (D == 2) ? M_PI * rl * rl : 4.0 / 3.0 * M_PI * rl * rl * rl;
+      const int want = (int)std::ceil(1.5 * vol_l * rho_max) + 20;
+      L->kmax_adj = std::min(kMaxPairSlots, (want + 3) / 4 * 4);
+    }
   }
   L->n_total = n_total;
   L->n_cells = cell_off;
@@ -578,10 +588,10 @@ size_t carve(mdlg_system* S, char* base) {
     S->xi_sums = c.take<unsigned long long>(base, (size_t)5 * L.Q);
     S->xi_part = c.take<long long>(base, (size_t)xi_blocks(L) * 5 * L.Q);
   }
-  if (L.kmax > 0) {
+  if (L.kmax > 0 || L.kmax_adj > 0) {
     S->smap = c.take<int2>(base, (size_t)L.nbricks * L.lcap);
     S->binfo = c.take<int4>(base, (size_t)L.nbricks);
-    S->nl = c.take<unsigned long long>(base, (size_t)(L.kmax / 4) * N);
+    S->nl = c.take<unsigned long long>(base, (size_t)(std::max(L.kmax, L.kmax_adj) / 4) * N);
     S->off0 = c.take<float>(base, N * D);
     S->trec = c.take<int2>(base, (size_t)L.nbricks * L.lcap);
   }
@@ -603,6 +613,33 @@ size_t carve(mdlg_system* S, char* base) {
   return c.off + 256;
 }
 
+// Pair-list parameters of P for lists of radius r_cut + 2 margin with kmax
+// slots (u, F and the brick extents already set).
+static void set_list_params(Phys& P, const mdlg_config* c, const Layout& L, double margin, int kmax) {
+  const double u = P.u_d;
+  const double rl = c->r_cut + 2 * margin;
+  P.rlq = (int)std::ceil(rl / u) + 1;
+  P.rl2_u = (float)((rl / u) * (rl / u) * (1 + 1e-5));
+  // The list builder compares coarser copies of the coordinates: the halo of
+  // the widest brick, widened by two cells on either side (a particle sits
+  // less than one cell outside its own), in 14-bit units, so that a squared
+  // distance over three axes cannot overflow 31 bits.  Each axis of a
+  // difference is off by less than one unit, so its length by less than
+  // sqrt(D) units: the threshold widened by that keeps every pair within
+  // the list radius (a few pairs just beyond it enter the list too).
+  const int hx16 = std::max(std::max(L.BX, L.BY), L.D == 3 ? L.BZ : 1) + 2 * L.ns + 4;
+  int lg16 = 0;
+  while ((1 << lg16) < hx16) ++lg16;
+  P.sh16 = std::max(0, P.F - (14 - lg16));
+  const double r16 = rl / (u * std::ldexp(1.0, P.sh16)) + std::sqrt((double)L.D);
+  P.rl16 = (int)std::ceil(r16 * r16) + 1;
+  // candidates of the row through the target: its reach plus one cell
+  const double row = (2 * rl + L.s) * std::pow(L.s, L.D - 1) * L.per_cell / std::pow(L.s, L.D);
+  P.nl_wide = row >= 48 ? 1 : 0;
+  P.kmax = kmax;
+  P.disp2 = (float)(margin * margin);
+}
+
 Phys make_phys(const mdlg_config* c, const Layout& L) {
   Phys P{};
   P.s = (float)L.s;
@@ -622,29 +659,7 @@ Phys make_phys(const mdlg_config* c, const Layout& L) {
   P.mq = (int)std::ceil(L.margin / u) + 4;
   P.rc_d = c->r_cut;
   P.u_d = u;
-  {
-    const double rl = c->r_cut + 2 * L.margin;
-    P.rlq = (int)std::ceil(rl / u) + 1;
-    P.rl2_u = (float)((rl / u) * (rl / u) * (1 + 1e-5));
-    // The list builder compares coarser copies of the coordinates: the halo of
-    // the widest brick, widened by two cells on either side (a particle sits
-    // less than one cell outside its own), in 14-bit units, so that a squared
-    // distance over three axes cannot overflow 31 bits.  Each axis of a
-    // difference is off by less than one unit, so its length by less than
-    // sqrt(D) units: the threshold widened by that keeps every pair within
-    // the list radius (a few pairs just beyond it enter the list too).
-    const int hx16 = std::max(std::max(L.BX, L.BY), L.D == 3 ? L.BZ : 1) + 2 * L.ns + 4;
-    int lg16 = 0;
-    while ((1 << lg16) < hx16) ++lg16;
-    P.sh16 = std::max(0, P.F - (14 - lg16));
-    const double r16 = rl / (u * std::ldexp(1.0, P.sh16)) + std::sqrt((double)L.D);
-    P.rl16 = (int)std::ceil(r16 * r16) + 1;
-    // candidates of the row through the target: its reach plus one cell
-    const double row = (2 * rl + L.s) * std::pow(L.s, L.D - 1) * L.per_cell / std::pow(L.s, L.D);
-    P.nl_wide = row >= 48 ? 1 : 0;
-    P.kmax = L.kmax;
-    P.disp2 = (float)(L.margin * L.margin);
-  }
+  set_list_params(P, c, L, L.margin, L.kmax);
   // dynamic LDS of the brick kernels: the halo cell table of the largest
   // brick and room for about 1.5x the expected halo particles (a fuller halo
   // is staged in several chunks); the adjoint also stages d floats each
@@ -779,6 +794,26 @@ SortArgs sort_args(mdlg_system* S) {
   return a;
 }
 
+// Pair lists of the current positions (all inside their cells) with the list
+// parameters of P.
+void enqueue_nlist(mdlg_system* S, const Phys& P) {
+  NlistArgs nl{};
+  nl.P = P;
+  nl.reps = S->reps;
+  nl.bricks = S->bricks;
+  nl.cell_start = S->cell_start;
+  nl.pos = S->pos[S->pcur];
+  nl.smap = S->smap;
+  nl.binfo = S->binfo;
+  nl.nl = S->nl;
+  nl.off0 = S->off0;
+  nl.trec = S->trec;
+  nl.nbricks = S->L.nbricks;
+  nl.xcd_remap = S->xcd_remap;
+  TimedLaunch t(S, MDLG_K_NLIST);
+  launch_nlist(S->D, nl, S->stream);
+}
+
 void enqueue_sort(mdlg_system* S) {
   SortArgs a = sort_args(S);
   {
@@ -802,23 +837,7 @@ void enqueue_sort(mdlg_system* S) {
   S->pcur ^= 1;
   S->scur ^= 1;
   S->since_sort = 0;
-  if (S->L.kmax > 0) {
-    NlistArgs nl{};
-    nl.P = S->P;
-    nl.reps = S->reps;
-    nl.bricks = S->bricks;
-    nl.cell_start = S->cell_start;
-    nl.pos = S->pos[S->pcur];
-    nl.smap = S->smap;
-    nl.binfo = S->binfo;
-    nl.nl = S->nl;
-    nl.off0 = S->off0;
-    nl.trec = S->trec;
-    nl.nbricks = S->L.nbricks;
-    nl.xcd_remap = S->xcd_remap;
-    TimedLaunch t(S, MDLG_K_NLIST);
-    launch_nlist(S->D, nl, S->stream);
-  }
+  if (S->L.kmax > 0) enqueue_nlist(S, S->P);
 }
 
 void enqueue_force(mdlg_system* S, int mode, bool sort_follows, float* acc_out, double* kpart) {
@@ -1542,10 +1561,29 @@ static Phys window_phys(const mdlg_system* S) {
   return P;
 }
 
+// The window's force launches with pair lists (radius r_cut + 2 margin_max,
+// the stencil's reach): the force kernel's LDS capacity, and the list
+// parameters for that margin.
+static Phys window_list_phys(const mdlg_system* S) {
+  Phys P = window_phys(S);
+  P.lcap = S->L.lcap;
+  set_list_params(P, &S->cfg, S->L, S->L.margin_max, S->L.kmax_adj);
+  return P;
+}
+
 static void launch_force_raw(mdlg_system* S, const Phys& P, int mode, const float* pos_in,
                              float* pos_out, float* vel) {
   ForceArgs a{};
   a.P = P;
+  if (P.kmax > 0) {
+    // lists built at the start of the window by enqueue_nlist(S, P)
+    a.smap = S->smap;
+    a.binfo = S->binfo;
+    a.nl = S->nl;
+    a.off0 = S->off0;
+    a.trec = S->trec;
+    a.check_disp = 1;
+  }
   a.reps = S->reps;
   a.bricks = S->bricks;
   a.cell_start = S->cell_start;
@@ -1592,12 +1630,16 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
     enqueue_force(S, kModeFinish, false, nullptr, nullptr);
     S->vel_full = true;
   }
+  // the window's force launches (forward and recomputed) walk pair lists
+  // built here on the frozen cells
+  const Phys PF = L.kmax_adj > 0 ? window_list_phys(S) : PW;
+  if (PF.kmax > 0) enqueue_nlist(S, PF);
   // forward window with checkpoints
   launch_copy_f32(S->pos[S->pcur], S->adj_off0, nd, S->stream);
   launch_copy_f32(S->pos[S->pcur], S->adj_ckpt_pos, nd, S->stream);
   launch_copy_f32(S->vel[S->scur], S->adj_ckpt_vel, nd, S->stream);
   for (int n = 1; n <= W; ++n) {
-    launch_force_raw(S, PW, n == 1 ? kModeStart : kModeStep, S->pos[S->pcur], S->pos[S->pcur ^ 1],
+    launch_force_raw(S, PF, n == 1 ? kModeStart : kModeStep, S->pos[S->pcur], S->pos[S->pcur ^ 1],
                      S->vel[S->scur]);
     S->pcur ^= 1;
     if (n % k == 0 && n < W) {
@@ -1622,7 +1664,7 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
     launch_copy_f32(S->adj_ckpt_pos + (size_t)seg * nd, S->adj_seg_pos, nd, S->stream);
     launch_copy_f32(S->adj_ckpt_vel + (size_t)seg * nd, S->adj_vel, nd, S->stream);
     for (int j = 1; j <= k; ++j)
-      launch_force_raw(S, PW, (seg == 0 && j == 1) ? kModeStart : kModeStep,
+      launch_force_raw(S, PF, (seg == 0 && j == 1) ? kModeStart : kModeStep,
                        S->adj_seg_pos + (size_t)(j - 1) * nd, S->adj_seg_pos + (size_t)j * nd,
                        S->adj_vel);
     for (int j = k; j >= (seg == 0 ? 0 : 1); --j) {
