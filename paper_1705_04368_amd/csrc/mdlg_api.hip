@@ -1685,6 +1685,13 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
       a.e2 = (float)(e1 / u);
       a.eps = S->cfg.epsilon;
       a.nbricks = L.nbricks;
+      a.err = S->err;
+      if (PF.kmax > 0) {
+        a.binfo = S->binfo;
+        a.trec = S->trec;
+        a.nl = S->nl;
+        a.lcap_list = PF.lcap;
+      }
       TimedLaunch t(S, MDLG_K_ADJOINT);
       launch_adjoint(D, a, S->stream);
       cur ^= 1;

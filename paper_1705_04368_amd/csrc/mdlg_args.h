@@ -234,6 +234,12 @@ struct AdjArgs {
   float e2;                // 24 eps / (m u^2)
   double eps;
   int nbricks;
+  unsigned* err;
+  // pair lists of the window (null nl: every brick walks its cell rows)
+  const int4* binfo;
+  const int2* trec;    // [nbricks][lcap_list] targets {particle, LDS slot | words << 16}
+  const unsigned long long* nl;
+  int lcap_list;
 };
 
 struct AdjLossArgs {

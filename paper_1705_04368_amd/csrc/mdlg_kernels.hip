@@ -1308,6 +1308,62 @@ __global__ __launch_bounds__(NT) void k_nlist_wide(NlistArgs a) {
 //   a_i      -= E1 ir2 s6 (2 s6 - 1) d
 //   da_i/ds  -= (E1 / sigma) ir2 s6 (24 s6 - 6) d
 //   (J l)_i  += E2 [ir2 s6 (2 s6 - 1) dl + ir2^2 s6 (8 - 28 s6) (d . dl) d]
+template <int D>
+__device__ __forceinline__ void adj_pair(const Coord<D>& q, const float* __restrict__ lj, int X, int Y,
+                                         int Z, const float (&li)[D], const Phys& P, float (&acc)[D],
+                                         float (&dacc)[D], float (&jl)[D]) {
+  float d[D], dl[D];
+  d[0] = (float)(q.x - X);
+  d[1] = (float)(q.y - Y);
+  if constexpr (D == 3) d[2] = (float)(q.z - Z);
+  float r2 = 0.f, ddl = 0.f;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    dl[k] = li[k] - lj[k];
+    r2 += d[k] * d[k];
+    ddl += d[k] * dl[k];
+  }
+  const bool in = (r2 < P.rc2_u) && (r2 > 0.f);
+  const float ir2 = in ? __builtin_amdgcn_rcpf(r2) : 0.f;
+  const float sr2 = P.sig2_u * ir2;
+  const float s6 = sr2 * sr2 * sr2;
+  const float t1 = ir2 * s6 * (2.f * s6 - 1.f);
+  const float ts = ir2 * s6 * (24.f * s6 - 6.f);
+  const float t2 = ir2 * ir2 * s6 * (8.f - 28.f * s6) * ddl;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    acc[k] -= t1 * d[k];
+    dacc[k] -= ts * d[k];
+    jl[k] += t1 * dl[k] + t2 * d[k];
+  }
+}
+
+// The updates of one target from its sums: lam_x, lam_v and the parameter
+// gradient partials.
+template <int D>
+__device__ __forceinline__ void adj_update(const AdjArgs& a, const Phys& P, int gi,
+                                           const float (&li)[D], const float (&acc)[D],
+                                           const float (&dacc)[D], const float (&jl)[D], double& ge,
+                                           double& gs) {
+  float lx[D], lv[D];
+  ldv<D>(a.lam_x, gi, lx);
+  double e = 0.0, s = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const float a_k = P.eps24m_u * acc[k];
+    const float da_k = a.e1_over_sigma * dacc[k];
+    const float jl_k = a.e2 * jl[k];
+    lx[k] = fmaf(a.c, jl_k, lx[k]);
+    e += (double)li[k] * (double)a_k;
+    s += (double)li[k] * (double)da_k;
+    lv[k] = a.drift ? fmaf(P.dt, lx[k], li[k]) : li[k];
+  }
+  ge += (double)a.c * e / a.eps;
+  gs += (double)a.c * s;
+  stv<D>(a.lam_x, gi, lx);
+  stv<D>(a.lam_v_out, gi, lv);
+}
+
 template <int D, int NT>
 __global__ __launch_bounds__(NT) void k_adjoint(AdjArgs a) {
   constexpr int NW = NT / 64;
@@ -1325,99 +1381,106 @@ __global__ __launch_bounds__(NT) void k_adjoint(AdjArgs a) {
   const BrickGeom G = brick_setup<D, NT>(P, R, br, a.cell_start, L);
   const int nchunks = (G.total + CAP - 1) / CAP;
   const bool interact = !P.forces_off;
+  double ge = 0.0, gs = 0.0;
+  // the window's pair lists, where the brick's halo fits one chunk: entries
+  // index the halo staged in cell order, as here
+  const int4 bi = a.nl ? a.binfo[b] : make_int4(0, 0, 0, 0);
+  const bool listed = interact && bi.z && bi.x == G.total && G.total < CAP;
   if (interact && nchunks == 1) {
     brick_stage<D, NT>(G, P, a.pos, a.lam_v_in, L, 0, G.total);
+    if (listed && threadIdx.x == 0) {
+      // the padding sentinel: far outside the cutoff, zero adjoint velocity
+      if constexpr (D == 2) L.p[G.total] = make_int2(kSentinel, kSentinel);
+      else L.p[G.total] = make_int4(kSentinel, kSentinel, kSentinel, 0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) L.lam[G.total * D + k] = 0.f;
+    }
     __syncthreads();
   }
-  double ge = 0.0, gs = 0.0;
-  for (int tb = 0; tb < G.ntg; tb += NT) {
-    const int t = tb + (int)threadIdx.x;
-    const bool valid = t < G.ntg;
-    int hxi = G.ns, hyi = G.ns, hzi = G.nsz, gi = 0, vi = 0;
-    if (valid) brick_target<D>(G, L, t, hxi, hyi, hzi, gi, vi);
-    float o[D], li[D], acc[D], dacc[D], jl[D];
+  if (listed) {
+    const int2* __restrict__ trec = a.trec + (size_t)b * a.lcap_list;
+    const size_t nt = (size_t)P.n_total;
+    for (int tb = 0; tb < G.ntg; tb += NT) {
+      const int t = tb + (int)threadIdx.x;
+      if (t >= G.ntg) break;
+      const int2 r = trec[t];
+      const int gi = r.x;
+      const int vi = r.y & 0xffff;
+      const int ng = (unsigned)r.y >> 16;
+      if ((size_t)(unsigned)gi >= nt || vi >= G.total) {
+        atomicOr(a.err, kErrRecord);
+        continue;
+      }
+      const Coord<D> me = L.p[vi];
+      const int X = me.x, Y = me.y;
+      int Z = 0;
+      if constexpr (D == 3) Z = me.z;
+      float li[D], acc[D], dacc[D], jl[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      o[k] = 0.f;
-      li[k] = 0.f;
-      acc[k] = 0.f;
-      dacc[k] = 0.f;
-      jl[k] = 0.f;
-    }
-    if (valid) {
-      ldv<D>(a.pos, gi, o);
-      ldv<D>(a.lam_v_in, gi, li);
-    }
-    if (interact) {
-      const int X = fixed_coord(hxi, o[0], P);
-      const int Y = fixed_coord(hyi, o[1], P);
-      const int Z = (D == 3) ? fixed_coord(hzi, o[D - 1], P) : 0;
-      const Reach rr = target_reach<D>(G, P, X, Y, Z, P.rcq);
-      for (int ci = 0; ci < nchunks; ++ci) {
-        const int cb = ci * CAP, ce = min(G.total, cb + CAP);
-        if (nchunks > 1) {
-          __syncthreads();
-          brick_stage<D, NT>(G, P, a.pos, a.lam_v_in, L, cb, ce);
-          __syncthreads();
+      for (int k = 0; k < D; ++k) {
+        li[k] = L.lam[vi * D + k];
+        acc[k] = 0.f;
+        dacc[k] = 0.f;
+        jl[k] = 0.f;
+      }
+      const unsigned long long* __restrict__ lp = a.nl + gi;
+      for (int k = 0; k < ng; ++k) {
+        const unsigned long long wd = lp[(size_t)k * nt];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = (int)((wd >> (16 * u)) & 0xffffu);
+          adj_pair<D>(L.p[e], &L.lam[e * D], X, Y, Z, li, P, acc, dacc, jl);
         }
-        if (valid) {
-          for (int cz = rr.cz0; cz <= rr.cz1; ++cz) {
-            for (int cy = rr.cy0; cy <= rr.cy1; ++cy) {
-              int cx0, cx1;
-              if (!row_columns<D>(G, P, X, Y, Z, cy, cz, P.rc2_u, P.mq, cx0, cx1)) continue;
-              const int hrow = G.HX * (cy + G.HY * cz);
-              const int jlo = max(L.hs[hrow + cx0], cb) - cb;
-              const int jhi = min(L.hs[hrow + cx1 + 1], ce) - cb;
-              for (int j = jlo; j < jhi; ++j) {
-                const Coord<D> q = L.p[j];
-                float d[D], dl[D];
-                d[0] = (float)(q.x - X);
-                d[1] = (float)(q.y - Y);
-                if constexpr (D == 3) d[2] = (float)(q.z - Z);
-                float r2 = 0.f, ddl = 0.f;
+      }
+      adj_update<D>(a, P, gi, li, acc, dacc, jl, ge, gs);
+    }
+  } else {
+    for (int tb = 0; tb < G.ntg; tb += NT) {
+      const int t = tb + (int)threadIdx.x;
+      const bool valid = t < G.ntg;
+      int hxi = G.ns, hyi = G.ns, hzi = G.nsz, gi = 0, vi = 0;
+      if (valid) brick_target<D>(G, L, t, hxi, hyi, hzi, gi, vi);
+      float o[D], li[D], acc[D], dacc[D], jl[D];
 #pragma unroll
-                for (int k = 0; k < D; ++k) {
-                  dl[k] = li[k] - L.lam[j * D + k];
-                  r2 += d[k] * d[k];
-                  ddl += d[k] * dl[k];
-                }
-                const bool in = (r2 < P.rc2_u) && (r2 > 0.f);
-                const float ir2 = in ? __builtin_amdgcn_rcpf(r2) : 0.f;
-                const float sr2 = P.sig2_u * ir2;
-                const float s6 = sr2 * sr2 * sr2;
-                const float t1 = ir2 * s6 * (2.f * s6 - 1.f);
-                const float ts = ir2 * s6 * (24.f * s6 - 6.f);
-                const float t2 = ir2 * ir2 * s6 * (8.f - 28.f * s6) * ddl;
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                  acc[k] -= t1 * d[k];
-                  dacc[k] -= ts * d[k];
-                  jl[k] += t1 * dl[k] + t2 * d[k];
-                }
+      for (int k = 0; k < D; ++k) {
+        o[k] = 0.f;
+        li[k] = 0.f;
+        acc[k] = 0.f;
+        dacc[k] = 0.f;
+        jl[k] = 0.f;
+      }
+      if (valid) {
+        ldv<D>(a.pos, gi, o);
+        ldv<D>(a.lam_v_in, gi, li);
+      }
+      if (interact) {
+        const int X = fixed_coord(hxi, o[0], P);
+        const int Y = fixed_coord(hyi, o[1], P);
+        const int Z = (D == 3) ? fixed_coord(hzi, o[D - 1], P) : 0;
+        const Reach rr = target_reach<D>(G, P, X, Y, Z, P.rcq);
+        for (int ci = 0; ci < nchunks; ++ci) {
+          const int cb = ci * CAP, ce = min(G.total, cb + CAP);
+          if (nchunks > 1) {
+            __syncthreads();
+            brick_stage<D, NT>(G, P, a.pos, a.lam_v_in, L, cb, ce);
+            __syncthreads();
+          }
+          if (valid) {
+            for (int cz = rr.cz0; cz <= rr.cz1; ++cz) {
+              for (int cy = rr.cy0; cy <= rr.cy1; ++cy) {
+                int cx0, cx1;
+                if (!row_columns<D>(G, P, X, Y, Z, cy, cz, P.rc2_u, P.mq, cx0, cx1)) continue;
+                const int hrow = G.HX * (cy + G.HY * cz);
+                const int jlo = max(L.hs[hrow + cx0], cb) - cb;
+                const int jhi = min(L.hs[hrow + cx1 + 1], ce) - cb;
+                for (int j = jlo; j < jhi; ++j)
+                  adj_pair<D>(L.p[j], &L.lam[j * D], X, Y, Z, li, P, acc, dacc, jl);
               }
             }
           }
         }
       }
-    }
-    if (valid) {
-      float lx[D], lv[D];
-      ldv<D>(a.lam_x, gi, lx);
-      double e = 0.0, s = 0.0;
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        const float a_k = P.eps24m_u * acc[k];
-        const float da_k = a.e1_over_sigma * dacc[k];
-        const float jl_k = a.e2 * jl[k];
-        lx[k] = fmaf(a.c, jl_k, lx[k]);
-        e += (double)li[k] * (double)a_k;
-        s += (double)li[k] * (double)da_k;
-        lv[k] = a.drift ? fmaf(P.dt, lx[k], li[k]) : li[k];
-      }
-      ge += (double)a.c * e / a.eps;
-      gs += (double)a.c * s;
-      stv<D>(a.lam_x, gi, lx);
-      stv<D>(a.lam_v_out, gi, lv);
+      if (valid) adj_update<D>(a, P, gi, li, acc, dacc, jl, ge, gs);
     }
   }
   const int w = threadIdx.x >> 6;
