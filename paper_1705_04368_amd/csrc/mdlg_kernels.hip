@@ -1536,15 +1536,21 @@ __global__ __launch_bounds__(kBlock) void k_adj_loss(AdjLossArgs a) {
 // Sum of the per-block partials of the loss and the parameter gradients, in
 // a fixed order.
 __global__ void k_adj_final(AdjFinalArgs a) {
+  // one wave: lane-strided partial sums, then a butterfly across the wave (a
+  // fixed summation order, so the result does not depend on timing)
+  double L = 0.0, ge = 0.0, gs = 0.0;
+  for (int i = threadIdx.x; i < a.nl; i += 64) L += a.lpart[i];
+  for (int b = threadIdx.x; b < a.nb; b += 64) {
+    ge += a.gpart[(size_t)b * 2];
+    gs += a.gpart[(size_t)b * 2 + 1];
+  }
+  L = wave_sum_d(L);
+  ge = wave_sum_d(ge);
+  gs = wave_sum_d(gs);
   if (threadIdx.x == 0) {
-    double L = 0.0;
-    for (int i = 0; i < a.nl; ++i) L += a.lpart[i];
     a.out[0] = L;
-  } else if (threadIdx.x <= 2) {
-    const int c = threadIdx.x - 1;
-    double t = 0.0;
-    for (int b = 0; b < a.nb; ++b) t += a.gpart[(size_t)b * 2 + c];
-    a.out[1 + c] = t;
+    a.out[1] = ge;
+    a.out[2] = gs;
   }
 }
 
