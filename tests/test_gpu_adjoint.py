@@ -59,6 +59,33 @@ def test_adjoint_msd_matches_oracle(dim, n, M, dx):
     assert np.abs(gv - ref["v0"]).max() <= 1e-3 * np.abs(ref["v0"]).max()
 
 
+@pytest.mark.parametrize("dim,n,M,dx", [(2, 2048, 16, 4.0), (3, 4740, 5, 4.0)])
+def test_adjoint_on_window_lists_equals_cell_walk(dim, n, M, dx):
+    # the window's force and reverse steps walk pair lists built at its start
+    # where pair lists are on, the frozen cells where they are off; both
+    # against the oracle, and against each other (same FP32 terms, summed in
+    # another order).  In 3D at rho = 0.6 a brick's halo of positions and
+    # adjoint velocities exceeds the reverse step's LDS chunk, so there the
+    # reverse step walks the cells either way (its force steps use the lists).
+    cfg_l, md, pos, vel = _setup(dim, n, M, dx, seed=60 + dim)
+    cfg_c, *_ = _setup(dim, n, M, dx, seed=60 + dim)
+    cfg_c.no_pair_list = 1
+    say(f"adjoint lists vs cell walk dim={dim} N={n}")
+    out = []
+    for cfg in (cfg_l, cfg_c):
+        sysg = make_system(cfg, pos, vel)
+        L, ge, gs, gv, ref = _compare(sysg, md, pos, vel, "msd")
+        assert ge == pytest.approx(ref["eps"], rel=1e-3)
+        assert gs == pytest.approx(ref["sigma"], rel=1e-3)
+        assert np.abs(gv - ref["v0"]).max() <= 1e-3 * np.abs(ref["v0"]).max()
+        out.append((L, ge, gs, gv))
+    (L1, e1, s1, g1), (L2, e2, s2, g2) = out
+    assert L1 == pytest.approx(L2, rel=1e-4)
+    assert e1 == pytest.approx(e2, rel=1e-4)
+    assert s1 == pytest.approx(s2, rel=1e-4)
+    assert np.abs(g1 - g2).max() <= 1e-4 * np.abs(g2).max()
+
+
 def test_adjoint_with_given_v0_and_state_after_window():
     cfg, md, pos, vel = _setup(2, 2048, 16, 4.0, seed=8)
     sysg = make_system(cfg, pos, vel)
