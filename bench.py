@@ -496,7 +496,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(replicas or domains would shard across GPUs; see DESIGN.md)", file=sys.stderr)
+              "(replicas, or spatial domains of one system, would shard across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "adjoint":
