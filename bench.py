@@ -27,8 +27,8 @@ if ROOT not in sys.path:
 
 import numpy as np  # noqa: E402
 
-# Workloads (synthetic stand-ins for the paper's LAMMPS runs; parameters of the
-# configurations this build measures).
+# Workloads: seeded synthetic stand-ins for the paper's LAMMPS runs, with
+# their sizes, densities, temperatures and lattice steps.
 WORKLOADS = {
     "2d_scale": dict(dim=2, n=262144, M=181, dx=4.0, kT=1.0, dt=0.005, steps=20, vmax=3,
                      desc="2D LJ N=262144, 724 sigma box (rho=0.5), kT=1, dt=0.005, "
@@ -495,7 +495,7 @@ def main():
         print(json.dumps({"copy_bytes": nbytes, "copies": 5}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(replicas, or spatial domains of one system, would shard across GPUs)", file=sys.stderr)
         sys.exit(2)
 
