@@ -51,6 +51,9 @@
  *   - Several independent replicas (boxes of different sizes) can share one
  *     handle; they run in the same kernel launches.  Particle arrays are the
  *     concatenation of the replicas in order; site arrays likewise.
+ *   - Results are deterministic: the same inputs give the same results bit
+ *     for bit, with or without graph replay (no floating-point sum depends on
+ *     the order in which atomics land).
  */
 #ifndef MDLG_H
 #define MDLG_H
@@ -175,9 +178,11 @@ mdlg_status mdlg_create(const mdlg_config *cfg, void *workspace_dev, size_t work
                         mdlg_system **out);
 
 /* Advance n_md_steps velocity-Verlet steps (asynchronous).  With
- * thermostat_every > 0 the velocities are rescaled to kT every that many steps
- * (equilibration).  Invalidates the lattice snapshot: the next
- * mdlg_coarse_grain takes a fresh one first. */
+ * thermostat_every > 0 the velocities of every replica are rescaled after
+ * every that many steps so that sum m v^2 = kT dim (N_r - 1) (equilibration;
+ * the paper sets the temperature of its run by the kinetic energy).
+ * Invalidates the lattice snapshot: the next mdlg_coarse_grain takes a fresh
+ * one first. */
 mdlg_status mdlg_step(mdlg_system *sys, int64_t n_md_steps);
 
 /* Run n_lattice_steps lattice time steps (asynchronous): each is
@@ -249,6 +254,32 @@ typedef enum { MDLG_LOSS_MSD = 0, MDLG_LOSS_MEAN_X = 1 } mdlg_loss;
 mdlg_status mdlg_adjoint(mdlg_system *sys, int32_t window_steps, int32_t ckpt_every, int32_t loss,
                          const float *v0_dev, double *out_loss, double *dL_deps, double *dL_dsigma,
                          float *g_v0_dev);
+
+/* Checkpoints.  The paper's run discards its start as equilibration and
+ * continues from the equilibrated state (section "MDLG for a two-dimensional
+ * Lennard-Jones gas"); a checkpoint makes such a run resumable.  A blob holds
+ * the complete state of a handle: the particle state in the library's own
+ * order, the lattice snapshot, every accumulator (n_i sums, moments,
+ * displacement sums, collision-operator and shifted-lattice sums), the
+ * kinetics of the last thermostat or readout, and the sequencing counters
+ * (MD steps, lattice steps, the position inside the rebuild interval and the
+ * collision-operator chain); between cell-list rebuilds also the pair lists.
+ * Loading it into a handle created with the same configuration (and the same
+ * LJ parameters) continues the run exactly: T lattice steps give the same
+ * results, bit for bit, as T/2, save, load, T/2.
+ *   mdlg_checkpoint_bytes: size of the blob of the current state (it grows
+ *                          between rebuilds, when the pair lists are saved).
+ *   mdlg_checkpoint_save:  writes the blob into host_blob (bytes >= the size
+ *                          above, else MDLG_E_NOMEM); synchronises; returns
+ *                          MDLG_E_UNSTABLE without writing when the device
+ *                          error word is set.
+ *   mdlg_checkpoint_load:  replaces the state of sys from the blob (exactly
+ *                          the size save wrote); synchronises.  MDLG_E_INVALID
+ *                          for a blob of another configuration or a damaged
+ *                          header.  The caller owns host_blob throughout. */
+mdlg_status mdlg_checkpoint_bytes(mdlg_system *sys, size_t *bytes);
+mdlg_status mdlg_checkpoint_save(mdlg_system *sys, void *host_blob, size_t bytes);
+mdlg_status mdlg_checkpoint_load(mdlg_system *sys, const void *host_blob, size_t bytes);
 
 /* Change the LJ parameters eps and sigma of an existing system (r_cut stays
  * fixed in absolute units).  Asynchronous. */

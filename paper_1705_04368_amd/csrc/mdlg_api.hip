@@ -434,6 +434,7 @@ struct mdlg_system {
   int* count = nullptr;
   int* cell_start = nullptr;
   int* tile_sum = nullptr;
+  unsigned* mcnt[2] = {nullptr, nullptr};  // arrivals per cell and direction (parity mpar)
   int* prev_u[2] = {nullptr, nullptr};    // snapshot, sorted order (set parity)
   float* prev_off[2] = {nullptr, nullptr};
   unsigned* A = nullptr;
@@ -493,14 +494,16 @@ struct mdlg_system {
   long long md_step = 0;
   long long n_lattice = 0;
   bool snapshot_valid = false;
-  bool lambda_pending = false;  // a thermostat factor waits for the next kModeStart
+  int mpar = 0;              // parity of the arrival counters the next rebuild uses
+  bool first_sort = false;   // the state arrays hold an input in arbitrary order
   int xcd_remap = 1;
   bool use_graph = true;
   hipStream_t cap_stream = nullptr;
   // host-side sequencing state a captured graph starts from and leaves
   struct SeqState {
     int pcur, scur, since_sort;
-    bool vel_full, lambda_pending;
+    bool vel_full;
+    int mpar;
     int xi_par;
     bool xi_have;
     long long md_step, n_lattice, xi_steps;
@@ -509,10 +512,10 @@ struct mdlg_system {
     hipGraphExec_t exec;
     SeqState after;  // counters as advanced by one replay from the key's state
   };
-  // key: (kind, pcur, scur, since_sort, vel_full, lambda_pending, xi_par,
-  // xi_have); kind 0 = a whole lattice step, B > 0 = a block of B MD steps,
-  // -n = the last n MD steps of a lattice step with its binning
-  std::map<std::tuple<int, int, int, int, bool, bool, int, bool>, GraphEntry> graphs;
+  // key: (kind, pcur, scur, since_sort, vel_full, mpar, xi_par, xi_have);
+  // kind 0 = a whole lattice step, B > 0 = a block of B MD steps, -n = the
+  // last n MD steps of a lattice step with its binning
+  std::map<std::tuple<int, int, int, int, bool, int, int, bool>, GraphEntry> graphs;
   // per-kernel event timing (measurement aid)
   bool timing = false;
   struct Timed {
@@ -529,6 +532,10 @@ struct mdlg_system {
 };
 
 namespace {
+
+// Words of arrival counters per MD cell: one byte for each of the 3^d - 1
+// directions a rebuild can move a particle in.
+int arrival_words(int D) { return D == 2 ? 2 : 7; }
 
 // Accumulators per displaced lattice: Q + 1 counts and d + d(d+1)/2 sums.
 int shift_per(const Layout& L) { return L.Q + 1 + L.D + L.D * (L.D + 1) / 2; }
@@ -553,6 +560,7 @@ size_t carve(mdlg_system* S, char* base) {
   S->count = c.take<int>(base, (size_t)L.n_cells);
   S->cell_start = c.take<int>(base, (size_t)L.n_cells + 1);
   S->tile_sum = c.take<int>(base, (size_t)L.ntiles * kTileCopies);
+  for (int i = 0; i < 2; ++i) S->mcnt[i] = c.take<unsigned>(base, (size_t)L.n_cells * arrival_words(L.D));
   for (int i = 0; i < 2; ++i) {
     S->prev_u[i] = c.take<int>(base, N * D);
     S->prev_off[i] = c.take<float>(base, N * D);
@@ -786,6 +794,10 @@ SortArgs sort_args(mdlg_system* S) {
   a.prev_off = S->prev_off[S->scur];
   a.prev_u_out = S->prev_u[S->scur ^ 1];
   a.prev_off_out = S->prev_off[S->scur ^ 1];
+  a.mcnt = S->mcnt[S->mpar];
+  a.mcnt_clear = S->mcnt[S->mpar ^ 1];
+  a.mwords = arrival_words(S->D);
+  a.first = S->first_sort ? 1 : 0;
   a.err = S->err;
   a.ntiles = S->L.ntiles;
   a.nchunks = S->L.nchunks;
@@ -834,8 +846,35 @@ void enqueue_sort(mdlg_system* S) {
     TimedLaunch t(S, MDLG_K_SCATTER);
     launch_scatter(S->D, S->L.nchunks, a, S->stream);
   }
-  S->pcur ^= 1;
-  S->scur ^= 1;
+  S->mpar ^= 1;
+  if (S->first_sort) {
+    // an input in arbitrary order: order every cell by id, back into the
+    // arrays the scatter read
+    if (S->timing) close_run(S);
+    CellsortArgs cs{};
+    cs.reps = S->reps;
+    cs.chunks = S->chunks;
+    cs.cell_start = S->cell_start;
+    cs.pos_src = a.pos_out;
+    cs.vel_src = a.vel_out;
+    cs.img_src = a.img_out;
+    cs.id_src = a.id_out;
+    cs.cell_src = a.cell_out;
+    cs.prev_u_src = a.prev_u_out;
+    cs.prev_off_src = a.prev_off_out;
+    cs.pos = S->pos[S->pcur];
+    cs.vel = S->vel[S->scur];
+    cs.img = S->img[S->scur];
+    cs.id = S->id[S->scur];
+    cs.cell = S->cell[S->scur];
+    cs.prev_u = S->prev_u[S->scur];
+    cs.prev_off = S->prev_off[S->scur];
+    launch_cellsort(S->D, S->L.nchunks, cs, S->stream);
+    S->first_sort = false;
+  } else {
+    S->pcur ^= 1;
+    S->scur ^= 1;
+  }
   S->since_sort = 0;
   if (S->L.kmax > 0) enqueue_nlist(S, S->P);
 }
@@ -855,7 +894,6 @@ void enqueue_force(mdlg_system* S, int mode, bool sort_follows, float* acc_out, 
   a.pos_out = S->pos[S->pcur ^ 1];
   a.vel = S->vel[S->scur];
   a.acc_out = acc_out;
-  a.lambda = (mode == kModeStart && S->lambda_pending) ? S->lambda : nullptr;
   a.kpart = kpart;
   a.err = S->err;
   a.mode = mode;
@@ -875,7 +913,6 @@ void enqueue_force(mdlg_system* S, int mode, bool sort_follows, float* acc_out, 
     launch_force(S->D, a, S->stream);
   }
   if (mode == kModeStep || mode == kModeStart) S->pcur ^= 1;
-  if (mode == kModeStart) S->lambda_pending = false;
 }
 
 void enqueue_kin(mdlg_system* S, bool thermostat) {
@@ -891,6 +928,14 @@ void enqueue_kin(mdlg_system* S, bool thermostat) {
   k.kT = S->cfg.kT;
   k.mass = S->cfg.mass;
   launch_kin(k, S->stream);
+  if (thermostat) {
+    // the velocities at the current time, rescaled now
+    RescaleArgs r{};
+    r.chunks = S->chunks;
+    r.lambda = S->lambda;
+    r.vel = S->vel[S->scur];
+    launch_rescale(S->D, S->L.nchunks, r, S->stream);
+  }
 }
 
 // One velocity-Verlet step; force_sort requests a rebuild right after it.
@@ -1038,6 +1083,101 @@ void zero_accumulators(mdlg_system* S) {
   S->n_lattice = 0;
 }
 
+// ----- checkpoints
+
+constexpr char kCkptMagic[8] = {'M', 'D', 'L', 'G', 'C', 'K', 'P', '1'};
+
+struct CkptHeader {
+  char magic[8];
+  uint64_t fingerprint;
+  uint64_t bytes;  // whole blob
+  int32_t pcur, scur, since_sort, vel_full, mpar, xi_par, xi_have, snapshot_valid, has_lists, pad;
+  int64_t md_step, n_lattice, xi_steps;
+};
+
+void fnv(uint64_t& h, const void* p, size_t n) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+}
+
+// Everything a trajectory depends on: the configuration (current LJ
+// parameters included) and the layout derived from it.
+uint64_t fingerprint(const mdlg_system* S) {
+  uint64_t h = 1469598103934665603ull;
+  const mdlg_config& c = S->cfg;
+  const Layout& L = S->L;
+  const int32_t ints[] = {c.dim, c.n_replicas, c.forces_off, c.md_steps_per_lattice_step, c.vmax,
+                          c.thermostat_every, L.k, L.sort_every, L.BX, L.BY, L.BZ, L.bthreads,
+                          L.kmax, L.lcap, L.Q, L.nm, L.nbricks, L.nstrips, L.xi ? 1 : 0,
+                          L.n_shifts};
+  fnv(h, ints, sizeof ints);
+  const double dbl[] = {c.lattice_dx, c.epsilon, c.sigma, c.mass, c.r_cut, c.dt, c.kT};
+  fnv(h, dbl, sizeof dbl);
+  fnv(h, S->n_particles.data(), S->n_particles.size() * sizeof(int32_t));
+  fnv(h, S->lattice.data(), S->lattice.size() * sizeof(int32_t));
+  fnv(h, S->shifts_host.data(), S->shifts_host.size() * sizeof(double));
+  return h;
+}
+
+struct Region {
+  void* dev;
+  size_t bytes;
+};
+
+// The device buffers of a checkpoint, in blob order.  The pair lists are
+// included only between rebuilds; at a rebuild they are rebuilt from the
+// restored positions, which reproduces them exactly.
+std::vector<Region> ckpt_regions(mdlg_system* S, bool lists) {
+  const Layout& L = S->L;
+  const int D = L.D;
+  const size_t N = (size_t)L.n_total;
+  std::vector<Region> r = {
+      {S->pos[S->pcur], N * D * sizeof(float)},
+      {S->vel[S->scur], N * D * sizeof(float)},
+      {S->img[S->scur], N * D * sizeof(int)},
+      {S->id[S->scur], N * sizeof(int)},
+      {S->cell[S->scur], N * sizeof(int)},
+      {S->prev_u[S->scur], N * D * sizeof(int)},
+      {S->prev_off[S->scur], N * D * sizeof(float)},
+      {S->cell_start, ((size_t)L.n_cells + 1) * sizeof(int)},
+      {S->A, (size_t)L.n_sites * L.Q * sizeof(unsigned)},
+      {S->mom, (size_t)L.n_sites * L.nm * sizeof(long long)},
+      {S->dpart, (size_t)L.nstrips * 2 * D * sizeof(double)},
+      {S->kin, L.reps.size() * (D + 1) * sizeof(double)},
+  };
+  if (L.n_shifts > 0) {
+    r.push_back({S->shift_k, sizeof(long long)});
+    r.push_back({S->shift_acc, (size_t)L.n_shifts * shift_per(L) * kTileCopies * sizeof(unsigned long long)});
+  }
+  if (L.xi) {
+    const size_t sq = (size_t)L.n_sites * L.Q;
+    r.push_back({S->nstep[0], sq * sizeof(unsigned)});
+    r.push_back({S->nstep[1], sq * sizeof(unsigned)});
+    r.push_back({S->xi_site, sq * sizeof(long long)});
+    r.push_back({S->xi_last, sq * sizeof(int)});
+    r.push_back({S->xi_sums, (size_t)5 * L.Q * sizeof(unsigned long long)});
+  }
+  if (lists) {
+    r.push_back({S->smap, (size_t)L.nbricks * L.lcap * sizeof(int2)});
+    r.push_back({S->binfo, (size_t)L.nbricks * sizeof(int4)});
+    r.push_back({S->nl, (size_t)(L.kmax / 4) * N * sizeof(unsigned long long)});
+    r.push_back({S->off0, N * D * sizeof(float)});
+    r.push_back({S->trec, (size_t)L.nbricks * L.lcap * sizeof(int2)});
+  }
+  return r;
+}
+
+bool ckpt_lists(const mdlg_system* S) { return S->L.kmax > 0 && S->since_sort > 0; }
+
+size_t ckpt_bytes(mdlg_system* S) {
+  size_t b = sizeof(CkptHeader);
+  for (const Region& r : ckpt_regions(S, ckpt_lists(S))) b += r.bytes;
+  return b;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- C ABI
@@ -1142,6 +1282,8 @@ mdlg_status mdlg_create(const mdlg_config* cfg, void* workspace_dev, size_t work
   }
   launch_fill_u32(reinterpret_cast<unsigned*>(S->count), 0u, L.n_cells, S->stream);
   launch_fill_u32(reinterpret_cast<unsigned*>(S->tile_sum), 0u, (long long)L.ntiles * kTileCopies, S->stream);
+  for (int i = 0; i < 2; ++i)
+    launch_fill_u32(S->mcnt[i], 0u, L.n_cells * arrival_words(L.D), S->stream);
   launch_fill_u32(S->err, 0u, 64, S->stream);
   launch_fill_f32(S->lambda, 1.f, (long long)L.reps.size(), S->stream);
   zero_accumulators(S);
@@ -1161,6 +1303,7 @@ mdlg_status mdlg_create(const mdlg_config* cfg, void* workspace_dev, size_t work
   launch_ingest(S->D, L.nchunks, ia, S->stream);
   S->pcur = 0;
   S->scur = 0;
+  S->first_sort = true;
   enqueue_sort(S);
   enqueue_bin(S, true);
   S->snapshot_valid = true;
@@ -1186,7 +1329,6 @@ mdlg_status mdlg_step(mdlg_system* S, int64_t n) {
       enqueue_force(S, kModeFinish, false, nullptr, S->kpart);
       enqueue_kin(S, true);
       S->vel_full = true;
-      S->lambda_pending = true;
     }
   }
   if (n > 0) S->snapshot_valid = false;
@@ -1196,7 +1338,7 @@ mdlg_status mdlg_step(mdlg_system* S, int64_t n) {
 extern "C++" {
 
 static mdlg_system::SeqState seq_state(const mdlg_system* S) {
-  return {S->pcur, S->scur, S->since_sort, S->vel_full, S->lambda_pending, S->xi_par, S->xi_have,
+  return {S->pcur, S->scur, S->since_sort, S->vel_full, S->mpar, S->xi_par, S->xi_have,
           S->md_step, S->n_lattice, S->xi_steps};
 }
 
@@ -1205,7 +1347,7 @@ static void set_seq_state(mdlg_system* S, const mdlg_system::SeqState& q) {
   S->scur = q.scur;
   S->since_sort = q.since_sort;
   S->vel_full = q.vel_full;
-  S->lambda_pending = q.lambda_pending;
+  S->mpar = q.mpar;
   S->xi_par = q.xi_par;
   S->xi_have = q.xi_have;
   S->md_step = q.md_step;
@@ -1219,7 +1361,7 @@ static void set_seq_state(mdlg_system* S, const mdlg_system::SeqState& q) {
 // state then advances as the body would have advanced it.
 template <class F>
 mdlg_status replay_graph(mdlg_system* S, int kind, F body) {
-  auto key = std::make_tuple(kind, S->pcur, S->scur, S->since_sort, S->vel_full, S->lambda_pending,
+  auto key = std::make_tuple(kind, S->pcur, S->scur, S->since_sort, S->vel_full, S->mpar,
                              S->xi_par, S->xi_have);
   auto it = S->graphs.find(key);
   const mdlg_system::SeqState before = seq_state(S);
@@ -1535,12 +1677,12 @@ mdlg_status mdlg_set_state(mdlg_system* S, const mdlg_particles* in) {
   HIPCHK(S, hipMemcpyAsync(x.x_vel, in->vel, nd * 4, hipMemcpyHostToDevice, S->stream));
   launch_import(D, L.nchunks, x, S->stream);
   S->since_sort = 1;  // the imported arrays are in id order: rebuild
+  S->first_sort = true;
   enqueue_sort(S);
   if (!in->prev_ucell) enqueue_bin(S, true);
   S->snapshot_valid = true;
   S->xi_have = false;
   S->vel_full = true;
-  S->lambda_pending = false;
   mdlg_status st = check_launch(S, "mdlg_set_state");
   if (st != MDLG_OK) return st;
   HIPCHK(S, hipStreamSynchronize(S->stream));
@@ -1625,7 +1767,6 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
     AdjIoArgs io{S->id[S->scur], S->vel[S->scur], const_cast<float*>(v0_dev), (int)L.n_total, 1};
     launch_adj_io(D, io, S->stream);
     S->vel_full = true;
-    S->lambda_pending = false;
   } else if (!S->vel_full) {
     enqueue_force(S, kModeFinish, false, nullptr, nullptr);
     S->vel_full = true;
@@ -1718,6 +1859,104 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
   if (dL_deps) *dL_deps = out[1];
   if (dL_dsigma) *dL_dsigma = out[2];
   return st;
+}
+
+mdlg_status mdlg_checkpoint_bytes(mdlg_system* S, size_t* bytes) {
+  if (!S || !bytes) return MDLG_E_INVALID;
+  *bytes = ckpt_bytes(S);
+  return MDLG_OK;
+}
+
+mdlg_status mdlg_checkpoint_save(mdlg_system* S, void* blob, size_t bytes) {
+  if (!S || !blob) return MDLG_E_INVALID;
+  const size_t need = ckpt_bytes(S);
+  if (bytes < need) {
+    S->last_error = "checkpoint buffer too small: need " + std::to_string(need) + " bytes";
+    return MDLG_E_NOMEM;
+  }
+  if (S->timing) close_run(S);
+  mdlg_status st = read_err(S);  // synchronises; a failed run is not saved
+  if (st != MDLG_OK) return st;
+  const bool lists = ckpt_lists(S);
+  CkptHeader h{};
+  std::memcpy(h.magic, kCkptMagic, sizeof h.magic);
+  h.fingerprint = fingerprint(S);
+  h.bytes = need;
+  h.pcur = S->pcur;
+  h.scur = S->scur;
+  h.since_sort = S->since_sort;
+  h.vel_full = S->vel_full ? 1 : 0;
+  h.mpar = S->mpar;
+  h.xi_par = S->xi_par;
+  h.xi_have = S->xi_have ? 1 : 0;
+  h.snapshot_valid = S->snapshot_valid ? 1 : 0;
+  h.has_lists = lists ? 1 : 0;
+  h.md_step = S->md_step;
+  h.n_lattice = S->n_lattice;
+  h.xi_steps = S->xi_steps;
+  char* out = static_cast<char*>(blob);
+  std::memcpy(out, &h, sizeof h);
+  size_t off = sizeof h;
+  for (const Region& r : ckpt_regions(S, lists)) {
+    HIPCHK(S, hipMemcpyAsync(out + off, r.dev, r.bytes, hipMemcpyDeviceToHost, S->stream));
+    off += r.bytes;
+  }
+  HIPCHK(S, hipStreamSynchronize(S->stream));
+  return MDLG_OK;
+}
+
+mdlg_status mdlg_checkpoint_load(mdlg_system* S, const void* blob, size_t bytes) {
+  if (!S || !blob) return MDLG_E_INVALID;
+  CkptHeader h{};
+  if (bytes < sizeof h) {
+    S->last_error = "checkpoint blob too short";
+    return MDLG_E_INVALID;
+  }
+  std::memcpy(&h, blob, sizeof h);
+  if (std::memcmp(h.magic, kCkptMagic, sizeof h.magic) != 0) {
+    S->last_error = "not an MDLG checkpoint";
+    return MDLG_E_INVALID;
+  }
+  if (h.fingerprint != fingerprint(S)) {
+    S->last_error = "checkpoint was taken with a different configuration";
+    return MDLG_E_INVALID;
+  }
+  if (h.bytes != bytes || h.pcur < 0 || h.pcur > 1 || h.scur < 0 || h.scur > 1 || h.mpar < 0 ||
+      h.mpar > 1 || h.xi_par < 0 || h.xi_par > 1 || h.since_sort < 0 ||
+      h.since_sort >= std::max(1, S->L.sort_every) ||
+      (h.has_lists != 0) != (S->L.kmax > 0 && h.since_sort > 0)) {
+    S->last_error = "checkpoint header is inconsistent";
+    return MDLG_E_INVALID;
+  }
+  // wait for queued work before overwriting the state
+  HIPCHK(S, hipStreamSynchronize(S->stream));
+  if (S->timing) close_run(S);
+  S->pcur = h.pcur;
+  S->scur = h.scur;
+  S->since_sort = h.since_sort;
+  S->vel_full = h.vel_full != 0;
+  S->mpar = h.mpar;
+  S->xi_par = h.xi_par;
+  S->xi_have = h.xi_have != 0;
+  S->snapshot_valid = h.snapshot_valid != 0;
+  S->md_step = h.md_step;
+  S->n_lattice = h.n_lattice;
+  S->xi_steps = h.xi_steps;
+  S->first_sort = false;
+  const char* in = static_cast<const char*>(blob);
+  size_t off = sizeof h;
+  for (const Region& r : ckpt_regions(S, h.has_lists != 0)) {
+    HIPCHK(S, hipMemcpyAsync(r.dev, in + off, r.bytes, hipMemcpyHostToDevice, S->stream));
+    off += r.bytes;
+  }
+  launch_fill_u32(S->err, 0u, 64, S->stream);
+  // the arrival counters the next rebuild uses start at zero
+  launch_fill_u32(S->mcnt[S->mpar], 0u, S->L.n_cells * arrival_words(S->D), S->stream);
+  if (S->L.kmax > 0 && h.has_lists == 0) enqueue_nlist(S, S->P);
+  mdlg_status st = check_launch(S, "mdlg_checkpoint_load");
+  if (st != MDLG_OK) return st;
+  HIPCHK(S, hipStreamSynchronize(S->stream));
+  return read_err(S);
 }
 
 mdlg_status mdlg_set_potential(mdlg_system* S, double epsilon, double sigma) {

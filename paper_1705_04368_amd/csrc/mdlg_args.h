@@ -43,11 +43,45 @@ struct SortArgs {
   const float* prev_off;
   int* prev_u_out;
   float* prev_off_out;
+  unsigned* mcnt;         // [n_cells][mwords] arrivals per cell and direction (one byte each)
+  unsigned* mcnt_clear;   // the other parity's counters, cleared by the scatter
   unsigned* err;
+  int mwords;             // words of arrival counters per cell: 2 (2D), 7 (3D)
+  int first;              // 1: input in arbitrary order (ingest, import): slots from
+                          // atomics, then k_cellsort orders every cell by id
   int ntiles;
   int nchunks;
   int ncchunks;
   int xcd_remap;
+};
+
+// First rebuild after ingest or import: the scattered state (src) is copied
+// back into the state arrays (dst) with every cell ordered by particle id.
+struct CellsortArgs {
+  const Replica* reps;
+  const int4* chunks;
+  const int* cell_start;
+  const float* pos_src;
+  const float* vel_src;
+  const int* img_src;
+  const int* id_src;
+  const int* cell_src;
+  const int* prev_u_src;
+  const float* prev_off_src;
+  float* pos;
+  float* vel;
+  int* img;
+  int* id;
+  int* cell;
+  int* prev_u;
+  float* prev_off;
+};
+
+// Thermostat: velocities of every replica scaled by its factor.
+struct RescaleArgs {
+  const int4* chunks;
+  const float* lambda;
+  float* vel;
 };
 
 struct ScanArgs {
@@ -67,7 +101,6 @@ struct ForceArgs {
   float* pos_out;
   float* vel;
   float* acc_out;      // optional
-  const float* lambda; // per replica rescale factor (kModeStart), null = 1
   double* kpart;       // optional per-brick partials [nbricks][D + 1]
   unsigned* err;
   int mode;
@@ -281,6 +314,8 @@ void launch_ingest(int D, int nchunks, const IngestArgs& a, hipStream_t s);
 void launch_count(int D, int nchunks, const SortArgs& a, hipStream_t s);
 void launch_scan(const ScanArgs& a, hipStream_t s);
 void launch_scatter(int D, int nchunks, const SortArgs& a, hipStream_t s);
+void launch_cellsort(int D, int nchunks, const CellsortArgs& a, hipStream_t s);
+void launch_rescale(int D, int nchunks, const RescaleArgs& a, hipStream_t s);
 void launch_force(int D, const ForceArgs& a, hipStream_t s);
 void launch_nlist(int D, const NlistArgs& a, hipStream_t s);
 void launch_kin(const KinArgs& a, hipStream_t s);

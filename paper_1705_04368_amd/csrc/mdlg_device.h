@@ -41,7 +41,7 @@ constexpr int kMaxListHalo = 255;    // halo cells per axis a packed coordinate 
 // force-kernel modes (what the velocity buffer holds on entry)
 enum StepMode : int {
   kModeStep = 0,    // v(t - dt/2): complete the kick, kick again, drift
-  kModeStart = 1,   // v(t) (times lambda): kick, drift
+  kModeStart = 1,   // v(t): kick, drift
   kModeFinish = 2,  // v(t - dt/2): complete the kick only, store v(t)
   kModeProbe = 3    // v(t): forces only (for readout of accelerations)
 };

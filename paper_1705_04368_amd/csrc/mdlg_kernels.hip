@@ -15,7 +15,10 @@
 //   k_ingest   absolute positions -> (cell, offset), unsorted
 //   k_count    canonicalise (cell, offset, image) and count particles per cell
 //   k_scan     exclusive scan of the counts into cell_start
-//   k_scatter  stable-by-slot permutation of the state into cell order
+//   k_scatter  permutation of the state into cell order (slots fixed by the
+//              old order: deterministic)
+//   k_cellsort first rebuild of an input in arbitrary order: cells by id
+//   k_rescale  thermostat rescale of the velocities
 //   k_nlist_narrow / k_nlist_wide    pair lists of radius r_cut + 2 margin
 //              per brick at each rebuild (14-bit candidate tests), with the
 //              staging map and target order the force kernel follows
@@ -269,25 +272,68 @@ __global__ __launch_bounds__(kBlock) void k_ingest(IngestArgs a) {
 
 // ---------------------------------------------------------------- counting sort
 
+// Deterministic counting sort.  Between rebuilds a particle leaves its cell
+// by less than one cell, so a rebuild moves it by a step d_a in {-1, 0, 1}
+// along every axis, numbered dir = sum_a (d_a + 1) 3^a (kStay: no move).  In
+// its new cell c the particles are ordered: first those that stayed in c, in
+// their old order; then the arrivals, by direction (all arrivals from one
+// direction come from a single old cell) and within one direction in their
+// old order.  Every slot is then a function of the old order alone, never of
+// the order in which atomics land, so two runs from one state are identical
+// bit for bit.  The count pass records per particle its key, its direction and
+// lrank, its rank among the particles of its old cell that moved the same
+// way; per cell it counts all particles and, in one byte per direction, the
+// arrivals.  The scatter places stayers at cell_start[c] + lrank and an
+// arrival after every stayer and every arrival from a lower direction.
+template <int D>
+constexpr int kDirs = (D == 2) ? 9 : 27;
+template <int D>
+constexpr int kStay = (kDirs<D> - 1) / 2;
+// words of arrival counters per cell (one byte per direction but kStay)
+template <int D>
+constexpr int kArrWords = (kDirs<D> - 1 + 3) / 4;
+
 template <int D>
 __device__ __forceinline__ bool canon_particle(const SortArgs& a, const Replica& R, int g,
-                                               float (&o)[D], int (&c)[D], int (&im)[D]) {
+                                               float (&o)[D], int (&c)[D], int (&im)[D],
+                                               int* oldcell = nullptr, int* dir = nullptr) {
   ldv<D>(a.pos, g, o);
   ldi<D>(a.img, g, im);
-  cell_coords<D>(a.cell[g] - R.cell_off, R, c);
+  const int oc = a.cell[g];
+  cell_coords<D>(oc - R.cell_off, R, c);
   bool ok = true;
-  for (int k = 0; k < D; ++k) ok = canon(o[k], c[k], im[k], R.Mc[k], a.P.s) && ok;
+  int dd = 0, p3 = 1;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const int c0 = c[k];
+    ok = canon(o[k], c[k], im[k], R.Mc[k], a.P.s) && ok;
+    // the step, with the periodic wrap undone (at least three cells per axis)
+    int d = c[k] - c0;
+    if (d > 1) d -= R.Mc[k];
+    else if (d < -1) d += R.Mc[k];
+    dd += (d + 1) * p3;
+    p3 *= 3;
+  }
+  if (oldcell) *oldcell = oc;
+  if (dir) *dir = dd;
   return ok;
 }
 
-// Slot of each particle inside its new cell.  A chunk of particles sorted by
-// their old cell moves into a narrow window of new cells: the old cells of the
-// chunk widened by one row of cells on either side (moves along x and y).  The
-// block counts those particles in an LDS histogram over the window (rank in
-// the block from the LDS atomic) and takes one global atomic per distinct
-// cell for its base; particles outside the window (moves along z in 3D) take
-// one global atomic each.  Scan-tile totals are summed in LDS first: same-
-// address global atomics serialise across the device.
+// Arrival field of a direction other than kStay.
+template <int D>
+__device__ __forceinline__ int arrival_field(int dir) {
+  return dir < kStay<D> ? dir : dir - 1;
+}
+
+// Counts and ranks.  Per-cell totals go through a block-local LDS histogram
+// over a window of new cells (the chunk's old cells widened by one row on
+// either side), one global atomic per distinct cell; keys outside the window
+// (moves along z in 3D) take one global atomic each.  Scan-tile totals are
+// summed in LDS first: same-address global atomics serialise across the
+// device.  The ranks need the directions of the chunk's particles (LDS) and of
+// the particles of the chunk's first old cell that precede the chunk.  With
+// `first` (input in arbitrary order) slots come from global atomics and the
+// ranks are skipped: k_cellsort orders the cells afterwards.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
   constexpr int kHist = 2048;
@@ -295,8 +341,13 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
   // scan-tile totals of the block: the window's tiles and those a particle
   // moving by one cell along the slowest axis reaches
   constexpr int kTiles = 64;
+  // particles of the chunk's first old cell that lie before the chunk
+  constexpr int kPrev = kBlock;
   __shared__ int s_cnt[kHist];
   __shared__ int s_tile[kTiles];
+  __shared__ unsigned char s_dir[kCountChunkMax];
+  __shared__ unsigned char s_pdir[kPrev];
+  __shared__ int s_p0;
   // consecutive chunks on one XCD: the per-cell count atomics of neighbouring
   // chunks then meet in one L2 instead of crossing XCDs
   int cb = blockIdx.x;
@@ -312,57 +363,96 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
   const Replica R = a.reps[ch.x];
   // window: the chunk's old cells (sorted) widened by one row on either side
   const int lo = a.cell[ch.y] - R.Mc[0] - 1;
-  const int nwin = min(kHist, a.cell[ch.z - 1] + R.Mc[0] + 2 - lo);
+  const int nwin = a.first ? 0 : min(kHist, a.cell[ch.z - 1] + R.Mc[0] + 2 - lo);
   for (int i = threadIdx.x; i < nwin; i += kBlock) s_cnt[i] = 0;
   if (threadIdx.x < kTiles) s_tile[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    // first particle of the chunk's first old cell
+    int p0 = ch.y;
+    if (!a.first && ch.y > R.part_off && a.cell[ch.y - 1] == a.cell[ch.y])
+      p0 = a.cell_start[a.cell[ch.y]];
+    if (ch.y - p0 > kPrev) {
+      atomicOr(a.err, kErrOverflow);
+      p0 = ch.y - kPrev;
+    }
+    s_p0 = p0;
+  }
   // (the reach below the window is capped so that the window's own tiles
   // always index inside s_tile: (16 + 2) tiles + 2 < kTiles)
   const int layer = min((D == 3) ? R.Mc[0] * R.Mc[1] : R.Mc[0], 16 * kScanTile);
   const int tile0 = max(0, lo - layer) / kScanTile;
   __syncthreads();
-  int key[kPer], rank[kPer];
-  bool inwin[kPer];
+  {
+    const int j = s_p0 + (int)threadIdx.x;
+    if (j < ch.y) {
+      float o[D];
+      int c[D], im[D], dd;
+      (void)canon_particle<D>(a, R, j, o, c, im, nullptr, &dd);
+      s_pdir[j - s_p0] = (unsigned char)dd;
+    }
+  }
+  int key[kPer], oc[kPer], dir[kPer];
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
     const int g = ch.y + u * kBlock + (int)threadIdx.x;
     key[u] = -1;
-    inwin[u] = false;
-    rank[u] = 0;
+    oc[u] = 0;
+    dir[u] = kStay<D>;
     if (ch.y + u * kBlock >= ch.z) continue;  // the chunk is shorter (uniform)
+    bool inwin = false;
     if (g < ch.z) {
       float o[D];
       int c[D], im[D];
-      if (!canon_particle<D>(a, R, g, o, c, im)) atomicOr(a.err, kErrJump);
+      if (!canon_particle<D>(a, R, g, o, c, im, &oc[u], &dir[u])) atomicOr(a.err, kErrJump);
       key[u] = R.cell_off + cell_linear<D>(c, R);
-      inwin[u] = key[u] >= lo && key[u] < lo + nwin;
-      if (inwin[u]) {
-        rank[u] = atomicAdd(&s_cnt[key[u] - lo], 1);
-      } else {
+      s_dir[g - ch.y] = (unsigned char)dir[u];
+      if (a.first) {
         a.keyslot[g] = make_int2(key[u], atomicAdd(a.count + key[u], 1));
+      } else {
+        inwin = key[u] >= lo && key[u] < lo + nwin;
+        if (inwin) atomicAdd(&s_cnt[key[u] - lo], 1);
+        else atomicAdd(a.count + key[u], 1);
+        if (dir[u] != kStay<D>) {
+          const int f = arrival_field<D>(dir[u]);
+          const unsigned sh = 8u * (unsigned)(f & 3);
+          const unsigned old =
+              atomicAdd(a.mcnt + (size_t)key[u] * kArrWords<D> + (f >> 2), 1u << sh);
+          if (((old >> sh) & 255u) == 255u) atomicOr(a.err, kErrOverflow);
+        }
       }
     }
-    if (key[u] >= 0 && !inwin[u]) {
+    if (key[u] >= 0 && !inwin) {
       const int tl = key[u] / kScanTile - tile0;
       if (tl >= 0 && tl < kTiles) atomicAdd(&s_tile[tl], 1);
     }
     const int tk = key[u] >= 0 ? key[u] / kScanTile - tile0 : 0;
     wave_agg_add_i(tsum, key[u] >= 0 ? key[u] / kScanTile : 0,
-                   key[u] >= 0 && !inwin[u] && (tk < 0 || tk >= kTiles));
+                   key[u] >= 0 && !inwin && (tk < 0 || tk >= kTiles));
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nwin; i += kBlock) {
     const int c = s_cnt[i];
     if (c) {
-      s_cnt[i] = atomicAdd(a.count + lo + i, c);
+      atomicAdd(a.count + lo + i, c);
       atomicAdd(&s_tile[(lo + i) / kScanTile - tile0], c);
     }
   }
   __syncthreads();
   if (threadIdx.x < kTiles && s_tile[threadIdx.x]) atomicAdd(tsum + tile0 + threadIdx.x, s_tile[threadIdx.x]);
+  if (a.first) return;
+  // rank among the earlier particles of the old cell that moved the same way
+  const int p0 = s_p0;
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
     const int g = ch.y + u * kBlock + (int)threadIdx.x;
-    if (inwin[u]) a.keyslot[g] = make_int2(key[u], s_cnt[key[u] - lo] + rank[u]);
+    if (key[u] < 0) continue;
+    const int run0 = a.cell_start[oc[u]];
+    int r = 0;
+    for (int j = max(run0, ch.y); j < g; ++j) r += (s_dir[j - ch.y] == dir[u]) ? 1 : 0;
+    if (run0 < ch.y)
+      for (int j = max(run0, p0); j < ch.y; ++j) r += (s_pdir[j - p0] == dir[u]) ? 1 : 0;
+    const int code = (dir[u] == kStay<D>) ? r : (r | ((arrival_field<D>(dir[u]) + 1) << 24));
+    a.keyslot[g] = make_int2(key[u], code);
   }
 }
 
@@ -397,10 +487,21 @@ __global__ __launch_bounds__(kBlock) void k_scan(ScanArgs a) {
   if (b == a.ntiles - 1 && threadIdx.x == 0) a.cell_start[a.n] = pre + total;
 }
 
+// Permutation of the state into the new cell order.  With `first` the slots
+// are the atomics' and k_cellsort follows; otherwise a stayer goes to
+// cell_start[c] + lrank and an arrival from field f to cell_start[c + 1] -
+// (all arrivals) + (arrivals from fields below f) + lrank.  The other
+// parity's arrival counters are cleared for the next rebuild.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_scatter(SortArgs a) {
   if (blockIdx.x == 0)
     for (int t = threadIdx.x; t < a.ntiles * kTileCopies; t += kBlock) a.tile_sum[t] = 0;
+  {
+    const long long nw = (long long)a.P.n_cells * kArrWords<D>;
+    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < nw;
+         i += (long long)gridDim.x * kBlock)
+      a.mcnt_clear[i] = 0u;
+  }
   const int4 ch = a.chunks[blockIdx.x];
   const Replica R = a.reps[ch.x];
   for (int g = ch.y + threadIdx.x; g < ch.z; g += kBlock) {
@@ -408,7 +509,36 @@ __global__ __launch_bounds__(kBlock) void k_scatter(SortArgs a) {
     int c[D], im[D];
     (void)canon_particle<D>(a, R, g, o, c, im);
     const int2 ks = a.keyslot[g];
-    const int dst = a.cell_start[ks.x] + ks.y;
+    int dst;
+    if (a.first) {
+      dst = a.cell_start[ks.x] + ks.y;
+    } else {
+      const int lr = ks.y & 0xffffff;
+      const int f1 = (int)((unsigned)ks.y >> 24);
+      if (f1 == 0) {
+        dst = a.cell_start[ks.x] + lr;
+      } else {
+        const unsigned* __restrict__ w = a.mcnt + (size_t)ks.x * kArrWords<D>;
+        int tot = 0, pre = 0;
+#pragma unroll
+        for (int i = 0; i < kArrWords<D>; ++i) {
+          const unsigned x = w[i];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int n = (int)((x >> (8 * b)) & 255u);
+            tot += n;
+            pre += (4 * i + b < f1 - 1) ? n : 0;
+          }
+        }
+        dst = a.cell_start[ks.x + 1] - tot + pre + lr;
+      }
+    }
+    // a slot outside the cell's range means inconsistent counts (an arrival
+    // counter overflowed): reported, and nothing is written out of range
+    if (dst < a.cell_start[ks.x] || dst >= a.cell_start[ks.x + 1]) {
+      atomicOr(a.err, kErrOverflow);
+      continue;
+    }
     float v[D];
     ldv<D>(a.vel, g, v);
     stv<D>(a.pos_out, dst, o);
@@ -422,6 +552,51 @@ __global__ __launch_bounds__(kBlock) void k_scatter(SortArgs a) {
     ldv<D>(a.prev_off, g, po);
     sti<D>(a.prev_u_out, dst, pu);
     stv<D>(a.prev_off_out, dst, po);
+  }
+}
+
+// After the first rebuild of an input in arbitrary order: every cell of the
+// scattered state ordered by particle id (rank = particles of the cell with a
+// smaller id), copied back into the state arrays.  Runs at creation and
+// import only.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_cellsort(CellsortArgs a) {
+  const int4 ch = a.chunks[blockIdx.x];
+  for (int g = ch.y + threadIdx.x; g < ch.z; g += kBlock) {
+    const int c = a.cell_src[g];
+    const int st = a.cell_start[c], en = a.cell_start[c + 1];
+    const int me = a.id_src[g];
+    int r = 0;
+    for (int j = st; j < en; ++j) r += (a.id_src[j] < me) ? 1 : 0;
+    const int dst = st + r;
+    float o[D], v[D], po[D];
+    int im[D], pu[D];
+    ldv<D>(a.pos_src, g, o);
+    ldv<D>(a.vel_src, g, v);
+    ldi<D>(a.img_src, g, im);
+    ldi<D>(a.prev_u_src, g, pu);
+    ldv<D>(a.prev_off_src, g, po);
+    stv<D>(a.pos, dst, o);
+    stv<D>(a.vel, dst, v);
+    sti<D>(a.img, dst, im);
+    a.id[dst] = me;
+    a.cell[dst] = c;
+    sti<D>(a.prev_u, dst, pu);
+    stv<D>(a.prev_off, dst, po);
+  }
+}
+
+// Thermostat rescale v <- lambda_r v of every particle of replica r.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_rescale(RescaleArgs a) {
+  const int4 ch = a.chunks[blockIdx.x];
+  const float lam = a.lambda[ch.x];
+  for (int g = ch.y + threadIdx.x; g < ch.z; g += kBlock) {
+    float v[D];
+    ldv<D>(a.vel, g, v);
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[k] = lam * v[k];
+    stv<D>(a.vel, g, v);
   }
 }
 
@@ -787,7 +962,6 @@ __device__ __forceinline__ void vv_update(const ForceArgs& a, const Phys& P, int
                                           const float (&f)[D], double (&kin)[D + 1],
                                           const float (&o0_pre)[D], bool have_o0) {
   float vf[D];
-  const float lam = (a.mode == kModeStart && a.lambda) ? a.lambda[rep] : 1.f;
   const bool drift = (a.mode == kModeStep || a.mode == kModeStart);
   float on[D], vh[D];
   bool ok = true;
@@ -796,7 +970,7 @@ __device__ __forceinline__ void vv_update(const ForceArgs& a, const Phys& P, int
     if (a.mode == kModeStep || a.mode == kModeFinish)
       vf[k] = fmaf(P.half_dt, f[k], v[k]);
     else
-      vf[k] = lam * v[k];
+      vf[k] = v[k];
     vh[k] = fmaf(P.half_dt, f[k], vf[k]);
     on[k] = fmaf(vh[k], P.dt, o[k]);
     ok = ok && (on[k] >= P.lo) && (on[k] < P.hi);
@@ -1273,10 +1447,38 @@ __device__ __forceinline__ void nlist_brick(const NlistArgs& a) {
       s_cnt[threadIdx.x] = x - c;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < G.ntg; t += NT) {
-      int hxi, hyi, hzi, gi, vi;
-      brick_target<D>(G, L, t, hxi, hyi, hzi, gi, vi);
-      trec[atomicAdd(&s_cnt[63 - s_words[t]], 1)] = make_int2(gi, vi | ((int)s_words[t] << 16));
+    // stable within a bin (targets in brick order): a target's slot is its
+    // bin's start plus the targets of the bin before it, counted across the
+    // wave with ballots and across the waves in wave order
+    const int lane = lane_id(), wv = (int)threadIdx.x >> 6;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    for (int tb = 0; tb < G.ntg; tb += NT) {
+      const int t = tb + (int)threadIdx.x;
+      const bool valid = t < G.ntg;
+      const int bin = valid ? 63 - (int)s_words[t] : -1;
+      unsigned long long same = 0ull, act = __ballot(valid);
+      while (act) {
+        const int leader = __ffsll((long long)act) - 1;
+        const int lb = __shfl(bin, leader, 64);
+        const unsigned long long m = __ballot(valid && bin == lb) & act;
+        if (valid && bin == lb) same = m;
+        act &= ~m;
+      }
+      const bool lead = valid && (same & lt) == 0ull;
+      int b0 = 0;
+      for (int w = 0; w < NW; ++w) {
+        if (wv == w && lead) {
+          b0 = s_cnt[bin];
+          s_cnt[bin] = b0 + __popcll(same);
+        }
+        __syncthreads();
+      }
+      const int base = __shfl(b0, valid ? __ffsll((long long)same) - 1 : lane, 64);
+      if (valid) {
+        int hxi, hyi, hzi, gi, vi;
+        brick_target<D>(G, L, t, hxi, hyi, hzi, gi, vi);
+        trec[base + __popcll(same & lt)] = make_int2(gi, vi | ((int)s_words[t] << 16));
+      }
     }
   }
   if (threadIdx.x == 0) a.binfo[b] = make_int4(G.total, G.ntg, (fits && !s_over) ? 1 : 0, 0);
@@ -2086,6 +2288,14 @@ void launch_scan(const ScanArgs& a, hipStream_t s) {
 
 void launch_scatter(int D, int nchunks, const SortArgs& a, hipStream_t s) {
   MDLG_LAUNCH_DIM(D, k_scatter, nchunks, 0, s, a);
+}
+
+void launch_cellsort(int D, int nchunks, const CellsortArgs& a, hipStream_t s) {
+  MDLG_LAUNCH_DIM(D, k_cellsort, nchunks, 0, s, a);
+}
+
+void launch_rescale(int D, int nchunks, const RescaleArgs& a, hipStream_t s) {
+  MDLG_LAUNCH_DIM(D, k_rescale, nchunks, 0, s, a);
 }
 
 size_t brick_lds_bytes(const Phys& P, int D, bool adj) {

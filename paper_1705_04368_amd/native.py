@@ -22,7 +22,8 @@ EXPORTED = ["mdlg_describe", "mdlg_workspace_bytes", "mdlg_create", "mdlg_step",
             "mdlg_coarse_grain", "mdlg_get_f", "mdlg_get_kinetics", "mdlg_reset_accumulators",
             "mdlg_get_state", "mdlg_set_state", "mdlg_adjoint", "mdlg_set_potential",
             "mdlg_set_timing", "mdlg_get_timing", "mdlg_sync", "mdlg_last_error", "mdlg_destroy",
-            "mdlg_autotune", "mdlg_autotune_workspace_bytes", "mdlg_get_xi", "mdlg_get_shifts"]
+            "mdlg_autotune", "mdlg_autotune_workspace_bytes", "mdlg_get_xi", "mdlg_get_shifts",
+            "mdlg_checkpoint_bytes", "mdlg_checkpoint_save", "mdlg_checkpoint_load"]
 LOSSES = {"msd": 0, "mean_x": 1}
 KERNEL_CLASSES = ["force", "count", "scan", "scatter", "bin", "nlist", "xi", "shift", "adjoint"]
 
@@ -118,6 +119,12 @@ def load():
     lib.mdlg_get_shifts.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, P(C.c_int64)]
     lib.mdlg_get_xi.restype = st
     lib.mdlg_get_xi.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, P(C.c_int64)]
+    lib.mdlg_checkpoint_bytes.restype = st
+    lib.mdlg_checkpoint_bytes.argtypes = [C.c_void_p, P(C.c_size_t)]
+    lib.mdlg_checkpoint_save.restype = st
+    lib.mdlg_checkpoint_save.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+    lib.mdlg_checkpoint_load.restype = st
+    lib.mdlg_checkpoint_load.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
     lib.mdlg_autotune_workspace_bytes.restype = st
     lib.mdlg_autotune_workspace_bytes.argtypes = [P(MdlgConfig), P(C.c_size_t)]
     _lib = lib
@@ -353,6 +360,23 @@ class System:
         _check(load().mdlg_get_timing(self.handle, ms.ctypes.data_as(C.c_void_p),
                                       n.ctypes.data_as(C.c_void_p)), self.handle)
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def checkpoint(self):
+        """The complete state as a host byte array (mdlg_checkpoint_save)."""
+        lib = load()
+        b = C.c_size_t(0)
+        _check(lib.mdlg_checkpoint_bytes(self.handle, C.byref(b)), self.handle)
+        blob = np.zeros(int(b.value), dtype=np.uint8)
+        _check(lib.mdlg_checkpoint_save(self.handle, blob.ctypes.data_as(C.c_void_p), blob.size),
+               self.handle)
+        return blob
+
+    def restore(self, blob):
+        """Continue from a checkpoint of a system with the same configuration
+        (mdlg_checkpoint_load)."""
+        blob = np.ascontiguousarray(blob, dtype=np.uint8)
+        _check(load().mdlg_checkpoint_load(self.handle, blob.ctypes.data_as(C.c_void_p), blob.size),
+               self.handle)
 
     def reset_accumulators(self):
         _check(load().mdlg_reset_accumulators(self.handle), self.handle)

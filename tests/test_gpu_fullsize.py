@@ -128,6 +128,26 @@ def test_full_size_forces_and_binning(w):
     sysg.close()
 
 
+@pytest.mark.parametrize("steps", [10, 40])
+def test_full_size_2d_binning_other_lattice_steps(steps):
+    # the configuration's other lattice steps Delta t = 10 and 40 MD steps: one
+    # and four cell-list rebuilds per lattice step (at the automatic interval)
+    w = dict(W2, steps=steps)
+    say(f"full size 2D, Delta t = {steps} MD steps: autotune, two lattice steps")
+    cfg, pos, vel, box = _single(w)
+    sysg = _tuned_system(cfg, pos, vel)
+    s = sysg.layout["cell_side"]
+    sysg.coarse_grain(1)
+    sysg.reset_accumulators()
+    st0 = sysg.get_state()
+    sysg.coarse_grain(1)
+    st1 = sysg.get_state()
+    np.testing.assert_array_equal(st1["prev_ucell"], st1["ucell"])
+    _check_binning(sysg, unwrapped(st0, s), unwrapped(st1, s), [(0, w["n"], w["M"], 0)], 2,
+                   w["dx"], w["vmax"])
+    sysg.close()
+
+
 def test_full_size_2d_trajectory():
     w = W2
     say("full size 2D: 20-step trajectory against the oracle")
