@@ -177,6 +177,25 @@ mdlg_status mdlg_create(const mdlg_config *cfg, void *workspace_dev, size_t work
                         void *hip_stream, const float *pos_dev, const float *vel_dev,
                         mdlg_system **out);
 
+/* Size of the static workspace of mdlg_create_static. */
+#define MDLG_STATIC_WORKSPACE_BYTES ((size_t)32 << 20)
+
+/* mdlg_create without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  The workspace is a static device array of
+ * MDLG_STATIC_WORKSPACE_BYTES (32 MiB) that the library holds on each GPU it
+ * runs on until the process ends; the call allocates nothing.  Arguments and
+ * the rest of the lifetime are those of mdlg_create, on the device current on
+ * the calling thread (hip_stream must belong to it).  The array keeps the
+ * last handle's contents; creation clears what must start at zero.  Every
+ * handle made this way on one GPU would share that GPU's array, so only one
+ * may be alive per device: a second call before mdlg_destroy of the first
+ * returns MDLG_E_STATE instead of letting the two race.  MDLG_E_NOMEM when
+ * mdlg_workspace_bytes(cfg) exceeds the array (about 65,000 particles in 2D;
+ * use mdlg_create beyond that). */
+mdlg_status mdlg_create_static(const mdlg_config *cfg, void *hip_stream, const float *pos_dev,
+                               const float *vel_dev, mdlg_system **out);
+
 /* Advance n_md_steps velocity-Verlet steps (asynchronous).  With
  * thermostat_every > 0 the velocities of every replica are rescaled after
  * every that many steps so that sum m v^2 = kT dim (N_r - 1) (equilibration;

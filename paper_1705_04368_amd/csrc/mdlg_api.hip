@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -21,6 +22,20 @@ using namespace mdlg;
 namespace {
 
 thread_local std::string g_create_error = "no error";
+
+// The workspace of mdlg_create_static: one array per GPU the library runs on,
+// held until the process ends.  Host code never passes `scratch` itself to a
+// kernel (in host code it names a host-side stand-in): it takes the device
+// address from hipGetSymbolAddress once per device and uses that.
+constexpr size_t kStaticWorkspaceBytes = MDLG_STATIC_WORKSPACE_BYTES;
+static __device__ __align__(256) char scratch[kStaticWorkspaceBytes];
+
+struct StaticSlot {
+  void* ptr = nullptr;  // device address of `scratch` on this device
+  bool in_use = false;  // a handle created by mdlg_create_static is alive
+};
+std::mutex g_static_mu;
+std::map<int, StaticSlot> g_static;
 
 constexpr int kPartChunk = kPartChunkMax;  // particles per block of the per-particle kernels
 // lattice steps of up to kGraphMaxSteps MD steps replay as one graph; longer
@@ -497,6 +512,7 @@ struct mdlg_system {
   int mpar = 0;              // parity of the arrival counters the next rebuild uses
   bool first_sort = false;   // the state arrays hold an input in arbitrary order
   int xcd_remap = 1;
+  int static_dev = -1;  // device whose static workspace this handle holds (-1: none)
   bool use_graph = true;
   hipStream_t cap_stream = nullptr;
   // host-side sequencing state a captured graph starts from and leaves
@@ -1316,6 +1332,47 @@ mdlg_status mdlg_create(const mdlg_config* cfg, void* workspace_dev, size_t work
   return MDLG_OK;
 }
 
+mdlg_status mdlg_create_static(const mdlg_config* cfg, void* hip_stream, const float* pos_dev,
+                               const float* vel_dev, mdlg_system** out) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return MDLG_E_INVALID;
+  }
+  *out = nullptr;
+  size_t need = 0;
+  mdlg_status st = mdlg_workspace_bytes(cfg, &need);
+  if (st != MDLG_OK) return st;
+  if (need > kStaticWorkspaceBytes) {
+    g_create_error = "configuration needs a workspace of " + std::to_string(need) +
+                     " bytes; the static workspace holds " + std::to_string(kStaticWorkspaceBytes) +
+                     " (use mdlg_create with a workspace of that size)";
+    return MDLG_E_NOMEM;
+  }
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  StaticSlot& slot = g_static[dev];
+  if (slot.in_use) {
+    g_create_error = "the static workspace of device " + std::to_string(dev) +
+                     " is held by another handle (mdlg_destroy it first)";
+    return MDLG_E_STATE;
+  }
+  if (!slot.ptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
+    slot.ptr = p;
+  }
+  // mdlg_create clears every buffer that must start at zero (the array holds
+  // whatever the last handle left)
+  st = mdlg_create(cfg, slot.ptr, kStaticWorkspaceBytes, hip_stream, pos_dev, vel_dev, out);
+  if (st != MDLG_OK) return st;
+  slot.in_use = true;
+  (*out)->static_dev = dev;
+  return MDLG_OK;
+}
+
 mdlg_status mdlg_step(mdlg_system* S, int64_t n) {
   if (!S) return MDLG_E_INVALID;
   if (n < 0) {
@@ -2014,6 +2071,10 @@ void mdlg_destroy(mdlg_system* S) {
   drain_timing(S);
   for (hipEvent_t e : S->event_pool) (void)hipEventDestroy(e);
   if (S->cap_stream) (void)hipStreamDestroy(S->cap_stream);
+  if (S->static_dev >= 0) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static[S->static_dev].in_use = false;
+  }
   delete S;
 }
 

@@ -23,7 +23,8 @@ EXPORTED = ["mdlg_describe", "mdlg_workspace_bytes", "mdlg_create", "mdlg_step",
             "mdlg_get_state", "mdlg_set_state", "mdlg_adjoint", "mdlg_set_potential",
             "mdlg_set_timing", "mdlg_get_timing", "mdlg_sync", "mdlg_last_error", "mdlg_destroy",
             "mdlg_autotune", "mdlg_autotune_workspace_bytes", "mdlg_get_xi", "mdlg_get_shifts",
-            "mdlg_checkpoint_bytes", "mdlg_checkpoint_save", "mdlg_checkpoint_load"]
+            "mdlg_checkpoint_bytes", "mdlg_checkpoint_save", "mdlg_checkpoint_load",
+            "mdlg_create_static"]
 LOSSES = {"msd": 0, "mean_x": 1}
 KERNEL_CLASSES = ["force", "count", "scan", "scatter", "bin", "nlist", "xi", "shift", "adjoint"]
 
@@ -82,6 +83,9 @@ def load():
     lib.mdlg_create.restype = st
     lib.mdlg_create.argtypes = [P(MdlgConfig), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
                                 C.c_void_p, P(C.c_void_p)]
+    lib.mdlg_create_static.restype = st
+    lib.mdlg_create_static.argtypes = [P(MdlgConfig), C.c_void_p, C.c_void_p, C.c_void_p,
+                                       P(C.c_void_p)]
     lib.mdlg_step.restype = st
     lib.mdlg_step.argtypes = [C.c_void_p, C.c_int64]
     lib.mdlg_coarse_grain.restype = st
@@ -245,9 +249,10 @@ class System:
     """One MDLG system (one or many replicas) on the current HIP device.
 
     pos, vel: torch float32 device tensors of shape (n_total, dim) holding the
-    initial positions in [0, box) and velocities."""
+    initial positions in [0, box) and velocities.  static: take the library's
+    static device workspace (mdlg_create_static) instead of allocating one."""
 
-    def __init__(self, cfg, pos, vel, stream=None):
+    def __init__(self, cfg, pos, vel, stream=None, static=False):
         import torch
         lib = load()
         self.cfg = cfg
@@ -264,19 +269,24 @@ class System:
         if not pos.is_cuda or not vel.is_cuda:
             raise ValueError("positions and velocities must be device tensors")
         self.device = pos.device
-        nbytes = workspace_bytes(cfg)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.workspace.data_ptr()
-        aligned = (base + 255) & ~255
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
         self._pos = pos.contiguous()
         self._vel = vel.contiguous()
         h = C.c_void_p(0)
-        st = lib.mdlg_create(C.byref(cfg), C.c_void_p(aligned), C.c_size_t(nbytes),
-                             C.c_void_p(stream.cuda_stream), C.c_void_p(self._pos.data_ptr()),
-                             C.c_void_p(self._vel.data_ptr()), C.byref(h))
+        if static:
+            self.workspace = None
+            st = lib.mdlg_create_static(C.byref(cfg), C.c_void_p(stream.cuda_stream),
+                                        C.c_void_p(self._pos.data_ptr()),
+                                        C.c_void_p(self._vel.data_ptr()), C.byref(h))
+        else:
+            nbytes = workspace_bytes(cfg)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            aligned = (self.workspace.data_ptr() + 255) & ~255
+            st = lib.mdlg_create(C.byref(cfg), C.c_void_p(aligned), C.c_size_t(nbytes),
+                                 C.c_void_p(stream.cuda_stream), C.c_void_p(self._pos.data_ptr()),
+                                 C.c_void_p(self._vel.data_ptr()), C.byref(h))
         _check(st, None)
         self.handle = h
 
