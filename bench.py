@@ -1,5 +1,6 @@
 """Throughput of the MDLG hot path on one MI355X: particle-steps/s of LJ MD
-fused with MDLG binning.
+fused with MDLG binning, for the batched replica ensemble (the default) and
+its plain one-system-per-replica counterpart, or for one large system.
 
 One bench step is one lattice time step: md_steps_per_lattice_step MD steps
 (forces + velocity Verlet + periodic wrap + cell-list rebuilds) followed by
@@ -8,8 +9,10 @@ value = particles x MD steps / wall time over the timed lattice steps, with
 the state resident in HBM.  Inputs are seeded and synthetic (the paper's own
 MD trajectories are not available); see the workload table below.
 
-The JSON line also carries the roofline of the dominant kernel (event-timed
-per launch inside this run) and the FP64 oracle timed on the host cores.
+The JSON line also carries the roofline of the dominant kernel (its
+kernel-only time per launch measured with HIP events inside this run), every
+kernel class against its own bound, and the FP64 oracle timed on the host
+cores (one thread and all threads).
 """
 from __future__ import annotations
 
@@ -27,9 +30,17 @@ if ROOT not in sys.path:
 
 import numpy as np  # noqa: E402
 
+METRIC = "particle-steps/s (LJ MD + MDLG binning), batched vs plain; % of HBM/FP32 roofline"
+
 # Workloads: seeded synthetic stand-ins for the paper's LAMMPS runs, with
 # their sizes, densities, temperatures and lattice steps.
 WORKLOADS = {
+    "batched": dict(dim=2, n=None, M=None, dx=4.0, kT=1.0, dt=0.005, steps=20, vmax=3,
+                    replicas=512,
+                    desc="512 2D LJ replicas, N_r log-uniform in [1024, 65536] (seed 4; N_r = 8 M_r^2, "
+                         "8,251,320 particles), rho=0.5, kT=1, dt=0.005, 4 sigma lattice per replica, "
+                         "Delta t=20 MD steps, V=3 (Q=49); batched (one launch per kernel for all "
+                         "replicas) vs plain (one system per replica, launched one after another)"),
     "2d_scale": dict(dim=2, n=262144, M=181, dx=4.0, kT=1.0, dt=0.005, steps=20, vmax=3,
                      desc="2D LJ N=262144, 724 sigma box (rho=0.5), kT=1, dt=0.005, "
                           "181x181 lattice of 4 sigma, Delta t=20 MD steps, V=3 (Q=49)"),
@@ -43,12 +54,6 @@ WORKLOADS = {
                desc="2D hot dilute LJ gas N=100000, 1000 sigma box (rho=0.1), kT=50, dt=1e-4, "
                     "10x10 lattice of 100 sigma, Delta t=341600 MD steps (34.16 tau), V=3 (Q=49), "
                     "plus lattices drifting at u_x = -/+0.05 for theta_3"),
-    "batched": dict(dim=2, n=None, M=None, dx=4.0, kT=1.0, dt=0.005, steps=20, vmax=3,
-                    replicas=512,
-                    desc="512 2D LJ replicas, N_r log-uniform in [1024, 65536] (seed 4), rho=0.5, "
-                         "kT=1, dt=0.005, 4 sigma lattice per replica, Delta t=20 MD steps, V=3; "
-                         "batched (one launch per kernel for all replicas) vs plain (one system "
-                         "per replica, launched one after another)"),
 }
 
 # the adjoint of one MD window (gradients of the displacement moments): not a
@@ -58,7 +63,7 @@ ADJOINT = dict(dim=2, n=65536, M=90, dx=362.04 / 90, kT=1.0, dt=0.005, vmax=3, w
                             "one window of W=20 velocity-Verlet steps, checkpoints every 5 steps, "
                             "loss = per-axis mean squared displacement")
 
-PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector, published
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector, published (256 CUs x 2.4 GHz x 256 FLOP/clk)
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E, published
 FLOP_PER_PAIR = {2: 18, 3: 23}  # interacting pair: differences, r^2, rcp, LJ factor, accumulate
 
@@ -69,13 +74,12 @@ def pairs_per_particle(dim, rho, rc=2.5):
     return math.pi * rc * rc * rho if dim == 2 else 4.0 / 3.0 * math.pi * rc ** 3 * rho
 
 
-def force_bytes_per_particle(dim, rho, rl=None):
-    """Algorithmic HBM bytes per particle of one force/velocity-Verlet step:
-    read and write offset and velocity; on the pair-list path (list radius
-    rl) also the reference offset of the displacement check and the list,
-    2 bytes per neighbour within rl at uniform density.  Every neighbour
-    position is one of the offsets read, so a halo read more than once (LDS
-    staging of overlapping bricks) is overhead, not algorithmic."""
+def force_bytes_per_particle(dim, rho=None, rl=None):
+    """HBM bytes per particle of one force/velocity-Verlet step, reported
+    beside the FP32 bound: read and write offset and velocity; on the
+    pair-list path (list radius rl) also the reference offset of the
+    displacement check and the list, 2 bytes per neighbour within rl at
+    uniform density."""
     base = 16 * dim
     if rl is None:
         return base
@@ -90,21 +94,21 @@ ADJ_FLOP_PER_PAIR = {2: 44, 3: 59}
 
 
 def adjoint_bytes_per_particle(dim):
-    """Algorithmic HBM bytes per particle of one reverse step: read the
-    position and the adjoint velocity, read and write the adjoint position,
-    write the new adjoint velocity."""
+    """HBM bytes per particle of one reverse step: read the position and the
+    adjoint velocity, read and write the adjoint position, write the new
+    adjoint velocity."""
     return 4 * dim * 5
 
 
 def count_bytes_per_particle(dim):
-    """Algorithmic HBM bytes per particle of the counting pass of a cell-list
-    rebuild: read offset, image and cell; write the key/slot word."""
+    """HBM bytes per particle of the counting pass of a cell-list rebuild:
+    read offset, image and cell; write the key/slot word."""
     return 4 * dim * 2 + 4 + 8
 
 
 def scatter_bytes_per_particle(dim):
-    """Algorithmic HBM bytes per particle of the permutation pass: read the
-    key/slot word, offset, image, cell, velocity, id and the lattice snapshot
+    """HBM bytes per particle of the permutation pass: read the key/slot
+    word, offset, image, cell, velocity, id and the lattice snapshot
     (unwrapped cell, offset); write all of it at the new slot."""
     reads = 8 + 4 * dim * 2 + 4 + 4 * dim + 4 + 8 * dim
     writes = 4 * dim * 3 + 8 + 8 * dim
@@ -116,12 +120,21 @@ def scan_bytes_per_cell():
     return 12
 
 
+def sort_bytes(dim, n, cells):
+    """Algorithmic bytes of one cell-list rebuild as a unit: keys written and
+    read (2 x 4 B) and the payload read and written (2P) per particle, with
+    P = offset + cell + velocity + image + id and the permuted lattice
+    snapshot (unwrapped cell, offset): 48 B in 2D, 68 B in 3D; 12 B per cell."""
+    payload = 48 if dim == 2 else 68
+    return n * (8 + 2 * payload) + 12 * cells
+
+
 def bin_bytes_per_particle(dim, q, nm, per_site_particles):
-    """Algorithmic HBM bytes per particle of one binning pass: read offset,
-    image, id, cell; gather and write back the snapshot (unwrapped cell and
-    offset, by id); per site one read-modify-write of the Q counters and the
-    moment accumulators, shared by the particles of the site."""
-    per_particle = 4 * dim * 2 + 8 + 2 * (8 * dim)
+    """Algorithmic bytes per particle of one binning pass: read offset, image
+    and cell, read and write the lattice snapshot (unwrapped cell and offset);
+    per site one read-modify-write of the Q counters and the moment
+    accumulators, shared by the particles of the site."""
+    per_particle = 4 * dim * 2 + 4 + 2 * (8 * dim)
     per_site = 2 * 4 * q + 2 * 8 * nm
     return per_particle + per_site / per_site_particles
 
@@ -249,27 +262,102 @@ def e1_analysis(sysg, w):
     return out
 
 
-def cpu_baseline(w, pos, vel, lattice_steps):
-    """The FP64 oracle, single-threaded on the host, on a bounded sample: the
-    full system for `lattice_steps` lattice steps from the same initial state."""
+def host_cpu():
+    """Host CPU model and the cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
+
+
+def _oracle_lattice_step(task):
+    """One lattice step of the FP64 oracle on one system: Delta t MD steps and
+    the binning (the state's forces are evaluated when it is built)."""
+    st, lat, steps = task
+    st.mdlg(lat, steps, 1)
+
+
+def cpu_baseline_single(w, x, v, box, M, lattice_steps):
+    """The FP64 oracle, one thread, on the full system for `lattice_steps`
+    lattice steps from the given (warmed-up) state."""
     import oracle
-    dim, n = w["dim"], w["n"]
-    box = w["M"] * w["dx"]
-    md = oracle.make_md(dim, n, box, dt=w["dt"])
-    st = oracle.OracleState(md, pos, vel)
-    lat = oracle.make_lattice(dim, (w["M"],) * dim, w["dx"], w["vmax"])
+    dim, n = w["dim"], x.shape[0]
+    st = oracle.OracleState(oracle.make_md(dim, n, box, dt=w["dt"]), x, v)
+    lat = oracle.make_lattice(dim, (M,) * dim, w["dx"], w["vmax"])
     t0 = time.perf_counter()
     st.mdlg(lat, w["steps"], lattice_steps)
     t = time.perf_counter() - t0
+    model, _ = host_cpu()
     return {"value": n * w["steps"] * lattice_steps / t, "unit": "particle-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"full system, {lattice_steps} lattice steps ({lattice_steps * w['steps']} MD "
-                      f"steps + binning), FP64 single thread, {t:.1f} s"}
+            "kind": "oracle", "cpu": model,
+            "sample": f"full system from the warmed-up state, {lattice_steps} lattice steps "
+                      f"({lattice_steps * w['steps']} MD steps + binning), FP64, one thread, {t:.1f} s"}
+
+
+def cpu_baseline_ensemble(w, xs, vs, m_r, single_target=400000, threads=None):
+    """The FP64 oracle on replicas of the ensemble from the warmed-up state,
+    one lattice step (Delta t MD steps + binning) each: on one thread over a
+    seeded subset of about `single_target` particles, and on every host core
+    available (one replica per task, a thread pool: the oracle's C calls run
+    outside the interpreter lock) over all replicas."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    model, avail = host_cpu()
+    cores = threads or min(16, avail)
+    dim, steps = w["dim"], w["steps"]
+
+    def build(r):
+        m = int(m_r[r])
+        md = oracle.make_md(dim, xs[r].shape[0], w["dx"] * m, dt=w["dt"])
+        return (oracle.OracleState(md, xs[r], vs[r]),
+                oracle.make_lattice(dim, (m,) * dim, w["dx"], w["vmax"]), steps)
+
+    order = np.random.default_rng(7).permutation(len(xs))
+    sub, tot = [], 0
+    for r in order:
+        if tot >= single_target:
+            break
+        sub.append(int(r))
+        tot += xs[r].shape[0]
+    tasks = [build(r) for r in sub]
+    t0 = time.perf_counter()
+    for t in tasks:
+        _oracle_lattice_step(t)
+    t1 = time.perf_counter() - t0
+    single = {"value": tot * steps / t1, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+              "cpu": model,
+              "sample": f"{len(sub)} replicas (seeded subset, {tot} particles), one lattice step "
+                        f"each ({steps} MD steps + binning), FP64, one thread, {t1:.1f} s"}
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        # largest replicas first for balance
+        big = sorted(range(len(xs)), key=lambda r: -xs[r].shape[0])
+        tasks = list(ex.map(build, big))
+        ntot = sum(xs[r].shape[0] for r in big)
+        t0 = time.perf_counter()
+        list(ex.map(_oracle_lattice_step, tasks))
+        t2 = time.perf_counter() - t0
+    return {"value": ntot * steps / t2, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+            "cpu": model, "cores_available": avail,
+            "sample": f"all {len(xs)} replicas ({ntot} particles), one lattice step each ({steps} MD "
+                      f"steps + binning), FP64, {cores} threads, {t2:.1f} s",
+            "single_thread": single}
 
 
 def equilibrated_state(sysg, cfg):
     """Positions in [0, box) and velocities of a system, in particle order
-    (host float32), to start another system from the same state."""
+    (host float32), to start another system from about the same state (the
+    float32 absolute position rounds the offset inside the cell)."""
     st = sysg.get_state()
     s = sysg.layout["cell_side"]
     k = sysg.layout["md_cell_split"]
@@ -283,34 +371,67 @@ def equilibrated_state(sysg, cfg):
     return np.ascontiguousarray(x32), np.ascontiguousarray(st["vel"].astype(np.float32))
 
 
-def plain_replicas(sysg, cfg, n_r, m_r, w, dev, lattice_steps):
+def replica_fi(f_site, m_r):
+    """Per replica, f_i = mean n_i per site and lattice step, from the per-site
+    time averages; and the replicas' site counts."""
+    sites = m_r.astype(np.int64) ** 2
+    off = np.concatenate([[0], np.cumsum(sites)[:-1]])
+    return np.add.reduceat(f_site, off, axis=0) / sites[:, None], sites
+
+
+def ensemble_mean_se(fr, w):
+    """Site-weighted mean of the replicas' f_i (the ensemble f_i of eq. fieq)
+    and its standard error from the spread of the replicas."""
+    W = float(w.sum())
+    mean = (w[:, None] * fr).sum(axis=0) / W
+    R = len(w)
+    var = (w[:, None] ** 2 * (fr - mean) ** 2).sum(axis=0) / W ** 2 * R / (R - 1)
+    return mean, np.sqrt(var)
+
+
+def compare_fi(fa, sea, fb, seb, counts_min):
+    """z of every bin whose expected count is at least 100 in both runs; the
+    Sidak-adjusted 1% threshold over those bins."""
+    from scipy.stats import norm
+    tested = (counts_min >= 100) & ((sea > 0) | (seb > 0))
+    z = (fa - fb)[tested] / np.sqrt(sea[tested] ** 2 + seb[tested] ** 2)
+    m = int(tested.sum())
+    thr = float(norm.isf((1 - 0.99 ** (1.0 / max(m, 1))) / 2))
+    return {"bins_tested": m, "max_abs_z": float(np.abs(z).max()) if m else 0.0,
+            "within_3se": int((np.abs(z) <= 3).sum()), "sidak_threshold": thr,
+            "agree": bool(m > 0 and np.abs(z).max() < thr and (np.abs(z) <= 3).mean() >= 0.9)}
+
+
+def plain_replicas(lay, n_r, m_r, w, dev, state, lattice_steps):
     """The same ensemble as one system per replica, launched one after the
-    other (each replica's lattice step is its own graph of launches).  The
-    replicas start from the batched system's equilibrated state."""
+    other (each replica's lattice step is its own graph of launches), with the
+    batched run's layout (MD-cell split, rebuild interval, brick, block size),
+    from `state` (the batched run's, in particle order, imported exactly).
+    Returns the throughput and the per-replica f_i."""
     import torch
 
     from paper_1705_04368_amd import System, make_config
-    st = sysg.get_state()
-    k = sysg.layout["md_cell_split"]
-    systems = []
+    systems, blobs = [], []
     off = 0
+    s = lay["cell_side"]
+    k = lay["md_cell_split"]
     for nr, mr in zip(n_r, m_r):
         nr, mr = int(nr), int(mr)
         c = make_config(2, nr, mr, lattice_dx=w["dx"], dt=w["dt"], md_steps_per_lattice_step=w["steps"],
-                        vmax=w["vmax"], kT=w["kT"], md_cell_split=k, sort_every=sysg.layout["sort_every"],
-                        pair_list=sysg.layout["pair_slots"] > 0)
+                        vmax=w["vmax"], kT=w["kT"], md_cell_split=k, sort_every=lay["sort_every"],
+                        brick=lay["brick"], block_threads=lay["block_threads"],
+                        pair_list=lay["pair_slots"] > 0)
         sl = slice(off, off + nr)
-        s = sysg.layout["cell_side"]
-        x = (np.mod(st["ucell"][sl], mr * k).astype(np.float64) * s + st["off"][sl]).astype(np.float32)
+        x = (np.mod(state["ucell"][sl], mr * k).astype(np.float64) * s + state["off"][sl]).astype(np.float32)
         x = np.where(x >= np.float32(mr * k * s), np.float32(0.0), x)
-        r = System(c, torch.from_numpy(x).to(dev), torch.from_numpy(st["vel"][sl].copy()).to(dev))
+        r = System(c, torch.from_numpy(x).to(dev), torch.from_numpy(state["vel"][sl].copy()).to(dev))
+        r.set_state(state["ucell"][sl], state["off"][sl], state["vel"][sl])
+        blobs.append(r.checkpoint())
         systems.append(r)
         off += nr
-    for r in systems:  # warm-up: captures each replica's lattice-step graph
+    for r, b in zip(systems, blobs):  # capture each replica's graph, then back to the start
         r.coarse_grain(1)
-    for r in systems:
-        r.sync()
-        r.reset_accumulators()
+        r.restore(b)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(lattice_steps):
@@ -321,15 +442,79 @@ def plain_replicas(sysg, cfg, n_r, m_r, w, dev, lattice_steps):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     n = int(np.sum(n_r))
-    counts = sum(r.get_f()["counts"] for r in systems)
-    sites = int(np.sum(m_r.astype(np.int64) ** 2))
-    q = len(counts)
-    f0 = float(counts[(q - 1) // 2]) / (lattice_steps * sites) / 8.0
+    fr = np.stack([r.get_f()["counts"].astype(np.float64) for r in systems])
+    fr /= lattice_steps * (m_r.astype(np.float64) ** 2)[:, None]
     for r in systems:
         r.close()
     return {"value": n * lattice_steps * w["steps"] / el, "unit": "particle-steps/s",
             "lattice_steps": lattice_steps, "ms_per_step": el / lattice_steps * 1e3,
-            "f0_plain": f0}
+            "layout": "the batched run's"}, fr
+
+
+def kernel_table(tim, dim, n, rho, lay, n_sites):
+    """Per kernel class: the kernel-only time per launch (HIP events recorded
+    around each kernel by its launch) and the kernel against its own bound:
+    the force kernel (and the adjoint's reverse step) on the FP32 vector
+    units, with the FLOPs of the interacting pairs; the rebuild passes, the
+    pair-list builder and the binning on HBM, with their algorithmic bytes."""
+    q, nm = lay["n_velocities"], lay["n_moments"]
+    per_site = n / n_sites
+    kernels = {}
+
+    def alu(flops, avg):
+        tf = flops / (avg * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": tf / PEAK_FP32_TFLOPS, "work_per_launch": flops}
+
+    def hbm(nbytes, avg):
+        gb = nbytes / (avg * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": gb, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": gb / PEAK_HBM_GBS, "work_per_launch": nbytes}
+
+    for k, (ms, cnt) in tim.items():
+        if cnt == 0:
+            continue
+        avg = ms / cnt
+        e = {"avg_ms": avg, "launches": cnt}
+        if k == "force":
+            e.update(alu(n * pairs_per_particle(dim, rho) * FLOP_PER_PAIR[dim], avg))
+            rl = 2.5 + 2 * lay["skin"] if lay["pair_slots"] > 0 else None
+            hb = n * force_bytes_per_particle(dim, rho, rl)
+            e["hbm_bytes_per_launch"] = hb
+            e["hbm_GBs"] = hb / (avg * 1e-3) / 1e9
+        elif k == "count":
+            e.update(hbm(n * count_bytes_per_particle(dim), avg))
+        elif k == "scatter":
+            e.update(hbm(n * scatter_bytes_per_particle(dim), avg))
+        elif k == "scan":
+            e.update(hbm(scan_bytes_per_cell() * lay["n_cells"], avg))
+        elif k == "nlist":
+            # read the offsets, write the lists (16-bit entries within
+            # r_cut + 2 margin), the target records and the reference offsets
+            rl = 2.5 + 2 * lay["skin"]
+            vol = math.pi * rl * rl if dim == 2 else 4.0 / 3.0 * math.pi * rl ** 3
+            e.update(hbm(n * (4 * dim + 2 * vol * rho + 8 + 4 * dim), avg))
+        elif k == "shift":
+            e.update(hbm(n * (4 + 16 * dim), avg))
+        elif k == "xi":
+            e.update(hbm(n_sites * q * (4 + 4 + 16 + 4), avg))
+        elif k == "bin":
+            e.update(hbm(n * bin_bytes_per_particle(dim, q, nm, per_site), avg))
+        elif k == "adjoint":
+            e.update(alu(n * pairs_per_particle(dim, rho) * ADJ_FLOP_PER_PAIR[dim], avg))
+        kernels[k] = e
+    sort_unit = None
+    if all(k in kernels for k in ("count", "scan", "scatter")):
+        t = sum(kernels[k]["avg_ms"] for k in ("count", "scan", "scatter"))
+        nbytes = sort_bytes(dim, n, lay["n_cells"])
+        gb = nbytes / (t * 1e-3) / 1e9
+        sort_unit = {"avg_ms": t, "bound": "hbm", "achieved": gb, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": gb / PEAK_HBM_GBS, "work_per_launch": nbytes}
+    return kernels, sort_unit
+
+
+def _r6(d):
+    return {k: (round(v, 6) if isinstance(v, float) else v) for k, v in d.items()}
 
 
 def bench_adjoint(args):
@@ -386,28 +571,8 @@ def bench_adjoint(args):
     tim = sysg.get_timing()
     sysg.set_timing(False)
     rho = n / box ** dim
-    kernels = {}
-    for k, (ms, cnt) in tim.items():
-        if cnt == 0:
-            continue
-        avg = ms / cnt
-        if k == "adjoint":
-            work = n * adjoint_bytes_per_particle(dim)
-            flops = n * pairs_per_particle(dim, rho) * ADJ_FLOP_PER_PAIR[dim]
-        elif k == "force":
-            # forward and recomputed steps of the window: cell walk, no lists
-            work = n * force_bytes_per_particle(dim, rho, None)
-            flops = n * pairs_per_particle(dim, rho) * FLOP_PER_PAIR[dim]
-        else:
-            continue
-        ach = work / (avg * 1e-3) / 1e9
-        tf = flops / (avg * 1e-3) / 1e12
-        kernels[k] = {"avg_ms": round(avg, 6), "launches": cnt, "bound": "hbm",
-                      "achieved": round(ach, 6), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                      "frac": round(ach / PEAK_HBM_GBS, 6), "work_per_launch": work,
-                      "flop_per_launch": flops, "flop_achieved": round(tf, 6),
-                      "flop_peak": PEAK_FP32_TFLOPS, "flop_frac": round(tf / PEAK_FP32_TFLOPS, 6),
-                      "flop_unit": "TFLOP/s"}
+    kernels, _ = kernel_table(tim, dim, n, rho, sysg.layout, 1)
+    kernels = {k: v for k, v in kernels.items() if k in ("adjoint", "force")}
     kd = kernels["adjoint"]
     roofline = {"kernel": "adjoint", "bound": kd["bound"], "achieved": kd["achieved"],
                 "peak": kd["peak"], "unit": kd["unit"], "frac": kd["frac"],
@@ -427,6 +592,7 @@ def bench_adjoint(args):
             oracle.adjoint(md, x, st["vel"].astype(np.float64), W, "msd")
         tc = time.perf_counter() - t0
         cpu = {"value": n * W * reps / tc, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+               "cpu": host_cpu()[0],
                "sample": f"full system, {reps} windows of W={W} (forward + reverse), FP64 single "
                          f"thread, {tc:.1f} s"}
     out = {
@@ -441,7 +607,7 @@ def bench_adjoint(args):
         "cpu_baseline": cpu,
         "adjoint": {"ms_per_window": adj * 1e3, "forward_ms_per_window": fwd * 1e3,
                     "gradient_over_forward": adj / fwd},
-        "kernels": kernels,
+        "kernels": {k: _r6(v) for k, v in kernels.items()},
     }
     print(json.dumps(out), flush=True)
 
@@ -451,18 +617,22 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50, help="timed lattice steps")
     ap.add_argument("--warmup", type=int, default=5, help="untimed lattice steps")
-    ap.add_argument("--workload", default="2d_scale", choices=sorted(WORKLOADS) + ["adjoint"])
+    ap.add_argument("--workload", default="batched", choices=sorted(WORKLOADS) + ["adjoint"])
     ap.add_argument("--equilibrate", type=int, default=2000, help="thermostatted MD steps")
     ap.add_argument("--timing-steps", type=int, default=10,
                     help="lattice steps of the event-timed per-kernel pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-lattice-steps", type=int, default=4,
-                    help="lattice steps of the oracle timed on the host (about 12 s at 2d_scale)")
-    ap.add_argument("--plain-steps", type=int, default=3,
+                    help="lattice steps of the oracle on one system (about 12 s at 2d_scale)")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the ensemble's oracle baseline (0 = every core available, at most 16)")
+    ap.add_argument("--plain-steps", type=int, default=10,
                     help="lattice steps timed for the plain (one system per replica) path")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain path of the ensemble")
     ap.add_argument("--sort-every", type=int, default=0, help="rebuild interval (0 = automatic)")
     ap.add_argument("--md-cell-split", type=int, default=0, help="MD cells per lattice cell (0 = auto)")
     ap.add_argument("--brick", type=int, nargs=3, default=(0, 0, 0), help="force brick (0 = auto)")
+    ap.add_argument("--block-threads", type=int, default=0, help="threads per force block (0 = auto)")
     ap.add_argument("--no-pair-list", action="store_true",
                     help="walk the neighbour cells at every MD step instead of using pair lists")
     ap.add_argument("--collision-stats", action="store_true",
@@ -512,7 +682,7 @@ def main():
     dim = w["dim"]
     tuning = dict(sort_every=args.sort_every, pair_list=not args.no_pair_list,
                   md_cell_split=args.md_cell_split, brick=tuple(args.brick),
-                  collision_stats=args.collision_stats)
+                  block_threads=args.block_threads, collision_stats=args.collision_stats)
     if args.workload == "e1":
         sh = np.zeros((2, 2, dim))
         sh[0, 1, 0], sh[1, 1, 0] = -E1_DU, E1_DU
@@ -524,7 +694,8 @@ def main():
         sh[:, 1, 0] = us
         tuning["shifts"] = sh
     dev = torch.device("cuda:0")
-    if w.get("replicas"):
+    ensemble = bool(w.get("replicas"))
+    if ensemble:
         n_r, m_r = synth.replica_sizes(w["replicas"], seed=4)
         seeds = synth.replica_seeds(w["replicas"], seed=4)
         parts = [synth.lj_initial_state(dim, int(nr), w["dx"] * int(mr), w["kT"], seed=sd)
@@ -532,7 +703,6 @@ def main():
         pos = np.concatenate([p for p, _ in parts])
         vel = np.concatenate([v for _, v in parts])
         n = int(n_r.sum())
-        M = None
         rho = 0.5
         lattice = np.stack([m_r, m_r], axis=1)
         n_sites = int((m_r.astype(np.int64) ** 2).sum())
@@ -570,6 +740,9 @@ def main():
     sysg.coarse_grain(args.warmup)
     sysg.sync()
     sysg.reset_accumulators()
+    # the state the timed run starts from (the plain path and the oracle
+    # start from it too); reading it does not perturb the trajectory
+    start = sysg.get_state()
     print(f"# warmed up ({args.warmup} lattice steps)", file=sys.stderr, flush=True)
 
     # the K timed lattice steps run as five consecutive chunks with HIP events
@@ -581,10 +754,10 @@ def main():
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(nch + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    evs[0].record()
+    evs[0].record(sysg.stream)
     for i, k in enumerate(sizes):
         sysg.coarse_grain(k)
-        evs[i + 1].record()
+        evs[i + 1].record(sysg.stream)
     sysg.sync()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -595,123 +768,74 @@ def main():
     repeats = {"chunks": nch, "lattice_steps": sizes, "values": chunk_values,
                "median": float(np.median(chunk_values))}
     print(f"# timed {args.steps} lattice steps in {elapsed:.4f} s", file=sys.stderr, flush=True)
-    f = sysg.get_f()
+    f = sysg.get_f(per_site=ensemble)
     assert f["counts"].sum() + f["n_overflow"] == n * f["n_lattice_steps"]
 
-    # per-kernel event timing over a separate pass of the same lattice steps
+    # kernel-only times per launch over a separate pass of the same lattice steps
     sysg.set_timing(True)
     sysg.coarse_grain(args.timing_steps)
     tim = sysg.get_timing()
     sysg.set_timing(False)
     print(f"# event-timed {args.timing_steps} lattice steps", file=sys.stderr, flush=True)
-    q, nm = lay["n_velocities"], lay["n_moments"]
-    per_site = n / n_sites
-    kernels = {}
-    for k, (ms, cnt) in tim.items():
-        if cnt == 0:
-            continue
-        avg = ms / cnt
-        if k == "force":
-            # arithmetic intensity (interacting-pair FLOPs over algorithmic
-            # bytes) of 2-5 FLOP/byte, far below the ridge point of 157.3 /
-            # 8 ~ 20: HBM is the bound; the FLOP rate is reported beside it
-            rl = 2.5 + 2 * lay["margin"] if lay["pair_slots"] > 0 else None
-            work = n * force_bytes_per_particle(dim, rho, rl)
-            ach = work / (avg * 1e-3) / 1e9
-            flops = n * pairs_per_particle(dim, rho) * FLOP_PER_PAIR[dim]
-            tf = flops / (avg * 1e-3) / 1e12
-            kernels[k] = {"avg_ms": avg, "launches": cnt, "bound": "hbm", "achieved": ach,
-                          "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-                          "work_per_launch": work, "flop_per_launch": flops,
-                          "flop_achieved": tf, "flop_peak": PEAK_FP32_TFLOPS,
-                          "flop_frac": tf / PEAK_FP32_TFLOPS, "flop_unit": "TFLOP/s"}
-        elif k in ("count", "scatter", "scan"):
-            if k == "scan":
-                work = scan_bytes_per_cell() * lay["n_cells"]
-            elif k == "count":
-                work = n * count_bytes_per_particle(dim)
-            else:
-                work = n * scatter_bytes_per_particle(dim)
-            ach = work / (avg * 1e-3) / 1e9
-            kernels[k] = {"avg_ms": avg, "launches": cnt, "bound": "hbm", "achieved": ach,
-                          "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-                          "work_per_launch": work}
-        elif k == "nlist":
-            # read the offsets, write the lists (16-bit entries within
-            # r_cut + 2 margin), the target records and the reference offsets
-            rl = 2.5 + 2 * lay["margin"]
-            vol = math.pi * rl * rl if dim == 2 else 4.0 / 3.0 * math.pi * rl ** 3
-            work = n * (4 * dim + 2 * vol * rho + 8 + 4 * dim)
-            ach = work / (avg * 1e-3) / 1e9
-            kernels[k] = {"avg_ms": avg, "launches": cnt, "bound": "hbm", "achieved": ach,
-                          "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-                          "work_per_launch": work}
-        elif k == "shift":
-            # per particle: cell, image, offset and the snapshot (cell, offset)
-            work = n * (4 + 16 * dim)
-            ach = work / (avg * 1e-3) / 1e9
-            kernels[k] = {"avg_ms": avg, "launches": cnt, "bound": "hbm", "achieved": ach,
-                          "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-                          "work_per_launch": work}
-        elif k == "xi":
-            # per (site, bin): n_i(x, t), the shifted n_i(x + v_i, t + 1), the
-            # running sum (read and write) and the latest value
-            work = n_sites * q * (4 + 4 + 16 + 4)
-            ach = work / (avg * 1e-3) / 1e9
-            kernels[k] = {"avg_ms": avg, "launches": cnt, "bound": "hbm", "achieved": ach,
-                          "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-                          "work_per_launch": work}
-        elif k == "bin":
-            work = n * bin_bytes_per_particle(dim, q, nm, per_site)
-            ach = work / (avg * 1e-3) / 1e9
-            kernels[k] = {"avg_ms": avg, "launches": cnt, "bound": "hbm", "achieved": ach,
-                          "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-                          "work_per_launch": work}
-    if all(k in kernels for k in ("count", "scan", "scatter")):
-        # the rebuild as one unit: its bytes over the summed kernel times
-        work = sum(kernels[k]["work_per_launch"] for k in ("count", "scan", "scatter"))
-        t = sum(kernels[k]["avg_ms"] for k in ("count", "scan", "scatter"))
-        ach = work / (t * 1e-3) / 1e9
-        sort_unit = {"avg_ms": t, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": ach / PEAK_HBM_GBS, "work_per_launch": work}
-    else:
-        sort_unit = None
+    kernels, sort_unit = kernel_table(tim, dim, n, rho, lay, n_sites)
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     kd = kernels[dom]
     roofline = {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
-                "unit": kd["unit"], "frac": kd["frac"],
-                "traffic": load_traffic(args.workload, dom)}
+                "unit": kd["unit"], "frac": kd["frac"], "traffic": load_traffic(args.workload, dom)}
 
     plain = None
-    if w.get("replicas"):
-        plain = plain_replicas(sysg, cfg, n_r, m_r, w, dev, args.plain_steps)
-        plain["batched_over_plain"] = value / plain["value"]
-        plain["f0_batched"] = float(f["f"][(q - 1) // 2]) / 8.0
+    fi = None
+    if ensemble:
+        fr_b, sites = replica_fi(f["f_site"], m_r)
+        fb, seb = ensemble_mean_se(fr_b, sites)
+        rho_site = n / n_sites
+        fi = {"f_i_over_rho_rest_axis_diag": [float(fb[24] / rho_site), float(fb[25] / rho_site),
+                                              float(fb[32] / rho_site)],
+              "replicas": int(len(m_r)), "lattice_steps": int(f["n_lattice_steps"])}
+        if not args.no_plain:
+            print(f"# plain path ({len(m_r)} systems, {args.plain_steps} lattice steps)",
+                  file=sys.stderr, flush=True)
+            plain, fr_p = plain_replicas(lay, n_r, m_r, w, dev, start, args.plain_steps)
+            plain["batched_over_plain"] = value / plain["value"]
+            fp, sep = ensemble_mean_se(fr_p, sites)
+            cmin = np.minimum(fb * n_sites * f["n_lattice_steps"], fp * n_sites * args.plain_steps)
+            plain["f_i_batched_vs_plain"] = compare_fi(fb, seb, fp, sep, cmin)
 
     cpu = None
-    if not args.no_cpu_baseline and not w.get("replicas") and args.workload != "e1":
+    if not args.no_cpu_baseline and args.workload != "e1":
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(w, pos, vel, args.cpu_lattice_steps)
+        s = lay["cell_side"]
+        k = lay["md_cell_split"]
+        if ensemble:
+            mc = np.repeat(lattice * k, n_r, axis=0)
+            xw = np.mod(start["ucell"], mc).astype(np.float64) * s + start["off"].astype(np.float64)
+            bounds = np.concatenate([[0], np.cumsum(n_r)])
+            xs = [xw[bounds[r]:bounds[r + 1]] for r in range(len(n_r))]
+            vs = [start["vel"][bounds[r]:bounds[r + 1]].astype(np.float64) for r in range(len(n_r))]
+            cpu = cpu_baseline_ensemble(w, xs, vs, m_r, threads=args.cpu_threads or None)
+        else:
+            xw = np.mod(start["ucell"], w["M"] * k).astype(np.float64) * s + start["off"].astype(np.float64)
+            cpu = cpu_baseline_single(w, xw, start["vel"].astype(np.float64), w["M"] * w["dx"], w["M"],
+                                      args.cpu_lattice_steps)
 
     out = {
-        "metric": "particle-steps/s (LJ MD + MDLG binning)",
+        "metric": METRIC if ensemble else "particle-steps/s (LJ MD + MDLG binning)",
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w["desc"], "lattice_steps": args.steps, "md_steps": md_steps,
-                   "md_cell_split": lay["md_cell_split"], "sort_every": lay["sort_every"],
-                   "brick": list(lay["brick"]), "pair_slots": lay["pair_slots"],
-                   "autotuned": tuned_ms is not None, "collision_stats": args.collision_stats,
-                   "galilean_lattices": args.galilean},
+                   "particles": n, "md_cell_split": lay["md_cell_split"], "sort_every": lay["sort_every"],
+                   "brick": list(lay["brick"]), "block_threads": lay["block_threads"],
+                   "pair_slots": lay["pair_slots"], "autotuned": tuned_ms is not None,
+                   "collision_stats": args.collision_stats, "galilean_lattices": args.galilean},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "repeats": repeats,
         "plain": plain,
-        "kernels": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
-                    for k, v in kernels.items()},
-        "sort": None if sort_unit is None else {kk: (round(vv, 6) if isinstance(vv, float) else vv)
-                                                for kk, vv in sort_unit.items()},
+        "f_i": fi,
+        "kernels": {k: _r6(v) for k, v in kernels.items()},
+        "sort": None if sort_unit is None else _r6(sort_unit),
     }
     if args.workload == "e1":
         print("# e1 analysis", file=sys.stderr, flush=True)

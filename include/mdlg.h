@@ -152,10 +152,12 @@ typedef struct {
     int64_t n_cells;            /* MD cells over all replicas */
     int64_t n_bricks;           /* force-kernel work units per MD step */
     double cell_side;           /* s */
-    double margin;              /* allowed excursion outside the cell between rebuilds, and
-                                   the largest displacement between pair-list builds */
+    double margin;              /* allowed excursion outside the cell between rebuilds */
     int32_t pair_slots;         /* pair-list entries per particle (0 = no pair lists) */
     int32_t block_threads;      /* threads per force / pair-list block actually used */
+    double skin;                /* pair lists hold the pairs within r_cut + 2 skin; a particle
+                                   that moves farther since the lists were built is a device
+                                   error (currently skin = margin) */
 } mdlg_layout;
 
 /* Validate cfg and report the derived layout.  Host only.  MDLG_E_INVALID on

@@ -59,6 +59,7 @@ struct Layout {
   std::vector<Replica> reps;
   std::vector<int4> bricks, chunks, cchunks, strips;
   double s = 0, margin = 0, margin_max = 0;
+  double skin = 0;     // pair-list skin: lists of radius r_cut + 2 skin
   int sort_every = 1;
   int halo_cells = 0;  // halo cells of the largest force brick
   int lcap = 0;        // staged particles per LDS chunk of a force brick
@@ -218,13 +219,18 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   // canonicalise offsets with it); the box side is Mc * s
   L->s = (double)(float)(c->lattice_dx / k);
   L->ns = (int)std::ceil(c->r_cut / L->s - 1e-12);
+  if (L->ns > 7)
+    return set_err(msg, "MD cells of side %g are too small for r_cut %g (stencil half-width %d > 7)",
+                   L->s, c->r_cut, L->ns);
   // largest excursion outside the cell that the stencil still covers
   const double m_max = (L->ns * L->s - c->r_cut) / 2;
   if (min_m * k < 2 * L->ns + 1)
     return set_err(msg, "too few MD cells per axis (%d) for the stencil half-width %d", min_m * k, L->ns);
   // rebuild interval and the margin it needs: eight standard deviations of
-  // the Maxwell speed per axis times the interval (the kernel checks the bound)
+  // the Maxwell speed per axis times the interval (the kernel checks the
+  // bound, and a particle beyond it is an error)
   const double vfast = c->kT > 0 ? 8.0 * std::sqrt(c->kT / c->mass) : 0.0;
+
   // with pair lists the margin also widens every list (radius r_cut + 2 m),
   // so the automatic interval aims at m <= 0.16 r_cut instead of the largest
   // margin the stencil allows
@@ -250,6 +256,9 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   L->margin_max = m_max;
   L->margin = (vfast > 0) ? std::min(m_max, R * vfast * c->dt) : m_max;
   if (L->margin < 0) L->margin = 0;
+  // the pair lists' skin is the margin: a particle moving farther since the
+  // lists were built is reported (a device error)
+  L->skin = L->margin;
   // a particle then sits less than one cell outside its own (the pair-list
   // builder's coordinate range relies on it)
   if (L->margin >= L->s) return set_err(msg, "rebuild margin %g reaches the cell side %g", L->margin, L->s);
@@ -323,14 +332,14 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   L->BX = BX;
   L->BY = BY;
   L->BZ = BZ;
-  // pair lists: radius r_cut + 2 margin; slots for 1.5x the neighbours
+  // pair lists: radius r_cut + 2 skin; slots for 1.5x the neighbours
   // expected at the densest replica's mean density plus 20 (a brick with a
   // fuller list walks its cells instead)
   L->kmax = 0;
   // (list entries are 16-bit staging indices: lcap < 2^16)
   if (want_list && R >= 2 && L->lcap < 65536 && BX + 2 * L->ns <= kMaxListHalo &&
       BY + 2 * L->ns <= kMaxListHalo && BZ + 2 * nsz <= kMaxListHalo) {
-    const double rl = c->r_cut + 2 * L->margin;
+    const double rl = c->r_cut + 2 * L->skin;
     const double vol_l = (D == 2) ? M_PI * rl * rl : 4.0 / 3.0 * M_PI * rl * rl * rl;
     const int want = (int)std::ceil(1.5 * vol_l * rho_max) + 20;
     L->kmax = std::min(kMaxPairSlots, (want + 3) / 4 * 4);
@@ -421,6 +430,7 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   P.n_bricks = L->nbricks;
   P.cell_side = L->s;
   P.margin = L->margin;
+  P.skin = L->skin;
   P.pair_slots = L->kmax;
   P.block_threads = L->bthreads;
   return true;
@@ -540,7 +550,6 @@ struct mdlg_system {
     hipEvent_t a, b;
   };
   std::vector<Timed> timed;
-  Timed open_run{-1, 0, nullptr, nullptr};  // consecutive launches of one class
   std::vector<hipEvent_t> event_pool;
   double timed_ms[MDLG_K_NCLASS] = {};
   int64_t timed_n[MDLG_K_NCLASS] = {};
@@ -549,9 +558,9 @@ struct mdlg_system {
 
 namespace {
 
-// Words of arrival counters per MD cell: one byte for each of the 3^d - 1
-// directions a rebuild can move a particle in.
-int arrival_words(int D) { return D == 2 ? 2 : 7; }
+// Words of arrival counters per MD cell: the number of arrivals, then one
+// byte for each of the 3^d - 1 directions a rebuild can move a particle in.
+int arrival_words(int D) { return D == 2 ? 3 : 8; }
 
 // Accumulators per displaced lattice: Q + 1 counts and d + d(d+1)/2 sums.
 int shift_per(const Layout& L) { return L.Q + 1 + L.D + L.D * (L.D + 1) / 2; }
@@ -683,7 +692,7 @@ Phys make_phys(const mdlg_config* c, const Layout& L) {
   P.mq = (int)std::ceil(L.margin / u) + 4;
   P.rc_d = c->r_cut;
   P.u_d = u;
-  set_list_params(P, c, L, L.margin, L.kmax);
+  set_list_params(P, c, L, L.skin, L.kmax);
   // dynamic LDS of the brick kernels: the halo cell table of the largest
   // brick and room for about 1.5x the expected halo particles (a fuller halo
   // is staged in several chunks); the adjoint also stages d floats each
@@ -746,34 +755,32 @@ hipEvent_t pool_event(mdlg_system* S) {
   return e;
 }
 
-// Close the open run of same-class launches with its stop event.
-void close_run(mdlg_system* S) {
-  if (S->open_run.cls < 0) return;
-  (void)hipEventRecord(S->open_run.b, S->stream);
-  S->timed.push_back(S->open_run);
-  S->open_run = {-1, 0, nullptr, nullptr};
-}
-
-// With timing on, consecutive launches of one kernel class share one event
-// pair, so the per-launch average carries the event overhead only once per
-// run (the gaps between the launches of a run are included).
+// With timing on, every launch of a timed class gets its own event pair,
+// which hipExtLaunchKernelGGL records around the kernel itself (the time of
+// the kernel alone, not of the gaps between launches).  A launcher that ends
+// up launching nothing leaves its events unused; they are returned.
 struct TimedLaunch {
-  TimedLaunch(mdlg_system* S, int cls) {
+  mdlg_system* S;
+  bool on = false;
+  TimedLaunch(mdlg_system* sys, int cls) : S(sys) {
     if (!S->timing) return;
-    if (S->open_run.cls == cls) {
-      S->open_run.launches += 1;
-      return;
-    }
-    close_run(S);
     hipEvent_t a = pool_event(S), b = pool_event(S);
     if (!a || !b) return;
-    (void)hipEventRecord(a, S->stream);
-    S->open_run = {cls, 1, a, b};
+    g_launch_events = LaunchEvents{a, b};
+    S->timed.push_back({cls, 1, a, b});
+    on = true;
+  }
+  ~TimedLaunch() {
+    if (!on || !g_launch_events.start) return;
+    g_launch_events = LaunchEvents{};
+    const mdlg_system::Timed t = S->timed.back();
+    S->timed.pop_back();
+    S->event_pool.push_back(t.a);
+    S->event_pool.push_back(t.b);
   }
 };
 
 void drain_timing(mdlg_system* S) {
-  close_run(S);
   for (auto& t : S->timed) {
     float ms = 0.f;
     if (hipEventSynchronize(t.b) == hipSuccess && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
@@ -866,7 +873,6 @@ void enqueue_sort(mdlg_system* S) {
   if (S->first_sort) {
     // an input in arbitrary order: order every cell by id, back into the
     // arrays the scatter read
-    if (S->timing) close_run(S);
     CellsortArgs cs{};
     cs.reps = S->reps;
     cs.chunks = S->chunks;
@@ -932,7 +938,6 @@ void enqueue_force(mdlg_system* S, int mode, bool sort_follows, float* acc_out, 
 }
 
 void enqueue_kin(mdlg_system* S, bool thermostat) {
-  if (S->timing) close_run(S);
   KinArgs k{};
   k.reps = S->reps;
   k.kpart = S->kpart;
@@ -1500,7 +1505,6 @@ mdlg_status mdlg_get_f(mdlg_system* S, double* f, double* f_site, double* mom_si
   if (!S) return MDLG_E_INVALID;
   const Layout& L = S->L;
   const int D = S->D;
-  if (S->timing) close_run(S);
   launch_fill_u32(reinterpret_cast<unsigned*>(S->fcount), 0u, kMaxQ * 2, S->stream);
   launch_fill_u32(reinterpret_cast<unsigned*>(S->momsum), 0u, 32, S->stream);
   FsumArgs fs{};
@@ -1590,7 +1594,6 @@ mdlg_status mdlg_get_shifts(mdlg_system* S, uint64_t* counts, int64_t* moments, 
     S->last_error = "no shifted lattices were configured (n_shifts = 0)";
     return MDLG_E_STATE;
   }
-  if (S->timing) close_run(S);
   const int per = shift_per(L), nmo = per - L.Q - 1;
   // the kernel's per-XCD copies of the accumulators, summed here (modulo
   // 2^64: the moments are two's-complement)
@@ -1620,7 +1623,6 @@ mdlg_status mdlg_get_xi(mdlg_system* S, int64_t* sums, int64_t* xi_site, int32_t
     S->last_error = "collision_stats was not enabled in the configuration";
     return MDLG_E_STATE;
   }
-  if (S->timing) close_run(S);
   const size_t sq = (size_t)L.n_sites * L.Q;
   if (sums)
     HIPCHK(S, hipMemcpyAsync(sums, S->xi_sums, sizeof(int64_t) * 5 * L.Q, hipMemcpyDeviceToHost,
@@ -1817,7 +1819,6 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
   const int D = S->D;
   const long long nd = L.n_total * D;
   const Phys PW = window_phys(S);
-  if (S->timing) close_run(S);
   // start of the window: canonical cells (frozen from here on), full-step v
   if (S->since_sort != 0) enqueue_sort(S);
   if (v0_dev) {
@@ -1841,7 +1842,6 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
                      S->vel[S->scur]);
     S->pcur ^= 1;
     if (n % k == 0 && n < W) {
-      if (S->timing) close_run(S);  // (the checkpoint copies are not force launches)
       launch_copy_f32(S->pos[S->pcur], S->adj_ckpt_pos + (size_t)(n / k) * nd, nd, S->stream);
       launch_copy_f32(S->vel[S->scur], S->adj_ckpt_vel + (size_t)(n / k) * nd, nd, S->stream);
     }
@@ -1858,7 +1858,6 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
   const double e1 = 24.0 * S->cfg.epsilon / (S->cfg.mass * u);
   int cur = 0;
   for (int seg = W / k - 1; seg >= 0; --seg) {
-    if (S->timing) close_run(S);  // (the segment copies are not timed launches)
     launch_copy_f32(S->adj_ckpt_pos + (size_t)seg * nd, S->adj_seg_pos, nd, S->stream);
     launch_copy_f32(S->adj_ckpt_vel + (size_t)seg * nd, S->adj_vel, nd, S->stream);
     for (int j = 1; j <= k; ++j)
@@ -1931,7 +1930,6 @@ mdlg_status mdlg_checkpoint_save(mdlg_system* S, void* blob, size_t bytes) {
     S->last_error = "checkpoint buffer too small: need " + std::to_string(need) + " bytes";
     return MDLG_E_NOMEM;
   }
-  if (S->timing) close_run(S);
   mdlg_status st = read_err(S);  // synchronises; a failed run is not saved
   if (st != MDLG_OK) return st;
   const bool lists = ckpt_lists(S);
@@ -1987,7 +1985,6 @@ mdlg_status mdlg_checkpoint_load(mdlg_system* S, const void* blob, size_t bytes)
   }
   // wait for queued work before overwriting the state
   HIPCHK(S, hipStreamSynchronize(S->stream));
-  if (S->timing) close_run(S);
   S->pcur = h.pcur;
   S->scur = h.scur;
   S->since_sort = h.since_sort;

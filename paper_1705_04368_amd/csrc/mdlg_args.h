@@ -43,10 +43,10 @@ struct SortArgs {
   const float* prev_off;
   int* prev_u_out;
   float* prev_off_out;
-  unsigned* mcnt;         // [n_cells][mwords] arrivals per cell and direction (one byte each)
+  unsigned* mcnt;         // [n_cells][mwords] arrivals per cell: total, then a byte per direction
   unsigned* mcnt_clear;   // the other parity's counters, cleared by the scatter
   unsigned* err;
-  int mwords;             // words of arrival counters per cell: 2 (2D), 7 (3D)
+  int mwords;             // words of arrival counters per cell: 3 (2D), 8 (3D)
   int first;              // 1: input in arbitrary order (ingest, import): slots from
                           // atomics, then k_cellsort orders every cell by id
   int ntiles;
@@ -301,6 +301,15 @@ struct AdjIoArgs {
   int n;
   int to_sorted;
 };
+
+// Events of the next launch of a timed kernel: when set, the launcher hands
+// them to hipExtLaunchKernelGGL, which records them immediately before and
+// after the kernel, and clears them.
+struct LaunchEvents {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+extern thread_local LaunchEvents g_launch_events;
 
 void launch_fill_u32(unsigned* p, unsigned v, long long n, hipStream_t s);
 size_t brick_lds_bytes(const Phys& P, int D, bool adj);

@@ -34,8 +34,10 @@
 //   k_fsum / k_ffinal / k_site_avg   f_i^eq readout (eq. fieq)
 //   k_kin      FP64 momentum / kinetic energy per replica, thermostat factor
 //   k_export / k_import              state in id order
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <type_traits>
 
 #include "mdlg_args.h"
@@ -207,7 +209,7 @@ __device__ __forceinline__ void wave_agg_add(unsigned* base, int key, bool valid
   unsigned long long act = __ballot(valid);
   while (act) {
     const int leader = __ffsll((long long)act) - 1;
-    const int lk = __shfl(key, leader, 64);
+    const int lk = __builtin_amdgcn_readlane(key, leader);
     const unsigned long long same = __ballot(valid && key == lk) & act;
     if (lane_id() == leader) atomicAdd(base + lk, (unsigned)__popcll(same));
     act &= ~same;
@@ -218,7 +220,7 @@ __device__ __forceinline__ void wave_agg_add_i(int* base, int key, bool valid) {
   unsigned long long act = __ballot(valid);
   while (act) {
     const int leader = __ffsll((long long)act) - 1;
-    const int lk = __shfl(key, leader, 64);
+    const int lk = __builtin_amdgcn_readlane(key, leader);
     const unsigned long long same = __ballot(valid && key == lk) & act;
     if (lane_id() == leader) atomicAdd(base + lk, (int)__popcll(same));
     act &= ~same;
@@ -289,9 +291,33 @@ template <int D>
 constexpr int kDirs = (D == 2) ? 9 : 27;
 template <int D>
 constexpr int kStay = (kDirs<D> - 1) / 2;
-// words of arrival counters per cell (one byte per direction but kStay)
+// words of arrival counters per cell: the exact number of arrivals, then one
+// byte per direction but kStay (a byte that wrapped makes the bytes' sum
+// differ from the exact count, which the scatter checks)
 template <int D>
-constexpr int kArrWords = (kDirs<D> - 1 + 3) / 4;
+constexpr int kArrWords = 1 + (kDirs<D> - 1 + 3) / 4;
+
+// Canonical (cell, offset, image) of a particle from its stored offset o,
+// image im and old cell oc (global index); dir receives the rebuild step.
+template <int D>
+__device__ __forceinline__ bool canon_state(const Replica& R, float s, int oc, float (&o)[D],
+                                            int (&c)[D], int (&im)[D], int& dir) {
+  cell_coords<D>(oc - R.cell_off, R, c);
+  bool ok = true;
+  int dd = 0, p3 = 1;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const int c0 = c[k];
+    ok = canon(o[k], c[k], im[k], R.Mc[k], s) && ok;
+    int d = c[k] - c0;
+    if (d > 1) d -= R.Mc[k];
+    else if (d < -1) d += R.Mc[k];
+    dd += (d + 1) * p3;
+    p3 *= 3;
+  }
+  dir = dd;
+  return ok;
+}
 
 template <int D>
 __device__ __forceinline__ bool canon_particle(const SortArgs& a, const Replica& R, int g,
@@ -346,6 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
   __shared__ int s_cnt[kHist];
   __shared__ int s_tile[kTiles];
   __shared__ unsigned char s_dir[kCountChunkMax];
+  __shared__ int s_oc[kCountChunkMax];
   __shared__ unsigned char s_pdir[kPrev];
   __shared__ int s_p0;
   // consecutive chunks on one XCD: the per-cell count atomics of neighbouring
@@ -391,43 +418,66 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
       s_pdir[j - s_p0] = (unsigned char)dd;
     }
   }
-  int key[kPer], oc[kPer], dir[kPer];
+  int key[kPer], dir[kPer];
+  // the particles' state is loaded kLoad at a time before any of it is used
+  // (the counting atomics below would otherwise keep the loads apart)
+  constexpr int kLoad = 8;
 #pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int g = ch.y + u * kBlock + (int)threadIdx.x;
-    key[u] = -1;
-    oc[u] = 0;
-    dir[u] = kStay<D>;
-    if (ch.y + u * kBlock >= ch.z) continue;  // the chunk is shorter (uniform)
-    bool inwin = false;
-    if (g < ch.z) {
-      float o[D];
-      int c[D], im[D];
-      if (!canon_particle<D>(a, R, g, o, c, im, &oc[u], &dir[u])) atomicOr(a.err, kErrJump);
-      key[u] = R.cell_off + cell_linear<D>(c, R);
-      s_dir[g - ch.y] = (unsigned char)dir[u];
-      if (a.first) {
-        a.keyslot[g] = make_int2(key[u], atomicAdd(a.count + key[u], 1));
-      } else {
-        inwin = key[u] >= lo && key[u] < lo + nwin;
-        if (inwin) atomicAdd(&s_cnt[key[u] - lo], 1);
-        else atomicAdd(a.count + key[u], 1);
-        if (dir[u] != kStay<D>) {
-          const int f = arrival_field<D>(dir[u]);
-          const unsigned sh = 8u * (unsigned)(f & 3);
-          const unsigned old =
-              atomicAdd(a.mcnt + (size_t)key[u] * kArrWords<D> + (f >> 2), 1u << sh);
-          if (((old >> sh) & 255u) == 255u) atomicOr(a.err, kErrOverflow);
-        }
+  for (int u0 = 0; u0 < kPer; u0 += kLoad) {
+    float o[kLoad][D];
+    int im[kLoad][D], oc[kLoad];
+#pragma unroll
+    for (int v = 0; v < kLoad; ++v) {
+      const int g = ch.y + (u0 + v) * kBlock + (int)threadIdx.x;
+      if (g < ch.z) {
+        ldv<D>(a.pos, g, o[v]);
+        ldi<D>(a.img, g, im[v]);
+        oc[v] = a.cell[g];
       }
     }
-    if (key[u] >= 0 && !inwin) {
-      const int tl = key[u] / kScanTile - tile0;
-      if (tl >= 0 && tl < kTiles) atomicAdd(&s_tile[tl], 1);
+#pragma unroll
+    for (int v = 0; v < kLoad; ++v) {
+      const int u = u0 + v;
+      const int g = ch.y + u * kBlock + (int)threadIdx.x;
+      key[u] = -1;
+      dir[u] = kStay<D>;
+      if (ch.y + u * kBlock >= ch.z) continue;  // the chunk is shorter (uniform)
+      bool inwin = false;
+      if (g < ch.z) {
+        int c[D];
+        if (!canon_state<D>(R, a.P.s, oc[v], o[v], c, im[v], dir[u])) atomicOr(a.err, kErrJump);
+        key[u] = R.cell_off + cell_linear<D>(c, R);
+        s_dir[g - ch.y] = (unsigned char)dir[u];
+        s_oc[g - ch.y] = oc[v];
+        if (a.first) {
+          a.keyslot[g] = make_int2(key[u], atomicAdd(a.count + key[u], 1));
+        } else {
+          inwin = key[u] >= lo && key[u] < lo + nwin;
+          if (inwin) atomicAdd(&s_cnt[key[u] - lo], 1);
+          else atomicAdd(a.count + key[u], 1);
+        }
+      }
+      if (key[u] >= 0 && !inwin) {
+        const int tl = key[u] / kScanTile - tile0;
+        if (tl >= 0 && tl < kTiles) atomicAdd(&s_tile[tl], 1);
+      }
+      const int tk = key[u] >= 0 ? key[u] / kScanTile - tile0 : 0;
+      wave_agg_add_i(tsum, key[u] >= 0 ? key[u] / kScanTile : 0,
+                     key[u] >= 0 && !inwin && (tk < 0 || tk >= kTiles));
     }
-    const int tk = key[u] >= 0 ? key[u] / kScanTile - tile0 : 0;
-    wave_agg_add_i(tsum, key[u] >= 0 ? key[u] / kScanTile : 0,
-                   key[u] >= 0 && !inwin && (tk < 0 || tk >= kTiles));
+  }
+  if (!a.first) {
+    // arrivals per cell: the exact count and the direction's byte (no
+    // returned values: nothing waits for these)
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      if (key[u] >= 0 && dir[u] != kStay<D>) {
+        const int f = arrival_field<D>(dir[u]);
+        unsigned* w = a.mcnt + (size_t)key[u] * kArrWords<D>;
+        atomicAdd(w, 1u);
+        atomicAdd(w + 1 + (f >> 2), 1u << (8u * (unsigned)(f & 3)));
+      }
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nwin; i += kBlock) {
@@ -440,17 +490,49 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
   __syncthreads();
   if (threadIdx.x < kTiles && s_tile[threadIdx.x]) atomicAdd(tsum + tile0 + threadIdx.x, s_tile[threadIdx.x]);
   if (a.first) return;
-  // rank among the earlier particles of the old cell that moved the same way
+  // rank among the earlier particles of the old cell that moved the same
+  // way.  The lanes of a wave hold consecutive particles, so inside the
+  // wave the old cell's run and the lanes of the same direction are bit
+  // masks; a run that began before the wave adds its earlier part, walked
+  // back through the chunk (LDS) and through the part of the chunk's first
+  // old cell that lies before the chunk.
   const int p0 = s_p0;
+  const int lane = lane_id();
+  const unsigned long long below = (1ull << lane) - 1ull;
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
+    if (ch.y + u * kBlock >= ch.z) continue;  // uniform
     const int g = ch.y + u * kBlock + (int)threadIdx.x;
-    if (key[u] < 0) continue;
-    const int run0 = a.cell_start[oc[u]];
-    int r = 0;
-    for (int j = max(run0, ch.y); j < g; ++j) r += (s_dir[j - ch.y] == dir[u]) ? 1 : 0;
-    if (run0 < ch.y)
-      for (int j = max(run0, p0); j < ch.y; ++j) r += (s_pdir[j - p0] == dir[u]) ? 1 : 0;
+    const bool valid = key[u] >= 0;
+    const int l = g - ch.y;
+    const int oc = valid ? s_oc[l] : -1;
+    // (the chunk's first particle starts a run unless its old cell began in
+    // the previous chunk)
+    const bool head = valid && (l == 0 ? p0 == ch.y : s_oc[l - 1] != oc);
+    const unsigned long long hm = __ballot(head) & (below | (1ull << lane));
+    unsigned long long same = 0ull, act = __ballot(valid);
+    while (act) {
+      const int leader = __ffsll((long long)act) - 1;
+      const int ld = __builtin_amdgcn_readlane(dir[u], leader);
+      const unsigned long long m = __ballot(valid && dir[u] == ld) & act;
+      if (valid && dir[u] == ld) same = m;
+      act &= ~m;
+    }
+    if (!valid) continue;
+    int r;
+    if (hm) {
+      const int rs = 63 - __clzll((long long)hm);
+      r = __popcll(same & below & ~((1ull << rs) - 1ull));
+    } else {
+      r = __popcll(same & below);
+      int j = l - lane - 1;
+      while (j >= 0 && s_oc[j] == oc) {
+        r += (s_dir[j] == dir[u]) ? 1 : 0;
+        --j;
+      }
+      if (j < 0)
+        for (int i = 0; i < ch.y - p0; ++i) r += (s_pdir[i] == dir[u]) ? 1 : 0;
+    }
     const int code = (dir[u] == kStay<D>) ? r : (r | ((arrival_field<D>(dir[u]) + 1) << 24));
     a.keyslot[g] = make_int2(key[u], code);
   }
@@ -521,20 +603,22 @@ __global__ __launch_bounds__(kBlock) void k_scatter(SortArgs a) {
         const unsigned* __restrict__ w = a.mcnt + (size_t)ks.x * kArrWords<D>;
         int tot = 0, pre = 0;
 #pragma unroll
-        for (int i = 0; i < kArrWords<D>; ++i) {
+        for (int i = 1; i < kArrWords<D>; ++i) {
           const unsigned x = w[i];
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             const int n = (int)((x >> (8 * b)) & 255u);
             tot += n;
-            pre += (4 * i + b < f1 - 1) ? n : 0;
+            pre += (4 * (i - 1) + b < f1 - 1) ? n : 0;
           }
         }
-        dst = a.cell_start[ks.x + 1] - tot + pre + lr;
+        // a wrapped byte: the slots cannot be trusted (reported below)
+        dst = (tot == (int)w[0]) ? a.cell_start[ks.x + 1] - tot + pre + lr : -1;
       }
     }
-    // a slot outside the cell's range means inconsistent counts (an arrival
-    // counter overflowed): reported, and nothing is written out of range
+    // a slot outside the cell's range means inconsistent counts (more than
+    // 255 arrivals from one direction): reported, and nothing is written out
+    // of range
     if (dst < a.cell_start[ks.x] || dst >= a.cell_start[ks.x + 1]) {
       atomicOr(a.err, kErrOverflow);
       continue;
@@ -875,7 +959,9 @@ __device__ __forceinline__ void lj_pair(const C& q, int X, int Y, int Z, const P
   const float ir2 = in ? __builtin_amdgcn_rcpf(r2) : 0.f;
   const float sr2 = P.sig2_u * ir2;
   const float sr6 = sr2 * sr2 * sr2;
-  const float gg = P.eps24m_u * ir2 * sr6 * (2.f * sr6 - 1.f);
+  // the same operations as lj_pair_listed, so that both paths give the same
+  // sums bit for bit (candidates beyond r_cut add exact zeros)
+  const float gg = (ir2 * sr6) * fmaf(2.f * P.eps24m_u, sr6, -P.eps24m_u);
   f[0] -= gg * dx;
   f[1] -= gg * dy;
   if constexpr (D == 3) f[D - 1] -= gg * dz;
@@ -957,7 +1043,7 @@ __device__ __forceinline__ bool row_columns(const BrickGeom& G, const Phys& P, i
 // Velocity-Verlet update of one particle from its acceleration f, shared by
 // both force paths; accumulates the kinetic partials.
 template <int D>
-__device__ __forceinline__ void vv_update(const ForceArgs& a, const Phys& P, int rep, int gi,
+__device__ __forceinline__ void vv_update(const ForceArgs& a, const Phys& P, int gi,
                                           const float (&o)[D], const float (&v)[D],
                                           const float (&f)[D], double (&kin)[D + 1],
                                           const float (&o0_pre)[D], bool have_o0) {
@@ -1175,7 +1261,7 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
           for (int u = 0; u < GW; ++u) w[u] = nx[u];
         }
       }
-      vv_update<D>(a, P, br.x, gi, o, v, f, kin, o0, true);
+      vv_update<D>(a, P, gi, o, v, f, kin, o0, true);
     }
   } else {
     const Replica R = a.reps[br.x];
@@ -1235,7 +1321,7 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
           }
         }
       }
-      if (valid) vv_update<D>(a, P, br.x, gi, o, v, f, kin, o, false);
+      if (valid) vv_update<D>(a, P, gi, o, v, f, kin, o, false);
     }
   }
   if (a.kpart) {
@@ -1459,7 +1545,7 @@ __device__ __forceinline__ void nlist_brick(const NlistArgs& a) {
       unsigned long long same = 0ull, act = __ballot(valid);
       while (act) {
         const int leader = __ffsll((long long)act) - 1;
-        const int lb = __shfl(bin, leader, 64);
+        const int lb = __builtin_amdgcn_readlane(bin, leader);
         const unsigned long long m = __ballot(valid && bin == lb) & act;
         if (valid && bin == lb) same = m;
         act &= ~m;
@@ -2251,12 +2337,27 @@ __global__ __launch_bounds__(kBlock) void k_xi_reduce(XiArgs a) {
 
 // ---------------------------------------------------------------- launchers
 
-#define MDLG_LAUNCH_DIM(D, kern, grid, lds, stream, args)                        \
-  do {                                                                           \
-    if ((D) == 2)                                                                \
-      hipLaunchKernelGGL(kern<2>, dim3(grid), dim3(kBlock), lds, stream, args);  \
-    else                                                                         \
-      hipLaunchKernelGGL(kern<3>, dim3(grid), dim3(kBlock), lds, stream, args);  \
+thread_local LaunchEvents g_launch_events;
+
+// One launch; with events pending (per-kernel timing) through
+// hipExtLaunchKernelGGL, which records them around the kernel.
+#define MDLG_GO(kern, grid, block, lds, stream, args)                                         \
+  do {                                                                                      \
+    if (g_launch_events.start) {                                                            \
+      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), (std::uint32_t)(lds), stream,     \
+                            g_launch_events.start, g_launch_events.stop, 0u, args);         \
+      g_launch_events = LaunchEvents{};                                                     \
+    } else {                                                                                \
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, stream, args);                 \
+    }                                                                                       \
+  } while (0)
+
+#define MDLG_LAUNCH_DIM(D, kern, grid, lds, stream, args)            \
+  do {                                                               \
+    if ((D) == 2)                                                    \
+      MDLG_GO(kern<2>, grid, kBlock, lds, stream, args);             \
+    else                                                             \
+      MDLG_GO(kern<3>, grid, kBlock, lds, stream, args);             \
   } while (0)
 
 void launch_fill_u32(unsigned* p, unsigned v, long long n, hipStream_t s) {
@@ -2283,7 +2384,7 @@ void launch_count(int D, int nchunks, const SortArgs& a, hipStream_t s) {
 }
 
 void launch_scan(const ScanArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan, dim3(a.ntiles), dim3(kBlock), 0, s, a);
+  MDLG_GO(k_scan, a.ntiles, kBlock, 0, s, a);
 }
 
 void launch_scatter(int D, int nchunks, const SortArgs& a, hipStream_t s) {
@@ -2305,18 +2406,18 @@ size_t brick_lds_bytes(const Phys& P, int D, bool adj) {
 }
 
 // Brick kernels come in 64-, 128- and 256-thread blocks (P.bthreads).
-#define MDLG_LAUNCH_BRICK(D, NT, kern, grid, lds, stream, args)                           \
-  do {                                                                                    \
-    if ((NT) == 64) {                                                                     \
-      if ((D) == 2) hipLaunchKernelGGL((kern<2, 64>), dim3(grid), dim3(64), lds, stream, args);   \
-      else hipLaunchKernelGGL((kern<3, 64>), dim3(grid), dim3(64), lds, stream, args);            \
-    } else if ((NT) == 128) {                                                             \
-      if ((D) == 2) hipLaunchKernelGGL((kern<2, 128>), dim3(grid), dim3(128), lds, stream, args); \
-      else hipLaunchKernelGGL((kern<3, 128>), dim3(grid), dim3(128), lds, stream, args);          \
-    } else {                                                                              \
-      if ((D) == 2) hipLaunchKernelGGL((kern<2, 256>), dim3(grid), dim3(256), lds, stream, args); \
-      else hipLaunchKernelGGL((kern<3, 256>), dim3(grid), dim3(256), lds, stream, args);          \
-    }                                                                                     \
+#define MDLG_LAUNCH_BRICK(D, NT, kern, grid, lds, stream, args)                 \
+  do {                                                                          \
+    if ((NT) == 64) {                                                           \
+      if ((D) == 2) MDLG_GO((kern<2, 64>), grid, 64, lds, stream, args);        \
+      else MDLG_GO((kern<3, 64>), grid, 64, lds, stream, args);                 \
+    } else if ((NT) == 128) {                                                   \
+      if ((D) == 2) MDLG_GO((kern<2, 128>), grid, 128, lds, stream, args);      \
+      else MDLG_GO((kern<3, 128>), grid, 128, lds, stream, args);               \
+    } else {                                                                    \
+      if ((D) == 2) MDLG_GO((kern<2, 256>), grid, 256, lds, stream, args);      \
+      else MDLG_GO((kern<3, 256>), grid, 256, lds, stream, args);               \
+    }                                                                           \
   } while (0)
 
 void launch_force(int D, const ForceArgs& a, hipStream_t s) {

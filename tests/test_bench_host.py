@@ -91,21 +91,55 @@ def test_stored_traffic_is_used_only_on_matching_sources(tmp_path, monkeypatch):
     assert bench.load_traffic("w", "force") is None
 
 
-def test_force_kernel_is_hbm_bound_on_the_benchmarked_workloads():
-    # algorithmic bytes: state read and written (16 d), reference offset (4 d)
-    # and 2 bytes per neighbour within the list radius; FLOPs of the
-    # interacting pairs within r_c.  Both workloads sit far below the ridge
-    # point of the FP32 peak over the HBM bandwidth.
+def test_kernel_table_grades_forces_on_fp32_and_sort_on_hbm():
+    # the force kernel on the FP32 vector units with the FLOPs of the
+    # interacting pairs (9.82 per particle in 2D at rho = 0.5, 18 FLOP each);
+    # the rebuild as one unit on HBM with 104 B per particle (2D) + 12 B per cell
+    n, rho = 262144, 0.5
+    lay = {"n_velocities": 49, "n_moments": 7, "margin": 0.4, "skin": 0.25, "pair_slots": 48,
+           "n_cells": 32761}
+    tim = {"force": (0.1, 10), "count": (0.02, 2), "scan": (0.01, 2), "scatter": (0.02, 2),
+           "bin": (0.015, 1), "nlist": (0.0, 0)}
+    k, sort = bench.kernel_table(tim, 2, n, rho, lay, 32761)
+    f = k["force"]
+    flops = n * 3.14159265 * 2.5 ** 2 * 0.5 * 18
+    assert f["bound"] == "alu" and f["unit"] == "TFLOP/s" and f["peak"] == 157.3
+    assert f["work_per_launch"] == pytest.approx(flops, rel=1e-6)
+    assert f["achieved"] == pytest.approx(flops / 1e-5 / 1e12, rel=1e-6)
+    assert f["frac"] == pytest.approx(f["achieved"] / 157.3)
+    assert "nlist" not in k
+    assert k["bin"]["bound"] == "hbm"
+    # 52 B per particle (offset, image, cell, snapshot read and written) and
+    # the per-site counters (2 x 4 x 49 + 2 x 8 x 7 B) shared by 8 particles
+    assert bench.bin_bytes_per_particle(2, 49, 7, 8.0) == pytest.approx(52 + 504 / 8)
+    assert sort["avg_ms"] == pytest.approx(0.025)
+    assert sort["work_per_launch"] == n * 104 + 12 * 32761
+    assert bench.sort_bytes(3, 1, 0) == 144
+    # the force kernel's arithmetic intensity is below the ridge point on
+    # HBM bytes too, but the FP32 bound is the one graded
     ridge = bench.PEAK_FP32_TFLOPS * 1e12 / (bench.PEAK_HBM_GBS * 1e9)
-    assert bench.force_bytes_per_particle(2, 0.5) == 32
-    assert bench.force_bytes_per_particle(2, 0.5, 3.3) == pytest.approx(40 + 3.14159265 * 3.3 ** 2,
-                                                                        rel=1e-6)
-    for dim, rho, margin in ((2, 0.5, 0.4), (3, 4194304 / 192.0 ** 3, 0.392)):
-        rl = 2.5 + 2 * margin
-        ai = (bench.pairs_per_particle(dim, rho) * bench.FLOP_PER_PAIR[dim]
-              / bench.force_bytes_per_particle(dim, rho, rl))
-        assert 1.0 < ai < ridge / 4
-    # the adjoint's reverse step likewise
-    ai = (bench.pairs_per_particle(2, 0.5) * bench.ADJ_FLOP_PER_PAIR[2]
-          / bench.adjoint_bytes_per_particle(2))
-    assert ai < ridge
+    assert bench.force_bytes_per_particle(2) == 32
+    ai = bench.pairs_per_particle(2, rho) * 18 / bench.force_bytes_per_particle(2, rho, 3.3)
+    assert 1.0 < ai < ridge
+
+
+def test_ensemble_statistics():
+    import numpy as np
+    rng = np.random.default_rng(3)
+    fr = rng.normal(1.0, 0.1, size=(512, 4))
+    w = rng.integers(10, 100, size=512)
+    mean, se = bench.ensemble_mean_se(fr, w)
+    assert mean == pytest.approx((w[:, None] * fr).sum(0) / w.sum())
+    # equal weights: the plain standard error of the mean
+    m2, se2 = bench.ensemble_mean_se(fr, np.ones(512))
+    assert se2 == pytest.approx(fr.std(axis=0, ddof=1) / np.sqrt(512))
+    c = bench.compare_fi(mean, se, mean + 0.5 * se, se, np.full(4, 1e6))
+    assert c["agree"] and c["bins_tested"] == 4 and c["max_abs_z"] == pytest.approx(0.5 / np.sqrt(2))
+    c = bench.compare_fi(mean, se, mean + 10 * se, se, np.full(4, 1e6))
+    assert not c["agree"]
+    # per-replica f_i from per-site averages
+    m_r = np.array([2, 3])
+    f_site = np.arange(13 * 2, dtype=float).reshape(13, 2)
+    fr, sites = bench.replica_fi(f_site, m_r)
+    assert list(sites) == [4, 9]
+    assert fr[0] == pytest.approx(f_site[:4].mean(0)) and fr[1] == pytest.approx(f_site[4:].mean(0))

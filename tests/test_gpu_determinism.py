@@ -188,3 +188,42 @@ def test_checkpoint_rejects_other_configuration():
         a.restore(bad)
     with pytest.raises(MdlgError):
         a.restore(blob[:-8])
+
+
+def test_sorted_layout_is_a_permutation_in_cell_order():
+    # white-box check of the counting sort through the checkpoint blob, which
+    # holds the state in the library's order: a header of 88 bytes, then
+    # offsets, velocities, images, ids, cells, snapshot, cell starts
+    for dim, n, lat in ((2, (968, 2048), (11, 16)), (3, (4740,), (5,))):
+        say(f"sorted layout dim={dim}")
+        cfg = _cfg(dim, n, lat)
+        pos, vel = _state(dim, n, lat, seed=451)
+        s = _run(cfg, pos, vel, thermo=40, T=3)
+        blob = s.checkpoint()
+        N = int(sum(n))
+        off = 88
+        take = {}
+        for name, cnt, dt in (("pos", N * dim, np.float32), ("vel", N * dim, np.float32),
+                              ("img", N * dim, np.int32), ("id", N, np.int32), ("cell", N, np.int32),
+                              ("prev_u", N * dim, np.int32), ("prev_off", N * dim, np.float32),
+                              ("cell_start", s.layout["n_cells"] + 1, np.int32)):
+            nb = cnt * np.dtype(dt).itemsize
+            take[name] = np.frombuffer(blob[off:off + nb].tobytes(), dtype=dt)
+            off += nb
+        np.testing.assert_array_equal(np.sort(take["id"]), np.arange(N))
+        cell = take["cell"]
+        assert np.all(np.diff(cell) >= 0)
+        cs = take["cell_start"]
+        np.testing.assert_array_equal(cs, np.searchsorted(cell, np.arange(len(cs)), side="left"))
+        side = s.layout["cell_side"]
+        p = take["pos"]
+        assert np.all(p >= 0) and np.all(p < side)
+        # every particle of a replica sits in a cell of that replica
+        k = s.layout["md_cell_split"]
+        bounds = np.concatenate([[0], np.cumsum(n)])
+        cbounds = np.concatenate([[0], np.cumsum([(m * k) ** dim for m in lat])])
+        for r in range(len(n)):
+            c = cell[bounds[r]:bounds[r + 1]]
+            assert c.min() >= cbounds[r] and c.max() < cbounds[r + 1]
+            ids = take["id"][bounds[r]:bounds[r + 1]]
+            assert ids.min() >= bounds[r] and ids.max() < bounds[r + 1]

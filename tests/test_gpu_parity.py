@@ -371,31 +371,39 @@ def test_empty_lattice_steps_and_single_particle():
 @pytest.mark.parametrize("dim", [2, 3])
 def test_pair_lists_match_cell_walk_and_oracle(dim):
     # the same 40 MD steps with per-particle pair lists (rebuilt with the cell
-    # list every 8 steps) and with the cell walk at every step
+    # list every 8 steps) and with the cell walk at every step, in the same
+    # layout: both sum the pairs within r_cut in the order of the brick's
+    # staging (list entries beyond r_cut add exact zeros), so the runs agree
+    # bit for bit; both within the bars of the oracle
     cfg_l, pos, vel, box, n, M = _force_case(dim, 78, 2 if dim == 3 else 1, equil_steps=300)
     cfg_c, *_ = _force_case(dim, 78, 2 if dim == 3 else 1)
-    cfg_c.no_pair_list = 1
+    say(f"pair lists vs cell walk dim={dim}")
+    sl = make_system(cfg_l, pos, vel)
+    lay = sl.layout
     for c in (cfg_l, cfg_c):
         c.sort_every = 8
-    say(f"pair lists vs cell walk dim={dim}")
+        c.md_cell_split = lay["md_cell_split"]
+        c.brick_x, c.brick_y, c.brick_z = lay["brick"]
+        c.block_threads = lay["block_threads"]
+    cfg_c.no_pair_list = 1
     sl = make_system(cfg_l, pos, vel)
     sc = make_system(cfg_c, pos, vel)
     assert sl.layout["pair_slots"] > 0 and sc.layout["pair_slots"] == 0
     s = sl.layout["cell_side"]
     f_l, f_c = sl.get_state()["acc"], sc.get_state()["acc"]
+    np.testing.assert_array_equal(f_l, f_c)
     md = oracle.make_md(dim, n, box, dt=0.005)
     acc, _ = oracle.forces(md, wrapped(sl.get_state(), s, M * sl.layout["md_cell_split"]))
     assert force_error(f_l, acc).max() <= 1e-5
-    assert force_error(f_c, acc).max() <= 1e-5
     sl.step(40)
     sc.step(40)
     a, b = sl.get_state(), sc.get_state()
+    for key in ("ucell", "off", "vel", "acc"):
+        np.testing.assert_array_equal(a[key], b[key])
     ost = oracle.OracleState(md, pos, vel)
     ost.run(40)
-    for st in (a, b):
-        assert np.abs(unwrapped(st, s) - ost.unwrapped).max() <= 1e-4
-        assert np.abs(st["vel"].astype(np.float64) - ost.v).max() <= 1e-4
-    say(f"  list vs walk max |dx| {np.abs(unwrapped(a, s) - unwrapped(b, s)).max():.3e}")
+    assert np.abs(unwrapped(a, s) - ost.unwrapped).max() <= 1e-4
+    assert np.abs(a["vel"].astype(np.float64) - ost.v).max() <= 1e-4
 
 
 def test_pair_list_overflow_falls_back_to_cell_walk():
@@ -422,13 +430,13 @@ def test_pair_list_overflow_falls_back_to_cell_walk():
     d = xw[:, None, :] - xw[None, :, :]
     d -= box * np.rint(d / box)
     r = np.sqrt((d ** 2).sum(-1))
-    rl = 2.5 + 2 * sysg.layout["margin"]
+    rl = 2.5 + 2 * sysg.layout["skin"]
     assert ((r < rl).sum(1) - 1).max() > kmax
 
 
 def test_pair_list_displacement_is_checked():
     # two particles far apart; one moves 0.15 sigma per step, inside its cell,
-    # and passes the list margin after a few steps
+    # and passes the list skin after a few steps
     from paper_1705_04368_amd import MdlgError, make_config
     cfg = make_config(2, 2, 4, lattice_dx=4.0, dt=0.005, vmax=1, md_cell_split=1, kT=1.0,
                       sort_every=18)
@@ -436,7 +444,7 @@ def test_pair_list_displacement_is_checked():
     vel = np.array([[30.0, 0.0], [0.0, 0.0]], np.float32)
     say("pair-list displacement check")
     sysg = make_system(cfg, pos, vel)
-    m = sysg.layout["margin"]
+    m = sysg.layout["skin"]
     assert sysg.layout["pair_slots"] > 0 and sysg.layout["sort_every"] == 18
     steps = int(np.ceil(m / (30.0 * 0.005))) + 2
     assert 1.0 + 30.0 * 0.005 * steps < 4.0  # still inside its cell
@@ -453,7 +461,7 @@ def test_forces_at_every_step_between_rebuilds(dim):
     # at its start, age by one step each time) against the oracle on the
     # GPU's own positions, with a few particles sent off at 7 (kT/m)^(1/2) so
     # that the largest displacement since the build grows past half the
-    # rebuild margin inside the interval.
+    # lists' skin inside the interval.
     from tests.gpu_util import check_forces_at_cutoff
     cfg, pos, vel, box, n, M = _force_case(dim, 91, 2 if dim == 3 else 1, equil_steps=300)
     cfg.sort_every = 12
@@ -464,7 +472,7 @@ def test_forces_at_every_step_between_rebuilds(dim):
     vel[hot] = (7.0 * d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
     say(f"forces between rebuilds dim={dim}")
     sysg = make_system(cfg, pos, vel)
-    m = sysg.layout["margin"]
+    m = sysg.layout["skin"]
     s = sysg.layout["cell_side"]
     mc = M * sysg.layout["md_cell_split"]
     assert sysg.layout["pair_slots"] > 0 and sysg.layout["sort_every"] == 12
@@ -478,7 +486,7 @@ def test_forces_at_every_step_between_rebuilds(dim):
         acc, _ = oracle.forces(md, xw)
         events, worst = check_forces_at_cutoff(st["acc"], acc, xw, xw, box, 2.5)
         deltas.append(np.sqrt(((unwrapped(st, s) - x0) ** 2).sum(1)).max())
-        say(f"  step {k}: largest displacement since the build {deltas[-1]:.4f} (margin {m:.4f}); "
+        say(f"  step {k}: largest displacement since the build {deltas[-1]:.4f} (skin {m:.4f}); "
             f"raw error {worst:.2e}, {events} at a cutoff pair")
         # (a pair within float rounding of r_c counts for both its particles)
         assert events <= 4
