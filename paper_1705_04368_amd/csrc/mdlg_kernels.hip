@@ -393,31 +393,11 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
   const int nwin = a.first ? 0 : min(kHist, a.cell[ch.z - 1] + R.Mc[0] + 2 - lo);
   for (int i = threadIdx.x; i < nwin; i += kBlock) s_cnt[i] = 0;
   if (threadIdx.x < kTiles) s_tile[threadIdx.x] = 0;
-  if (threadIdx.x == 0) {
-    // first particle of the chunk's first old cell
-    int p0 = ch.y;
-    if (!a.first && ch.y > R.part_off && a.cell[ch.y - 1] == a.cell[ch.y])
-      p0 = a.cell_start[a.cell[ch.y]];
-    if (ch.y - p0 > kPrev) {
-      atomicOr(a.err, kErrOverflow);
-      p0 = ch.y - kPrev;
-    }
-    s_p0 = p0;
-  }
   // (the reach below the window is capped so that the window's own tiles
   // always index inside s_tile: (16 + 2) tiles + 2 < kTiles)
   const int layer = min((D == 3) ? R.Mc[0] * R.Mc[1] : R.Mc[0], 16 * kScanTile);
   const int tile0 = max(0, lo - layer) / kScanTile;
   __syncthreads();
-  {
-    const int j = s_p0 + (int)threadIdx.x;
-    if (j < ch.y) {
-      float o[D];
-      int c[D], im[D], dd;
-      (void)canon_particle<D>(a, R, j, o, c, im, nullptr, &dd);
-      s_pdir[j - s_p0] = (unsigned char)dd;
-    }
-  }
   int key[kPer], dir[kPer];
   // the particles' state is loaded kLoad at a time before any of it is used
   // (the counting atomics below would otherwise keep the loads apart)
@@ -478,8 +458,28 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
         atomicAdd(w + 1 + (f >> 2), 1u << (8u * (unsigned)(f & 3)));
       }
     }
+    if (threadIdx.x == 0) {
+      // first particle of the chunk's first old cell (the ranks below count
+      // the part of that cell before the chunk)
+      int p0 = ch.y;
+      if (ch.y > R.part_off && a.cell[ch.y - 1] == a.cell[ch.y]) p0 = a.cell_start[a.cell[ch.y]];
+      if (ch.y - p0 > kPrev) {
+        atomicOr(a.err, kErrOverflow);
+        p0 = ch.y - kPrev;
+      }
+      s_p0 = p0;
+    }
   }
   __syncthreads();
+  if (!a.first) {
+    const int j = s_p0 + (int)threadIdx.x;
+    if (j < ch.y) {
+      float o[D];
+      int c[D], im[D], dd;
+      (void)canon_particle<D>(a, R, j, o, c, im, nullptr, &dd);
+      s_pdir[j - s_p0] = (unsigned char)dd;
+    }
+  }
   for (int i = threadIdx.x; i < nwin; i += kBlock) {
     const int c = s_cnt[i];
     if (c) {
@@ -586,21 +586,45 @@ __global__ __launch_bounds__(kBlock) void k_scatter(SortArgs a) {
   }
   const int4 ch = a.chunks[blockIdx.x];
   const Replica R = a.reps[ch.x];
-  for (int g = ch.y + threadIdx.x; g < ch.z; g += kBlock) {
-    float o[D];
-    int c[D], im[D];
-    (void)canon_particle<D>(a, R, g, o, c, im);
-    const int2 ks = a.keyslot[g];
+  // every particle of the thread is loaded before any slot is computed: the
+  // slot needs the cell start of its key (a dependent load), so the state's
+  // loads and that one are the only round trips before the stores
+  constexpr int kS = kPartChunkMax / kBlock;
+  float o[kS][D], v[kS][D], po[kS][D];
+  int im[kS][D], pu[kS][D], oc[kS], pid[kS];
+  int2 ks[kS];
+#pragma unroll
+  for (int q = 0; q < kS; ++q) {
+    const int g = ch.y + q * kBlock + (int)threadIdx.x;
+    if (g < ch.z) {
+      ldv<D>(a.pos, g, o[q]);
+      ldi<D>(a.img, g, im[q]);
+      oc[q] = a.cell[g];
+      ks[q] = a.keyslot[g];
+      ldv<D>(a.vel, g, v[q]);
+      pid[q] = a.id[g];
+      ldi<D>(a.prev_u, g, pu[q]);
+      ldv<D>(a.prev_off, g, po[q]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kS; ++q) {
+    const int g = ch.y + q * kBlock + (int)threadIdx.x;
+    if (g >= ch.z) continue;
+    int c[D], dd;
+    (void)canon_state<D>(R, a.P.s, oc[q], o[q], c, im[q], dd);
+    const int key = ks[q].x;
+    const int c0 = a.cell_start[key], c1 = a.cell_start[key + 1];
     int dst;
     if (a.first) {
-      dst = a.cell_start[ks.x] + ks.y;
+      dst = c0 + ks[q].y;
     } else {
-      const int lr = ks.y & 0xffffff;
-      const int f1 = (int)((unsigned)ks.y >> 24);
+      const int lr = ks[q].y & 0xffffff;
+      const int f1 = (int)((unsigned)ks[q].y >> 24);
       if (f1 == 0) {
-        dst = a.cell_start[ks.x] + lr;
+        dst = c0 + lr;
       } else {
-        const unsigned* __restrict__ w = a.mcnt + (size_t)ks.x * kArrWords<D>;
+        const unsigned* __restrict__ w = a.mcnt + (size_t)key * kArrWords<D>;
         int tot = 0, pre = 0;
 #pragma unroll
         for (int i = 1; i < kArrWords<D>; ++i) {
@@ -613,29 +637,23 @@ __global__ __launch_bounds__(kBlock) void k_scatter(SortArgs a) {
           }
         }
         // a wrapped byte: the slots cannot be trusted (reported below)
-        dst = (tot == (int)w[0]) ? a.cell_start[ks.x + 1] - tot + pre + lr : -1;
+        dst = (tot == (int)w[0]) ? c1 - tot + pre + lr : -1;
       }
     }
     // a slot outside the cell's range means inconsistent counts (more than
     // 255 arrivals from one direction): reported, and nothing is written out
     // of range
-    if (dst < a.cell_start[ks.x] || dst >= a.cell_start[ks.x + 1]) {
+    if (dst < c0 || dst >= c1) {
       atomicOr(a.err, kErrOverflow);
       continue;
     }
-    float v[D];
-    ldv<D>(a.vel, g, v);
-    stv<D>(a.pos_out, dst, o);
-    stv<D>(a.vel_out, dst, v);
-    sti<D>(a.img_out, dst, im);
-    a.id_out[dst] = a.id[g];
-    a.cell_out[dst] = ks.x;
-    int pu[D];
-    float po[D];
-    ldi<D>(a.prev_u, g, pu);
-    ldv<D>(a.prev_off, g, po);
-    sti<D>(a.prev_u_out, dst, pu);
-    stv<D>(a.prev_off_out, dst, po);
+    stv<D>(a.pos_out, dst, o[q]);
+    stv<D>(a.vel_out, dst, v[q]);
+    sti<D>(a.img_out, dst, im[q]);
+    a.id_out[dst] = pid[q];
+    a.cell_out[dst] = key;
+    sti<D>(a.prev_u_out, dst, pu[q]);
+    stv<D>(a.prev_off_out, dst, po[q]);
   }
 }
 
