@@ -270,10 +270,11 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   if (NT == 0) NT = 256;
   L->bthreads = NT;
   if (D == 2) {
-    // targets per block: about 3/4 of the threads with pair lists, half for
-    // the cell walk (measured best on the 2D workloads)
-    const double cells = (want_list ? 0.75 * NT : 0.5 * NT) / std::max(per_cell, 0.05);
-    if (BY == 0) BY = cells >= (want_list ? 16 : 32) ? 2 : 1;
+    // targets per block: about one per thread in bricks of four rows with
+    // pair lists, half a thread's worth in two rows for the cell walk
+    // (measured best on the 2D workloads)
+    const double cells = (want_list ? 1.0 * NT : 0.5 * NT) / std::max(per_cell, 0.05);
+    if (BY == 0) BY = want_list ? (cells >= 32 ? 4 : (cells >= 16 ? 2 : 1)) : (cells >= 32 ? 2 : 1);
     if (BX == 0) BX = std::max(4, std::min(128, (int)std::lround(cells / BY)));
     BZ = 1;
   } else if (want_list) {

@@ -73,7 +73,7 @@ std::vector<Cand> brick_candidates(const mdlg_config& base, const Cand& c, doubl
     for (double f : {0.75, 1.0, 1.5}) {
       const double cells = f * nt / pc;
       if (D == 2) {
-        for (int by : {1, 2}) {
+        for (int by : {1, 2, 4}) {
           const int bx = std::max(2, (int)std::lround(cells / by));
           if (bx > 128) continue;
           out.push_back({c.k, c.R, bx, by, 1, c.nolist, nt});
