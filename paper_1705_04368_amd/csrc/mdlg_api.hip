@@ -71,6 +71,7 @@ struct Layout {
   int adj_ckpts = 0;   // checkpoints the workspace holds (0 = no adjoint)
   int kmax_adj = 0;    // pair-list slots of the adjoint window (radius r_cut + 2 margin_max; 0 = none)
   int adj_seg = 0;     // segment positions the workspace holds
+  int adj_window = 0;  // longest adjoint window (MD steps)
 };
 
 // Workspace carve-out, in the order buffers are laid out.
@@ -316,8 +317,10 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
     // than a few percent from its mean, and a brick that overflows takes the
     // chunked cell walk)
     const double expect = halo * per_cell;
-    const size_t head = ((size_t)(2 * halo + 1) * sizeof(int) + 15) & ~size_t(15);
-    const size_t coord = (D == 2 ? sizeof(int2) : sizeof(int4));
+    // (the halo tables, and 16-byte alignment of each part of the layout)
+    const size_t head = ((size_t)(2 * halo + 1) * sizeof(int) + 15) / 16 * 16 + 64;
+    // a staged particle: its coordinates and its halo cell (16 bits)
+    const size_t coord = (D == 2 ? sizeof(int2) : sizeof(int4)) + sizeof(unsigned short);
     auto fit = [&](double grow, long long extra, size_t per) {
       long long cap = (long long)std::ceil(grow * expect) + extra;
       cap = (cap + 63) / 64 * 64;
@@ -369,6 +372,8 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
       nsite *= rep.M[a];
     }
     if (cell_off + ncell > (1ll << 30)) return set_err(msg, "too many MD cells");
+    // (a replica has at least three MD cells per axis, checked above)
+    for (int a = 0; a < 2; ++a) div_magic_of(std::max(2, rep.Mc[a]), &rep.dmul[a], &rep.dsh[a]);
     rep.cell_off = (int)cell_off;
     rep.part_off = (int)part_off;
     rep.site_off = (int)site_off;
@@ -397,6 +402,7 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   L->n_shifts = c->n_shifts;
   if (c->adjoint_window > 0) {
     L->adj_ckpts = c->adjoint_window / c->adjoint_every + 1;
+    L->adj_window = c->adjoint_window;
     L->adj_seg = c->adjoint_every + 1;
     // the window's force launches walk pair lists of radius r_cut + 2
     // margin_max, built once at its start (cells stay frozen for the window,
@@ -498,7 +504,7 @@ struct mdlg_system {
   int2* smap = nullptr;
   int4* binfo = nullptr;
   unsigned long long* nl = nullptr;
-  float* off0 = nullptr;
+  unsigned* disp = nullptr;  // displacement bound rows [disp_rows][kDispRow]
   int2* trec = nullptr;
   // adjoint window buffers (sorted order)
   float* adj_off0 = nullptr;
@@ -563,6 +569,10 @@ namespace {
 // byte for each of the 3^d - 1 directions a rebuild can move a particle in.
 int arrival_words(int D) { return D == 2 ? 3 : 8; }
 
+// Rows of the displacement bound: one per MD step of the longest stretch
+// that uses one set of pair lists (a rebuild interval, or an adjoint window).
+int disp_rows(const Layout& L) { return std::max(L.sort_every, L.adj_window) + 1; }
+
 // Accumulators per displaced lattice: Q + 1 counts and d + d(d+1)/2 sums.
 int shift_per(const Layout& L) { return L.Q + 1 + L.D + L.D * (L.D + 1) / 2; }
 
@@ -626,7 +636,7 @@ size_t carve(mdlg_system* S, char* base) {
     S->smap = c.take<int2>(base, (size_t)L.nbricks * L.lcap);
     S->binfo = c.take<int4>(base, (size_t)L.nbricks);
     S->nl = c.take<unsigned long long>(base, (size_t)(std::max(L.kmax, L.kmax_adj) / 4) * N);
-    S->off0 = c.take<float>(base, N * D);
+    S->disp = c.take<unsigned>(base, (size_t)disp_rows(L) * kDispRow);
     S->trec = c.take<int2>(base, (size_t)L.nbricks * L.lcap);
   }
   if (L.adj_ckpts > 0) {
@@ -671,7 +681,12 @@ static void set_list_params(Phys& P, const mdlg_config* c, const Layout& L, doub
   const double row = (2 * rl + L.s) * std::pow(L.s, L.D - 1) * L.per_cell / std::pow(L.s, L.D);
   P.nl_wide = row >= 48 ? 1 : 0;
   P.kmax = kmax;
-  P.disp2 = (float)(margin * margin);
+  P.skin = (float)margin;
+  // half an ulp of the largest offset magnitude s + margin: the rounding of
+  // one drift of an offset
+  int ex = 0;
+  std::frexp((double)L.s + margin, &ex);  // s + margin in [2^(ex-1), 2^ex)
+  P.dslack = (float)std::ldexp(1.0, ex - 1 - 24);
 }
 
 Phys make_phys(const mdlg_config* c, const Layout& L) {
@@ -842,8 +857,9 @@ void enqueue_nlist(mdlg_system* S, const Phys& P) {
   nl.smap = S->smap;
   nl.binfo = S->binfo;
   nl.nl = S->nl;
-  nl.off0 = S->off0;
   nl.trec = S->trec;
+  nl.disp_clear = S->disp;
+  nl.ndisp_clear = disp_rows(S->L);
   nl.nbricks = S->L.nbricks;
   nl.xcd_remap = S->xcd_remap;
   TimedLaunch t(S, MDLG_K_NLIST);
@@ -926,10 +942,13 @@ void enqueue_force(mdlg_system* S, int mode, bool sort_follows, float* acc_out, 
     a.smap = S->smap;
     a.binfo = S->binfo;
     a.nl = S->nl;
-    a.off0 = S->off0;
     a.trec = S->trec;
-    // the rebuild that follows makes new lists
-    a.check_disp = sort_follows ? 0 : 1;
+    // the drifts since the lists were built are checked; this one is
+    // recorded unless the rebuild that follows makes new lists
+    a.disp_in = S->disp;
+    a.ndisp = S->since_sort;
+    const bool drift = (mode == kModeStep || mode == kModeStart);
+    a.disp_out = (drift && !sort_follows) ? S->disp + (size_t)S->since_sort * kDispRow : nullptr;
   }
   {
     TimedLaunch t(S, MDLG_K_FORCE);
@@ -1069,7 +1088,7 @@ mdlg_status read_err(mdlg_system* S) {
   if (e) {
     std::string m = "device error word 0x" + std::to_string(e) + ":";
     if (e & kErrMargin) m += " a particle left its cell by more than the rebuild margin (lower sort_every or dt);";
-    if (e & kErrSkin) m += " a particle moved farther than the rebuild margin since the pair lists were built (lower sort_every or dt);";
+    if (e & kErrSkin) m += " the particles' speeds since the pair lists were built could have carried one farther than the lists' skin (lower sort_every or dt);";
     if (e & kErrRecord) m += " internal: a pair-list target record named no particle;";
     if (e & kErrNonFinite) m += " non-finite coordinates;";
     if (e & kErrJump) m += " a particle moved more than one cell between rebuilds or started outside the box;";
@@ -1186,7 +1205,7 @@ std::vector<Region> ckpt_regions(mdlg_system* S, bool lists) {
     r.push_back({S->smap, (size_t)L.nbricks * L.lcap * sizeof(int2)});
     r.push_back({S->binfo, (size_t)L.nbricks * sizeof(int4)});
     r.push_back({S->nl, (size_t)(L.kmax / 4) * N * sizeof(unsigned long long)});
-    r.push_back({S->off0, N * D * sizeof(float)});
+    r.push_back({S->disp, (size_t)disp_rows(L) * kDispRow * sizeof(unsigned)});
     r.push_back({S->trec, (size_t)L.nbricks * L.lcap * sizeof(int2)});
   }
   return r;
@@ -1773,8 +1792,10 @@ static Phys window_list_phys(const mdlg_system* S) {
   return P;
 }
 
+// kdisp: drifts made since the lists were built (checked, and this one
+// recorded), or -1 for a recomputation of steps already checked.
 static void launch_force_raw(mdlg_system* S, const Phys& P, int mode, const float* pos_in,
-                             float* pos_out, float* vel) {
+                             float* pos_out, float* vel, int kdisp) {
   ForceArgs a{};
   a.P = P;
   if (P.kmax > 0) {
@@ -1782,9 +1803,12 @@ static void launch_force_raw(mdlg_system* S, const Phys& P, int mode, const floa
     a.smap = S->smap;
     a.binfo = S->binfo;
     a.nl = S->nl;
-    a.off0 = S->off0;
     a.trec = S->trec;
-    a.check_disp = 1;
+    if (kdisp >= 0) {
+      a.disp_in = S->disp;
+      a.ndisp = kdisp;
+      a.disp_out = S->disp + (size_t)kdisp * kDispRow;
+    }
   }
   a.reps = S->reps;
   a.bricks = S->bricks;
@@ -1840,7 +1864,7 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
   launch_copy_f32(S->vel[S->scur], S->adj_ckpt_vel, nd, S->stream);
   for (int n = 1; n <= W; ++n) {
     launch_force_raw(S, PF, n == 1 ? kModeStart : kModeStep, S->pos[S->pcur], S->pos[S->pcur ^ 1],
-                     S->vel[S->scur]);
+                     S->vel[S->scur], n - 1);
     S->pcur ^= 1;
     if (n % k == 0 && n < W) {
       launch_copy_f32(S->pos[S->pcur], S->adj_ckpt_pos + (size_t)(n / k) * nd, nd, S->stream);
@@ -1864,7 +1888,7 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
     for (int j = 1; j <= k; ++j)
       launch_force_raw(S, PF, (seg == 0 && j == 1) ? kModeStart : kModeStep,
                        S->adj_seg_pos + (size_t)(j - 1) * nd, S->adj_seg_pos + (size_t)j * nd,
-                       S->adj_vel);
+                       S->adj_vel, -1);
     for (int j = k; j >= (seg == 0 ? 0 : 1); --j) {
       const int sg = seg * k + j;
       AdjArgs a{};

@@ -110,9 +110,14 @@ struct ForceArgs {
   const int2* smap;    // [nbricks][lcap] staged halo in LDS order {particle, hx | hy << 8 | hz << 16}
   const int4* binfo;   // [nbricks] {staged, targets, lists valid, -}
   const unsigned long long* nl;  // [kmax / 4][n_total] four 16-bit halo indices per word
-  const float* off0;   // offsets when the lists were built
   const int2* trec;    // [nbricks][lcap] targets in processing order {particle, slot | words << 16}
-  int check_disp;      // 1: flag drifts farther than sqrt(P.disp2) from off0
+  // displacement bound since the lists were built: rows [0, ndisp) of the
+  // earlier drifts are checked against P.skin by the first block; this
+  // launch's drift is folded into disp_out (null: no later launch uses the
+  // lists)
+  const unsigned* disp_in;
+  int ndisp;
+  unsigned* disp_out;
 };
 
 struct NlistArgs {
@@ -124,8 +129,9 @@ struct NlistArgs {
   int2* smap;
   int4* binfo;
   unsigned long long* nl;
-  float* off0;
   int2* trec;
+  unsigned* disp_clear;  // rows of the displacement bound cleared for the new lists
+  int ndisp_clear;
   int nbricks;
   int xcd_remap;
 };

@@ -23,6 +23,34 @@ constexpr int kMaxHalo3 = 2560;      // halo cells per brick (3D)
 constexpr int kBrickLdsBytes = 60 * 1024;  // dynamic LDS budget of a brick kernel
 constexpr int kMaxRows = 64;         // brick rows (BY * BZ)
 
+// Byte layout of a brick kernel's dynamic LDS: the staged coordinates (cap +
+// pad of `coord` bytes, first, so that a list entry addresses them with one
+// shift), the adjoint velocities (`lam` bytes per staged particle), the halo
+// tables (LDS start and global start of every halo cell) and the halo cell of
+// every staged slot (16 bits), each part on a 16-byte boundary.
+struct BrickLdsLayout {
+  size_t lam, hs, scell, end;
+};
+__host__ __device__ inline size_t lds_up16(size_t x) { return (x + 15) & ~size_t(15); }
+__host__ __device__ inline BrickLdsLayout brick_lds_layout(int cap, int pad, size_t coord, size_t lam,
+                                                           int lmaxh) {
+  BrickLdsLayout o;
+  o.lam = lds_up16((size_t)(cap + pad) * coord);
+  o.hs = o.lam + lds_up16((size_t)cap * lam);
+  o.scell = o.hs + lds_up16((size_t)(2 * lmaxh + 1) * sizeof(int));
+  o.end = o.scell + lds_up16((size_t)cap * sizeof(unsigned short));
+  return o;
+}
+
+// Displacement bound of the pair lists: every force launch that drifts the
+// particles folds the largest squared half-step speed of each wave into one of
+// kDispSlots words (float bits, atomic maximum; one 128-byte line per word
+// so that the waves' updates spread over the memory channels), one row of
+// words per MD step since the lists were built.
+constexpr int kDispSlots = 64;
+constexpr int kDispStride = 32;      // words between two slots of a row
+constexpr int kDispRow = kDispSlots * kDispStride;
+
 // device error word bits
 constexpr unsigned kErrMargin = 1u;     // particle left its cell by more than the rebuild margin
 constexpr unsigned kErrNonFinite = 2u;  // non-finite position or velocity
@@ -48,6 +76,8 @@ enum StepMode : int {
 
 struct Replica {
   int Mc[3];     // MD cells per axis
+  unsigned dmul[2];  // exact division by Mc[0] and Mc[1] (div_magic)
+  int dsh[2];
   int M[3];      // lattice sites per axis
   int cell_off;  // first global MD cell
   int part_off;  // first global particle
@@ -56,6 +86,21 @@ struct Replica {
   int brick_off; // first force brick
   int nbricks;   // force bricks
 };
+
+// Exact quotient n / d for 0 <= n < 2^31 and a divisor d >= 2 given as the
+// multiplier m = ceil(2^(31 + s0) / d) and shift s = s0 - 1, s0 = ceil(log2 d):
+// n m / 2^(31 + s0) exceeds n / d by less than n / 2^(31 + s0) < 1 / d, too
+// little to reach the next integer, so the floor is exact.
+__host__ __device__ inline void div_magic_of(int d, unsigned* m, int* s) {
+  int s0 = 0;
+  while ((1ll << s0) < d) ++s0;
+  const unsigned long long num = 1ull << (31 + s0);
+  *m = (unsigned)((num + (unsigned long long)d - 1) / (unsigned long long)d);
+  *s = s0 - 1;
+}
+__device__ __forceinline__ int div_magic(int n, unsigned m, int s) {
+  return (int)(__umulhi((unsigned)n, m) >> s);
+}
 
 // Global physical and layout parameters (identical for all replicas).
 struct Phys {
@@ -72,7 +117,8 @@ struct Phys {
   int rl16;         // list builder: accept a candidate when |d|^2 < rl16 in 14-bit units
   int nl_wide;      // list builder: test 32 candidates per step (long rows) instead of 16
   int kmax;         // pair-list slots per particle (multiple of 4; 0 = no lists)
-  float disp2;      // largest squared displacement since the lists were built
+  float skin;       // largest displacement allowed since the lists were built
+  float dslack;     // rounding of one drift of an offset (half an ulp of s + margin)
   int lmaxh;        // halo cells of the largest brick (dynamic LDS table)
   int lcap;         // staged particles per LDS chunk
   float sig2_u;     // (sigma / u)^2

@@ -109,13 +109,14 @@ __device__ __forceinline__ int floor_div(int a, int b) {
 
 template <int D>
 __device__ __forceinline__ void cell_coords(int local, const Replica& R, int (&c)[D]) {
-  c[0] = local % R.Mc[0];
+  const int q = div_magic(local, R.dmul[0], R.dsh[0]);
+  c[0] = local - q * R.Mc[0];
   if constexpr (D == 2) {
-    c[1] = local / R.Mc[0];
+    c[1] = q;
   } else {
-    int r = local / R.Mc[0];
-    c[1] = r % R.Mc[1];
-    c[2] = r / R.Mc[1];
+    const int q2 = div_magic(q, R.dmul[1], R.dsh[1]);
+    c[1] = q - q2 * R.Mc[1];
+    c[2] = q2;
   }
 }
 
@@ -737,6 +738,7 @@ template <int D, bool ADJ, class CT = Coord<D>>
 struct BrickLds {
   int* hs;            // LDS start of every halo cell (exclusive scan of counts)
   int* gs;            // global start of every halo cell
+  unsigned short* scell;  // halo cell of every staged slot below cap
   CT* p;              // fixed-point coordinates of the staged particles
   float* lam;         // adjoint velocity of the staged particles (ADJ)
   int* rowpre;
@@ -745,27 +747,22 @@ struct BrickLds {
   int cap;
 };
 
-// Dynamic LDS of the pair-list builder: the 14-bit coordinates with their
-// padding, then the halo tables.
-template <int D>
-__device__ __forceinline__ size_t nlist_lds_bytes_dev(const Phys& P) {
-  const size_t tables = ((size_t)(2 * P.lmaxh + 1) * sizeof(int) + 15) & ~size_t(15);
-  return tables + (((size_t)(P.lcap + kNlPad) * sizeof(Coord14<D>) + 15) & ~size_t(15));
+template <int D, bool ADJ, class CT>
+__device__ __forceinline__ BrickLdsLayout brick_lds_layout_dev(const Phys& P, int pad) {
+  return brick_lds_layout(P.lcap, pad, sizeof(CT), ADJ ? D * sizeof(float) : 0, P.lmaxh);
 }
 
 template <int D, bool ADJ, class CT = Coord<D>>
 __device__ __forceinline__ BrickLds<D, ADJ, CT> brick_lds(char* dyn, int* rowpre, int* tmp,
                                                           double (*red)[4], const Phys& P,
                                                           int pad = 0) {
-  // the staged coordinates come first, at the fixed start of the dynamic LDS,
-  // so that a list entry (a staging index) addresses them with one shift
+  const BrickLdsLayout lay = brick_lds_layout_dev<D, ADJ, CT>(P, pad);
   BrickLds<D, ADJ, CT> L;
   L.p = reinterpret_cast<CT*>(dyn);
-  size_t off = ((size_t)(P.lcap + pad) * sizeof(CT) + 15) & ~size_t(15);
-  L.lam = reinterpret_cast<float*>(dyn + off);
-  if (ADJ) off += (size_t)P.lcap * D * sizeof(float);
-  L.hs = reinterpret_cast<int*>(dyn + off);
+  L.lam = reinterpret_cast<float*>(dyn + lay.lam);
+  L.hs = reinterpret_cast<int*>(dyn + lay.hs);
   L.gs = L.hs + P.lmaxh + 1;
+  L.scell = reinterpret_cast<unsigned short*>(dyn + lay.scell);
   L.rowpre = rowpre;
   L.tmp = tmp;
   L.red = red;
@@ -775,7 +772,25 @@ __device__ __forceinline__ BrickLds<D, ADJ, CT> brick_lds(char* dyn, int* rowpre
 
 struct BrickGeom {
   int ns, nsz, x0, y0, z0, wx, wy, wz, HX, HY, HZ, nh, total, nrows, ntg;
+  float rHX, rHY, rwy;  // reciprocals of HX, HY and wy (small_div)
 };
+
+// q = n / d and r = n % d for 0 <= n < 2^20 and 1 <= d < 2^12, from rd ~ 1 / d
+// (v_rcp, within two ulp): the float quotient lies within a third of n / d,
+// so its truncation is off by at most one either way, which the remainder
+// corrects.
+__device__ __forceinline__ int small_div(int n, int d, float rd, int& r) {
+  int q = (int)((float)n * rd);
+  r = n - q * d;
+  if (r < 0) {
+    q -= 1;
+    r += d;
+  } else if (r >= d) {
+    q += 1;
+    r -= d;
+  }
+  return q;
+}
 
 __device__ __forceinline__ int fixed_coord(int h, float off, const Phys& P) {
   return (h << P.F) + __float2int_rn(off * P.fscale);
@@ -819,11 +834,16 @@ __device__ __forceinline__ BrickGeom brick_setup(const Phys& P, const Replica& R
   G.HY = G.wy + 2 * G.ns;
   G.HZ = G.wz + 2 * G.nsz;
   G.nh = G.HX * G.HY * G.HZ;
+  G.rHX = __builtin_amdgcn_rcpf((float)G.HX);
+  G.rHY = __builtin_amdgcn_rcpf((float)G.HY);
+  G.rwy = __builtin_amdgcn_rcpf((float)G.wy);
   const int ipt = (G.nh + NT - 1) / NT;
   const int h0 = threadIdx.x * ipt, h1 = min(G.nh, h0 + ipt);
   int mysum = 0;
   for (int h = h0; h < h1; ++h) {
-    const int hx = h % G.HX, r = h / G.HX, hy = r % G.HY, hz = r / G.HY;
+    int hx, hy;
+    const int r = small_div(h, G.HX, G.rHX, hx);
+    const int hz = small_div(r, G.HY, G.rHY, hy);
     const int cx = wrap_cell(G.x0 - G.ns + hx, R.Mc[0]);
     const int cy = wrap_cell(G.y0 - G.ns + hy, R.Mc[1]);
     const int cz = (D == 3) ? wrap_cell(G.z0 - G.nsz + hz, R.Mc[2]) : 0;
@@ -837,6 +857,9 @@ __device__ __forceinline__ BrickGeom brick_setup(const Phys& P, const Replica& R
   for (int h = h0; h < h1; ++h) {
     const int cnt = L.hs[h];
     L.hs[h] = run;
+    // the halo cell of each of its slots (for the staging; slots past the
+    // LDS capacity are staged chunk by chunk and search the table instead)
+    for (int v = run, ve = min(run + cnt, L.cap); v < ve; ++v) L.scell[v] = (unsigned short)h;
     run += cnt;
   }
   G.nrows = G.wy * G.wz;
@@ -850,7 +873,9 @@ __device__ __forceinline__ BrickGeom brick_setup(const Phys& P, const Replica& R
       const int r = r0 + (int)threadIdx.x;
       int c = 0;
       if (r < G.nrows) {
-        const int hlo = G.ns + G.HX * ((G.ns + r % G.wy) + G.HY * (G.nsz + r / G.wy));
+        int ry;
+        const int rz = small_div(r, G.wy, G.rwy, ry);
+        const int hlo = G.ns + G.HX * ((G.ns + ry) + G.HY * (G.nsz + rz));
         c = L.hs[hlo + G.wx] - L.hs[hlo];
       }
       int x = c;
@@ -874,19 +899,18 @@ __device__ __forceinline__ int pack_halo(int hx, int hy, int hz) {
 }
 
 // Stage halo particles [cb, ce) (LDS order) as fixed-point coordinates, and
-// their adjoint velocities when `lam` is given.  For the pair lists, `smap`
-// receives every staged particle's {index, packed halo cell} in LDS order
-// (the force kernel's staging map) and `off0` the positions of the brick's
-// own particles (the targets), the reference offsets of the displacement
-// check.
+// their adjoint velocities when `lam` is given.  A slot's halo cell comes from
+// the slot table of brick_setup (one chunk), else from a search of the halo
+// starts.  For the pair lists, `smap` receives every staged particle's
+// {index, packed halo cell} in LDS order: the force kernel's staging map.
 template <int D, int NT, class Lds>
 __device__ __forceinline__ void brick_stage(const BrickGeom& G, const Phys& P,
                                             const float* __restrict__ pos, const float* __restrict__ lam,
-                                            Lds& L, int cb, int ce, int2* __restrict__ smap = nullptr,
-                                            float* __restrict__ off0 = nullptr) {
-  // SU particles per thread in flight (their halo-cell searches, then their
-  // position reads)
+                                            Lds& L, int cb, int ce, int2* __restrict__ smap = nullptr) {
+  // SU particles per thread in flight (their halo cells, then their position
+  // reads)
   constexpr int SU = 4;
+  const bool table = (ce <= L.cap);
   for (int v0 = cb + (int)threadIdx.x; v0 < ce; v0 += SU * NT) {
     int hh[SU], g[SU];
     float p[SU][D];
@@ -895,10 +919,14 @@ __device__ __forceinline__ void brick_stage(const BrickGeom& G, const Phys& P,
       const int v = v0 + u * NT;
       int lo = 0;
       if (v < ce) {
-        int hi = G.nh - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (L.hs[mid] <= v) lo = mid; else hi = mid - 1;
+        if (table) {
+          lo = L.scell[v];
+        } else {
+          int hi = G.nh - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (L.hs[mid] <= v) lo = mid; else hi = mid - 1;
+          }
         }
       }
       hh[u] = lo;
@@ -911,25 +939,23 @@ __device__ __forceinline__ void brick_stage(const BrickGeom& G, const Phys& P,
     for (int u = 0; u < SU; ++u) {
       const int v = v0 + u * NT;
       if (v < ce) {
-        const int hx = hh[u] % G.HX, r = hh[u] / G.HX;
-        if constexpr (D == 2)
-          put_coord(L.p, v - cb, fixed_coord(hx, p[u][0], P), fixed_coord(r, p[u][1], P), 0, P);
-        else
-          put_coord(L.p, v - cb, fixed_coord(hx, p[u][0], P), fixed_coord(r % G.HY, p[u][1], P),
-                    fixed_coord(r / G.HY, p[u][2], P), P);
+        int hx, hy = 0;
+        const int r = small_div(hh[u], G.HX, G.rHX, hx);
+        const int hz = (D == 2) ? 0 : small_div(r, G.HY, G.rHY, hy);
+        if constexpr (D == 2) {
+          hy = r;
+          put_coord(L.p, v - cb, fixed_coord(hx, p[u][0], P), fixed_coord(hy, p[u][1], P), 0, P);
+        } else {
+          put_coord(L.p, v - cb, fixed_coord(hx, p[u][0], P), fixed_coord(hy, p[u][1], P),
+                    fixed_coord(hz, p[u][2], P), P);
+        }
         if (lam) {
           float l[D];
           ldv<D>(lam, g[u], l);
 #pragma unroll
           for (int k = 0; k < D; ++k) L.lam[(v - cb) * D + k] = l[k];
         }
-        if (smap) {
-          const int hy = (D == 2) ? r : r % G.HY, hz = (D == 2) ? 0 : r / G.HY;
-          smap[v - cb] = make_int2(g[u], pack_halo(hx, hy, hz));
-          if (off0 && hx >= G.ns && hx < G.ns + G.wx && hy >= G.ns && hy < G.ns + G.wy &&
-              hz >= G.nsz && hz < G.nsz + G.wz)
-            stv<D>(off0, g[u], p[u]);
-        }
+        if (smap) smap[v - cb] = make_int2(g[u], pack_halo(hx, hy, hz));
       }
     }
   }
@@ -945,8 +971,10 @@ __device__ __forceinline__ void brick_target(const BrickGeom& G, const Lds& L, i
     if (L.rowpre[mid] <= t) lo = mid; else hi = mid - 1;
   }
   const int row = lo;
-  hyi = G.ns + row % G.wy;
-  hzi = G.nsz + row / G.wy;
+  int ry;
+  const int rz = small_div(row, G.wy, G.rwy, ry);
+  hyi = G.ns + ry;
+  hzi = G.nsz + rz;
   const int hbase = G.HX * (hyi + G.HY * hzi);
   vi = L.hs[hbase + G.ns] + (t - L.rowpre[row]);
   int clo = G.ns, chi = G.ns + G.wx - 1;
@@ -1059,16 +1087,17 @@ __device__ __forceinline__ bool row_columns(const BrickGeom& G, const Phys& P, i
 }
 
 // Velocity-Verlet update of one particle from its acceleration f, shared by
-// both force paths; accumulates the kinetic partials.
+// both force paths; accumulates the kinetic partials and, for a drift, the
+// largest squared half-step speed (vmx).
 template <int D>
 __device__ __forceinline__ void vv_update(const ForceArgs& a, const Phys& P, int gi,
                                           const float (&o)[D], const float (&v)[D],
-                                          const float (&f)[D], double (&kin)[D + 1],
-                                          const float (&o0_pre)[D], bool have_o0) {
+                                          const float (&f)[D], double (&kin)[D + 1], float& vmx) {
   float vf[D];
   const bool drift = (a.mode == kModeStep || a.mode == kModeStart);
   float on[D], vh[D];
   bool ok = true;
+  float v2 = 0.f;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     if (a.mode == kModeStep || a.mode == kModeFinish)
@@ -1078,22 +1107,11 @@ __device__ __forceinline__ void vv_update(const ForceArgs& a, const Phys& P, int
     vh[k] = fmaf(P.half_dt, f[k], vf[k]);
     on[k] = fmaf(vh[k], P.dt, o[k]);
     ok = ok && (on[k] >= P.lo) && (on[k] < P.hi);
+    v2 = fmaf(vh[k], vh[k], v2);
   }
   if (drift) {
     if (!ok) atomicOr(a.err, kErrMargin);
-    if (a.check_disp) {
-      float o0[D];
-      if (have_o0) {
-#pragma unroll
-        for (int k = 0; k < D; ++k) o0[k] = o0_pre[k];
-      } else {
-        ldv<D>(a.off0, gi, o0);
-      }
-      float d2 = 0.f;
-#pragma unroll
-      for (int k = 0; k < D; ++k) d2 = fmaf(on[k] - o0[k], on[k] - o0[k], d2);
-      if (!(d2 <= P.disp2)) atomicOr(a.err, kErrSkin);
-    }
+    vmx = fmaxf(vmx, v2);
     stv<D>(a.pos_out, gi, on);
     stv<D>(a.vel, gi, vh);
   } else if (a.mode == kModeFinish) {
@@ -1111,24 +1129,61 @@ __device__ __forceinline__ void vv_update(const ForceArgs& a, const Phys& P, int
   }
 }
 
+// Largest value over the wave.
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// The pair lists hold every pair within r_cut + 2 skin at their build, so
+// they cover every pair within r_cut as long as no particle has moved
+// farther than the skin since.  A particle's drift in one step is
+// |v_half| dt plus the rounding of the offset update, so the sum over the
+// earlier drifts of dt times the largest |v_half| of the step (rows of
+// disp_in), plus that rounding, bounds every displacement; a bound beyond
+// the skin is an error.  Run by one wave, one row per lane.
+__device__ __forceinline__ void check_disp_bound(const unsigned* __restrict__ disp, int nrows, float dt,
+                                              float dslack, float skin, unsigned* err) {
+  const int lane = lane_id();
+  double dsum = 0.0;
+  for (int r0 = 0; r0 < nrows; r0 += 64) {
+    const int r = r0 + lane;
+    if (r < nrows) {
+      const unsigned* row = disp + (size_t)r * kDispRow;
+      unsigned m = 0u;
+#pragma unroll 16
+      for (int q = 0; q < kDispSlots; ++q) m = max(m, row[q * kDispStride]);
+      dsum += sqrt((double)__uint_as_float(m)) * (double)dt + (double)dslack;
+    }
+  }
+  dsum = wave_sum_d(dsum);
+  if (lane == 0 && dsum * (1.0 + 1e-6) > (double)skin) atomicOr(err, kErrSkin);
+}
+
+// Staged coordinates of the four staging indices packed in e.
+template <int D, class Lds>
+__device__ __forceinline__ void list_gather(const Lds& L, unsigned long long e, Coord<D> (&q)[4]) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) q[u] = L.p[(unsigned)(e >> (16 * u)) & 0xffffu];
+}
+
 // Accumulate the LJ acceleration from the four staging indices packed in e.
 template <int D, class Lds>
 __device__ __forceinline__ void list_word(const Lds& L, unsigned long long e, int X, int Y, int Z,
                                           const Phys& P, float (&f)[D]) {
   Coord<D> q[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) q[u] = L.p[(unsigned)(e >> (16 * u)) & 0xffffu];
+  list_gather<D>(L, e, q);
 #pragma unroll
   for (int u = 0; u < 4; ++u) lj_pair_listed<D>(q[u], X, Y, Z, P, f);
 }
 
 // Target record {particle, LDS slot | words << 16} of the list path, with the
-// particle's offset, velocity, reference offset and first list words.
+// particle's offset, velocity and first list words.
 template <int D, int GW>
 __device__ __forceinline__ void list_fetch(const ForceArgs& a, int2 r, bool has, size_t nt,
                                            unsigned long long pad, int& gi, int& t, int& ng,
-                                           float (&o)[D], float (&v)[D], float (&o0)[D],
-                                           unsigned long long (&w)[GW]) {
+                                           float (&o)[D], float (&v)[D], unsigned long long (&w)[GW]) {
   gi = r.x;
   t = r.y & 0xffff;
   if (has && (size_t)(unsigned)gi >= nt) {
@@ -1141,7 +1196,6 @@ __device__ __forceinline__ void list_fetch(const ForceArgs& a, int2 r, bool has,
   if (has) {
     ldv<D>(a.pos_in, gi, o);
     ldv<D>(a.vel, gi, v);
-    if (a.check_disp) ldv<D>(a.off0, gi, o0);
   }
 #pragma unroll
   for (int u = 0; u < GW; ++u) w[u] = (u < ng) ? a.nl[(size_t)u * nt + gi] : pad;
@@ -1172,6 +1226,8 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
 #pragma unroll
   for (int k = 0; k <= D; ++k) kin[k] = 0.0;
 
+  float vmx = 0.f;  // largest squared half-step speed of this thread's drifts
+
   // the list path's first staging-map entries and target record are
   // requested together with the brick's header (their addresses do not
   // depend on it; entries past the brick's counts are ignored)
@@ -1201,11 +1257,9 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
     constexpr int GW = (D == 2) ? 8 : 4;
     const unsigned long long pad = 0x0001000100010001ull * (unsigned)total;
     int gi = 0, t = 0, ng = 0;
-    float o[D], v[D], o0[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) o0[k] = 0.f;
+    float o[D], v[D];
     unsigned long long w[GW];
-    list_fetch<D, GW>(a, pre_r, (int)threadIdx.x < ntg, nt, pad, gi, t, ng, o, v, o0, w);
+    list_fetch<D, GW>(a, pre_r, (int)threadIdx.x < ntg, nt, pad, gi, t, ng, o, v, w);
     if (threadIdx.x == 0) {
       if constexpr (D == 2) L.p[total] = make_int2(kSentinel, kSentinel);
       else L.p[total] = make_int4(kSentinel, kSentinel, kSentinel, 0);
@@ -1248,8 +1302,7 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
     __syncthreads();
     for (int tb = 0; tb < ntg; tb += NT) {
       if (tb + (int)threadIdx.x >= ntg) break;
-      if (tb > 0)
-        list_fetch<D, GW>(a, trec[tb + threadIdx.x], true, nt, pad, gi, t, ng, o, v, o0, w);
+      if (tb > 0) list_fetch<D, GW>(a, trec[tb + threadIdx.x], true, nt, pad, gi, t, ng, o, v, w);
       const Coord<D> me = L.p[t];
       const int X = me.x, Y = me.y;
       int Z = 0;
@@ -1279,7 +1332,7 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
           for (int u = 0; u < GW; ++u) w[u] = nx[u];
         }
       }
-      vv_update<D>(a, P, gi, o, v, f, kin, o0, true);
+      vv_update<D>(a, P, gi, o, v, f, kin, vmx);
     }
   } else {
     const Replica R = a.reps[br.x];
@@ -1339,7 +1392,7 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
           }
         }
       }
-      if (valid) vv_update<D>(a, P, gi, o, v, f, kin, o, false);
+      if (valid) vv_update<D>(a, P, gi, o, v, f, kin, vmx);
     }
   }
   if (a.kpart) {
@@ -1356,6 +1409,15 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
       a.kpart[(size_t)b * (D + 1) + threadIdx.x] = s;
     }
   }
+  if (a.disp_out) {
+    // this drift's largest squared half-step speed, one atomic per wave
+    // (non-negative floats order as their bit patterns)
+    const float m = wave_max_f(vmx);
+    if (lane_id() == 0 && m > 0.f)
+      atomicMax(a.disp_out + (size_t)(b & (kDispSlots - 1)) * kDispStride, __float_as_uint(m));
+  }
+  if (a.ndisp > 0 && b == 0 && threadIdx.x < 64)
+    check_disp_bound(a.disp_in, a.ndisp, P.dt, P.dslack, P.skin, a.err);
 }
 
 // Pair lists of one brick, built right after each cell-list rebuild (all
@@ -1461,8 +1523,8 @@ __device__ __forceinline__ void nlist_brick(const NlistArgs& a) {
   __shared__ int s_cnt[64];
   auto L = brick_lds<D, false, Coord14<D>>(s_dyn_brick, s_rowpre, s_tmp, s_red, a.P, kNlPad);
   // word count of every target's list (dynamic LDS behind the brick's own)
-  unsigned char* s_words =
-      reinterpret_cast<unsigned char*>(s_dyn_brick) + nlist_lds_bytes_dev<D>(a.P);
+  unsigned char* s_words = reinterpret_cast<unsigned char*>(s_dyn_brick) +
+                           brick_lds_layout_dev<D, false, Coord14<D>>(a.P, kNlPad).end;
   const int CAP = L.cap;
   int b = blockIdx.x;
   if (a.xcd_remap) {
@@ -1476,8 +1538,12 @@ __device__ __forceinline__ void nlist_brick(const NlistArgs& a) {
   if (threadIdx.x == 0) s_over = 0;
   const BrickGeom G = brick_setup<D, NT>(P, R, br, a.cell_start, L);
   const bool fits = G.total < CAP;  // one slot stays free for the padding sentinel
-  int2* __restrict__ smap = a.smap + (size_t)b * CAP;
-  if (fits) brick_stage<D, NT>(G, P, a.pos, nullptr, L, 0, G.total, smap, a.off0);
+  if (fits) brick_stage<D, NT>(G, P, a.pos, nullptr, L, 0, G.total, a.smap + (size_t)b * CAP);
+  if (b == 0) {
+    // a new displacement bound starts with these lists
+    for (int i = threadIdx.x; i < a.ndisp_clear * kDispSlots; i += NT)
+      a.disp_clear[(size_t)(i / kDispSlots) * kDispRow + (i % kDispSlots) * kDispStride] = 0u;
+  }
   __syncthreads();
   const size_t nt = (size_t)P.n_total;
   const int kmax = P.kmax;
@@ -1485,18 +1551,12 @@ __device__ __forceinline__ void nlist_brick(const NlistArgs& a) {
   for (int tb = 0; tb < G.ntg; tb += NT) {
     const int t = tb + (int)threadIdx.x;
     if (t >= G.ntg) break;
+    if (!fits) break;  // (block-uniform) the brick walks its cells
     int hxi, hyi, hzi, gi, vi;
     brick_target<D>(G, L, t, hxi, hyi, hzi, gi, vi);
-    if (!fits) {
-      // the cell walk's displacement check still reads the reference offsets
-      float o[D];
-      ldv<D>(a.pos, gi, o);
-      stv<D>(a.off0, gi, o);
-      continue;
-    }
-    // the target's own 14-bit coordinates (its reference offset was stored
-    // by the staging) and the fixed-point coordinates they stand for, within
-    // half a 14-bit unit, which widens the reach and the row bounds
+    // the target's own 14-bit coordinates and the fixed-point coordinates
+    // they stand for, within half a 14-bit unit, which widens the reach and
+    // the row bounds
     const Coord14<D> me = L.p[vi];
     unsigned Txy;
     int Tz = 0;
@@ -2418,9 +2478,8 @@ void launch_rescale(int D, int nchunks, const RescaleArgs& a, hipStream_t s) {
 }
 
 size_t brick_lds_bytes(const Phys& P, int D, bool adj) {
-  const size_t tables = ((size_t)(2 * P.lmaxh + 1) * sizeof(int) + 15) & ~size_t(15);
   const size_t coord = (D == 2) ? sizeof(int2) : sizeof(int4);
-  return tables + (size_t)P.lcap * (coord + (adj ? D * sizeof(float) : 0));
+  return brick_lds_layout(P.lcap, 0, coord, adj ? D * sizeof(float) : 0, P.lmaxh).end;
 }
 
 // Brick kernels come in 64-, 128- and 256-thread blocks (P.bthreads).
@@ -2449,10 +2508,8 @@ void launch_nlist(int D, const NlistArgs& a, hipStream_t s) {
   if (a.xcd_remap) grid = ((a.nbricks + 7) / 8) * 8;
   // the brick's LDS (14-bit coordinates) plus one byte per target for the
   // list word counts
-  const size_t tables = ((size_t)(2 * a.P.lmaxh + 1) * sizeof(int) + 15) & ~size_t(15);
   const size_t coord = (D == 2) ? sizeof(unsigned) : sizeof(uint2);
-  const size_t lds = tables + (((size_t)(a.P.lcap + kNlPad) * coord + 15) & ~size_t(15)) +
-                     (size_t)a.P.lcap;
+  const size_t lds = brick_lds_layout(a.P.lcap, kNlPad, coord, 0, a.P.lmaxh).end + (size_t)a.P.lcap;
   // 16 or 32 candidates per test step: separate instantiations, so that
   // neither carries the other's registers
   if (a.P.nl_wide) MDLG_LAUNCH_BRICK(D, a.P.bthreads, k_nlist_wide, grid, lds, s, a);
