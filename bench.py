@@ -77,14 +77,13 @@ def pairs_per_particle(dim, rho, rc=2.5):
 def force_bytes_per_particle(dim, rho=None, rl=None):
     """HBM bytes per particle of one force/velocity-Verlet step, reported
     beside the FP32 bound: read and write offset and velocity; on the
-    pair-list path (list radius rl) also the reference offset of the
-    displacement check and the list, 2 bytes per neighbour within rl at
-    uniform density."""
+    pair-list path (list radius rl) also the list, 2 bytes per neighbour
+    within rl at uniform density."""
     base = 16 * dim
     if rl is None:
         return base
     vol = math.pi * rl * rl if dim == 2 else 4.0 / 3.0 * math.pi * rl ** 3
-    return base + 4 * dim + 2 * vol * rho
+    return base + 2 * vol * rho
 
 
 # FLOPs per interacting pair of the adjoint's reverse step: the force term
@@ -752,6 +751,7 @@ def main():
     nch = min(5, args.steps)
     sizes = [args.steps // nch + (1 if i < args.steps % nch else 0) for i in range(nch)]
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(nch + 1)]
+    fallbacks0 = sysg.list_fallbacks()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     evs[0].record(sysg.stream)
@@ -768,6 +768,7 @@ def main():
     repeats = {"chunks": nch, "lattice_steps": sizes, "values": chunk_values,
                "median": float(np.median(chunk_values))}
     print(f"# timed {args.steps} lattice steps in {elapsed:.4f} s", file=sys.stderr, flush=True)
+    fallbacks = sysg.list_fallbacks() - fallbacks0
     f = sysg.get_f(per_site=ensemble)
     assert f["counts"].sum() + f["n_overflow"] == n * f["n_lattice_steps"]
 
@@ -827,7 +828,8 @@ def main():
         "config": {"workload": w["desc"], "lattice_steps": args.steps, "md_steps": md_steps,
                    "particles": n, "md_cell_split": lay["md_cell_split"], "sort_every": lay["sort_every"],
                    "brick": list(lay["brick"]), "block_threads": lay["block_threads"],
-                   "pair_slots": lay["pair_slots"], "autotuned": tuned_ms is not None,
+                   "pair_slots": lay["pair_slots"], "list_skin": lay["skin"],
+                   "list_fallback_launches": fallbacks, "autotuned": tuned_ms is not None,
                    "collision_stats": args.collision_stats, "galilean_lattices": args.galilean},
         "roofline": roofline,
         "cpu_baseline": cpu,

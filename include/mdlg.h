@@ -330,6 +330,16 @@ mdlg_status mdlg_set_timing(mdlg_system *sys, int enable);
  * timing was enabled (synchronises).  Both arrays are host [MDLG_K_NCLASS]. */
 mdlg_status mdlg_get_timing(mdlg_system *sys, double *total_ms, int64_t *launches);
 
+/* Force launches since creation that walked the cells because the pair
+ * lists might have been stale: the pair lists hold the pairs within
+ * r_cut + 2 skin of their build, and each MD step folds the largest
+ * half-step speed into a bound on every particle's displacement since; a
+ * launch whose bound passes the skin walks the cell rows instead (exact for
+ * moves within the rebuild margin), until the next rebuild.  A measure of
+ * how often the skin (sized from the expected largest speed of the
+ * system's particles) is too small.  Synchronises; *launches is host. */
+mdlg_status mdlg_get_list_fallbacks(mdlg_system *sys, int64_t *launches);
+
 /* Wait for all work queued on the handle's stream; report the error word. */
 mdlg_status mdlg_sync(mdlg_system *sys);
 

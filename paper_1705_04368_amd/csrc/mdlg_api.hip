@@ -59,6 +59,7 @@ struct Layout {
   std::vector<Replica> reps;
   std::vector<int4> bricks, chunks, cchunks, strips;
   double s = 0, margin = 0, margin_max = 0;
+  double vfast = 0;  // design speed of the rebuild margin (8 (kT/m)^(1/2))
   double skin = 0;     // pair-list skin: lists of radius r_cut + 2 skin
   int sort_every = 1;
   int halo_cells = 0;  // halo cells of the largest force brick
@@ -255,11 +256,22 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
                    L->ns * L->s, c->r_cut);
   L->sort_every = R;
   L->margin_max = m_max;
+  L->vfast = vfast;
   L->margin = (vfast > 0) ? std::min(m_max, R * vfast * c->dt) : m_max;
   if (L->margin < 0) L->margin = 0;
-  // the pair lists' skin is the margin: a particle moving farther since the
-  // lists were built is reported (a device error)
+  // the pair lists' skin: R drifts at a speed that the fastest of the
+  // n_total particles passes only rarely (a Maxwell tail of about e^-5 per
+  // step: v^2 = (kT/m) (2 ln n + 10) in 2D, + 14 in 3D for the extra degree
+  // of freedom), at most the margin.  The force kernel bounds the actual
+  // drifts since the build; past the skin the bricks walk their cells (exact
+  // within the margin) until the next rebuild.
   L->skin = L->margin;
+  if (vfast > 0) {
+    const double vs = std::min(8.0, std::sqrt(2.0 * std::log((double)std::max(2ll, n_total)) +
+                                              (D == 3 ? 14.0 : 10.0))) *
+                      std::sqrt(c->kT / c->mass);
+    L->skin = std::min(L->margin, R * vs * c->dt);
+  }
   // a particle then sits less than one cell outside its own (the pair-list
   // builder's coordinate range relies on it)
   if (L->margin >= L->s) return set_err(msg, "rebuild margin %g reaches the cell side %g", L->margin, L->s);
@@ -505,6 +517,8 @@ struct mdlg_system {
   int4* binfo = nullptr;
   unsigned long long* nl = nullptr;
   unsigned* disp = nullptr;  // displacement bound rows [disp_rows][kDispRow]
+  unsigned long long* fallbacks = nullptr;  // force launches that walked cells for stale lists
+  unsigned* stale = nullptr;  // [disp_rows] lists possibly stale after that many drifts
   int2* trec = nullptr;
   // adjoint window buffers (sorted order)
   float* adj_off0 = nullptr;
@@ -523,6 +537,7 @@ struct mdlg_system {
   int pcur = 0, scur = 0;
   bool vel_full = true;
   int since_sort = 0;
+  int adj_window_steps = 0;  // MD steps of the adjoint window in progress
   long long md_step = 0;
   long long n_lattice = 0;
   bool snapshot_valid = false;
@@ -637,6 +652,8 @@ size_t carve(mdlg_system* S, char* base) {
     S->binfo = c.take<int4>(base, (size_t)L.nbricks);
     S->nl = c.take<unsigned long long>(base, (size_t)(std::max(L.kmax, L.kmax_adj) / 4) * N);
     S->disp = c.take<unsigned>(base, (size_t)disp_rows(L) * kDispRow);
+    S->fallbacks = c.take<unsigned long long>(base, 1);
+    S->stale = c.take<unsigned>(base, (size_t)disp_rows(L));
     S->trec = c.take<int2>(base, (size_t)L.nbricks * L.lcap);
   }
   if (L.adj_ckpts > 0) {
@@ -682,6 +699,9 @@ static void set_list_params(Phys& P, const mdlg_config* c, const Layout& L, doub
   P.nl_wide = row >= 48 ? 1 : 0;
   P.kmax = kmax;
   P.skin = (float)margin;
+  // speed cap of one drift: the margin's design speed
+  const double vcap = L.vfast > 0 ? L.vfast : margin / c->dt;
+  P.vcap2 = (float)(vcap * vcap);
   // half an ulp of the largest offset magnitude s + margin: the rounding of
   // one drift of an offset
   int ex = 0;
@@ -860,6 +880,7 @@ void enqueue_nlist(mdlg_system* S, const Phys& P) {
   nl.trec = S->trec;
   nl.disp_clear = S->disp;
   nl.ndisp_clear = disp_rows(S->L);
+  nl.stale_clear = S->stale;
   nl.nbricks = S->L.nbricks;
   nl.xcd_remap = S->xcd_remap;
   TimedLaunch t(S, MDLG_K_NLIST);
@@ -945,10 +966,15 @@ void enqueue_force(mdlg_system* S, int mode, bool sort_follows, float* acc_out, 
     a.trec = S->trec;
     // the drifts since the lists were built are checked; this one is
     // recorded unless the rebuild that follows makes new lists
+    a.stale_in = S->stale + S->since_sort;
     a.disp_in = S->disp;
     a.ndisp = S->since_sort;
     const bool drift = (mode == kModeStep || mode == kModeStart);
-    a.disp_out = (drift && !sort_follows) ? S->disp + (size_t)S->since_sort * kDispRow : nullptr;
+    if (drift && !sort_follows) {
+      a.disp_out = S->disp + (size_t)S->since_sort * kDispRow;
+      a.stale_out = S->stale + S->since_sort + 1;
+    }
+    a.fallbacks = S->fallbacks;
   }
   {
     TimedLaunch t(S, MDLG_K_FORCE);
@@ -1088,7 +1114,6 @@ mdlg_status read_err(mdlg_system* S) {
   if (e) {
     std::string m = "device error word 0x" + std::to_string(e) + ":";
     if (e & kErrMargin) m += " a particle left its cell by more than the rebuild margin (lower sort_every or dt);";
-    if (e & kErrSkin) m += " the particles' speeds since the pair lists were built could have carried one farther than the lists' skin (lower sort_every or dt);";
     if (e & kErrRecord) m += " internal: a pair-list target record named no particle;";
     if (e & kErrNonFinite) m += " non-finite coordinates;";
     if (e & kErrJump) m += " a particle moved more than one cell between rebuilds or started outside the box;";
@@ -1206,6 +1231,7 @@ std::vector<Region> ckpt_regions(mdlg_system* S, bool lists) {
     r.push_back({S->binfo, (size_t)L.nbricks * sizeof(int4)});
     r.push_back({S->nl, (size_t)(L.kmax / 4) * N * sizeof(unsigned long long)});
     r.push_back({S->disp, (size_t)disp_rows(L) * kDispRow * sizeof(unsigned)});
+    r.push_back({S->stale, (size_t)disp_rows(L) * sizeof(unsigned)});
     r.push_back({S->trec, (size_t)L.nbricks * L.lcap * sizeof(int2)});
   }
   return r;
@@ -1327,6 +1353,7 @@ mdlg_status mdlg_create(const mdlg_config* cfg, void* workspace_dev, size_t work
     launch_fill_u32(S->mcnt[i], 0u, L.n_cells * arrival_words(L.D), S->stream);
   launch_fill_u32(S->err, 0u, 64, S->stream);
   launch_fill_f32(S->lambda, 1.f, (long long)L.reps.size(), S->stream);
+  if (S->fallbacks) launch_fill_u32(reinterpret_cast<unsigned*>(S->fallbacks), 0u, 2, S->stream);
   zero_accumulators(S);
   // ingest into set 0, then the first counting sort
   IngestArgs ia{};
@@ -1805,9 +1832,15 @@ static void launch_force_raw(mdlg_system* S, const Phys& P, int mode, const floa
     a.nl = S->nl;
     a.trec = S->trec;
     if (kdisp >= 0) {
+      a.stale_in = S->stale + kdisp;
       a.disp_in = S->disp;
       a.ndisp = kdisp;
       a.disp_out = S->disp + (size_t)kdisp * kDispRow;
+      a.stale_out = S->stale + kdisp + 1;
+      a.fallbacks = S->fallbacks;
+    } else {
+      // a recomputation inside the window: the flag at its end covers it
+      a.stale_in = S->stale + S->adj_window_steps;
     }
   }
   a.reps = S->reps;
@@ -1857,6 +1890,7 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
   // the window's force launches (forward and recomputed) walk pair lists
   // built here on the frozen cells
   const Phys PF = L.kmax_adj > 0 ? window_list_phys(S) : PW;
+  S->adj_window_steps = W;
   if (PF.kmax > 0) enqueue_nlist(S, PF);
   // forward window with checkpoints
   launch_copy_f32(S->pos[S->pcur], S->adj_off0, nd, S->stream);
@@ -1913,6 +1947,7 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
         a.trec = S->trec;
         a.nl = S->nl;
         a.lcap_list = PF.lcap;
+        a.stale = S->stale + W;
       }
       TimedLaunch t(S, MDLG_K_ADJOINT);
       launch_adjoint(D, a, S->stream);
@@ -1940,6 +1975,17 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
   if (dL_deps) *dL_deps = out[1];
   if (dL_dsigma) *dL_dsigma = out[2];
   return st;
+}
+
+mdlg_status mdlg_get_list_fallbacks(mdlg_system* S, int64_t* launches) {
+  if (!S || !launches) return MDLG_E_INVALID;
+  unsigned long long v = 0;
+  if (S->fallbacks) {
+    HIPCHK(S, hipMemcpyAsync(&v, S->fallbacks, sizeof v, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(S, hipStreamSynchronize(S->stream));
+  }
+  *launches = (int64_t)v;
+  return read_err(S);
 }
 
 mdlg_status mdlg_checkpoint_bytes(mdlg_system* S, size_t* bytes) {

@@ -111,13 +111,18 @@ struct ForceArgs {
   const int4* binfo;   // [nbricks] {staged, targets, lists valid, -}
   const unsigned long long* nl;  // [kmax / 4][n_total] four 16-bit halo indices per word
   const int2* trec;    // [nbricks][lcap] targets in processing order {particle, slot | words << 16}
-  // displacement bound since the lists were built: rows [0, ndisp) of the
-  // earlier drifts are checked against P.skin by the first block; this
-  // launch's drift is folded into disp_out (null: no later launch uses the
-  // lists)
+  // displacement bound since the lists were built: stale_in set means the
+  // lists may miss a pair and every brick walks its cells (counted in
+  // fallbacks).  Unless no later launch uses the lists (disp_out null), this
+  // launch folds its drift into row disp_out and sets stale_out when the
+  // bound over rows [0, ndisp) of disp_in, plus this drift at the speed cap,
+  // passes P.skin, or when a speed passes the cap.
+  const unsigned* stale_in;
   const unsigned* disp_in;
   int ndisp;
   unsigned* disp_out;
+  unsigned* stale_out;
+  unsigned long long* fallbacks;
 };
 
 struct NlistArgs {
@@ -132,6 +137,7 @@ struct NlistArgs {
   int2* trec;
   unsigned* disp_clear;  // rows of the displacement bound cleared for the new lists
   int ndisp_clear;
+  unsigned* stale_clear;  // their staleness flags, cleared too
   int nbricks;
   int xcd_remap;
 };
@@ -279,6 +285,9 @@ struct AdjArgs {
   const int2* trec;    // [nbricks][lcap_list] targets {particle, LDS slot | words << 16}
   const unsigned long long* nl;
   int lcap_list;
+  // set when the window's drifts may have made the lists stale: the bricks
+  // then walk their cells
+  const unsigned* stale;
 };
 
 struct AdjLossArgs {

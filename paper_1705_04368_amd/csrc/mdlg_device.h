@@ -57,7 +57,6 @@ constexpr unsigned kErrNonFinite = 2u;  // non-finite position or velocity
 constexpr unsigned kErrJump = 4u;       // moved more than one cell between rebuilds / bad input
 constexpr unsigned kErrImage = 8u;      // image counter or unwrapped cell out of range
 constexpr unsigned kErrOverflow = 16u;  // more particles in one cell than a slot can index
-constexpr unsigned kErrSkin = 32u;      // moved farther than the margin since the pair lists were built
 constexpr unsigned kErrRecord = 64u;    // a pair-list target record names no particle (internal)
 
 // pair lists: halo-local indices of 16 bits, four per 64-bit word; at most
@@ -118,6 +117,7 @@ struct Phys {
   int nl_wide;      // list builder: test 32 candidates per step (long rows) instead of 16
   int kmax;         // pair-list slots per particle (multiple of 4; 0 = no lists)
   float skin;       // largest displacement allowed since the lists were built
+  float vcap2;      // squared speed cap of one drift in the lists' displacement bound
   float dslack;     // rounding of one drift of an offset (half an ulp of s + margin)
   int lmaxh;        // halo cells of the largest brick (dynamic LDS table)
   int lcap;         // staged particles per LDS chunk

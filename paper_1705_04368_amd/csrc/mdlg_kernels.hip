@@ -1136,29 +1136,39 @@ __device__ __forceinline__ float wave_max_f(float v) {
   return v;
 }
 
+// Largest value over the wave (unsigned).
+__device__ __forceinline__ unsigned wave_max_u(unsigned v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, o, 64));
+  return v;
+}
+
 // The pair lists hold every pair within r_cut + 2 skin at their build, so
 // they cover every pair within r_cut as long as no particle has moved
 // farther than the skin since.  A particle's drift in one step is
 // |v_half| dt plus the rounding of the offset update, so the sum over the
-// earlier drifts of dt times the largest |v_half| of the step (rows of
-// disp_in), plus that rounding, bounds every displacement; a bound beyond
-// the skin is an error.  Run by one wave, one row per lane.
-__device__ __forceinline__ void check_disp_bound(const unsigned* __restrict__ disp, int nrows, float dt,
-                                              float dslack, float skin, unsigned* err) {
+// drifts since the build of dt times the step's largest |v_half| (rows of
+// disp, one slot word per lane), plus that rounding, bounds every
+// displacement.  This returns that sum over rows [0, nrows) plus an
+// allowance of `extra` for one more drift.  One wave.
+__device__ __forceinline__ double disp_bound(const unsigned* __restrict__ disp, int nrows, float dt,
+                                             float dslack, double extra) {
   const int lane = lane_id();
-  double dsum = 0.0;
-  for (int r0 = 0; r0 < nrows; r0 += 64) {
-    const int r = r0 + lane;
-    if (r < nrows) {
-      const unsigned* row = disp + (size_t)r * kDispRow;
-      unsigned m = 0u;
-#pragma unroll 16
-      for (int q = 0; q < kDispSlots; ++q) m = max(m, row[q * kDispStride]);
-      dsum += sqrt((double)__uint_as_float(m)) * (double)dt + (double)dslack;
+  double dsum = extra + (double)dslack;
+  for (int r0 = 0; r0 < nrows; r0 += 8) {
+    unsigned m[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      m[i] = (r0 + i < nrows) ? disp[(size_t)(r0 + i) * kDispRow + lane * kDispStride] : 0u;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (r0 + i < nrows) {
+        const unsigned w = wave_max_u(m[i]);
+        dsum += sqrt((double)__uint_as_float(w)) * (double)dt + (double)dslack;
+      }
     }
   }
-  dsum = wave_sum_d(dsum);
-  if (lane == 0 && dsum * (1.0 + 1e-6) > (double)skin) atomicOr(err, kErrSkin);
+  return dsum;
 }
 
 // Staged coordinates of the four staging indices packed in e.
@@ -1239,7 +1249,11 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
     pre_r = a.trec[(size_t)b * CAP + min((int)threadIdx.x, CAP - 1)];
   }
   const int4 bi = a.nl ? a.binfo[b] : make_int4(0, 0, 0, 0);
-  if (bi.z) {
+  // (uniform) whether the drifts since the lists were built may have carried
+  // a particle farther than the skin: then the brick walks its cells, which
+  // is exact for any move within the cell margin
+  const bool stale = a.stale_in ? (*a.stale_in != 0u) : false;
+  if (bi.z && !stale) {
     // pair-list path: stage the halo through the map written by the list
     // builder (halo cells in order), then each target walks its own list.  The
     // targets come in the builder's order (decreasing list length, so that
@@ -1411,13 +1425,26 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
   }
   if (a.disp_out) {
     // this drift's largest squared half-step speed, one atomic per wave
-    // (non-negative floats order as their bit patterns)
+    // (non-negative floats order as their bit patterns); a speed above the
+    // cap marks the lists stale for the next launch at once
     const float m = wave_max_f(vmx);
-    if (lane_id() == 0 && m > 0.f)
+    if (lane_id() == 0 && m > 0.f) {
       atomicMax(a.disp_out + (size_t)(b & (kDispSlots - 1)) * kDispStride, __float_as_uint(m));
+      if (m > P.vcap2) atomicOr(a.stale_out, 1u);
+    }
+    // the next launch's flag from the first block: the bound over the
+    // completed drifts plus this one at the cap, or a flag already set
+    if (b == 0 && threadIdx.x < 64) {
+      const double bound = disp_bound(a.disp_in, a.ndisp, P.dt, P.dslack,
+                                      (double)sqrtf(P.vcap2) * (double)P.dt);
+      if (threadIdx.x == 0) {
+        if (stale || bound * (1.0 + 1e-6) > (double)P.skin) atomicOr(a.stale_out, 1u);
+        if (stale && a.fallbacks) atomicAdd(a.fallbacks, 1ull);
+      }
+    }
+  } else if (stale && b == 0 && threadIdx.x == 0 && a.fallbacks) {
+    atomicAdd(a.fallbacks, 1ull);
   }
-  if (a.ndisp > 0 && b == 0 && threadIdx.x < 64)
-    check_disp_bound(a.disp_in, a.ndisp, P.dt, P.dslack, P.skin, a.err);
 }
 
 // Pair lists of one brick, built right after each cell-list rebuild (all
@@ -1543,6 +1570,7 @@ __device__ __forceinline__ void nlist_brick(const NlistArgs& a) {
     // a new displacement bound starts with these lists
     for (int i = threadIdx.x; i < a.ndisp_clear * kDispSlots; i += NT)
       a.disp_clear[(size_t)(i / kDispSlots) * kDispRow + (i % kDispSlots) * kDispStride] = 0u;
+    for (int i = threadIdx.x; i < a.ndisp_clear; i += NT) a.stale_clear[i] = 0u;
   }
   __syncthreads();
   const size_t nt = (size_t)P.n_total;
@@ -1744,6 +1772,9 @@ __global__ __launch_bounds__(NT) void k_adjoint(AdjArgs a) {
   const Phys& P = a.P;
   const int4 br = a.bricks[b];
   const Replica R = a.reps[br.x];
+  // (the flag after the whole forward window covers each of its positions:
+  // once set, it stays set)
+  const bool stale = a.nl && a.stale && *a.stale != 0u;
   const BrickGeom G = brick_setup<D, NT>(P, R, br, a.cell_start, L);
   const int nchunks = (G.total + CAP - 1) / CAP;
   const bool interact = !P.forces_off;
@@ -1751,7 +1782,7 @@ __global__ __launch_bounds__(NT) void k_adjoint(AdjArgs a) {
   // the window's pair lists, where the brick's halo fits one chunk: entries
   // index the halo staged in cell order, as here
   const int4 bi = a.nl ? a.binfo[b] : make_int4(0, 0, 0, 0);
-  const bool listed = interact && bi.z && bi.x == G.total && G.total < CAP;
+  const bool listed = interact && bi.z && !stale && bi.x == G.total && G.total < CAP;
   if (interact && nchunks == 1) {
     brick_stage<D, NT>(G, P, a.pos, a.lam_v_in, L, 0, G.total);
     if (listed && threadIdx.x == 0) {

@@ -24,7 +24,7 @@ EXPORTED = ["mdlg_describe", "mdlg_workspace_bytes", "mdlg_create", "mdlg_step",
             "mdlg_set_timing", "mdlg_get_timing", "mdlg_sync", "mdlg_last_error", "mdlg_destroy",
             "mdlg_autotune", "mdlg_autotune_workspace_bytes", "mdlg_get_xi", "mdlg_get_shifts",
             "mdlg_checkpoint_bytes", "mdlg_checkpoint_save", "mdlg_checkpoint_load",
-            "mdlg_create_static"]
+            "mdlg_create_static", "mdlg_get_list_fallbacks"]
 LOSSES = {"msd": 0, "mean_x": 1}
 KERNEL_CLASSES = ["force", "count", "scan", "scatter", "bin", "nlist", "xi", "shift", "adjoint"]
 
@@ -111,6 +111,8 @@ def load():
     lib.mdlg_set_timing.argtypes = [C.c_void_p, C.c_int]
     lib.mdlg_get_timing.restype = st
     lib.mdlg_get_timing.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.mdlg_get_list_fallbacks.restype = st
+    lib.mdlg_get_list_fallbacks.argtypes = [C.c_void_p, C.c_void_p]
     lib.mdlg_sync.restype = st
     lib.mdlg_sync.argtypes = [C.c_void_p]
     lib.mdlg_last_error.restype = C.c_char_p
@@ -371,6 +373,12 @@ class System:
         _check(load().mdlg_get_timing(self.handle, ms.ctypes.data_as(C.c_void_p),
                                       n.ctypes.data_as(C.c_void_p)), self.handle)
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def list_fallbacks(self):
+        """Force launches that walked the cells for possibly stale pair lists."""
+        n = C.c_int64(0)
+        _check(load().mdlg_get_list_fallbacks(self.handle, C.byref(n)), self.handle)
+        return int(n.value)
 
     def checkpoint(self):
         """The complete state as a host byte array (mdlg_checkpoint_save)."""
