@@ -12,7 +12,7 @@ constexpr int kScanTile = 1024;      // cells per block of the cell-start scan
 constexpr int kTileCopies = 8;       // copies of the scan-tile totals (one per XCD of the adding block)
 constexpr int kScanItems = kScanTile / kBlock;
 constexpr int kPartChunkMax = 512;   // particles per block of the per-particle kernels
-constexpr int kCountChunkMax = 4096; // particles per block of the counting pass (at most)
+constexpr int kCountChunkMax = 2048; // particles per block of the counting pass (at most)
 constexpr int kMaxStripSites = 16;   // lattice sites per block of the binning kernel
 constexpr int kMaxQ = 225;           // largest velocity window handled (V <= 7 in 2D, V <= 2 in 3D)
 constexpr int kMaxShifts = 32;       // displaced / moving lattices binned beside the main one

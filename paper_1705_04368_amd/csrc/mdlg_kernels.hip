@@ -401,8 +401,10 @@ __global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
   __syncthreads();
   int key[kPer], dir[kPer];
   // the particles' state is loaded kLoad at a time before any of it is used
-  // (the counting atomics below would otherwise keep the loads apart)
-  constexpr int kLoad = 8;
+  // (the counting atomics below would otherwise keep the loads apart); the
+  // groups tile the thread's kPer particles exactly
+  constexpr int kLoad = kPer < 8 ? kPer : 8;
+  static_assert(kPer % kLoad == 0, "load groups must tile a thread's particles");
 #pragma unroll
   for (int u0 = 0; u0 < kPer; u0 += kLoad) {
     float o[kLoad][D];
@@ -1080,7 +1082,8 @@ __device__ __forceinline__ bool row_columns(const BrickGeom& G, const Phys& P, i
     r2 -= dz * dz;
   }
   if (r2 <= 0.f) return false;
-  const int hw = (int)sqrtf(r2) + mq + 64;
+  // (v_sqrt, within an ulp or so: the reach is widened by 64 units anyway)
+  const int hw = (int)__builtin_amdgcn_sqrtf(r2) + mq + 64;
   cx0 = max(0, (X - hw) >> P.F);
   cx1 = min(G.HX - 1, (X + hw) >> P.F);
   return true;
