@@ -54,6 +54,7 @@ struct Layout {
   int BX = 1, BY = 1, BZ = 1;
   int bthreads = 256;
   int BSX = 1;
+  int BSY = 1;
   long long n_total = 0, n_cells = 0, n_sites = 0;
   int nbricks = 0, nchunks = 0, ncchunks = 0, nstrips = 0, ntiles = 0;
   std::vector<Replica> reps;
@@ -360,8 +361,17 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
     const int want = (int)std::ceil(1.5 * vol_l * rho_max) + 20;
     L->kmax = std::min(kMaxPairSlots, (want + 3) / 4 * 4);
   }
-  // binning strip width (LDS budget 60 kB)
+  // binning strips: BSX sites along x (LDS budget 60 kB) times BSY site rows,
+  // about 512 particles per block (two per thread), at most 64 MD-cell rows
   L->BSX = std::max(1, std::min(kMaxStripSites, 60000 / ((L->Q + L->nm) * 4)));
+  {
+    const int rows_per = (D == 2) ? L->k : L->k * L->k;
+    const double per_site = rho * std::pow(c->lattice_dx, D);
+    int bsy = (int)std::lround(512.0 / std::max(1.0, L->BSX * per_site));
+    bsy = std::min(bsy, 64 / rows_per);
+    bsy = std::min(bsy, 60000 / (L->BSX * (L->Q + L->nm) * 4));
+    L->BSY = std::max(1, bsy);
+  }
   // tables
   L->reps.clear();
   L->bricks.clear();
@@ -403,7 +413,7 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
       L->cchunks.push_back(make_int4(r, (int)g, (int)std::min(part_off + rep.n, g + cchunk), 0));
     const int nsz_rows = (D == 3) ? rep.M[2] : 1;
     for (int sz = 0; sz < nsz_rows; ++sz)
-      for (int sy = 0; sy < rep.M[1]; ++sy)
+      for (int sy = 0; sy < rep.M[1]; sy += L->BSY)
         for (int sx = 0; sx < rep.M[0]; sx += L->BSX) L->strips.push_back(make_int4(r, sx, sy, sz));
     L->reps.push_back(rep);
     cell_off += ncell;
@@ -1034,6 +1044,7 @@ void enqueue_bin(mdlg_system* S, bool snapshot_only) {
   b.err = S->err;
   b.snapshot_only = snapshot_only ? 1 : 0;
   b.BSX = S->L.BSX;
+  b.BSY = S->L.BSY;
   b.nstep = (S->L.xi && !snapshot_only) ? S->nstep[S->xi_par] : nullptr;
   b.shift_k = (S->L.n_shifts > 0 && !snapshot_only) ? S->shift_k : nullptr;
   {

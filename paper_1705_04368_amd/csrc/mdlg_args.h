@@ -170,7 +170,8 @@ struct BinArgs {
   double* dpart;       // [nstrips][2D]
   unsigned* err;
   int snapshot_only;
-  int BSX;
+  int BSX;             // sites per strip row
+  int BSY;             // site rows per strip
   unsigned* nstep;     // optional: this step's n_i(x,t) [sites][Q], overwritten
   long long* shift_k;  // optional: lattice-time counter of the shifted lattices, advanced here
 };

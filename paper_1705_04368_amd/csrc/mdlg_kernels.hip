@@ -2019,28 +2019,44 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs a) {
   const int4 st = a.strips[blockIdx.x];
   const Replica R = a.reps[st.x];
   const int k = 1 << P.log2k;
-  const int sx0 = st.y, sy = st.z, sz = st.w;
+  // a strip: site rows sy0 .. sy0 + wsy - 1 of BSX sites from sx0 (layer sz)
+  const int sx0 = st.y, sy0 = st.z, sz = st.w;
   const int wsx = min(a.BSX, R.M[0] - sx0);
+  const int wsy = min(a.BSY, R.M[1] - sy0);
   const int Q = P.Q, nm = P.nm;
-  unsigned* s_h = reinterpret_cast<unsigned*>(s_dyn);  // [wsx][Q]
-  int* s_m = s_dyn + a.BSX * Q;                        // [wsx][nm]
+  const int nsite = a.BSX * a.BSY;
+  unsigned* s_h = reinterpret_cast<unsigned*>(s_dyn);  // [BSY][BSX][Q]
+  int* s_m = s_dyn + nsite * Q;                        // [BSY][BSX][nm]
   if (!a.snapshot_only) {
-    for (int e = threadIdx.x; e < a.BSX * (Q + nm); e += kBlock) s_dyn[e] = 0;
+    for (int e = threadIdx.x; e < nsite * (Q + nm); e += kBlock) s_dyn[e] = 0;
   }
-  // MD-cell rows covering this strip of sites
-  const int nrows = (D == 2) ? k : k * k;
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int r = 0; r < nrows; ++r) {
-      const int ry = sy * k + (r % k);
-      const int rz = (D == 3) ? sz * k + r / k : 0;
+  // the MD-cell rows covering the strip (at most 64), one per lane of the
+  // first wave: their first particle and, by a scan, their start in the
+  // strip's particle order
+  const int rows_per = (D == 2) ? k : k * k;  // MD-cell rows of one site row
+  const int nrows = wsy * rows_per;
+  if (threadIdx.x < 64) {
+    const int r = threadIdx.x;
+    int g0 = 0, cnt = 0;
+    if (r < nrows) {
+      const int j = r / rows_per, rr = r - j * rows_per;
+      const int ry = (sy0 + j) * k + (rr & (k - 1));
+      const int rz = (D == 3) ? sz * k + (rr >> P.log2k) : 0;
       const int rowbase = R.cell_off + R.Mc[0] * (ry + R.Mc[1] * rz);
-      const int c0 = rowbase + sx0 * k, c1 = rowbase + (sx0 + wsx) * k;
-      s_rg[r] = a.cell_start[c0];
-      s_rp[r] = acc;
-      acc += a.cell_start[c1] - a.cell_start[c0];
+      g0 = a.cell_start[rowbase + sx0 * k];
+      cnt = a.cell_start[rowbase + (sx0 + wsx) * k] - g0;
     }
-    s_rp[nrows] = acc;
+    int x = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (r >= o) x += y;
+    }
+    if (r < nrows) {
+      s_rg[r] = g0;
+      s_rp[r] = x - cnt;
+    }
+    if (r == nrows - 1) s_rp[nrows] = x;
   }
   __syncthreads();
   const int np = s_rp[nrows];
@@ -2088,7 +2104,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs a) {
           ds[q] += dd;
           dq[q] += dd * dd;
         }
-        sitek = (c[0] >> P.log2k) - sx0;
+        sitek = ((c[1] >> P.log2k) - sy0) * a.BSX + (c[0] >> P.log2k) - sx0;
         bink = sitek * Q + (inside ? bin : 0);
       }
       sti<D>(a.prev_u, g, u);
@@ -2117,20 +2133,32 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs a) {
   if (a.snapshot_only) return;
   if (a.shift_k && blockIdx.x == 0 && threadIdx.x == 0) *a.shift_k += 1;
   __syncthreads();
-  const int sy_lin = (D == 2) ? R.M[0] * sy : R.M[0] * (sy + R.M[1] * sz);
-  const size_t site0 = (size_t)R.site_off + sy_lin + sx0;
-  // flush: this block is the only writer of its sites; atomics without a
-  // return value let every update leave without waiting for the read
-  for (int e = threadIdx.x; e < wsx * Q; e += kBlock) {
-    const unsigned c = s_h[e];
-    if (c) atomicAdd(a.A + site0 * Q + e, c);
-    if (a.nstep) a.nstep[site0 * Q + e] = c;
-  }
-  for (int e = threadIdx.x; e < wsx * nm; e += kBlock) {
-    const int c = s_m[e];
-    if (c)
-      atomicAdd(reinterpret_cast<unsigned long long*>(a.mom) + site0 * nm + e,
-                (unsigned long long)(long long)c);
+  // flush, row by row of the strip: this block is the only writer of its
+  // sites; atomics without a return value let every update leave without
+  // waiting for the read
+  const int sy_lin = (D == 2) ? R.M[0] * sy0 : R.M[0] * (sy0 + R.M[1] * sz);
+  const size_t site0 = (size_t)R.site_off + sy_lin + sx0;  // first site of the first row
+  {
+    const int rq = wsx * Q;
+    const float rrq = __builtin_amdgcn_rcpf((float)rq);
+    for (int e = threadIdx.x; e < wsy * rq; e += kBlock) {
+      int x;
+      const int j = small_div(e, rq, rrq, x);
+      const unsigned c = s_h[j * a.BSX * Q + x];
+      const size_t ga = (site0 + (size_t)j * R.M[0]) * Q + x;
+      if (c) atomicAdd(a.A + ga, c);
+      if (a.nstep) a.nstep[ga] = c;
+    }
+    const int rm = wsx * nm;
+    const float rrm = __builtin_amdgcn_rcpf((float)rm);
+    for (int e = threadIdx.x; e < wsy * rm; e += kBlock) {
+      int x;
+      const int j = small_div(e, rm, rrm, x);
+      const int c = s_m[j * a.BSX * nm + x];
+      if (c)
+        atomicAdd(reinterpret_cast<unsigned long long*>(a.mom) + (site0 + (size_t)j * R.M[0]) * nm + x,
+                  (unsigned long long)(long long)c);
+    }
   }
   const int w = threadIdx.x >> 6;
 #pragma unroll
@@ -2555,7 +2583,7 @@ void launch_kin(const KinArgs& a, hipStream_t s) {
 }
 
 void launch_bin(int D, int nstrips, const BinArgs& a, hipStream_t s) {
-  const size_t lds = (size_t)a.BSX * (a.P.Q + a.P.nm) * sizeof(int);
+  const size_t lds = (size_t)a.BSX * a.BSY * (a.P.Q + a.P.nm) * sizeof(int);
   MDLG_LAUNCH_DIM(D, k_bin, nstrips, lds, s, a);
 }
 
