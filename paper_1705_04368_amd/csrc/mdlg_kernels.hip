@@ -587,7 +587,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter(SortArgs a) {
          i += (long long)gridDim.x * kBlock)
       a.mcnt_clear[i] = 0u;
   }
-  const int4 ch = a.chunks[blockIdx.x];
+  // consecutive chunks on one XCD: the cache lines where the destinations
+  // of neighbouring chunks meet are then completed in one L2
+  int cb = blockIdx.x;
+  if (a.xcd_remap) {
+    const int per = gridDim.x >> 3;
+    cb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  if (cb >= a.nchunks) return;
+  const int4 ch = a.chunks[cb];
   const Replica R = a.reps[ch.x];
   // every particle of the thread is loaded before any slot is computed: the
   // slot needs the cell start of its key (a dependent load), so the state's
@@ -2016,7 +2024,10 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs a) {
   __shared__ int s_rg[64];
   __shared__ double s_red[kWaves][2 * D];
   const Phys& P = a.P;
-  const int4 st = a.strips[blockIdx.x];
+  // (strips in dispatch order: keeping consecutive strips on one XCD
+  // measured slower)
+  const int sb = blockIdx.x;
+  const int4 st = a.strips[sb];
   const Replica R = a.reps[st.x];
   const int k = 1 << P.log2k;
   // a strip: site rows sy0 .. sy0 + wsy - 1 of BSX sites from sx0 (layer sz)
@@ -2131,7 +2142,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs a) {
     }
   }
   if (a.snapshot_only) return;
-  if (a.shift_k && blockIdx.x == 0 && threadIdx.x == 0) *a.shift_k += 1;
+  if (a.shift_k && sb == 0 && threadIdx.x == 0) *a.shift_k += 1;
   __syncthreads();
   // flush, row by row of the strip: this block is the only writer of its
   // sites; atomics without a return value let every update leave without
@@ -2174,7 +2185,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs a) {
   if (threadIdx.x < 2 * D) {
     double s = 0.0;
     for (int i = 0; i < kWaves; ++i) s += s_red[i][threadIdx.x];
-    a.dpart[(size_t)blockIdx.x * 2 * D + threadIdx.x] += s;
+    a.dpart[(size_t)sb * 2 * D + threadIdx.x] += s;
   }
 }
 
@@ -2528,7 +2539,8 @@ void launch_scan(const ScanArgs& a, hipStream_t s) {
 }
 
 void launch_scatter(int D, int nchunks, const SortArgs& a, hipStream_t s) {
-  MDLG_LAUNCH_DIM(D, k_scatter, nchunks, 0, s, a);
+  const int grid = a.xcd_remap ? (nchunks + 7) / 8 * 8 : nchunks;
+  MDLG_LAUNCH_DIM(D, k_scatter, grid, 0, s, a);
 }
 
 void launch_cellsort(int D, int nchunks, const CellsortArgs& a, hipStream_t s) {
