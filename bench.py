@@ -286,21 +286,47 @@ def _oracle_lattice_step(task):
     st.mdlg(lat, steps, 1)
 
 
-def cpu_baseline_single(w, x, v, box, M, lattice_steps):
-    """The FP64 oracle, one thread, on the full system for `lattice_steps`
-    lattice steps from the given (warmed-up) state."""
+def cpu_baseline_single(w, x, v, box, M, lattice_steps, budget_s=15.0):
+    """The FP64 oracle, one thread, on the full system from the given
+    (warmed-up) state, or for more than 300k particles on a smaller periodic
+    system of the same density and temperature: MD steps timed one at a time
+    until about budget_s seconds (at most lattice_steps lattice steps' worth),
+    then one binning pass; the rate is particle-steps per second of that
+    work."""
     import oracle
     dim, n = w["dim"], x.shape[0]
-    st = oracle.OracleState(oracle.make_md(dim, n, box, dt=w["dt"]), x, v)
+    model, _ = host_cpu()
+    what = "full system from the warmed-up state"
+    if n > 300000:
+        # one full-system step of the oracle takes about a minute here: a
+        # smaller periodic system of the same density and temperature (a whole
+        # number of lattice cells, about 300k particles, synthetic start)
+        import synth
+        Ms = max(2, int(round(M * (300000.0 / n) ** (1.0 / dim))))
+        box = Ms * w["dx"]
+        n = int(round(n * (Ms / M) ** dim))
+        xs, vs = synth.lj_initial_state(dim, n, box, w["kT"], seed=17)
+        x, v, M = xs.astype(np.float64), vs.astype(np.float64), Ms
+        what = (f"a {n}-particle system of the same density and temperature ({Ms}^{dim} lattice "
+                f"cells, synthetic start)")
+        print(f"# cpu baseline: {what}", file=sys.stderr, flush=True)
+    md = oracle.make_md(dim, n, box, dt=w["dt"])
+    st = oracle.OracleState(md, x, v)
     lat = oracle.make_lattice(dim, (M,) * dim, w["dx"], w["vmax"])
     t0 = time.perf_counter()
-    st.mdlg(lat, w["steps"], lattice_steps)
+    steps = 0
+    while steps < lattice_steps * w["steps"] - 1 and time.perf_counter() - t0 < budget_s:
+        st.run(1)
+        steps += 1
+        print(f"# cpu baseline: {steps} MD steps, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
+    st.mdlg(lat, 1, 1)  # one more MD step and the binning
+    steps += 1
     t = time.perf_counter() - t0
-    model, _ = host_cpu()
-    return {"value": n * w["steps"] * lattice_steps / t, "unit": "particle-steps/s", "cores": 1,
+    return {"value": n * steps / t, "unit": "particle-steps/s", "cores": 1,
             "kind": "oracle", "cpu": model,
-            "sample": f"full system from the warmed-up state, {lattice_steps} lattice steps "
-                      f"({lattice_steps * w['steps']} MD steps + binning), FP64, one thread, {t:.1f} s"}
+            "sample": f"{what}, {steps} MD steps and one binning pass, FP64, one thread, "
+                      f"{t:.1f} s"}
 
 
 def cpu_baseline_ensemble(w, xs, vs, m_r, single_target=400000, threads=None):
