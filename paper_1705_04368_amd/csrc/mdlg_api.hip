@@ -42,6 +42,8 @@ constexpr int kPartChunk = kPartChunkMax;  // particles per block of the per-par
 // ones as graphs of about kGraphBlockSteps MD steps (whole rebuild intervals)
 constexpr int kGraphMaxSteps = 400;
 constexpr int kGraphBlockSteps = 200;
+constexpr int kStepGraph = 1 << 30;      // graph kind of a block of plain MD steps
+constexpr int kAdjointGraph = (1 << 30) + 1;  // graph kind of an adjoint window
 
 struct Layout {
   mdlg_layout pub;
@@ -531,11 +533,9 @@ struct mdlg_system {
   unsigned* stale = nullptr;  // [disp_rows] lists possibly stale after that many drifts
   int2* trec = nullptr;
   // adjoint window buffers (sorted order)
-  float* adj_off0 = nullptr;
   float* adj_ckpt_pos = nullptr;
   float* adj_ckpt_vel = nullptr;
   float* adj_seg_pos = nullptr;
-  float* adj_vel = nullptr;
   float* adj_lx = nullptr;
   float* adj_lv[2] = {nullptr, nullptr};
   double* adj_gpart = nullptr;
@@ -570,10 +570,12 @@ struct mdlg_system {
     hipGraphExec_t exec;
     SeqState after;  // counters as advanced by one replay from the key's state
   };
-  // key: (kind, pcur, scur, since_sort, vel_full, mpar, xi_par, xi_have);
+  // key: (kind, pcur, scur, since_sort, vel_full, mpar, xi_par, xi_have, tag);
   // kind 0 = a whole lattice step, B > 0 = a block of B MD steps, -n = the
-  // last n MD steps of a lattice step with its binning
-  std::map<std::tuple<int, int, int, int, bool, int, int, bool>, GraphEntry> graphs;
+  // last n MD steps of a lattice step with its binning, kStepGraph = a block
+  // of plain MD steps and kAdjointGraph = an adjoint window (their tags
+  // carry the rest of what the work depends on)
+  std::map<std::tuple<int, int, int, int, bool, int, int, bool, unsigned long long>, GraphEntry> graphs;
   // per-kernel event timing (measurement aid)
   bool timing = false;
   struct Timed {
@@ -667,15 +669,14 @@ size_t carve(mdlg_system* S, char* base) {
     S->trec = c.take<int2>(base, (size_t)L.nbricks * L.lcap);
   }
   if (L.adj_ckpts > 0) {
-    S->adj_off0 = c.take<float>(base, N * D);
     S->adj_ckpt_pos = c.take<float>(base, N * D * L.adj_ckpts);
     S->adj_ckpt_vel = c.take<float>(base, N * D * L.adj_ckpts);
     S->adj_seg_pos = c.take<float>(base, N * D * L.adj_seg);
-    S->adj_vel = c.take<float>(base, N * D);
     S->adj_lx = c.take<float>(base, N * D);
     S->adj_lv[0] = c.take<float>(base, N * D);
     S->adj_lv[1] = c.take<float>(base, N * D);
-    S->adj_gpart = c.take<double>(base, (size_t)L.nbricks * 2);
+    // per-brick parameter partials of every reverse step of the longest window
+    S->adj_gpart = c.take<double>(base, (size_t)(L.adj_window + 1) * L.nbricks * 2);
     S->adj_lpart = c.take<double>(base, 1024);
     S->adj_out = c.take<double>(base, 4);
   }
@@ -1436,25 +1437,6 @@ mdlg_status mdlg_create_static(const mdlg_config* cfg, void* hip_stream, const f
   return MDLG_OK;
 }
 
-mdlg_status mdlg_step(mdlg_system* S, int64_t n) {
-  if (!S) return MDLG_E_INVALID;
-  if (n < 0) {
-    S->last_error = "n_md_steps must be >= 0";
-    return MDLG_E_INVALID;
-  }
-  const int te = S->cfg.thermostat_every;
-  for (int64_t i = 0; i < n; ++i) {
-    enqueue_md_step(S, false);
-    if (te > 0 && S->md_step % te == 0) {
-      enqueue_force(S, kModeFinish, false, nullptr, S->kpart);
-      enqueue_kin(S, true);
-      S->vel_full = true;
-    }
-  }
-  if (n > 0) S->snapshot_valid = false;
-  return check_launch(S, "mdlg_step");
-}
-
 extern "C++" {
 
 static mdlg_system::SeqState seq_state(const mdlg_system* S) {
@@ -1480,9 +1462,9 @@ static void set_seq_state(mdlg_system* S, const mdlg_system::SeqState& q) {
 // sequencing state, replayed on the user's stream every time.  The host
 // state then advances as the body would have advanced it.
 template <class F>
-mdlg_status replay_graph(mdlg_system* S, int kind, F body) {
+mdlg_status replay_graph(mdlg_system* S, int kind, F body, unsigned long long tag = 0) {
   auto key = std::make_tuple(kind, S->pcur, S->scur, S->since_sort, S->vel_full, S->mpar,
-                             S->xi_par, S->xi_have);
+                             S->xi_par, S->xi_have, tag);
   auto it = S->graphs.find(key);
   const mdlg_system::SeqState before = seq_state(S);
   if (it == S->graphs.end()) {
@@ -1518,6 +1500,45 @@ mdlg_status replay_graph(mdlg_system* S, int kind, F body) {
 }
 
 }  // extern "C++"
+
+// One block of plain MD steps, with the equilibration thermostat at every
+// thermostat_every-th step.
+static void enqueue_md_steps(mdlg_system* S, int64_t n) {
+  const int te = S->cfg.thermostat_every;
+  for (int64_t i = 0; i < n; ++i) {
+    enqueue_md_step(S, false);
+    if (te > 0 && S->md_step % te == 0) {
+      enqueue_force(S, kModeFinish, false, nullptr, S->kpart);
+      enqueue_kin(S, true);
+      S->vel_full = true;
+    }
+  }
+}
+
+mdlg_status mdlg_step(mdlg_system* S, int64_t n) {
+  if (!S) return MDLG_E_INVALID;
+  if (n < 0) {
+    S->last_error = "n_md_steps must be >= 0";
+    return MDLG_E_INVALID;
+  }
+  if (!S->use_graph || S->timing) {
+    enqueue_md_steps(S, n);
+  } else {
+    // graphs of up to kGraphBlockSteps steps, keyed by the block length and
+    // the thermostat's phase
+    const int te = S->cfg.thermostat_every;
+    for (int64_t left = n; left > 0;) {
+      const int m = (int)std::min<int64_t>(left, kGraphBlockSteps);
+      const unsigned long long tag =
+          ((unsigned long long)m << 32) | (unsigned long long)(te > 0 ? S->md_step % te : 0);
+      mdlg_status st = replay_graph(S, kStepGraph, [S, m] { enqueue_md_steps(S, m); }, tag);
+      if (st != MDLG_OK) return st;
+      left -= m;
+    }
+  }
+  if (n > 0) S->snapshot_valid = false;
+  return check_launch(S, "mdlg_step");
+}
 
 mdlg_status mdlg_coarse_grain(mdlg_system* S, int64_t T) {
   if (!S) return MDLG_E_INVALID;
@@ -1833,9 +1854,10 @@ static Phys window_list_phys(const mdlg_system* S) {
 // kdisp: drifts made since the lists were built (checked, and this one
 // recorded), or -1 for a recomputation of steps already checked.
 static void launch_force_raw(mdlg_system* S, const Phys& P, int mode, const float* pos_in,
-                             float* pos_out, float* vel, int kdisp) {
+                             float* pos_out, float* vel, int kdisp, float* vel_full_out = nullptr) {
   ForceArgs a{};
   a.P = P;
+  a.vel_full_out = vel_full_out;
   if (P.kmax > 0) {
     // lists built at the start of the window by enqueue_nlist(S, P)
     a.smap = S->smap;
@@ -1868,6 +1890,14 @@ static void launch_force_raw(mdlg_system* S, const Phys& P, int mode, const floa
   launch_force(S->D, a, S->stream);
 }
 
+// The adjoint velocity buffer that receives dL/dv0 in id order after the
+// reverse sweep of a window of W steps: the sweep flips the two buffers once
+// per reverse step (W + 1 of them, whatever the checkpoint interval), leaving
+// lam_v in buffer (W + 1) & 1; the other one is free.
+static int adjoint_grad_buffer(int W) { return ((W + 1) & 1) ^ 1; }
+
+static int enqueue_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, bool want_g);
+
 mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, const float* v0_dev,
                          double* out_loss, double* dL_deps, double* dL_dsigma, float* g_v0_dev) {
   if (!S) return MDLG_E_INVALID;
@@ -1885,55 +1915,105 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
     S->last_error = "unknown loss";
     return MDLG_E_INVALID;
   }
-  const int D = S->D;
-  const long long nd = L.n_total * D;
-  const Phys PW = window_phys(S);
-  // start of the window: canonical cells (frozen from here on), full-step v
+  // start of the window: canonical cells (frozen from here on), and the
+  // caller's v0 (id order) if given
   if (S->since_sort != 0) enqueue_sort(S);
   if (v0_dev) {
     AdjIoArgs io{S->id[S->scur], S->vel[S->scur], const_cast<float*>(v0_dev), (int)L.n_total, 1};
-    launch_adj_io(D, io, S->stream);
-    S->vel_full = true;
-  } else if (!S->vel_full) {
-    enqueue_force(S, kModeFinish, false, nullptr, nullptr);
+    launch_adj_io(S->D, io, S->stream);
     S->vel_full = true;
   }
+  const bool want_g = g_v0_dev != nullptr;
+  int gbuf = 0;  // the adjoint buffer that receives dL/dv0 in id order
+  if (!S->use_graph || S->timing) {
+    gbuf = enqueue_adjoint(S, W, k, loss, want_g);
+  } else {
+    // one graph per window shape and loss (no caller pointer inside it)
+    const unsigned long long tag = ((unsigned long long)W << 40) | ((unsigned long long)k << 20) |
+                                   ((unsigned long long)loss << 1) | (want_g ? 1ull : 0ull);
+    mdlg_status gs = replay_graph(S, kAdjointGraph, [&] { gbuf = enqueue_adjoint(S, W, k, loss, want_g); },
+                                  tag);
+    if (gs != MDLG_OK) return gs;
+    // (the buffer index follows from W and k alone)
+    gbuf = adjoint_grad_buffer(W);
+  }
+  if (want_g) launch_copy_f32(S->adj_lv[gbuf], g_v0_dev, L.n_total * S->D, S->stream);
+  S->snapshot_valid = false;
+  mdlg_status st = check_launch(S, "mdlg_adjoint");
+  if (st != MDLG_OK) return st;
+  double out[3] = {0, 0, 0};
+  HIPCHK(S, hipMemcpyAsync(out, S->adj_out, sizeof out, hipMemcpyDeviceToHost, S->stream));
+  st = read_err(S);
+  if (out_loss) *out_loss = out[0];
+  if (dL_deps) *dL_deps = out[1];
+  if (dL_dsigma) *dL_dsigma = out[2];
+  return st;
+}
+
+
+// The device work of mdlg_adjoint (arguments checked; the cells canonical and
+// v0, if given, in place): the forward window with checkpoints, the loss,
+// the reverse sweep segment by segment, the gradient reductions, dL/dv0 in id
+// order into the other adjoint velocity buffer (want_g), and the rebuild at
+// the end of the window.  Returns that buffer's index.
+static int enqueue_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, bool want_g) {
+  const Layout& L = S->L;
+  const int D = S->D;
+  const long long nd = L.n_total * D;
+  const Phys PW = window_phys(S);
   // the window's force launches (forward and recomputed) walk pair lists
   // built here on the frozen cells
   const Phys PF = L.kmax_adj > 0 ? window_list_phys(S) : PW;
   S->adj_window_steps = W;
   if (PF.kmax > 0) enqueue_nlist(S, PF);
-  // forward window with checkpoints
-  launch_copy_f32(S->pos[S->pcur], S->adj_off0, nd, S->stream);
-  launch_copy_f32(S->pos[S->pcur], S->adj_ckpt_pos, nd, S->stream);
-  launch_copy_f32(S->vel[S->scur], S->adj_ckpt_vel, nd, S->stream);
+  // Forward window.  x(0) goes to checkpoint 0 (the loss and the
+  // recomputation of segment 0 read it there); each later checkpoint
+  // position, and every position of the last segment, is written there by
+  // the step that makes it (the last segment is not recomputed: the reverse
+  // sweep reads its positions from the segment buffer, and x(W) from the
+  // state).  The first step writes the full-step v(0) into checkpoint 0 (a
+  // half-step state is completed by that step's kick, as a finishing launch
+  // would), and later checkpoints copy the velocities.
+  const int last0 = W - k;  // first position of the last segment
+  float* x0 = S->adj_ckpt_pos;
+  launch_copy_f32(S->pos[S->pcur], x0, nd, S->stream);
+  const float* cur_pos = S->pos[S->pcur];
   for (int n = 1; n <= W; ++n) {
-    launch_force_raw(S, PF, n == 1 ? kModeStart : kModeStep, S->pos[S->pcur], S->pos[S->pcur ^ 1],
-                     S->vel[S->scur], n - 1);
+    float* pout;
+    if (n == W) pout = S->pos[S->pcur ^ 1];
+    else if (n >= last0) pout = S->adj_seg_pos + (size_t)(n - last0) * nd;
+    else if (n % k == 0) pout = S->adj_ckpt_pos + (size_t)(n / k) * nd;
+    else pout = S->pos[S->pcur ^ 1];
+    const int mode = (n == 1 && S->vel_full) ? kModeStart : kModeStep;
+    launch_force_raw(S, PF, mode, cur_pos, pout, S->vel[S->scur], n - 1,
+                     n == 1 ? S->adj_ckpt_vel : nullptr);
     S->pcur ^= 1;
-    if (n % k == 0 && n < W) {
-      launch_copy_f32(S->pos[S->pcur], S->adj_ckpt_pos + (size_t)(n / k) * nd, nd, S->stream);
+    cur_pos = pout;
+    if (n % k == 0 && n < last0)
       launch_copy_f32(S->vel[S->scur], S->adj_ckpt_vel + (size_t)(n / k) * nd, nd, S->stream);
-    }
   }
+  S->vel_full = false;
   // loss and dL/dx(W); lam_v(W) = 0
   const int nlb = (int)std::min<long long>(1024, (L.n_total + kBlock - 1) / kBlock);
-  AdjLossArgs la{S->adj_off0, S->pos[S->pcur], S->adj_lx, S->adj_lv[0], S->adj_lpart,
-                 (int)L.n_total, loss, nlb};
+  const float* xW = S->pos[S->pcur];
+  AdjLossArgs la{x0, xW, S->adj_lx, S->adj_lv[0], S->adj_lpart, (int)L.n_total, loss, nlb};
   launch_adj_loss(D, la, S->stream);
-  launch_fill_u32(reinterpret_cast<unsigned*>(S->adj_gpart), 0u, (long long)L.nbricks * 4, S->stream);
   // reverse sweep, segment by segment
   const float h = (float)S->cfg.dt;
   const double u = PW.u_d;
   const double e1 = 24.0 * S->cfg.epsilon / (S->cfg.mass * u);
   int cur = 0;
   for (int seg = W / k - 1; seg >= 0; --seg) {
-    launch_copy_f32(S->adj_ckpt_pos + (size_t)seg * nd, S->adj_seg_pos, nd, S->stream);
-    launch_copy_f32(S->adj_ckpt_vel + (size_t)seg * nd, S->adj_vel, nd, S->stream);
-    for (int j = 1; j <= k; ++j)
-      launch_force_raw(S, PF, (seg == 0 && j == 1) ? kModeStart : kModeStep,
-                       S->adj_seg_pos + (size_t)(j - 1) * nd, S->adj_seg_pos + (size_t)j * nd,
-                       S->adj_vel, -1);
+    const bool last = seg == W / k - 1;
+    const float* seg0 = S->adj_ckpt_pos + (size_t)seg * nd;  // x at the segment's start
+    if (!last) {
+      // recompute the segment's positions from its checkpoint (its
+      // velocities run in place in the checkpoint, used only here)
+      for (int j = 1; j <= k; ++j)
+        launch_force_raw(S, PF, (seg == 0 && j == 1) ? kModeStart : kModeStep,
+                         j == 1 ? seg0 : S->adj_seg_pos + (size_t)(j - 1) * nd,
+                         S->adj_seg_pos + (size_t)j * nd, S->adj_ckpt_vel + (size_t)seg * nd, -1);
+    }
     for (int j = k; j >= (seg == 0 ? 0 : 1); --j) {
       const int sg = seg * k + j;
       AdjArgs a{};
@@ -1941,11 +2021,12 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
       a.reps = S->reps;
       a.bricks = S->bricks;
       a.cell_start = S->cell_start;
-      a.pos = S->adj_seg_pos + (size_t)j * nd;
+      a.pos = (last && j == k) ? xW : (j == 0 ? seg0 : S->adj_seg_pos + (size_t)j * nd);
       a.lam_v_in = S->adj_lv[cur];
       a.lam_v_out = S->adj_lv[cur ^ 1];
       a.lam_x = S->adj_lx;
-      a.gpart = S->adj_gpart;
+      // (each reverse step writes its own row of partials: no read-modify-write)
+      a.gpart = S->adj_gpart + (size_t)(W - sg) * L.nbricks * 2;
       a.c = (sg == W || sg == 0) ? 0.5f * h : h;
       a.drift = sg > 0 ? 1 : 0;
       a.e1_over_sigma = (float)(e1 / S->cfg.sigma);
@@ -1954,6 +2035,7 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
       a.nbricks = L.nbricks;
       a.err = S->err;
       if (PF.kmax > 0) {
+        a.smap = S->smap;
         a.binfo = S->binfo;
         a.trec = S->trec;
         a.nl = S->nl;
@@ -1965,10 +2047,11 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
       cur ^= 1;
     }
   }
-  AdjFinalArgs fa{S->adj_lpart, S->adj_gpart, S->adj_out, nlb, L.nbricks};
+  AdjFinalArgs fa{S->adj_lpart, S->adj_gpart, S->adj_out, nlb, (W + 1) * L.nbricks};
   launch_adj_final(fa, S->stream);
-  if (g_v0_dev) {
-    AdjIoArgs io{S->id[S->scur], S->adj_lv[cur], g_v0_dev, (int)L.n_total, 0};
+  if (want_g) {
+    // dL/dv0 in id order into the buffer the sweep no longer needs
+    AdjIoArgs io{S->id[S->scur], S->adj_lv[cur], S->adj_lv[cur ^ 1], (int)L.n_total, 0};
     launch_adj_io(D, io, S->stream);
   }
   // leave the system at the end of the window, cells rebuilt
@@ -1977,15 +2060,7 @@ mdlg_status mdlg_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, con
   S->md_step += W;
   enqueue_sort(S);
   S->snapshot_valid = false;
-  mdlg_status st = check_launch(S, "mdlg_adjoint");
-  if (st != MDLG_OK) return st;
-  double out[3] = {0, 0, 0};
-  HIPCHK(S, hipMemcpyAsync(out, S->adj_out, sizeof out, hipMemcpyDeviceToHost, S->stream));
-  st = read_err(S);
-  if (out_loss) *out_loss = out[0];
-  if (dL_deps) *dL_deps = out[1];
-  if (dL_dsigma) *dL_dsigma = out[2];
-  return st;
+  return cur ^ 1;
 }
 
 mdlg_status mdlg_get_list_fallbacks(mdlg_system* S, int64_t* launches) {

@@ -101,6 +101,7 @@ struct ForceArgs {
   float* pos_out;
   float* vel;
   float* acc_out;      // optional
+  float* vel_full_out; // optional: the full-step velocities v(t) of this launch's kick
   double* kpart;       // optional per-brick partials [nbricks][D + 1]
   unsigned* err;
   int mode;
@@ -273,7 +274,7 @@ struct AdjArgs {
   const float* lam_v_in;   // adjoint velocity before this step
   float* lam_v_out;        // adjoint velocity after this step
   float* lam_x;            // adjoint position, updated in place
-  double* gpart;           // per-brick partials of (dL/deps, dL/dsigma), accumulated
+  double* gpart;           // this reverse step's per-brick partials of (dL/deps, dL/dsigma)
   float c;                 // weight of the two half kicks that use a(x_s): h or h/2
   int drift;               // 1: apply lam_v += h lam_x (not at the first position)
   float e1_over_sigma;     // 24 eps / (m u sigma)
@@ -282,6 +283,7 @@ struct AdjArgs {
   int nbricks;
   unsigned* err;
   // pair lists of the window (null nl: every brick walks its cell rows)
+  const int2* smap;    // [nbricks][lcap_list] staged halo of the list builder
   const int4* binfo;
   const int2* trec;    // [nbricks][lcap_list] targets {particle, LDS slot | words << 16}
   const unsigned long long* nl;
@@ -307,7 +309,7 @@ struct AdjFinalArgs {
   const double* gpart;
   double* out;             // loss, dL/deps, dL/dsigma
   int nl;
-  int nb;
+  int nb;                  // partial pairs in gpart (reverse steps x bricks)
 };
 
 struct AdjIoArgs {

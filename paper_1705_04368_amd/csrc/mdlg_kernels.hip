@@ -1120,6 +1120,7 @@ __device__ __forceinline__ void vv_update(const ForceArgs& a, const Phys& P, int
     ok = ok && (on[k] >= P.lo) && (on[k] < P.hi);
     v2 = fmaf(vh[k], vh[k], v2);
   }
+  if (a.vel_full_out) stv<D>(a.vel_full_out, gi, vf);
   if (drift) {
     if (!ok) atomicOr(a.err, kErrMargin);
     vmx = fmaxf(vmx, v2);
@@ -1782,40 +1783,65 @@ __global__ __launch_bounds__(NT) void k_adjoint(AdjArgs a) {
   if (b >= a.nbricks) return;
   const Phys& P = a.P;
   const int4 br = a.bricks[b];
-  const Replica R = a.reps[br.x];
-  // (the flag after the whole forward window covers each of its positions:
-  // once set, it stays set)
-  const bool stale = a.nl && a.stale && *a.stale != 0u;
-  const BrickGeom G = brick_setup<D, NT>(P, R, br, a.cell_start, L);
-  const int nchunks = (G.total + CAP - 1) / CAP;
   const bool interact = !P.forces_off;
   double ge = 0.0, gs = 0.0;
-  // the window's pair lists, where the brick's halo fits one chunk: entries
-  // index the halo staged in cell order, as here
+  // the window's pair lists, where the builder's halo fits this kernel's LDS
+  // chunk with the padding sentinel; (the flag after the whole forward window
+  // covers each of its positions: once set, it stays set)
   const int4 bi = a.nl ? a.binfo[b] : make_int4(0, 0, 0, 0);
-  const bool listed = interact && bi.z && !stale && bi.x == G.total && G.total < CAP;
-  if (interact && nchunks == 1) {
-    brick_stage<D, NT>(G, P, a.pos, a.lam_v_in, L, 0, G.total);
-    if (listed && threadIdx.x == 0) {
-      // the padding sentinel: far outside the cutoff, zero adjoint velocity
-      if constexpr (D == 2) L.p[G.total] = make_int2(kSentinel, kSentinel);
-      else L.p[G.total] = make_int4(kSentinel, kSentinel, kSentinel, 0);
+  const bool stale = a.nl && a.stale && *a.stale != 0u;
+  if (interact && bi.z && !stale && bi.x < CAP) {
+    // the halo staged through the builder's map (halo cells in order, the
+    // order the entries index): positions and adjoint velocities, with the
+    // first target records requested together with the map entries
+    const int2* __restrict__ smap = a.smap + (size_t)b * a.lcap_list;
+    const int2* __restrict__ trec = a.trec + (size_t)b * a.lcap_list;
+    const int total = bi.x, ntg = bi.y;
+    const size_t nt = (size_t)P.n_total;
+    const int2 r0 = trec[min((int)threadIdx.x, a.lcap_list - 1)];
+    for (int v0 = (int)threadIdx.x; v0 < total; v0 += 2 * NT) {
+      int2 e[2];
+      float p[2][D], l[2][D];
 #pragma unroll
-      for (int k = 0; k < D; ++k) L.lam[G.total * D + k] = 0.f;
+      for (int u = 0; u < 2; ++u) e[u] = smap[min(v0 + u * NT, total - 1)];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (v0 + u * NT < total) {
+          ldv<D>(a.pos, e[u].x, p[u]);
+          ldv<D>(a.lam_v_in, e[u].x, l[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int vv = v0 + u * NT;
+        if (vv < total) {
+          const int hx = e[u].y & 255, hy = (e[u].y >> 8) & 255;
+          if constexpr (D == 2)
+            L.p[vv] = make_int2(fixed_coord(hx, p[u][0], P), fixed_coord(hy, p[u][1], P));
+          else
+            L.p[vv] = make_int4(fixed_coord(hx, p[u][0], P), fixed_coord(hy, p[u][1], P),
+                                fixed_coord((e[u].y >> 16) & 255, p[u][2], P), 0);
+#pragma unroll
+          for (int k = 0; k < D; ++k) L.lam[vv * D + k] = l[u][k];
+        }
+      }
+    }
+    if (threadIdx.x == 0) {
+      // the padding sentinel: far outside the cutoff, zero adjoint velocity
+      if constexpr (D == 2) L.p[total] = make_int2(kSentinel, kSentinel);
+      else L.p[total] = make_int4(kSentinel, kSentinel, kSentinel, 0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) L.lam[total * D + k] = 0.f;
     }
     __syncthreads();
-  }
-  if (listed) {
-    const int2* __restrict__ trec = a.trec + (size_t)b * a.lcap_list;
-    const size_t nt = (size_t)P.n_total;
-    for (int tb = 0; tb < G.ntg; tb += NT) {
+    for (int tb = 0; tb < ntg; tb += NT) {
       const int t = tb + (int)threadIdx.x;
-      if (t >= G.ntg) break;
-      const int2 r = trec[t];
+      if (t >= ntg) break;
+      const int2 r = (tb == 0) ? r0 : trec[t];
       const int gi = r.x;
       const int vi = r.y & 0xffff;
       const int ng = (unsigned)r.y >> 16;
-      if ((size_t)(unsigned)gi >= nt || vi >= G.total) {
+      if ((size_t)(unsigned)gi >= nt || vi >= total) {
         atomicOr(a.err, kErrRecord);
         continue;
       }
@@ -1843,6 +1869,14 @@ __global__ __launch_bounds__(NT) void k_adjoint(AdjArgs a) {
       adj_update<D>(a, P, gi, li, acc, dacc, jl, ge, gs);
     }
   } else {
+    // the frozen cells, walked row by row
+    const Replica R = a.reps[br.x];
+    const BrickGeom G = brick_setup<D, NT>(P, R, br, a.cell_start, L);
+    const int nchunks = (G.total + CAP - 1) / CAP;
+    if (interact && nchunks == 1) {
+      brick_stage<D, NT>(G, P, a.pos, a.lam_v_in, L, 0, G.total);
+      __syncthreads();
+    }
     for (int tb = 0; tb < G.ntg; tb += NT) {
       const int t = tb + (int)threadIdx.x;
       const bool valid = t < G.ntg;
@@ -1901,7 +1935,7 @@ __global__ __launch_bounds__(NT) void k_adjoint(AdjArgs a) {
   if (threadIdx.x < 2) {
     double t = 0.0;
     for (int i = 0; i < NW; ++i) t += L.red[i][threadIdx.x];
-    a.gpart[(size_t)b * 2 + threadIdx.x] += t;
+    a.gpart[(size_t)b * 2 + threadIdx.x] = t;
   }
 }
 
@@ -1943,22 +1977,40 @@ __global__ __launch_bounds__(kBlock) void k_adj_loss(AdjLossArgs a) {
 
 // Sum of the per-block partials of the loss and the parameter gradients, in
 // a fixed order.
-__global__ void k_adj_final(AdjFinalArgs a) {
-  // one wave: lane-strided partial sums, then a butterfly across the wave (a
-  // fixed summation order, so the result does not depend on timing)
-  double L = 0.0, ge = 0.0, gs = 0.0;
-  for (int i = threadIdx.x; i < a.nl; i += 64) L += a.lpart[i];
-  for (int b = threadIdx.x; b < a.nb; b += 64) {
-    ge += a.gpart[(size_t)b * 2];
-    gs += a.gpart[(size_t)b * 2 + 1];
+__global__ __launch_bounds__(kBlock) void k_adj_final(AdjFinalArgs a) {
+  // one block: thread-strided partial sums (four independent chains per
+  // thread, so the loads overlap), then the waves' sums in LDS, added in
+  // wave order (a fixed summation order, so the result does not depend on
+  // timing)
+  __shared__ double s_red[kWaves][3];
+  double L = 0.0, ge[4] = {0.0, 0.0, 0.0, 0.0}, gs[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < a.nl; i += kBlock) L += a.lpart[i];
+  int b = threadIdx.x;
+  for (; b + 3 * kBlock < a.nb; b += 4 * kBlock) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ge[u] += a.gpart[(size_t)(b + u * kBlock) * 2];
+      gs[u] += a.gpart[(size_t)(b + u * kBlock) * 2 + 1];
+    }
   }
+  for (; b < a.nb; b += kBlock) {
+    ge[0] += a.gpart[(size_t)b * 2];
+    gs[0] += a.gpart[(size_t)b * 2 + 1];
+  }
+  const double e = wave_sum_d((ge[0] + ge[1]) + (ge[2] + ge[3]));
+  const double g = wave_sum_d((gs[0] + gs[1]) + (gs[2] + gs[3]));
   L = wave_sum_d(L);
-  ge = wave_sum_d(ge);
-  gs = wave_sum_d(gs);
-  if (threadIdx.x == 0) {
-    a.out[0] = L;
-    a.out[1] = ge;
-    a.out[2] = gs;
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    s_red[w][0] = L;
+    s_red[w][1] = e;
+    s_red[w][2] = g;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double t = 0.0;
+    for (int i = 0; i < kWaves; ++i) t += s_red[i][threadIdx.x];
+    a.out[threadIdx.x] = t;
   }
 }
 
@@ -2643,7 +2695,7 @@ void launch_adj_loss(int D, const AdjLossArgs& a, hipStream_t s) {
 }
 
 void launch_adj_final(const AdjFinalArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_final, dim3(1), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_adj_final, dim3(1), dim3(kBlock), 0, s, a);
 }
 
 void launch_adj_io(int D, const AdjIoArgs& a, hipStream_t s) {

@@ -188,3 +188,38 @@ def test_autograd_function_matches_direct_call():
     # the window is evaluated again from the same state
     L2 = window_loss(sysg, v0.detach(), eps.detach(), sig.detach(), W, K, "msd")
     assert float(L2) == pytest.approx(float(L), rel=1e-6)
+
+
+def test_adjoint_graph_replay_equals_eager():
+    # mdlg_adjoint and mdlg_step replay captured graphs; three windows in a
+    # row (each leaves the system W steps on, cells rebuilt), with plain MD
+    # steps and synchronisations between them, against the same calls
+    # launched one by one: every loss and gradient bit for bit, every replay
+    import os
+    cfg, md, pos, vel = _setup(2, 2048, 16, 4.0, seed=61)
+    say("adjoint: graph replay vs eager, three windows")
+    outs = {}
+    for graph in (True, False):
+        old = os.environ.get("MDLG_NO_GRAPH")
+        os.environ["MDLG_NO_GRAPH"] = "0" if graph else "1"
+        try:
+            sysg = make_system(cfg, pos, vel)
+        finally:
+            if old is None:
+                os.environ.pop("MDLG_NO_GRAPH", None)
+            else:
+                os.environ["MDLG_NO_GRAPH"] = old
+        res = []
+        for _ in range(3):
+            L, ge, gs, gv = sysg.adjoint(W, K, "msd", want_v0=True)
+            res.append((L, ge, gs, gv.cpu().numpy().copy()))
+            sysg.step(7)
+            sysg.sync()
+        res.append(sysg.get_state())
+        outs[graph] = res
+    for i in range(3):
+        a, b = outs[True][i], outs[False][i]
+        assert a[0] == b[0] and a[1] == b[1] and a[2] == b[2]
+        np.testing.assert_array_equal(a[3], b[3])
+    for key in ("ucell", "off", "vel"):
+        np.testing.assert_array_equal(outs[True][3][key], outs[False][3][key])
