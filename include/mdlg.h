@@ -161,7 +161,10 @@ typedef struct {
 } mdlg_layout;
 
 /* Validate cfg and report the derived layout.  Host only.  MDLG_E_INVALID on
- * any inconsistent field; *out untouched on error. */
+ * any inconsistent field, and on MD cells (lattice_dx / md_cell_split) that
+ * hold more than 128 particles on average at the densest replica's density
+ * (the counting sort ranks a particle among a bounded number of earlier
+ * particles of its cell); *out untouched on error. */
 mdlg_status mdlg_describe(const mdlg_config *cfg, mdlg_layout *out);
 
 /* Workspace size in bytes for cfg.  Host only. */

@@ -38,6 +38,11 @@ std::mutex g_static_mu;
 std::map<int, StaticSlot> g_static;
 
 constexpr int kPartChunk = kPartChunkMax;  // particles per block of the per-particle kernels
+// largest mean MD-cell occupancy (at the densest replica) of a layout: the
+// counting pass ranks a particle among at most kBlock earlier particles of
+// its cell that precede its chunk, and a cell twice as full as the mean
+// still fits that window
+constexpr int kMaxCellMean = kBlock / 2;
 // lattice steps of up to kGraphMaxSteps MD steps replay as one graph; longer
 // ones as graphs of about kGraphBlockSteps MD steps (whole rebuild intervals)
 constexpr int kGraphMaxSteps = 400;
@@ -227,6 +232,13 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   if (L->ns > 7)
     return set_err(msg, "MD cells of side %g are too small for r_cut %g (stencil half-width %d > 7)",
                    L->s, c->r_cut, L->ns);
+  // the counting sort ranks within a bounded window of each cell's particles
+  const double occ = rho_max * std::pow(L->s, D);
+  if (occ > kMaxCellMean)
+    return set_err(msg,
+                   "MD cells of side %g hold %.0f particles on average (densest replica), more than "
+                   "the %d the counting sort supports: raise md_cell_split",
+                   L->s, occ, kMaxCellMean);
   // largest excursion outside the cell that the stencil still covers
   const double m_max = (L->ns * L->s - c->r_cut) / 2;
   if (min_m * k < 2 * L->ns + 1)
@@ -806,11 +818,18 @@ hipEvent_t pool_event(mdlg_system* S) {
 // which hipExtLaunchKernelGGL records around the kernel itself (the time of
 // the kernel alone, not of the gaps between launches).  A launcher that ends
 // up launching nothing leaves its events unused; they are returned.
+void drain_timing(mdlg_system* S);
+
+// pending pairs are read back once this many are in flight (a lattice step of
+// many MD steps launches hundreds of thousands of kernels)
+constexpr size_t kMaxTimedPending = 16384;
+
 struct TimedLaunch {
   mdlg_system* S;
   bool on = false;
   TimedLaunch(mdlg_system* sys, int cls) : S(sys) {
     if (!S->timing) return;
+    if (S->timed.size() >= kMaxTimedPending) drain_timing(S);
     hipEvent_t a = pool_event(S), b = pool_event(S);
     if (!a || !b) return;
     g_launch_events = LaunchEvents{a, b};

@@ -74,6 +74,21 @@ def test_invalid_configs_rejected(change, msg):
     assert msg in str(e.value)
 
 
+def test_overfull_md_cells_rejected():
+    # the hot dilute gas (N = 100000 in a 1000 sigma box, 10^2 lattice of
+    # 100 sigma): one or two MD cells per lattice cell hold 1000 or 250
+    # particles on average, beyond the counting sort's window; four hold 62.5
+    def cfg(k):
+        return native.make_config(2, 100000, 10, lattice_dx=100.0, dt=1e-4, kT=50.0, vmax=3,
+                                  md_steps_per_lattice_step=341600, md_cell_split=k)
+    for k in (1, 2):
+        with pytest.raises(native.MdlgError, match="counting sort") as e:
+            native.describe(cfg(k))
+        assert e.value.status == -1
+    for k in (0, 4, 8):
+        assert native.describe(cfg(k))["md_cell_split"] in (4, 8)
+
+
 def test_vmax_window_limit_3d():
     cfg = native.make_config(3, 1000, 8, vmax=3)
     with pytest.raises(native.MdlgError, match="velocity window"):

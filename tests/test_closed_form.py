@@ -61,7 +61,7 @@ def test_feq_products_and_d2q9_regime():
     axis = f[(v[:, 0] == 1) & (v[:, 1] == 0)][0]
     diag = f[(v[:, 0] == 1) & (v[:, 1] == 1)][0]
     w0, w1, w5 = cf.D2Q9_WEIGHTS
-    # the paper: the three D2Q9 matches give a^2 ~ 1/6 "to very good approximation"
+    # the paper: each of the three D2Q9 matches gives a^2 close to 1/6
     for val, w in ((rest, w0), (axis, w1), (diag, w5)):
         assert val == pytest.approx(w, rel=0.08)
 
