@@ -527,6 +527,10 @@ def kernel_table(tim, dim, n, rho, lay, n_sites):
             e.update(hbm(n * bin_bytes_per_particle(dim, q, nm, per_site), avg))
         elif k == "adjoint":
             e.update(alu(n * pairs_per_particle(dim, rho) * ADJ_FLOP_PER_PAIR[dim], avg))
+        elif k == "adjoint_force":
+            # a reverse step and a recomputed force step in one launch
+            e.update(alu(n * pairs_per_particle(dim, rho) * (ADJ_FLOP_PER_PAIR[dim] + FLOP_PER_PAIR[dim]),
+                         avg))
         kernels[k] = e
     sort_unit = None
     if all(k in kernels for k in ("count", "scan", "scatter")):
@@ -597,7 +601,7 @@ def bench_adjoint(args):
     sysg.set_timing(False)
     rho = n / box ** dim
     kernels, _ = kernel_table(tim, dim, n, rho, sysg.layout, 1)
-    kernels = {k: v for k, v in kernels.items() if k in ("adjoint", "force")}
+    kernels = {k: v for k, v in kernels.items() if k in ("adjoint", "adjoint_force", "force")}
     kd = kernels["adjoint"]
     roofline = {"kernel": "adjoint", "bound": kd["bound"], "achieved": kd["achieved"],
                 "peak": kd["peak"], "unit": kd["unit"], "frac": kd["frac"],

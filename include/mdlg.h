@@ -320,7 +320,9 @@ typedef enum {
     MDLG_K_XI = 6,      /* collision operator of consecutive lattice steps (eq. Xi) */
     MDLG_K_SHIFT = 7,   /* binning on displaced and moving lattices */
     MDLG_K_ADJOINT = 8, /* reverse step of the adjoint window (mdlg_adjoint) */
-    MDLG_K_NCLASS = 9
+    MDLG_K_ADJOINT_FORCE = 9, /* a reverse step launched together with a force step that
+                                 recomputes an earlier checkpoint segment */
+    MDLG_K_NCLASS = 10
 } mdlg_kernel_class;
 
 /* Enable (1) or disable (0) per-kernel timing with HIP events on the handle's

@@ -548,6 +548,7 @@ struct mdlg_system {
   float* adj_ckpt_pos = nullptr;
   float* adj_ckpt_vel = nullptr;
   float* adj_seg_pos = nullptr;
+  float* adj_seg_pos2 = nullptr;  // second segment buffer (recomputation beside the sweep)
   float* adj_lx = nullptr;
   float* adj_lv[2] = {nullptr, nullptr};
   double* adj_gpart = nullptr;
@@ -684,6 +685,7 @@ size_t carve(mdlg_system* S, char* base) {
     S->adj_ckpt_pos = c.take<float>(base, N * D * L.adj_ckpts);
     S->adj_ckpt_vel = c.take<float>(base, N * D * L.adj_ckpts);
     S->adj_seg_pos = c.take<float>(base, N * D * L.adj_seg);
+    S->adj_seg_pos2 = c.take<float>(base, N * D * L.adj_seg);
     S->adj_lx = c.take<float>(base, N * D);
     S->adj_lv[0] = c.take<float>(base, N * D);
     S->adj_lv[1] = c.take<float>(base, N * D);
@@ -1872,8 +1874,8 @@ static Phys window_list_phys(const mdlg_system* S) {
 
 // kdisp: drifts made since the lists were built (checked, and this one
 // recorded), or -1 for a recomputation of steps already checked.
-static void launch_force_raw(mdlg_system* S, const Phys& P, int mode, const float* pos_in,
-                             float* pos_out, float* vel, int kdisp, float* vel_full_out = nullptr) {
+static ForceArgs force_args_raw(mdlg_system* S, const Phys& P, int mode, const float* pos_in,
+                                float* pos_out, float* vel, int kdisp, float* vel_full_out) {
   ForceArgs a{};
   a.P = P;
   a.vel_full_out = vel_full_out;
@@ -1905,6 +1907,12 @@ static void launch_force_raw(mdlg_system* S, const Phys& P, int mode, const floa
   a.mode = mode;
   a.nbricks = S->L.nbricks;
   a.xcd_remap = S->xcd_remap;
+  return a;
+}
+
+static void launch_force_raw(mdlg_system* S, const Phys& P, int mode, const float* pos_in,
+                             float* pos_out, float* vel, int kdisp, float* vel_full_out = nullptr) {
+  const ForceArgs a = force_args_raw(S, P, mode, pos_in, pos_out, vel, kdisp, vel_full_out);
   TimedLaunch t(S, MDLG_K_FORCE);
   launch_force(S->D, a, S->stream);
 }
@@ -2017,22 +2025,29 @@ static int enqueue_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, b
   const float* xW = S->pos[S->pcur];
   AdjLossArgs la{x0, xW, S->adj_lx, S->adj_lv[0], S->adj_lpart, (int)L.n_total, loss, nlb};
   launch_adj_loss(D, la, S->stream);
-  // reverse sweep, segment by segment
+  // Reverse sweep, segment by segment.  The segments before the last are
+  // recomputed from their checkpoints (their velocities run in place in the
+  // checkpoint, used only here), each during the sweep over the segment
+  // after it: recomputation step i of segment seg - 1 goes in the same
+  // launch as reverse step k + 1 - i of segment seg, so that the force
+  // step, which depends on nothing the reverse steps write, costs no launch
+  // of its own.  The last segment's positions are in segment buffer 0 (the
+  // forward window wrote them); the recomputed segments alternate between
+  // the two buffers, so that a segment is recomputed into the buffer the
+  // sweep left one segment earlier.
   const float h = (float)S->cfg.dt;
   const double u = PW.u_d;
   const double e1 = 24.0 * S->cfg.epsilon / (S->cfg.mass * u);
+  const int nseg = W / k;
+  float* segbuf[2] = {S->adj_seg_pos, S->adj_seg_pos2};
+  auto buf_of = [&](int seg) { return segbuf[(nseg - 1 - seg) & 1]; };
   int cur = 0;
-  for (int seg = W / k - 1; seg >= 0; --seg) {
-    const bool last = seg == W / k - 1;
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const bool last = seg == nseg - 1;
     const float* seg0 = S->adj_ckpt_pos + (size_t)seg * nd;  // x at the segment's start
-    if (!last) {
-      // recompute the segment's positions from its checkpoint (its
-      // velocities run in place in the checkpoint, used only here)
-      for (int j = 1; j <= k; ++j)
-        launch_force_raw(S, PF, (seg == 0 && j == 1) ? kModeStart : kModeStep,
-                         j == 1 ? seg0 : S->adj_seg_pos + (size_t)(j - 1) * nd,
-                         S->adj_seg_pos + (size_t)j * nd, S->adj_ckpt_vel + (size_t)seg * nd, -1);
-    }
+    float* buf = buf_of(seg);
+    float* nbuf = seg > 0 ? buf_of(seg - 1) : nullptr;  // the previous segment's, being recomputed
+    const float* nseg0 = seg > 0 ? S->adj_ckpt_pos + (size_t)(seg - 1) * nd : nullptr;
     for (int j = k; j >= (seg == 0 ? 0 : 1); --j) {
       const int sg = seg * k + j;
       AdjArgs a{};
@@ -2040,7 +2055,7 @@ static int enqueue_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, b
       a.reps = S->reps;
       a.bricks = S->bricks;
       a.cell_start = S->cell_start;
-      a.pos = (last && j == k) ? xW : (j == 0 ? seg0 : S->adj_seg_pos + (size_t)j * nd);
+      a.pos = (last && j == k) ? xW : (j == 0 ? seg0 : buf + (size_t)j * nd);
       a.lam_v_in = S->adj_lv[cur];
       a.lam_v_out = S->adj_lv[cur ^ 1];
       a.lam_x = S->adj_lx;
@@ -2061,8 +2076,20 @@ static int enqueue_adjoint(mdlg_system* S, int32_t W, int32_t k, int32_t loss, b
         a.lcap_list = PF.lcap;
         a.stale = S->stale + W;
       }
-      TimedLaunch t(S, MDLG_K_ADJOINT);
-      launch_adjoint(D, a, S->stream);
+      if (seg > 0) {
+        const int i = k + 1 - j;  // recomputation step of segment seg - 1
+        AdjForceArgs af{};
+        af.adj = a;
+        af.force = force_args_raw(S, PF, (seg == 1 && i == 1) ? kModeStart : kModeStep,
+                                  i == 1 ? nseg0 : nbuf + (size_t)(i - 1) * nd, nbuf + (size_t)i * nd,
+                                  S->adj_ckpt_vel + (size_t)(seg - 1) * nd, -1, nullptr);
+        af.force.xcd_remap = 0;
+        TimedLaunch t(S, MDLG_K_ADJOINT_FORCE);
+        launch_adjoint_force(D, af, S->stream);
+      } else {
+        TimedLaunch t(S, MDLG_K_ADJOINT);
+        launch_adjoint(D, a, S->stream);
+      }
       cur ^= 1;
     }
   }

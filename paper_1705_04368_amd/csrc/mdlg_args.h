@@ -332,6 +332,13 @@ extern thread_local LaunchEvents g_launch_events;
 void launch_fill_u32(unsigned* p, unsigned v, long long n, hipStream_t s);
 size_t brick_lds_bytes(const Phys& P, int D, bool adj);
 void launch_adjoint(int D, const AdjArgs& a, hipStream_t s);
+// a reverse step and an independent force step in one launch (both on the
+// layout's block size; the force part takes no XCD remapping)
+struct AdjForceArgs {
+  AdjArgs adj;
+  ForceArgs force;
+};
+void launch_adjoint_force(int D, const AdjForceArgs& a, hipStream_t s);
 void launch_adj_loss(int D, const AdjLossArgs& a, hipStream_t s);
 void launch_adj_final(const AdjFinalArgs& a, hipStream_t s);
 void launch_adj_io(int D, const AdjIoArgs& a, hipStream_t s);

@@ -1224,7 +1224,7 @@ __device__ __forceinline__ void list_fetch(const ForceArgs& a, int2 r, bool has,
 }
 
 template <int D, int NT>
-__global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
+__device__ __forceinline__ void force_brick(const ForceArgs& a, int b) {
   extern __shared__ __align__(16) char s_dyn_brick[];
   __shared__ int s_rowpre[kMaxRows + 1];
   constexpr int NW = NT / 64;
@@ -1232,14 +1232,6 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
   __shared__ double s_red[NW][4];
   auto L = brick_lds<D, false>(s_dyn_brick, s_rowpre, s_tmp, s_red, a.P);
   const int CAP = L.cap;
-  int b = blockIdx.x;
-  if (a.xcd_remap) {
-    // blocks are dispatched round-robin over the 8 XCDs; give each XCD a
-    // contiguous range of bricks so neighbouring bricks share an L2
-    const int per = gridDim.x >> 3;
-    b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  }
-  if (b >= a.nbricks) return;
   const Phys& P = a.P;
   const int4 br = a.bricks[b];
   const bool interact = !P.forces_off;
@@ -1771,7 +1763,7 @@ __device__ __forceinline__ void adj_update(const AdjArgs& a, const Phys& P, int 
 }
 
 template <int D, int NT>
-__global__ __launch_bounds__(NT) void k_adjoint(AdjArgs a) {
+__device__ __forceinline__ void adjoint_brick(const AdjArgs& a, int b) {
   constexpr int NW = NT / 64;
   extern __shared__ __align__(16) char s_dyn_brick[];
   __shared__ int s_rowpre[kMaxRows + 1];
@@ -1779,8 +1771,6 @@ __global__ __launch_bounds__(NT) void k_adjoint(AdjArgs a) {
   __shared__ double s_red[NW][4];
   auto L = brick_lds<D, true>(s_dyn_brick, s_rowpre, s_tmp, s_red, a.P);
   const int CAP = L.cap;
-  const int b = blockIdx.x;
-  if (b >= a.nbricks) return;
   const Phys& P = a.P;
   const int4 br = a.bricks[b];
   const bool interact = !P.forces_off;
@@ -1937,6 +1927,39 @@ __global__ __launch_bounds__(NT) void k_adjoint(AdjArgs a) {
     for (int i = 0; i < NW; ++i) t += L.red[i][threadIdx.x];
     a.gpart[(size_t)b * 2 + threadIdx.x] = t;
   }
+}
+
+// One block per brick: the force kernel (a force / velocity-Verlet step of
+// every particle) and the adjoint's reverse step.
+template <int D, int NT>
+__global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
+  int b = blockIdx.x;
+  if (a.xcd_remap) {
+    // blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous range of bricks so neighbouring bricks share an L2
+    const int per = gridDim.x >> 3;
+    b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  if (b >= a.nbricks) return;
+  force_brick<D, NT>(a, b);
+}
+
+template <int D, int NT>
+__global__ __launch_bounds__(NT) void k_adjoint(AdjArgs a) {
+  const int b = blockIdx.x;
+  if (b >= a.nbricks) return;
+  adjoint_brick<D, NT>(a, b);
+}
+
+// A reverse step and, in the same launch, an independent force step (the
+// recomputation of an earlier segment of the window, on other buffers): the
+// reverse step's bricks first, then the force step's.  Each block runs one
+// or the other exactly as its own kernel would.
+template <int D, int NT>
+__global__ __launch_bounds__(NT) void k_adjoint_force(AdjForceArgs a) {
+  const int b = blockIdx.x;
+  if (b < a.adj.nbricks) adjoint_brick<D, NT>(a.adj, b);
+  else if (b - a.adj.nbricks < a.force.nbricks) force_brick<D, NT>(a.force, b - a.adj.nbricks);
 }
 
 // Loss of the window and its gradient with respect to the final positions.
@@ -2683,6 +2706,13 @@ void launch_site_avg(const SiteAvgArgs& a, hipStream_t s) {
 void launch_adjoint(int D, const AdjArgs& a, hipStream_t s) {
   // the layout's block size, as for the force kernel
   MDLG_LAUNCH_BRICK(D, a.P.bthreads, k_adjoint, a.nbricks, brick_lds_bytes(a.P, D, true), s, a);
+}
+
+void launch_adjoint_force(int D, const AdjForceArgs& a, hipStream_t s) {
+  // both parts take the layout's block size; the LDS is the larger of the two
+  const size_t la = brick_lds_bytes(a.adj.P, D, true), lf = brick_lds_bytes(a.force.P, D, false);
+  const size_t lds = la > lf ? la : lf;
+  MDLG_LAUNCH_BRICK(D, a.adj.P.bthreads, k_adjoint_force, a.adj.nbricks + a.force.nbricks, lds, s, a);
 }
 
 static int grid_for(long long n) {

@@ -26,7 +26,8 @@ EXPORTED = ["mdlg_describe", "mdlg_workspace_bytes", "mdlg_create", "mdlg_step",
             "mdlg_checkpoint_bytes", "mdlg_checkpoint_save", "mdlg_checkpoint_load",
             "mdlg_create_static", "mdlg_get_list_fallbacks"]
 LOSSES = {"msd": 0, "mean_x": 1}
-KERNEL_CLASSES = ["force", "count", "scan", "scatter", "bin", "nlist", "xi", "shift", "adjoint"]
+KERNEL_CLASSES = ["force", "count", "scan", "scatter", "bin", "nlist", "xi", "shift", "adjoint",
+                  "adjoint_force"]
 
 
 class MdlgConfig(C.Structure):
