@@ -541,6 +541,7 @@ struct mdlg_system {
   int4* binfo = nullptr;
   unsigned long long* nl = nullptr;
   unsigned* disp = nullptr;  // displacement bound rows [disp_rows][kDispRow]
+  double* psum = nullptr;    // its running sums [disp_rows]
   unsigned long long* fallbacks = nullptr;  // force launches that walked cells for stale lists
   unsigned* stale = nullptr;  // [disp_rows] lists possibly stale after that many drifts
   int2* trec = nullptr;
@@ -677,6 +678,7 @@ size_t carve(mdlg_system* S, char* base) {
     S->binfo = c.take<int4>(base, (size_t)L.nbricks);
     S->nl = c.take<unsigned long long>(base, (size_t)(std::max(L.kmax, L.kmax_adj) / 4) * N);
     S->disp = c.take<unsigned>(base, (size_t)disp_rows(L) * kDispRow);
+    S->psum = c.take<double>(base, (size_t)disp_rows(L));
     S->fallbacks = c.take<unsigned long long>(base, 1);
     S->stale = c.take<unsigned>(base, (size_t)disp_rows(L));
     S->trec = c.take<int2>(base, (size_t)L.nbricks * L.lcap);
@@ -1000,6 +1002,7 @@ void enqueue_force(mdlg_system* S, int mode, bool sort_follows, float* acc_out, 
     // recorded unless the rebuild that follows makes new lists
     a.stale_in = S->stale + S->since_sort;
     a.disp_in = S->disp;
+    a.psum = S->psum;
     a.ndisp = S->since_sort;
     const bool drift = (mode == kModeStep || mode == kModeStart);
     if (drift && !sort_follows) {
@@ -1184,7 +1187,7 @@ void zero_accumulators(mdlg_system* S) {
 
 // ----- checkpoints
 
-constexpr char kCkptMagic[8] = {'M', 'D', 'L', 'G', 'C', 'K', 'P', '1'};
+constexpr char kCkptMagic[8] = {'M', 'D', 'L', 'G', 'C', 'K', 'P', '2'};
 
 struct CkptHeader {
   char magic[8];
@@ -1265,6 +1268,7 @@ std::vector<Region> ckpt_regions(mdlg_system* S, bool lists) {
     r.push_back({S->nl, (size_t)(L.kmax / 4) * N * sizeof(unsigned long long)});
     r.push_back({S->disp, (size_t)disp_rows(L) * kDispRow * sizeof(unsigned)});
     r.push_back({S->stale, (size_t)disp_rows(L) * sizeof(unsigned)});
+    r.push_back({S->psum, (size_t)disp_rows(L) * sizeof(double)});
     r.push_back({S->trec, (size_t)L.nbricks * L.lcap * sizeof(int2)});
   }
   return r;
@@ -1888,6 +1892,7 @@ static ForceArgs force_args_raw(mdlg_system* S, const Phys& P, int mode, const f
     if (kdisp >= 0) {
       a.stale_in = S->stale + kdisp;
       a.disp_in = S->disp;
+      a.psum = S->psum;
       a.ndisp = kdisp;
       a.disp_out = S->disp + (size_t)kdisp * kDispRow;
       a.stale_out = S->stale + kdisp + 1;

@@ -116,13 +116,15 @@ struct ForceArgs {
   // lists may miss a pair and every brick walks its cells (counted in
   // fallbacks).  Unless no later launch uses the lists (disp_out null), this
   // launch folds its drift into row disp_out and sets stale_out when the
-  // bound over rows [0, ndisp) of disp_in, plus this drift at the speed cap,
-  // passes P.skin, or when a speed passes the cap.
+  // bound over the ndisp completed drifts (the running sum psum[ndisp - 1]
+  // plus row ndisp - 1 of disp_in), plus this drift at the speed cap, passes
+  // P.skin, or when a speed passes the cap.
   const unsigned* stale_in;
   const unsigned* disp_in;
   int ndisp;
   unsigned* disp_out;
   unsigned* stale_out;
+  double* psum;        // running sums of the bound: psum[ndisp] written here, psum[ndisp - 1] read
   unsigned long long* fallbacks;
 };
 

@@ -1159,28 +1159,17 @@ __device__ __forceinline__ unsigned wave_max_u(unsigned v) {
 // they cover every pair within r_cut as long as no particle has moved
 // farther than the skin since.  A particle's drift in one step is
 // |v_half| dt plus the rounding of the offset update, so the sum over the
-// drifts since the build of dt times the step's largest |v_half| (rows of
-// disp, one slot word per lane), plus that rounding, bounds every
-// displacement.  This returns that sum over rows [0, nrows) plus an
-// allowance of `extra` for one more drift.  One wave.
-__device__ __forceinline__ double disp_bound(const unsigned* __restrict__ disp, int nrows, float dt,
-                                             float dslack, double extra) {
-  const int lane = lane_id();
-  double dsum = extra + (double)dslack;
-  for (int r0 = 0; r0 < nrows; r0 += 8) {
-    unsigned m[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-      m[i] = (r0 + i < nrows) ? disp[(size_t)(r0 + i) * kDispRow + lane * kDispStride] : 0u;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      if (r0 + i < nrows) {
-        const unsigned w = wave_max_u(m[i]);
-        dsum += sqrt((double)__uint_as_float(w)) * (double)dt + (double)dslack;
-      }
-    }
-  }
-  return dsum;
+// drifts since the build of dt times the step's largest |v_half| (the rows
+// of disp, one slot word per lane), plus that rounding, bounds every
+// displacement.  The sum runs from launch to launch: drift n adds row n - 1
+// (complete once the launch that made it ended) to the sum drift n - 1
+// passed on.  One wave; lane 0's value.
+__device__ __forceinline__ double disp_running(const unsigned* __restrict__ disp,
+                                               const double* __restrict__ psum, int n, float dt,
+                                               float dslack) {
+  if (n == 0) return 0.0;
+  const unsigned w = wave_max_u(disp[(size_t)(n - 1) * kDispRow + lane_id() * kDispStride]);
+  return psum[n - 1] + sqrt((double)__uint_as_float(w)) * (double)dt + (double)dslack;
 }
 
 // Staged coordinates of the four staging indices packed in e.
@@ -1257,6 +1246,18 @@ __device__ __forceinline__ void force_brick(const ForceArgs& a, int b) {
   // a particle farther than the skin: then the brick walks its cells, which
   // is exact for any move within the cell margin
   const bool stale = a.stale_in ? (*a.stale_in != 0u) : false;
+  if (a.disp_out && b == 0 && threadIdx.x < 64) {
+    // the next launch's flag, from the first wave: the bound over the
+    // completed drifts (passed on as psum[ndisp]) plus this drift at the
+    // speed cap, or a flag already set
+    const double sum = disp_running(a.disp_in, a.psum, a.ndisp, P.dt, P.dslack);
+    if (threadIdx.x == 0) {
+      a.psum[a.ndisp] = sum;
+      const double bound = sum + (double)P.dslack + (double)sqrtf(P.vcap2) * (double)P.dt;
+      if (stale || bound * (1.0 + 1e-6) > (double)P.skin) atomicOr(a.stale_out, 1u);
+      if (stale && a.fallbacks) atomicAdd(a.fallbacks, 1ull);
+    }
+  }
   if (bi.z && !stale) {
     // pair-list path: stage the halo through the map written by the list
     // builder (halo cells in order), then each target walks its own list.  The
@@ -1435,16 +1436,6 @@ __device__ __forceinline__ void force_brick(const ForceArgs& a, int b) {
     if (lane_id() == 0 && m > 0.f) {
       atomicMax(a.disp_out + (size_t)(b & (kDispSlots - 1)) * kDispStride, __float_as_uint(m));
       if (m > P.vcap2) atomicOr(a.stale_out, 1u);
-    }
-    // the next launch's flag from the first block: the bound over the
-    // completed drifts plus this one at the cap, or a flag already set
-    if (b == 0 && threadIdx.x < 64) {
-      const double bound = disp_bound(a.disp_in, a.ndisp, P.dt, P.dslack,
-                                      (double)sqrtf(P.vcap2) * (double)P.dt);
-      if (threadIdx.x == 0) {
-        if (stale || bound * (1.0 + 1e-6) > (double)P.skin) atomicOr(a.stale_out, 1u);
-        if (stale && a.fallbacks) atomicAdd(a.fallbacks, 1ull);
-      }
     }
   } else if (stale && b == 0 && threadIdx.x == 0 && a.fallbacks) {
     atomicAdd(a.fallbacks, 1ull);
