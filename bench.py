@@ -143,7 +143,7 @@ def source_digest():
     that a stored counter summary stays valid across comment edits."""
     import re
     h = hashlib.sha256()
-    for f in ("mdlg_kernels.hip", "mdlg_args.h", "mdlg_device.h"):
+    for f in ("mdlg_kernels.hip", "mdlg_force_block.inc", "mdlg_args.h", "mdlg_device.h"):
         with open(os.path.join(ROOT, "paper_1705_04368_amd", "csrc", f)) as fh:
             text = fh.read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)

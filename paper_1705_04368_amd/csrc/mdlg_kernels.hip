@@ -1213,233 +1213,8 @@ __device__ __forceinline__ void list_fetch(const ForceArgs& a, int2 r, bool has,
 }
 
 template <int D, int NT>
-__device__ __forceinline__ void force_brick(const ForceArgs& a, int b) {
-  extern __shared__ __align__(16) char s_dyn_brick[];
-  __shared__ int s_rowpre[kMaxRows + 1];
-  constexpr int NW = NT / 64;
-  __shared__ int s_tmp[NW + 1];
-  __shared__ double s_red[NW][4];
-  auto L = brick_lds<D, false>(s_dyn_brick, s_rowpre, s_tmp, s_red, a.P);
-  const int CAP = L.cap;
-  const Phys& P = a.P;
-  const int4 br = a.bricks[b];
-  const bool interact = !P.forces_off;
-
-  double kin[D + 1];
-#pragma unroll
-  for (int k = 0; k <= D; ++k) kin[k] = 0.0;
-
-  float vmx = 0.f;  // largest squared half-step speed of this thread's drifts
-
-  // the list path's first staging-map entries and target record are
-  // requested together with the brick's header (their addresses do not
-  // depend on it; entries past the brick's counts are ignored)
-  int2 pre_e0 = make_int2(0, 0), pre_e1 = make_int2(0, 0), pre_r = make_int2(0, 0);
-  if (a.nl) {
-    const int2* __restrict__ sm = a.smap + (size_t)b * CAP;
-    pre_e0 = sm[min((int)threadIdx.x, CAP - 1)];
-    pre_e1 = sm[min((int)threadIdx.x + NT, CAP - 1)];
-    pre_r = a.trec[(size_t)b * CAP + min((int)threadIdx.x, CAP - 1)];
-  }
-  const int4 bi = a.nl ? a.binfo[b] : make_int4(0, 0, 0, 0);
-  // (uniform) whether the drifts since the lists were built may have carried
-  // a particle farther than the skin: then the brick walks its cells, which
-  // is exact for any move within the cell margin
-  const bool stale = a.stale_in ? (*a.stale_in != 0u) : false;
-  if (a.disp_out && b == 0 && threadIdx.x < 64) {
-    // the next launch's flag, from the first wave: the bound over the
-    // completed drifts (passed on as psum[ndisp]) plus this drift at the
-    // speed cap, or a flag already set
-    const double sum = disp_running(a.disp_in, a.psum, a.ndisp, P.dt, P.dslack);
-    if (threadIdx.x == 0) {
-      a.psum[a.ndisp] = sum;
-      const double bound = sum + (double)P.dslack + (double)sqrtf(P.vcap2) * (double)P.dt;
-      if (stale || bound * (1.0 + 1e-6) > (double)P.skin) atomicOr(a.stale_out, 1u);
-      if (stale && a.fallbacks) atomicAdd(a.fallbacks, 1ull);
-    }
-  }
-  if (bi.z && !stale) {
-    // pair-list path: stage the halo through the map written by the list
-    // builder (halo cells in order), then each target walks its own list.  The
-    // targets come in the builder's order (decreasing list length, so that
-    // the lanes of a wave walk lists of similar length) as records
-    // {particle, LDS slot | words << 16}; the first pass's records, state and
-    // first list words are requested before the staging so that their
-    // latency overlaps it.
-    const int2* __restrict__ smap = a.smap + (size_t)b * CAP;
-    const int2* __restrict__ trec = a.trec + (size_t)b * CAP;
-    const int total = bi.x, ntg = bi.y;
-    const size_t nt = (size_t)P.n_total;
-    // list words requested with the target's record: in 2D all of a list
-    // up to 32 entries (the rare longer list reads the rest word by word);
-    // in 3D four, the rest streamed a group ahead
-    constexpr int GW = (D == 2) ? 8 : 4;
-    const unsigned long long pad = 0x0001000100010001ull * (unsigned)total;
-    int gi = 0, t = 0, ng = 0;
-    float o[D], v[D];
-    unsigned long long w[GW];
-    list_fetch<D, GW>(a, pre_r, (int)threadIdx.x < ntg, nt, pad, gi, t, ng, o, v, w);
-    if (threadIdx.x == 0) {
-      if constexpr (D == 2) L.p[total] = make_int2(kSentinel, kSentinel);
-      else L.p[total] = make_int4(kSentinel, kSentinel, kSentinel, 0);
-    }
-    // SU map entries per thread in flight, then their positions: the map
-    // read and the position read it feeds are two dependent round trips, so
-    // a halo of total particles takes about 2 total / (SU NT) of them (2D
-    // halos of a few hundred particles take one pass either way; more
-    // registers there only cost occupancy).  The first pass starts from the
-    // two entries requested with the brick's header.
-    constexpr int SU = (D == 2) ? 2 : 8;
-    int2 e[SU];
-    e[0] = pre_e0;
-    e[1] = pre_e1;
-#pragma unroll
-    for (int u = 2; u < SU; ++u) e[u] = smap[min((int)threadIdx.x + u * NT, total - 1)];
-    for (int v0 = (int)threadIdx.x; v0 < total; v0 += SU * NT) {
-      float p[SU][D];
-#pragma unroll
-      for (int u = 0; u < SU; ++u)
-        if (v0 + u * NT < total) ldv<D>(a.pos_in, e[u].x, p[u]);
-#pragma unroll
-      for (int u = 0; u < SU; ++u) {
-        const int vv = v0 + u * NT;
-        if (vv < total) {
-          const int hx = e[u].y & 255, hy = (e[u].y >> 8) & 255;
-          if constexpr (D == 2)
-            L.p[vv] = make_int2(fixed_coord(hx, p[u][0], P), fixed_coord(hy, p[u][1], P));
-          else
-            L.p[vv] = make_int4(fixed_coord(hx, p[u][0], P), fixed_coord(hy, p[u][1], P),
-                                fixed_coord((e[u].y >> 16) & 255, p[u][2], P), 0);
-        }
-      }
-      const int vn = v0 + SU * NT;
-      if (vn < total) {
-#pragma unroll
-        for (int u = 0; u < SU; ++u) e[u] = smap[min(vn + u * NT, total - 1)];
-      }
-    }
-    __syncthreads();
-    for (int tb = 0; tb < ntg; tb += NT) {
-      if (tb + (int)threadIdx.x >= ntg) break;
-      if (tb > 0) list_fetch<D, GW>(a, trec[tb + threadIdx.x], true, nt, pad, gi, t, ng, o, v, w);
-      const Coord<D> me = L.p[t];
-      const int X = me.x, Y = me.y;
-      int Z = 0;
-      if constexpr (D == 3) Z = me.z;
-      float f[D];
-#pragma unroll
-      for (int k = 0; k < D; ++k) f[k] = 0.f;
-      const unsigned long long* __restrict__ lp = a.nl + gi;
-      if constexpr (D == 2) {
-        // (a word is skipped by a wave none of whose lanes' lists reach it)
-#pragma unroll
-        for (int u = 0; u < GW; ++u)
-          if (u < ng) list_word<D>(L, w[u], X, Y, Z, P, f);
-        for (int k = GW; k < ng; ++k) list_word<D>(L, lp[(size_t)k * nt], X, Y, Z, P, f);
-      } else {
-        // one group of words in flight ahead of the group being summed;
-        // words past the end of the list stand in as four copies of the
-        // sentinel (zero terms)
-        for (int k = 0; k < ng; k += GW) {
-          unsigned long long nx[GW];
-#pragma unroll
-          for (int u = 0; u < GW; ++u)
-            nx[u] = (k + GW + u < ng) ? lp[(size_t)(k + GW + u) * nt] : pad;
-#pragma unroll
-          for (int u = 0; u < GW; ++u) list_word<D>(L, w[u], X, Y, Z, P, f);
-#pragma unroll
-          for (int u = 0; u < GW; ++u) w[u] = nx[u];
-        }
-      }
-      vv_update<D>(a, P, gi, o, v, f, kin, vmx);
-    }
-  } else {
-    const Replica R = a.reps[br.x];
-    const BrickGeom G = brick_setup<D, NT>(P, R, br, a.cell_start, L);
-    const int nchunks = (G.total + CAP - 1) / CAP;
-    if (interact && nchunks == 1) {
-      brick_stage<D, NT>(G, P, a.pos_in, nullptr, L, 0, G.total);
-      __syncthreads();
-    }
-    for (int tb = 0; tb < G.ntg; tb += NT) {
-      const int t = tb + (int)threadIdx.x;
-      const bool valid = t < G.ntg;
-      int hxi = G.ns, hyi = G.ns, hzi = G.nsz, gi = 0, vi = 0;
-      if (valid) brick_target<D>(G, L, t, hxi, hyi, hzi, gi, vi);
-      float o[D], f[D], v[D];
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        o[k] = 0.f;
-        f[k] = 0.f;
-        v[k] = 0.f;
-      }
-      if (valid) {
-        ldv<D>(a.pos_in, gi, o);
-        ldv<D>(a.vel, gi, v);
-      }
-      if (interact) {
-        const int X = fixed_coord(hxi, o[0], P);
-        const int Y = fixed_coord(hyi, o[1], P);
-        const int Z = (D == 3) ? fixed_coord(hzi, o[D - 1], P) : 0;
-        const Reach rr = target_reach<D>(G, P, X, Y, Z, P.rcq);
-        for (int ci = 0; ci < nchunks; ++ci) {
-          const int cb = ci * CAP, ce = min(G.total, cb + CAP);
-          if (nchunks > 1) {
-            __syncthreads();
-            brick_stage<D, NT>(G, P, a.pos_in, nullptr, L, cb, ce);
-            __syncthreads();
-          }
-          if (valid) {
-            for (int cz = rr.cz0; cz <= rr.cz1; ++cz) {
-              for (int cy = rr.cy0; cy <= rr.cy1; ++cy) {
-                int cx0, cx1;
-                if (!row_columns<D>(G, P, X, Y, Z, cy, cz, P.rc2_u, P.mq, cx0, cx1)) continue;
-                const int hrow = G.HX * (cy + G.HY * cz);
-                const int jlo = max(L.hs[hrow + cx0], cb) - cb;
-                const int jhi = min(L.hs[hrow + cx1 + 1], ce) - cb;
-                int j = jlo;
-                for (; j + 3 < jhi; j += 4) {
-                  Coord<D> q[4];
-#pragma unroll
-                  for (int u = 0; u < 4; ++u) q[u] = L.p[j + u];
-#pragma unroll
-                  for (int u = 0; u < 4; ++u) lj_pair<D>(q[u], X, Y, Z, P, f);
-                }
-                for (; j < jhi; ++j) lj_pair<D>(L.p[j], X, Y, Z, P, f);
-              }
-            }
-          }
-        }
-      }
-      if (valid) vv_update<D>(a, P, gi, o, v, f, kin, vmx);
-    }
-  }
-  if (a.kpart) {
-    const int w = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k <= D; ++k) {
-      const double s = wave_sum_d(kin[k]);
-      if (lane_id() == 0) L.red[w][k] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x <= D) {
-      double s = 0.0;
-      for (int i = 0; i < NW; ++i) s += L.red[i][threadIdx.x];
-      a.kpart[(size_t)b * (D + 1) + threadIdx.x] = s;
-    }
-  }
-  if (a.disp_out) {
-    // this drift's largest squared half-step speed, one atomic per wave
-    // (non-negative floats order as their bit patterns); a speed above the
-    // cap marks the lists stale for the next launch at once
-    const float m = wave_max_f(vmx);
-    if (lane_id() == 0 && m > 0.f) {
-      atomicMax(a.disp_out + (size_t)(b & (kDispSlots - 1)) * kDispStride, __float_as_uint(m));
-      if (m > P.vcap2) atomicOr(a.stale_out, 1u);
-    }
-  } else if (stale && b == 0 && threadIdx.x == 0 && a.fallbacks) {
-    atomicAdd(a.fallbacks, 1ull);
-  }
+__device__ __forceinline__ void force_brick(const ForceArgs& a, int boff) {
+#include "mdlg_force_block.inc"
 }
 
 // Pair lists of one brick, built right after each cell-list rebuild (all
@@ -1924,15 +1699,8 @@ __device__ __forceinline__ void adjoint_brick(const AdjArgs& a, int b) {
 // every particle) and the adjoint's reverse step.
 template <int D, int NT>
 __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
-  int b = blockIdx.x;
-  if (a.xcd_remap) {
-    // blocks are dispatched round-robin over the 8 XCDs; give each XCD a
-    // contiguous range of bricks so neighbouring bricks share an L2
-    const int per = gridDim.x >> 3;
-    b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  }
-  if (b >= a.nbricks) return;
-  force_brick<D, NT>(a, b);
+  constexpr int boff = 0;
+#include "mdlg_force_block.inc"
 }
 
 template <int D, int NT>
@@ -1950,7 +1718,7 @@ template <int D, int NT>
 __global__ __launch_bounds__(NT) void k_adjoint_force(AdjForceArgs a) {
   const int b = blockIdx.x;
   if (b < a.adj.nbricks) adjoint_brick<D, NT>(a.adj, b);
-  else if (b - a.adj.nbricks < a.force.nbricks) force_brick<D, NT>(a.force, b - a.adj.nbricks);
+  else force_brick<D, NT>(a.force, a.adj.nbricks);
 }
 
 // Loss of the window and its gradient with respect to the final positions.

@@ -60,7 +60,7 @@ def _tree_with_sources(tmp_path):
     src = os.path.join(ROOT, "paper_1705_04368_amd", "csrc")
     dst = tmp_path / "paper_1705_04368_amd" / "csrc"
     os.makedirs(dst)
-    for f in ("mdlg_kernels.hip", "mdlg_args.h", "mdlg_device.h"):
+    for f in ("mdlg_kernels.hip", "mdlg_force_block.inc", "mdlg_args.h", "mdlg_device.h"):
         shutil.copy(os.path.join(src, f), dst / f)
     return dst
 
@@ -74,6 +74,14 @@ def test_source_digest_ignores_comments_and_follows_code(tmp_path, monkeypatch):
     k.write_text("// a new comment\n/* and a\n   block comment */\n" + text.replace("\n", "\n\n", 3))
     assert bench.source_digest() == d0
     k.write_text(text.replace("constexpr int kSentinel = 1 << 30;", "constexpr int kSentinel = 1 << 29;"))
+    assert bench.source_digest() != d0
+    # the force block's body, pasted into the kernels, counts as kernel source
+    k.write_text(text)
+    assert bench.source_digest() == d0
+    f = dst / "mdlg_force_block.inc"
+    body = f.read_text()
+    assert "const bool interact = !P.forces_off;" in body
+    f.write_text(body.replace("const bool interact = !P.forces_off;", "const bool interact = true;"))
     assert bench.source_digest() != d0
 
 

@@ -458,6 +458,43 @@ def test_stale_pair_lists_walk_the_cells():
     assert abs(x[1, 0] - 9.0) < 1e-6
 
 
+@pytest.mark.parametrize("speed,stale", [(6.0, True), (2.0, False)])
+def test_displacement_bound_sums_the_drifts(speed, stale):
+    # one particle at a speed under the cap 8 (kT/m)^(1/2), so that only the
+    # bound summed over the drifts since the build (carried from launch to
+    # launch) can mark the lists stale: at 6 sigma/tau it passes the skin
+    # inside the 18-step interval and the later launches walk the cells; at
+    # 2 sigma/tau it never does.  The flight is exact either way.
+    from paper_1705_04368_amd import make_config
+    cfg = make_config(2, 2, 4, lattice_dx=4.0, dt=0.005, vmax=1, md_cell_split=1, kT=1.0,
+                      sort_every=18)
+    pos = np.array([[1.0, 2.0], [9.0, 10.0]], np.float32)
+    vel = np.array([[speed, 0.0], [0.0, 0.0]], np.float32)
+    say(f"displacement bound, speed {speed}")
+    sysg = make_system(cfg, pos, vel)
+    skin = sysg.layout["skin"]
+    assert sysg.layout["pair_slots"] > 0 and sysg.layout["sort_every"] == 18
+    cap = 8.0 * 0.005  # one drift at the speed cap
+    assert speed < 8.0
+    # the bound before drift n is about n speed dt + cap: past the skin at
+    # 6 sigma/tau by drift 10, below it at 2 sigma/tau through drift 17
+    if stale:
+        assert 10 * speed * 0.005 + cap > skin * 1.01
+    else:
+        assert 17 * speed * 0.005 + cap < skin * 0.99
+    sysg.step(18)
+    sysg.sync()
+    fb = sysg.list_fallbacks()
+    say(f"  skin {skin:.4f}, launches that walked the cells: {fb}")
+    if stale:
+        assert 1 <= fb <= 9
+    else:
+        assert fb == 0
+    x = unwrapped(sysg.get_state(), sysg.layout["cell_side"])
+    assert abs(x[0, 0] - (1.0 + speed * 0.005 * 18)) < 1e-4
+    assert abs(x[1, 0] - 9.0) < 1e-6
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_forces_at_every_step_between_rebuilds(dim):
     # Forces at each MD step of one rebuild interval (the pair lists, built
