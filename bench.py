@@ -515,10 +515,10 @@ def kernel_table(tim, dim, n, rho, lay, n_sites):
             e.update(hbm(scan_bytes_per_cell() * lay["n_cells"], avg))
         elif k == "nlist":
             # read the offsets, write the lists (16-bit entries within
-            # r_cut + 2 margin), the target records and the reference offsets
+            # r_cut + 2 skin) and the target records
             rl = 2.5 + 2 * lay["skin"]
             vol = math.pi * rl * rl if dim == 2 else 4.0 / 3.0 * math.pi * rl ** 3
-            e.update(hbm(n * (4 * dim + 2 * vol * rho + 8 + 4 * dim), avg))
+            e.update(hbm(n * (4 * dim + 2 * vol * rho + 8), avg))
         elif k == "shift":
             e.update(hbm(n * (4 + 16 * dim), avg))
         elif k == "xi":

@@ -421,8 +421,10 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
       for (int by = 0; by < nby; ++by)
         for (int bx = 0; bx < nbx; ++bx) L->bricks.push_back(make_int4(r, bx, by, bz));
     rep.nbricks = (int)L->bricks.size() - rep.brick_off;
+    rep.chunk_off = (int)L->chunks.size();
     for (long long g = part_off; g < part_off + rep.n; g += kPartChunk)
       L->chunks.push_back(make_int4(r, (int)g, (int)std::min(part_off + rep.n, g + kPartChunk), 0));
+    rep.nchunks = (int)L->chunks.size() - rep.chunk_off;
     for (long long g = part_off; g < part_off + rep.n; g += cchunk)
       L->cchunks.push_back(make_int4(r, (int)g, (int)std::min(part_off + rep.n, g + cchunk), 0));
     const int nsz_rows = (D == 3) ? rep.M[2] : 1;
@@ -645,7 +647,7 @@ size_t carve(mdlg_system* S, char* base) {
   S->A = c.take<unsigned>(base, (size_t)L.n_sites * L.Q);
   S->mom = c.take<long long>(base, (size_t)L.n_sites * L.nm);
   S->dpart = c.take<double>(base, (size_t)L.nstrips * 2 * D);
-  S->kpart = c.take<double>(base, (size_t)L.nbricks * (D + 1));
+  S->kpart = c.take<double>(base, (size_t)L.nchunks * (D + 1));
   S->kin = c.take<double>(base, L.reps.size() * (D + 1));
   S->lambda = c.take<float>(base, L.reps.size());
   S->err = c.take<unsigned>(base, 64);
@@ -973,7 +975,7 @@ void enqueue_sort(mdlg_system* S) {
   if (S->L.kmax > 0) enqueue_nlist(S, S->P);
 }
 
-void enqueue_force(mdlg_system* S, int mode, bool sort_follows, float* acc_out, double* kpart) {
+void enqueue_force(mdlg_system* S, int mode, bool sort_follows, float* acc_out) {
   ForceArgs a{};
   a.P = S->P;
   if (sort_follows) {
@@ -988,7 +990,6 @@ void enqueue_force(mdlg_system* S, int mode, bool sort_follows, float* acc_out, 
   a.pos_out = S->pos[S->pcur ^ 1];
   a.vel = S->vel[S->scur];
   a.acc_out = acc_out;
-  a.kpart = kpart;
   a.err = S->err;
   a.mode = mode;
   a.nbricks = S->L.nbricks;
@@ -1018,7 +1019,16 @@ void enqueue_force(mdlg_system* S, int mode, bool sort_follows, float* acc_out, 
   if (mode == kModeStep || mode == kModeStart) S->pcur ^= 1;
 }
 
+// Kinetics of the full-step velocities in the state (per replica, FP64):
+// per-chunk partials, then their sum per replica; with thermostat, the
+// rescale to kT as well.
 void enqueue_kin(mdlg_system* S, bool thermostat) {
+  KinPartArgs kp{};
+  kp.chunks = S->chunks;
+  kp.vel = S->vel[S->scur];
+  kp.kpart = S->kpart;
+  kp.mass = S->cfg.mass;
+  launch_kinpart(S->D, S->L.nchunks, kp, S->stream);
   KinArgs k{};
   k.reps = S->reps;
   k.kpart = S->kpart;
@@ -1044,7 +1054,7 @@ void enqueue_kin(mdlg_system* S, bool thermostat) {
 void enqueue_md_step(mdlg_system* S, bool force_sort) {
   const int mode = S->vel_full ? kModeStart : kModeStep;
   const bool sort_next = force_sort || (S->since_sort + 1 >= S->L.sort_every);
-  enqueue_force(S, mode, sort_next, nullptr, nullptr);
+  enqueue_force(S, mode, sort_next, nullptr);
   S->vel_full = false;
   S->since_sort += 1;
   S->md_step += 1;
@@ -1533,7 +1543,7 @@ static void enqueue_md_steps(mdlg_system* S, int64_t n) {
   for (int64_t i = 0; i < n; ++i) {
     enqueue_md_step(S, false);
     if (te > 0 && S->md_step % te == 0) {
-      enqueue_force(S, kModeFinish, false, nullptr, S->kpart);
+      enqueue_force(S, kModeFinish, false, nullptr);
       enqueue_kin(S, true);
       S->vel_full = true;
     }
@@ -1681,7 +1691,8 @@ mdlg_status mdlg_get_f(mdlg_system* S, double* f, double* f_site, double* mom_si
 
 mdlg_status mdlg_get_kinetics(mdlg_system* S, double* out) {
   if (!S || !out) return MDLG_E_INVALID;
-  enqueue_force(S, S->vel_full ? kModeProbe : kModeFinish, false, nullptr, S->kpart);
+  // (a half-step state is completed first)
+  if (!S->vel_full) enqueue_force(S, kModeFinish, false, nullptr);
   S->vel_full = true;
   enqueue_kin(S, false);
   mdlg_status st = check_launch(S, "mdlg_get_kinetics");
@@ -1753,7 +1764,7 @@ mdlg_status mdlg_get_state(mdlg_system* S, mdlg_particles* out) {
   const Layout& L = S->L;
   const int D = S->D;
   const size_t nd = (size_t)L.n_total * D;
-  enqueue_force(S, S->vel_full ? kModeProbe : kModeFinish, false, S->acc_sorted, nullptr);
+  enqueue_force(S, S->vel_full ? kModeProbe : kModeFinish, false, S->acc_sorted);
   S->vel_full = true;
   XportArgs x{};
   x.P = S->P;

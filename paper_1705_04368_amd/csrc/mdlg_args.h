@@ -102,7 +102,6 @@ struct ForceArgs {
   float* vel;
   float* acc_out;      // optional
   float* vel_full_out; // optional: the full-step velocities v(t) of this launch's kick
-  double* kpart;       // optional per-brick partials [nbricks][D + 1]
   unsigned* err;
   int mode;
   int nbricks;
@@ -145,9 +144,19 @@ struct NlistArgs {
   int xcd_remap;
 };
 
+// FP64 kinetic partials of every particle chunk (sum of m v and of m v^2 / 2
+// over the chunk's full-step velocities, in particle order).
+struct KinPartArgs {
+  const int4* chunks;
+  const float* vel;
+  double* kpart;   // [nchunks][D + 1]
+  double mass;
+};
+void launch_kinpart(int D, int nchunks, const KinPartArgs& a, hipStream_t s);
+
 struct KinArgs {
   const Replica* reps;
-  const double* kpart;
+  const double* kpart;  // per-chunk partials (k_kinpart)
   double* kin;     // [n_rep][D + 1]
   float* lambda;   // [n_rep]
   int n_rep;

@@ -84,6 +84,8 @@ struct Replica {
   int n;         // particles
   int brick_off; // first force brick
   int nbricks;   // force bricks
+  int chunk_off; // first particle chunk
+  int nchunks;   // particle chunks
 };
 
 // Exact quotient n / d for 0 <= n < 2^31 and a divisor d >= 2 given as the

@@ -1098,12 +1098,12 @@ __device__ __forceinline__ bool row_columns(const BrickGeom& G, const Phys& P, i
 }
 
 // Velocity-Verlet update of one particle from its acceleration f, shared by
-// both force paths; accumulates the kinetic partials and, for a drift, the
-// largest squared half-step speed (vmx).
+// both force paths; for a drift, also the largest squared half-step speed
+// (vmx).
 template <int D>
 __device__ __forceinline__ void vv_update(const ForceArgs& a, const Phys& P, int gi,
                                           const float (&o)[D], const float (&v)[D],
-                                          const float (&f)[D], double (&kin)[D + 1], float& vmx) {
+                                          const float (&f)[D], float& vmx) {
   float vf[D];
   const bool drift = (a.mode == kModeStep || a.mode == kModeStart);
   float on[D], vh[D];
@@ -1130,15 +1130,6 @@ __device__ __forceinline__ void vv_update(const ForceArgs& a, const Phys& P, int
     stv<D>(a.vel, gi, vf);
   }
   if (a.acc_out) stv<D>(a.acc_out, gi, f);
-  if (a.kpart) {
-    double e = 0.0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      kin[k] += (double)P.mass * (double)vf[k];
-      e += (double)vf[k] * (double)vf[k];
-    }
-    kin[D] += 0.5 * (double)P.mass * e;
-  }
 }
 
 // Largest value over the wave.
@@ -1822,13 +1813,48 @@ __global__ void k_copy_f32(const float* __restrict__ src, float* __restrict__ ds
 // ---------------------------------------------------------------- kinetics
 
 // One block per replica: FP64 sums of the per-brick partials in a fixed order.
+// FP64 kinetic partials of one particle chunk: each thread sums its strided
+// particles, then the waves and the block in a fixed order, so that the sums
+// depend on the state alone.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_kinpart(KinPartArgs a) {
+  __shared__ double s_red[kWaves][4];
+  const int4 ch = a.chunks[blockIdx.x];
+  double s[D + 1];
+#pragma unroll
+  for (int k = 0; k <= D; ++k) s[k] = 0.0;
+  for (int g = ch.y + threadIdx.x; g < ch.z; g += kBlock) {
+    float v[D];
+    ldv<D>(a.vel, g, v);
+    double e = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      s[k] += a.mass * (double)v[k];
+      e += (double)v[k] * (double)v[k];
+    }
+    s[D] += 0.5 * a.mass * e;
+  }
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k <= D; ++k) {
+    const double t = wave_sum_d(s[k]);
+    if (lane_id() == 0) s_red[w][k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x <= D) {
+    double t = 0.0;
+    for (int i = 0; i < kWaves; ++i) t += s_red[i][threadIdx.x];
+    a.kpart[(size_t)blockIdx.x * (D + 1) + threadIdx.x] = t;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_kin(KinArgs a) {
   __shared__ double s_red[kWaves][4];
   const int r = blockIdx.x;
   const Replica R = a.reps[r];
   double s[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int b = R.brick_off + threadIdx.x; b < R.brick_off + R.nbricks; b += kBlock)
-    for (int k = 0; k <= a.D; ++k) s[k] += a.kpart[(size_t)b * (a.D + 1) + k];
+  for (int c = R.chunk_off + threadIdx.x; c < R.chunk_off + R.nchunks; c += kBlock)
+    for (int k = 0; k <= a.D; ++k) s[k] += a.kpart[(size_t)c * (a.D + 1) + k];
   const int w = threadIdx.x >> 6;
   for (int k = 0; k <= a.D; ++k) {
     const double t = wave_sum_d(s[k]);
@@ -2422,6 +2448,10 @@ void launch_nlist(int D, const NlistArgs& a, hipStream_t s) {
   // neither carries the other's registers
   if (a.P.nl_wide) MDLG_LAUNCH_BRICK(D, a.P.bthreads, k_nlist_wide, grid, lds, s, a);
   else MDLG_LAUNCH_BRICK(D, a.P.bthreads, k_nlist_narrow, grid, lds, s, a);
+}
+
+void launch_kinpart(int D, int nchunks, const KinPartArgs& a, hipStream_t s) {
+  MDLG_LAUNCH_DIM(D, k_kinpart, nchunks, 0, s, a);
 }
 
 void launch_kin(const KinArgs& a, hipStream_t s) {
