@@ -235,9 +235,11 @@ mdlg_status mdlg_get_f(mdlg_system *sys, double *f, double *f_site, double *mom_
                        uint64_t *counts, int64_t *n_samples, int64_t *n_overflow, double *disp,
                        int64_t *n_lattice_steps);
 
-/* Diagnostics per replica at the last lattice step or thermostat step (FP64):
+/* Kinetics per replica of the current state (FP64; a half-step state is first
+ * completed by its finishing kick, as a lattice step's end would):
  * out[r][0..dim-1] = total momentum sum m v, out[r][dim] = kinetic energy
- * sum m v^2 / 2.  Synchronises.  out is host [n_replicas][dim + 1]. */
+ * sum m v^2 / 2, summed in particle order (the same sums for a replica alone
+ * and in a batch).  Synchronises.  out is host [n_replicas][dim + 1]. */
 mdlg_status mdlg_get_kinetics(mdlg_system *sys, double *out);
 
 /* Zero all accumulators (n_i sums, moments, displacement sums, lattice-step
