@@ -19,7 +19,7 @@
 //              old order: deterministic)
 //   k_cellsort first rebuild of an input in arbitrary order: cells by id
 //   k_rescale  thermostat rescale of the velocities
-//   k_nlist_narrow / k_nlist_wide    pair lists of radius r_cut + 2 margin
+//   k_nlist_narrow / k_nlist_wide    pair lists of radius r_cut + 2 skin
 //              per brick at each rebuild (14-bit candidate tests), with the
 //              staging map and target order the force kernel follows
 //   k_force    LJ forces with the neighbour cells of a brick staged in LDS
@@ -1210,9 +1210,9 @@ __device__ __forceinline__ void force_brick(const ForceArgs& a, int boff) {
 
 // Pair lists of one brick, built right after each cell-list rebuild (all
 // particles then lie inside their cells).  For every target the list holds
-// the halo particles within r_cut + 2 m, m the rebuild margin, so that it
-// covers every pair within r_cut while no particle has moved farther than m
-// since (the force kernel checks that bound).  Entries are 16-bit indices
+// the halo particles within r_cut + 2 skin (the skin at most the rebuild
+// margin), so that it covers every pair within r_cut while no particle has
+// moved farther than the skin since (the force kernel checks that bound).  Entries are 16-bit indices
 // into the brick's LDS staging of its halo (halo cells in order, from the
 // cell table, which stays fixed until the next rebuild), four to a word, the
 // last word padded with the index of a sentinel slot beyond the halo (a zero
