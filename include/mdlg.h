@@ -24,10 +24,10 @@
  * Conventions
  *   - All entry points return mdlg_status (0 = MDLG_OK, negative = error) and
  *     never throw.  Config errors are found synchronously on the host.
- *   - Device-side failures (a particle leaving the cell-list margin between
- *     rebuilds or moving farther than the margin since the pair lists were
- *     built, non-finite coordinates, a velocity so large that a particle
- *     crosses more than one cell per step) set a device error word; it is
+ *   - Device-side failures (a particle leaving its MD cell between rebuilds
+ *     by more than the stencil's reach, non-finite coordinates, a velocity
+ *     so large that a particle crosses more than one cell per step) set a
+ *     device error word; it is
  *     reported as MDLG_E_UNSTABLE by the next call that synchronises
  *     (mdlg_get_f, mdlg_get_state, mdlg_sync), and mdlg_last_error() explains.
  *   - The caller owns all device memory: one workspace of
@@ -152,12 +152,17 @@ typedef struct {
     int64_t n_cells;            /* MD cells over all replicas */
     int64_t n_bricks;           /* force-kernel work units per MD step */
     double cell_side;           /* s */
-    double margin;              /* allowed excursion outside the cell between rebuilds */
+    double margin;              /* design excursion outside the cell between rebuilds (eight
+                                   thermal speeds per axis over the interval); it sets the
+                                   automatic rebuild interval and bounds the skin */
     int32_t pair_slots;         /* pair-list entries per particle (0 = no pair lists) */
     int32_t block_threads;      /* threads per force / pair-list block actually used */
-    double skin;                /* pair lists hold the pairs within r_cut + 2 skin; a particle
-                                   that moves farther since the lists were built is a device
-                                   error (currently skin = margin) */
+    double skin;                /* pair lists hold the pairs within r_cut + 2 skin (skin <=
+                                   margin); past it the force launches walk the cells until
+                                   the next rebuild (mdlg_get_list_fallbacks) */
+    double reach;               /* stencil's reach (stencil * s - r_cut) / 2 >= margin: the
+                                   cell walk is exact for any excursion outside the cell up to
+                                   it; a particle beyond it between rebuilds is a device error */
 } mdlg_layout;
 
 /* Validate cfg and report the derived layout.  Host only.  MDLG_E_INVALID on
@@ -342,7 +347,8 @@ mdlg_status mdlg_get_timing(mdlg_system *sys, double *total_ms, int64_t *launche
  * r_cut + 2 skin of their build, and each MD step folds the largest
  * half-step speed into a bound on every particle's displacement since; a
  * launch whose bound passes the skin walks the cell rows instead (exact for
- * moves within the rebuild margin), until the next rebuild.  A measure of
+ * excursions outside the cell up to the stencil's reach), until the next
+ * rebuild.  A measure of
  * how often the skin (sized from the expected largest speed of the
  * system's particles) is too small.  Synchronises; *launches is host. */
 mdlg_status mdlg_get_list_fallbacks(mdlg_system *sys, int64_t *launches);

@@ -244,8 +244,9 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   if (min_m * k < 2 * L->ns + 1)
     return set_err(msg, "too few MD cells per axis (%d) for the stencil half-width %d", min_m * k, L->ns);
   // rebuild interval and the margin it needs: eight standard deviations of
-  // the Maxwell speed per axis times the interval (the kernel checks the
-  // bound, and a particle beyond it is an error)
+  // the Maxwell speed per axis times the interval.  The margin is a design
+  // figure: the cell walk stays exact up to the stencil's reach m_max, and
+  // only a particle beyond that is an error
   const double vfast = c->kT > 0 ? 8.0 * std::sqrt(c->kT / c->mass) : 0.0;
 
   // with pair lists the margin also widens every list (radius r_cut + 2 m),
@@ -279,7 +280,7 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   // step: v^2 = (kT/m) (2 ln n + 10) in 2D, + 14 in 3D for the extra degree
   // of freedom), at most the margin.  The force kernel bounds the actual
   // drifts since the build; past the skin the bricks walk their cells (exact
-  // within the margin) until the next rebuild.
+  // within the stencil's reach) until the next rebuild.
   L->skin = L->margin;
   if (vfast > 0) {
     const double vs = std::min(8.0, std::sqrt(2.0 * std::log((double)std::max(2ll, n_total)) +
@@ -475,6 +476,7 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   P.n_bricks = L->nbricks;
   P.cell_side = L->s;
   P.margin = L->margin;
+  P.reach = L->margin_max;
   P.skin = L->skin;
   P.pair_slots = L->kmax;
   P.block_threads = L->bthreads;
@@ -753,8 +755,12 @@ Phys make_phys(const mdlg_config* c, const Layout& L) {
   P.F = std::min(26, 31 - lg);
   const double u = L.s / std::ldexp(1.0, P.F);
   P.fscale = (float)(std::ldexp(1.0, P.F) / L.s);
-  P.rcq = (int)std::ceil((c->r_cut + L.margin) / u) + 1;
-  P.mq = (int)std::ceil(L.margin / u) + 4;
+  // the cell walk prunes with the stencil's full reach, the largest
+  // excursion outside its cell that the staged halo still covers, not with
+  // the rebuild margin (the design excursion that sets the interval): a
+  // particle that outruns the margin between rebuilds is then still exact
+  P.rcq = (int)std::ceil((c->r_cut + L.margin_max) / u) + 1;
+  P.mq = (int)std::ceil(L.margin_max / u) + 4;
   P.rc_d = c->r_cut;
   P.u_d = u;
   set_list_params(P, c, L, L.skin, L.kmax);
@@ -768,8 +774,8 @@ Phys make_phys(const mdlg_config* c, const Layout& L) {
   P.eps24m_u = (float)(24.0 * c->epsilon / (c->mass * u));
   P.dt = (float)c->dt;
   P.half_dt = (float)(0.5 * c->dt);
-  P.lo = (float)(-L.margin);
-  P.hi = (float)(L.s + L.margin);
+  P.lo = (float)(-L.margin_max);
+  P.hi = (float)(L.s + L.margin_max);
   P.mass = (float)c->mass;
   P.ns = L.ns;
   P.log2k = L.log2k;
@@ -1159,7 +1165,8 @@ mdlg_status read_err(mdlg_system* S) {
   HIPCHK(S, hipStreamSynchronize(S->stream));
   if (e) {
     std::string m = "device error word 0x" + std::to_string(e) + ":";
-    if (e & kErrMargin) m += " a particle left its cell by more than the rebuild margin (lower sort_every or dt);";
+    if (e & kErrMargin)
+      m += " a particle left its cell between rebuilds by more than the stencil's reach (stencil s - r_cut) / 2 (lower sort_every or dt);";
     if (e & kErrRecord) m += " internal: a pair-list target record named no particle;";
     if (e & kErrNonFinite) m += " non-finite coordinates;";
     if (e & kErrJump) m += " a particle moved more than one cell between rebuilds or started outside the box;";
@@ -1864,14 +1871,10 @@ mdlg_status mdlg_set_state(mdlg_system* S, const mdlg_particles* in) {
 }
 
 // Phys of an adjoint window: the cell list stays frozen for the whole window,
-// so particles may use the full stencil margin (ns s - r_cut) / 2.
+// so particles may use the stencil's full reach (ns s - r_cut) / 2, which the
+// cell walk's pruning and drift bounds already take.
 static Phys window_phys(const mdlg_system* S) {
   Phys P = S->P;
-  const double m = S->L.margin_max;
-  P.lo = (float)(-m);
-  P.hi = (float)(S->L.s + m);
-  P.rcq = (int)std::ceil((P.rc_d + m) / P.u_d) + 1;
-  P.mq = (int)std::ceil(m / P.u_d) + 4;
   P.lcap = S->L.lcap_adj;
   P.kmax = 0;
   return P;

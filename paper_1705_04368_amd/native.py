@@ -57,7 +57,7 @@ class MdlgLayout(C.Structure):
                 ("brick", C.c_int32 * 3), ("n_total", C.c_int64), ("n_sites", C.c_int64),
                 ("n_cells", C.c_int64), ("n_bricks", C.c_int64), ("cell_side", C.c_double),
                 ("margin", C.c_double), ("pair_slots", C.c_int32), ("block_threads", C.c_int32),
-                ("skin", C.c_double)]
+                ("skin", C.c_double), ("reach", C.c_double)]
 
 
 _lib = None
@@ -207,7 +207,7 @@ def describe(cfg):
             "n_moments": out.n_moments, "brick": tuple(out.brick), "n_total": out.n_total,
             "n_sites": out.n_sites, "n_cells": out.n_cells, "n_bricks": out.n_bricks,
             "cell_side": out.cell_side, "margin": out.margin, "pair_slots": out.pair_slots,
-            "block_threads": out.block_threads, "skin": out.skin}
+            "block_threads": out.block_threads, "skin": out.skin, "reach": out.reach}
 
 
 def workspace_bytes(cfg):

@@ -42,6 +42,20 @@ def test_describe_config1():
     assert d["margin"] > 0
     assert 1 <= d["sort_every"] <= 20
     assert native.workspace_bytes(cfg) > 2048 * 2 * 4 * 4
+    # the cell walk's reach: the excursion the one-cell halo still covers
+    # when two particles, each that far outside its cell, are r_cut apart
+    assert d["reach"] == pytest.approx((d["stencil"] * d["cell_side"] - 2.5) / 2, rel=1e-12)
+    assert d["skin"] <= d["margin"] <= d["reach"] < d["cell_side"] / 2
+
+
+def test_reach_is_independent_of_the_rebuild_interval():
+    # the margin grows with the interval up to the reach; the reach does not
+    lays = [native.describe(native.make_config(2, 2048, 16, lattice_dx=4.0, dt=0.005,
+                                               md_cell_split=1, kT=1.0, sort_every=r))
+            for r in (2, 10, 18, 40)]
+    assert len({d["reach"] for d in lays}) == 1
+    margins = [d["margin"] for d in lays]
+    assert margins == sorted(margins) and margins[-1] == lays[0]["reach"]
 
 
 def test_describe_3d_and_replicas():

@@ -332,7 +332,7 @@ def test_unstable_step_is_reported():
     cfg, pos, vel, box, n, M = _force_case(2, 9, 1)
     cfg.sort_every = 10
     vel = vel.copy()
-    vel[0] = [400.0, 0.0]  # crosses more than the margin within one step
+    vel[0] = [400.0, 0.0]  # 2 sigma per step: past the stencil's reach within a few
     say("unstable step")
     sysg = make_system(cfg, pos, vel)
     sysg.step(3)
@@ -493,6 +493,50 @@ def test_displacement_bound_sums_the_drifts(speed, stale):
     x = unwrapped(sysg.get_state(), sysg.layout["cell_side"])
     assert abs(x[0, 0] - (1.0 + speed * 0.005 * 18)) < 1e-4
     assert abs(x[1, 0] - 9.0) < 1e-6
+
+
+@pytest.mark.parametrize("dim,lists", [(2, True), (2, False), (3, True)])
+def test_particles_past_the_margin_stay_exact(dim, lists):
+    # The rebuild margin is sized for kT = 0.01 while the particles move at
+    # kT = 1, so between rebuilds many leave their cells by more than the
+    # margin, none by the stencil's reach.  Speeds above the cap mark the
+    # lists stale at the first drift; the cell walk, pruned with the reach,
+    # then follows the oracle over two rebuild intervals with no error.
+    cfg, pos, vel, box, n, M = _force_case(dim, 77, 2 if dim == 3 else 1, equil_steps=300)
+    cfg.kT = 0.01
+    cfg.sort_every = 18
+    cfg.no_pair_list = 0 if lists else 1
+    say(f"past the margin dim={dim} lists={lists}")
+    sysg = make_system(cfg, pos, vel)
+    lay = sysg.layout
+    s, margin, reach = lay["cell_side"], lay["margin"], lay["reach"]
+    assert lay["sort_every"] == 18 and (lay["pair_slots"] > 0) == lists
+    md = oracle.make_md(dim, n, box, dt=0.005)
+    ost = oracle.OracleState(md, pos, vel)
+    # largest excursion outside the cell of the last rebuild (steps 0 and
+    # 18), over the drifts that no rebuild follows
+    excursion = 0.0
+    cell = np.floor(ost.unwrapped / s)
+    for step in range(1, 37):
+        ost.run(1)
+        x = ost.unwrapped
+        if step % 18:
+            out = np.maximum(cell * s - x, x - (cell + 1) * s)
+            excursion = max(excursion, float(out.max()))
+        else:
+            cell = np.floor(x / s)
+    say(f"  margin {margin:.4f}, reach {reach:.4f}, largest excursion {excursion:.4f}")
+    assert margin < excursion < reach
+    sysg.step(36)
+    sysg.sync()
+    if lists:
+        assert sysg.list_fallbacks() >= 1
+    st = sysg.get_state()
+    dxmax = np.abs(unwrapped(st, s) - ost.unwrapped).max()
+    dvmax = np.abs(st["vel"].astype(np.float64) - ost.v).max()
+    say(f"  max |dx| {dxmax:.3e}  max |dv| {dvmax:.3e}")
+    assert dxmax <= 1e-4
+    assert dvmax <= 1e-4
 
 
 @pytest.mark.parametrize("dim", [2, 3])
