@@ -361,6 +361,12 @@ bool build_layout(const mdlg_config* c, Layout* L, std::string* msg) {
   if (halo > maxh) return set_err(msg, "brick %dx%dx%d with stencil %d needs %lld halo cells > %d",
                                   BX, BY, BZ, L->ns, halo, maxh);
   if ((long long)BY * BZ > kMaxRows) return set_err(msg, "brick has more than %d rows", kMaxRows);
+  // the staging map of the pair lists packs a halo cell in 8 bits per axis
+  // in 2D and in 5 in 3D
+  const int hlim = (D == 2) ? 256 : 32;
+  if (BX + 2 * L->ns > hlim || BY + 2 * L->ns > hlim || BZ + 2 * nsz > hlim)
+    return set_err(msg, "brick %dx%dx%d with stencil %d has a halo wider than %d cells", BX, BY, BZ,
+                   L->ns, hlim);
   L->BX = BX;
   L->BY = BY;
   L->BZ = BZ;
@@ -1204,7 +1210,9 @@ void zero_accumulators(mdlg_system* S) {
 
 // ----- checkpoints
 
-constexpr char kCkptMagic[8] = {'M', 'D', 'L', 'G', 'C', 'K', 'P', '2'};
+// the blob format, raised whenever a saved region changes its layout (3: the
+// staging-map entries carry their LDS slot)
+constexpr char kCkptMagic[8] = {'M', 'D', 'L', 'G', 'C', 'K', 'P', '3'};
 
 struct CkptHeader {
   char magic[8];

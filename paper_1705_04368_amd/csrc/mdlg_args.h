@@ -107,8 +107,9 @@ struct ForceArgs {
   int nbricks;
   int xcd_remap;
   // pair lists (null nl: every brick walks its cell rows)
-  const int2* smap;    // [nbricks][lcap] staged halo in LDS order {particle, hx | hy << 8 | hz << 16}
-  const int4* binfo;   // [nbricks] {staged, targets, lists valid, -}
+  const int2* smap;    // [nbricks][lcap] halo particles the lists may name, in LDS order:
+                       // {particle, LDS slot << 16 | halo cell (8 bits per axis in 2D, 5 in 3D)}
+  const int4* binfo;   // [nbricks] {halo slots, targets, lists valid, map entries}
   const unsigned long long* nl;  // [kmax / 4][n_total] four 16-bit halo indices per word
   const int2* trec;    // [nbricks][lcap] targets in processing order {particle, slot | words << 16}
   // displacement bound since the lists were built: stale_in set means the

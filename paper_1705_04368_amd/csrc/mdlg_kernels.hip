@@ -904,19 +904,36 @@ __device__ __forceinline__ BrickGeom brick_setup(const Phys& P, const Replica& R
   return G;
 }
 
-__device__ __forceinline__ int pack_halo(int hx, int hy, int hz) {
-  return hx | (hy << 8) | (hz << 16);
+// A staging-map entry's second word: the particle's LDS slot in the upper 16
+// bits, its halo cell below (8 bits per axis in 2D, 5 in 3D; the layout
+// bounds the halo extents accordingly).
+template <int D>
+__device__ __forceinline__ int pack_map(int hx, int hy, int hz, int slot) {
+  if constexpr (D == 2) return hx | (hy << 8) | (slot << 16);
+  else return hx | (hy << 5) | (hz << 10) | (slot << 16);
+}
+template <int D>
+__device__ __forceinline__ void unpack_map(int w, int& hx, int& hy, int& hz, int& slot) {
+  slot = (int)((unsigned)w >> 16);
+  if constexpr (D == 2) {
+    hx = w & 255;
+    hy = (w >> 8) & 255;
+    hz = 0;
+  } else {
+    hx = w & 31;
+    hy = (w >> 5) & 31;
+    hz = (w >> 10) & 31;
+  }
 }
 
 // Stage halo particles [cb, ce) (LDS order) as fixed-point coordinates, and
 // their adjoint velocities when `lam` is given.  A slot's halo cell comes from
 // the slot table of brick_setup (one chunk), else from a search of the halo
-// starts.  For the pair lists, `smap` receives every staged particle's
-// {index, packed halo cell} in LDS order: the force kernel's staging map.
+// starts.
 template <int D, int NT, class Lds>
 __device__ __forceinline__ void brick_stage(const BrickGeom& G, const Phys& P,
                                             const float* __restrict__ pos, const float* __restrict__ lam,
-                                            Lds& L, int cb, int ce, int2* __restrict__ smap = nullptr) {
+                                            Lds& L, int cb, int ce) {
   // SU particles per thread in flight (their halo cells, then their position
   // reads)
   constexpr int SU = 4;
@@ -965,7 +982,6 @@ __device__ __forceinline__ void brick_stage(const BrickGeom& G, const Phys& P,
 #pragma unroll
           for (int k = 0; k < D; ++k) L.lam[(v - cb) * D + k] = l[k];
         }
-        if (smap) smap[v - cb] = make_int2(g[u], pack_halo(hx, hy, hz));
       }
     }
   }
@@ -1300,6 +1316,88 @@ __device__ __forceinline__ void nl_row(const Coord14<D>* __restrict__ p, int jlo
   }
 }
 
+// The force kernel's staging map of a brick: the staged halo particles that
+// some target's list may name, each as {particle, LDS slot and halo cell}, in
+// LDS order.  At the build every target lies in the brick's cells, so in 3D a
+// particle farther than the list radius from their box is in no list: it is
+// left out, and the slot it holds here stays unstaged in the force kernel (no
+// entry names it).  The test takes the list test's own 14-bit units, so it
+// keeps every particle that the list test can accept.  (In 2D a halo of one
+// cell keeps nearly all of its particles, and the map holds every slot.)
+// s_cnt holds 64 ints of scratch.  Returns the number of entries.
+template <int D, int NT, class Lds>
+__device__ __forceinline__ int nl_stage_map(const BrickGeom& G, const Phys& P, Lds& L,
+                                            int2* __restrict__ smap, int* s_cnt) {
+  constexpr int NW = NT / 64;
+  const int rounds = (G.total + NT - 1) / NT;
+  // the box of the brick's cells in 14-bit units (a target's offset may round
+  // up to the cell side, so its upper bound is inclusive)
+  const unsigned lift = 2u << P.F;
+  auto lo14 = [&](int h) { return (int)((((unsigned)h << P.F) + lift) >> P.sh16); };
+  const int bx0 = lo14(G.ns), bx1 = lo14(G.ns + G.wx);
+  const int by0 = lo14(G.ns), by1 = lo14(G.ns + G.wy);
+  const int bz0 = lo14(G.nsz), bz1 = lo14(G.nsz + G.wz);
+  const bool filter = (D == 3) && rounds * NW <= 64;  // (block-uniform)
+  auto near = [&](int v) {
+    const Coord14<D> q = L.p[v];
+    unsigned qxy;
+    if constexpr (D == 2) qxy = q;
+    else qxy = q.x;
+    const int qx = (int)(qxy & 0xffffu), qy = (int)(qxy >> 16);
+    const int dx = max(0, max(bx0 - qx, qx - bx1));
+    const int dy = max(0, max(by0 - qy, qy - by1));
+    int d2 = dx * dx + dy * dy;
+    if constexpr (D == 3) {
+      const int qz = (int)q.y;
+      const int dz = max(0, max(bz0 - qz, qz - bz1));
+      d2 += dz * dz;
+    }
+    return d2 < P.rl16;
+  };
+  auto put = [&](int v, int slot) {
+    const int h = L.scell[v];
+    int hx, hy = 0, hz = 0;
+    const int r = small_div(h, G.HX, G.rHX, hx);
+    if constexpr (D == 2) hy = r;
+    else hz = small_div(r, G.HY, G.rHY, hy);
+    smap[slot] = make_int2(L.gs[h] + (v - L.hs[h]), pack_map<D>(hx, hy, hz, v));
+  };
+  if (!filter) {
+    for (int v = (int)threadIdx.x; v < G.total; v += NT) put(v, v);
+    return G.total;
+  }
+  // slot v = k NT + thread of round k: the wave's count of kept slots per
+  // round, then each kept slot's entry from the counts before it
+  const int lane = lane_id(), w = (int)threadIdx.x >> 6;
+  unsigned long long kb = 0ull;  // kept slots of this thread, bit k for round k
+  for (int k = 0; k < rounds; ++k) {
+    const int v = k * NT + (int)threadIdx.x;
+    const bool keep = v < G.total && near(v);
+    if (keep) kb |= 1ull << k;
+    const unsigned long long m = __ballot(keep);
+    if (lane == 0) s_cnt[k * NW + w] = __popcll(m);
+  }
+  __syncthreads();
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  int base = 0;
+  for (int k = 0; k < rounds; ++k) {
+    const bool keep = (kb >> k) & 1ull;
+    const unsigned long long m = __ballot(keep);
+    int pre = 0, sum = 0;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) {
+      const int c = s_cnt[k * NW + ww];
+      sum += c;
+      if (ww < w) pre += c;
+    }
+    if (keep) put(k * NT + (int)threadIdx.x, base + pre + __popcll(m & lt));
+    base += sum;
+  }
+  // (s_cnt is reused by the caller)
+  __syncthreads();
+  return base;
+}
+
 template <int D, int NT, int GR>
 __device__ __forceinline__ void nlist_brick(const NlistArgs& a) {
   extern __shared__ __align__(16) char s_dyn_brick[];
@@ -1326,7 +1424,7 @@ __device__ __forceinline__ void nlist_brick(const NlistArgs& a) {
   if (threadIdx.x == 0) s_over = 0;
   const BrickGeom G = brick_setup<D, NT>(P, R, br, a.cell_start, L);
   const bool fits = G.total < CAP;  // one slot stays free for the padding sentinel
-  if (fits) brick_stage<D, NT>(G, P, a.pos, nullptr, L, 0, G.total, a.smap + (size_t)b * CAP);
+  if (fits) brick_stage<D, NT>(G, P, a.pos, nullptr, L, 0, G.total);
   if (b == 0) {
     // a new displacement bound starts with these lists
     for (int i = threadIdx.x; i < a.ndisp_clear * kDispSlots; i += NT)
@@ -1334,6 +1432,8 @@ __device__ __forceinline__ void nlist_brick(const NlistArgs& a) {
     for (int i = threadIdx.x; i < a.ndisp_clear; i += NT) a.stale_clear[i] = 0u;
   }
   __syncthreads();
+  // (block-uniform)
+  const int nmap = fits ? nl_stage_map<D, NT>(G, P, L, a.smap + (size_t)b * CAP, s_cnt) : 0;
   const size_t nt = (size_t)P.n_total;
   const int kmax = P.kmax;
   const int thr = P.rl16;
@@ -1434,7 +1534,7 @@ __device__ __forceinline__ void nlist_brick(const NlistArgs& a) {
       }
     }
   }
-  if (threadIdx.x == 0) a.binfo[b] = make_int4(G.total, G.ntg, (fits && !s_over) ? 1 : 0, 0);
+  if (threadIdx.x == 0) a.binfo[b] = make_int4(G.total, G.ntg, (fits && !s_over) ? 1 : 0, nmap);
 }
 
 // The list builder with 16 candidates per test step (short rows) and with 32
@@ -1538,38 +1638,39 @@ __device__ __forceinline__ void adjoint_brick(const AdjArgs& a, int b) {
   const int4 bi = a.nl ? a.binfo[b] : make_int4(0, 0, 0, 0);
   const bool stale = a.nl && a.stale && *a.stale != 0u;
   if (interact && bi.z && !stale && bi.x < CAP) {
-    // the halo staged through the builder's map (halo cells in order, the
-    // order the entries index): positions and adjoint velocities, with the
-    // first target records requested together with the map entries
+    // the halo particles the lists name, staged through the builder's map
+    // (each entry with its LDS slot): positions and adjoint velocities, with
+    // the first target records requested together with the map entries
     const int2* __restrict__ smap = a.smap + (size_t)b * a.lcap_list;
     const int2* __restrict__ trec = a.trec + (size_t)b * a.lcap_list;
-    const int total = bi.x, ntg = bi.y;
+    const int total = bi.x, ntg = bi.y, nmap = bi.w;
     const size_t nt = (size_t)P.n_total;
     const int2 r0 = trec[min((int)threadIdx.x, a.lcap_list - 1)];
-    for (int v0 = (int)threadIdx.x; v0 < total; v0 += 2 * NT) {
+    const int elast = max(nmap - 1, 0);
+    for (int v0 = (int)threadIdx.x; v0 < nmap; v0 += 2 * NT) {
       int2 e[2];
       float p[2][D], l[2][D];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) e[u] = smap[min(v0 + u * NT, total - 1)];
+      for (int u = 0; u < 2; ++u) e[u] = smap[min(v0 + u * NT, elast)];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        if (v0 + u * NT < total) {
+        if (v0 + u * NT < nmap) {
           ldv<D>(a.pos, e[u].x, p[u]);
           ldv<D>(a.lam_v_in, e[u].x, l[u]);
         }
       }
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int vv = v0 + u * NT;
-        if (vv < total) {
-          const int hx = e[u].y & 255, hy = (e[u].y >> 8) & 255;
+        if (v0 + u * NT < nmap) {
+          int hx, hy, hz, slot;
+          unpack_map<D>(e[u].y, hx, hy, hz, slot);
           if constexpr (D == 2)
-            L.p[vv] = make_int2(fixed_coord(hx, p[u][0], P), fixed_coord(hy, p[u][1], P));
+            L.p[slot] = make_int2(fixed_coord(hx, p[u][0], P), fixed_coord(hy, p[u][1], P));
           else
-            L.p[vv] = make_int4(fixed_coord(hx, p[u][0], P), fixed_coord(hy, p[u][1], P),
-                                fixed_coord((e[u].y >> 16) & 255, p[u][2], P), 0);
+            L.p[slot] = make_int4(fixed_coord(hx, p[u][0], P), fixed_coord(hy, p[u][1], P),
+                                  fixed_coord(hz, p[u][2], P), 0);
 #pragma unroll
-          for (int k = 0; k < D; ++k) L.lam[vv * D + k] = l[u][k];
+          for (int k = 0; k < D; ++k) L.lam[slot * D + k] = l[u][k];
         }
       }
     }
