@@ -103,6 +103,24 @@ def test_overfull_md_cells_rejected():
         assert native.describe(cfg(k))["md_cell_split"] in (4, 8)
 
 
+def test_brick_halo_extent_bounded_by_the_map_packing():
+    # a staging-map entry packs a halo cell in 8 bits per axis in 2D and 5 in
+    # 3D: wider halos are refused (the halo-cell count alone allows them)
+    def cfg2(bx):
+        return native.make_config(2, 80000, 100, lattice_dx=4.0, md_cell_split=1, brick=(bx, 1, 1))
+    assert native.describe(cfg2(254))["brick"] == (254, 1, 1)
+    with pytest.raises(native.MdlgError, match="halo wider than 256") as e:
+        native.describe(cfg2(255))
+    assert e.value.status == -1
+
+    def cfg3(bx):
+        return native.make_config(3, 4740, 5, lattice_dx=4.0, vmax=1, md_cell_split=1,
+                                  brick=(bx, 2, 2))
+    assert native.describe(cfg3(30))["brick"] == (30, 2, 2)
+    with pytest.raises(native.MdlgError, match="halo wider than 32"):
+        native.describe(cfg3(31))
+
+
 def test_vmax_window_limit_3d():
     cfg = native.make_config(3, 1000, 8, vmax=3)
     with pytest.raises(native.MdlgError, match="velocity window"):
