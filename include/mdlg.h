@@ -342,6 +342,17 @@ mdlg_status mdlg_set_timing(mdlg_system *sys, int enable);
  * timing was enabled (synchronises).  Both arrays are host [MDLG_K_NCLASS]. */
 mdlg_status mdlg_get_timing(mdlg_system *sys, double *total_ms, int64_t *launches);
 
+/* The constant that an event pair adds to a kernel's time, in milliseconds,
+ * measured on the handle's stream: reps launches (1..1000) of a one-wave
+ * kernel that waits about 20 microseconds on the device's constant-rate wall
+ * clock, each between its own event pair, as mdlg_set_timing records them;
+ * *offset_ms = the median of (event time - the wait).  Subtracted from the
+ * per-launch averages of mdlg_get_timing it gives each kernel's own duration.
+ * Synchronises; leaves the timing counters as they are.  MDLG_E_INVALID for a
+ * NULL argument or reps out of range, MDLG_E_DEVICE when the device reports
+ * no wall clock rate or a launch fails.  A measurement aid. */
+mdlg_status mdlg_timing_offset(mdlg_system *sys, int reps, double *offset_ms);
+
 /* Force launches since creation that walked the cells because the pair
  * lists might have been stale: the pair lists hold the pairs within
  * r_cut + 2 skin of their build, and each MD step folds the largest

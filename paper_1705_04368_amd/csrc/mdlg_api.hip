@@ -2282,6 +2282,51 @@ mdlg_status mdlg_get_timing(mdlg_system* S, double* total_ms, int64_t* launches)
   return read_err(S);
 }
 
+mdlg_status mdlg_timing_offset(mdlg_system* S, int reps, double* offset_ms) {
+  if (!S || !offset_ms || reps < 1 || reps > 1000) return MDLG_E_INVALID;
+  int dev = 0, khz = 0;
+  HIPCHK(S, hipGetDevice(&dev));
+  HIPCHK(S, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  if (khz <= 0) {
+    S->last_error = "device reports no wall clock rate";
+    return MDLG_E_DEVICE;
+  }
+  // a wait of about 20 microseconds on the device's wall clock
+  const long long ticks = std::max(1LL, (long long)std::llround(0.02 * khz));
+  const double span_ms = (double)ticks / (double)khz;
+  HIPCHK(S, hipStreamSynchronize(S->stream));
+  drain_timing(S);
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  for (int r = 0; r < reps; ++r) {
+    hipEvent_t a = pool_event(S), b = pool_event(S);
+    if (!a || !b) {
+      if (a) S->event_pool.push_back(a);
+      if (b) S->event_pool.push_back(b);
+      break;
+    }
+    ev.emplace_back(a, b);
+    launch_clock_wait(ticks, S->stream, a, b);
+  }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+  std::vector<double> d;
+  for (auto& p : ev) {
+    float ms = 0.f;
+    if (e == hipSuccess && hipEventElapsedTime(&ms, p.first, p.second) == hipSuccess)
+      d.push_back((double)ms - span_ms);
+    S->event_pool.push_back(p.first);
+    S->event_pool.push_back(p.second);
+  }
+  if (e != hipSuccess) return hip_fail(S, e, "clock wait");
+  if (d.empty()) {
+    S->last_error = "no event pair could be timed";
+    return MDLG_E_DEVICE;
+  }
+  std::sort(d.begin(), d.end());
+  *offset_ms = d[d.size() / 2];
+  return MDLG_OK;
+}
+
 mdlg_status mdlg_sync(mdlg_system* S) {
   if (!S) return MDLG_E_INVALID;
   return read_err(S);

@@ -342,6 +342,7 @@ struct LaunchEvents {
 extern thread_local LaunchEvents g_launch_events;
 
 void launch_fill_u32(unsigned* p, unsigned v, long long n, hipStream_t s);
+void launch_clock_wait(long long ticks, hipStream_t s, hipEvent_t start, hipEvent_t stop);
 size_t brick_lds_bytes(const Phys& P, int D, bool adj);
 void launch_adjoint(int D, const AdjArgs& a, hipStream_t s);
 // a reverse step and an independent force step in one launch (both on the

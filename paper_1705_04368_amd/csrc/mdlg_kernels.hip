@@ -2472,6 +2472,20 @@ thread_local LaunchEvents g_launch_events;
       MDLG_GO(kern<3>, grid, kBlock, lds, stream, args);             \
   } while (0)
 
+// A single wave that waits until the device's constant-rate wall clock has
+// advanced by `ticks` (the clock always advances, so the wait ends).  A kernel
+// of known length: event pairs recorded around it read that length plus the
+// constant the events themselves add.
+__global__ void k_clock_wait(long long ticks) {
+  const long long t0 = wall_clock64();
+  while (wall_clock64() - t0 < ticks) {
+  }
+}
+
+void launch_clock_wait(long long ticks, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
+  hipExtLaunchKernelGGL(k_clock_wait, dim3(1), dim3(64), 0u, s, start, stop, 0u, ticks);
+}
+
 void launch_fill_u32(unsigned* p, unsigned v, long long n, hipStream_t s) {
   if (n <= 0) return;
   long long blocks = (n + kBlock - 1) / kBlock;

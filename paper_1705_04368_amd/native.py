@@ -24,7 +24,7 @@ EXPORTED = ["mdlg_describe", "mdlg_workspace_bytes", "mdlg_create", "mdlg_step",
             "mdlg_set_timing", "mdlg_get_timing", "mdlg_sync", "mdlg_last_error", "mdlg_destroy",
             "mdlg_autotune", "mdlg_autotune_workspace_bytes", "mdlg_get_xi", "mdlg_get_shifts",
             "mdlg_checkpoint_bytes", "mdlg_checkpoint_save", "mdlg_checkpoint_load",
-            "mdlg_create_static", "mdlg_get_list_fallbacks"]
+            "mdlg_create_static", "mdlg_get_list_fallbacks", "mdlg_timing_offset"]
 LOSSES = {"msd": 0, "mean_x": 1}
 KERNEL_CLASSES = ["force", "count", "scan", "scatter", "bin", "nlist", "xi", "shift", "adjoint",
                   "adjoint_force"]
@@ -112,6 +112,8 @@ def load():
     lib.mdlg_set_timing.argtypes = [C.c_void_p, C.c_int]
     lib.mdlg_get_timing.restype = st
     lib.mdlg_get_timing.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.mdlg_timing_offset.restype = st
+    lib.mdlg_timing_offset.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
     lib.mdlg_get_list_fallbacks.restype = st
     lib.mdlg_get_list_fallbacks.argtypes = [C.c_void_p, C.c_void_p]
     lib.mdlg_sync.restype = st
@@ -374,6 +376,12 @@ class System:
         _check(load().mdlg_get_timing(self.handle, ms.ctypes.data_as(C.c_void_p),
                                       n.ctypes.data_as(C.c_void_p)), self.handle)
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def timing_offset(self, reps=50):
+        """Milliseconds an event pair adds to a kernel's time (mdlg_timing_offset)."""
+        v = C.c_double(0.0)
+        _check(load().mdlg_timing_offset(self.handle, int(reps), C.byref(v)), self.handle)
+        return float(v.value)
 
     def list_fallbacks(self):
         """Force launches that walked the cells for possibly stale pair lists."""

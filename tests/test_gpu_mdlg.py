@@ -107,3 +107,23 @@ def test_mass_and_momentum_identities_on_lj_run(equilibrated):
     kin = sysg.kinetics()
     assert np.abs(kin[0, :DIM]).max() < 1e-2
     assert abs(2 * kin[0, DIM] / (DIM * (N - 1)) - KT) < 0.2
+
+
+def test_event_timing_offset(equilibrated):
+    """mdlg_timing_offset: the constant an event pair adds, from a kernel that
+    waits a known span of the device's wall clock.  Non-negative (the wait is
+    never shorter than its span), a few microseconds, repeatable; per-launch
+    timing of a lattice step is not disturbed by it."""
+    pos, vel = equilibrated
+    sysg = make_system(_cfg(), pos, vel)
+    sysg.set_timing(True)
+    sysg.coarse_grain(2)
+    tim = sysg.get_timing()
+    say("event offset: two measurements")
+    o1 = sysg.timing_offset(50)
+    o2 = sysg.timing_offset(50)
+    assert sysg.get_timing() == tim
+    sysg.set_timing(False)
+    assert 0.0 <= o1 < 0.05 and 0.0 <= o2 < 0.05
+    assert abs(o1 - o2) < 0.01
+    assert tim["force"][1] == 40 and tim["force"][0] / 40 > o1
