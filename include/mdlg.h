@@ -353,6 +353,16 @@ mdlg_status mdlg_get_timing(mdlg_system *sys, double *total_ms, int64_t *launche
  * no wall clock rate or a launch fails.  A measurement aid. */
 mdlg_status mdlg_timing_offset(mdlg_system *sys, int reps, double *offset_ms);
 
+/* Enqueue on the handle's stream a one-wave kernel that waits the given time
+ * (0..1e6 microseconds) on the device's wall clock.  The host meanwhile
+ * enqueues the launches that follow, so that an event-timed pass after it runs
+ * its kernels back to back rather than at the host's launch rate (event pairs
+ * around kernels shorter than a launch would otherwise take in the gaps).
+ * Asynchronous.  MDLG_E_INVALID for a time out of range, MDLG_E_DEVICE when
+ * the device reports no wall clock rate or the launch fails.  A measurement
+ * aid. */
+mdlg_status mdlg_timing_head_start(mdlg_system *sys, double microseconds);
+
 /* Force launches since creation that walked the cells because the pair
  * lists might have been stale: the pair lists hold the pairs within
  * r_cut + 2 skin of their build, and each MD step folds the largest

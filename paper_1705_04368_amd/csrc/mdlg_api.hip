@@ -2327,6 +2327,19 @@ mdlg_status mdlg_timing_offset(mdlg_system* S, int reps, double* offset_ms) {
   return MDLG_OK;
 }
 
+mdlg_status mdlg_timing_head_start(mdlg_system* S, double microseconds) {
+  if (!S || !(microseconds >= 0.0) || microseconds > 1e6) return MDLG_E_INVALID;
+  int dev = 0, khz = 0;
+  HIPCHK(S, hipGetDevice(&dev));
+  HIPCHK(S, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  if (khz <= 0) {
+    S->last_error = "device reports no wall clock rate";
+    return MDLG_E_DEVICE;
+  }
+  launch_clock_wait((long long)std::llround(microseconds * 1e-3 * khz), S->stream, nullptr, nullptr);
+  return check_launch(S, "clock wait");
+}
+
 mdlg_status mdlg_sync(mdlg_system* S) {
   if (!S) return MDLG_E_INVALID;
   return read_err(S);

@@ -24,7 +24,8 @@ EXPORTED = ["mdlg_describe", "mdlg_workspace_bytes", "mdlg_create", "mdlg_step",
             "mdlg_set_timing", "mdlg_get_timing", "mdlg_sync", "mdlg_last_error", "mdlg_destroy",
             "mdlg_autotune", "mdlg_autotune_workspace_bytes", "mdlg_get_xi", "mdlg_get_shifts",
             "mdlg_checkpoint_bytes", "mdlg_checkpoint_save", "mdlg_checkpoint_load",
-            "mdlg_create_static", "mdlg_get_list_fallbacks", "mdlg_timing_offset"]
+            "mdlg_create_static", "mdlg_get_list_fallbacks", "mdlg_timing_offset",
+            "mdlg_timing_head_start"]
 LOSSES = {"msd": 0, "mean_x": 1}
 KERNEL_CLASSES = ["force", "count", "scan", "scatter", "bin", "nlist", "xi", "shift", "adjoint",
                   "adjoint_force"]
@@ -114,6 +115,8 @@ def load():
     lib.mdlg_get_timing.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
     lib.mdlg_timing_offset.restype = st
     lib.mdlg_timing_offset.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
+    lib.mdlg_timing_head_start.restype = st
+    lib.mdlg_timing_head_start.argtypes = [C.c_void_p, C.c_double]
     lib.mdlg_get_list_fallbacks.restype = st
     lib.mdlg_get_list_fallbacks.argtypes = [C.c_void_p, C.c_void_p]
     lib.mdlg_sync.restype = st
@@ -382,6 +385,11 @@ class System:
         v = C.c_double(0.0)
         _check(load().mdlg_timing_offset(self.handle, int(reps), C.byref(v)), self.handle)
         return float(v.value)
+
+    def timing_head_start(self, microseconds):
+        """Enqueue a device-side wait so that the launches after it run back to
+        back (mdlg_timing_head_start)."""
+        _check(load().mdlg_timing_head_start(self.handle, float(microseconds)), self.handle)
 
     def list_fallbacks(self):
         """Force launches that walked the cells for possibly stale pair lists."""

@@ -17,6 +17,7 @@ from scipy.stats import norm
 
 import oracle
 import synth
+from paper_1705_04368_amd.native import MdlgError
 from tests.gpu_util import make_system, say
 
 pytestmark = pytest.mark.gpu
@@ -117,8 +118,13 @@ def test_event_timing_offset(equilibrated):
     pos, vel = equilibrated
     sysg = make_system(_cfg(), pos, vel)
     sysg.set_timing(True)
+    # the launches of the pass are enqueued while the device waits 2 ms
+    sysg.timing_head_start(2000)
     sysg.coarse_grain(2)
     tim = sysg.get_timing()
+    for bad in (-1.0, 2e6):
+        with pytest.raises(MdlgError):
+            sysg.timing_head_start(bad)
     say("event offset: two measurements")
     o1 = sysg.timing_offset(50)
     o2 = sysg.timing_offset(50)
