@@ -361,8 +361,9 @@ __device__ __forceinline__ int arrival_field(int dir) {
 // the particles of the chunk's first old cell that precede the chunk.  With
 // `first` (input in arbitrary order) slots come from global atomics and the
 // ranks are skipped: k_cellsort orders the cells afterwards.
+// (eight waves per SIMD: the 2D instance otherwise takes 76 VGPRs and six)
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_count(SortArgs a) {
+__global__ __attribute__((amdgpu_flat_work_group_size(1, kBlock), amdgpu_waves_per_eu(8))) void k_count(SortArgs a) {
   constexpr int kHist = 2048;
   constexpr int kPer = kCountChunkMax / kBlock;
   // scan-tile totals of the block: the window's tiles and those a particle
@@ -1789,8 +1790,11 @@ __device__ __forceinline__ void adjoint_brick(const AdjArgs& a, int b) {
 
 // One block per brick: the force kernel (a force / velocity-Verlet step of
 // every particle) and the adjoint's reverse step.
+// (at most 96 SGPRs: with the 106 it takes otherwise, the SGPR file holds
+// seven waves per SIMD where the 2D instance's 63 VGPRs allow eight; the
+// excess is kept in VGPR lanes, not in scratch)
 template <int D, int NT>
-__global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_num_sgpr(96))) void k_force(ForceArgs a) {
   constexpr int boff = 0;
 #include "mdlg_force_block.inc"
 }
