@@ -341,6 +341,31 @@ def test_unstable_step_is_reported():
     assert e.value.status == -4
 
 
+def test_force_launches_stop_after_an_error():
+    """Once the device error word is set (every error is fatal), force launches
+    do nothing: the fast particle keeps the lists stale, so each launch that
+    still ran would walk the cells and count a fallback; none is counted after
+    the error."""
+    import ctypes as C
+
+    from paper_1705_04368_amd.native import load
+    cfg, pos, vel, box, n, M = _force_case(2, 9, 1)
+    cfg.sort_every = 10
+    vel = vel.copy()
+    vel[0] = [400.0, 0.0]  # past the speed cap at once, past the reach within a step or two
+    say("force launches after an error")
+    sysg = make_system(cfg, pos, vel)
+    assert sysg.layout["pair_slots"] > 0
+    sysg.step(3)
+    lib = load()
+    f1, f2 = C.c_int64(-1), C.c_int64(-1)
+    assert lib.mdlg_get_list_fallbacks(sysg.handle, C.byref(f1)) == -4
+    sysg.step(50)
+    assert lib.mdlg_get_list_fallbacks(sysg.handle, C.byref(f2)) == -4
+    assert 0 <= f1.value <= 3
+    assert f2.value == f1.value
+
+
 def test_empty_lattice_steps_and_single_particle():
     from paper_1705_04368_amd import make_config
     say("single particle")
