@@ -131,6 +131,32 @@ def test_kernel_table_grades_forces_on_fp32_and_sort_on_hbm():
     assert 1.0 < ai < ridge
 
 
+def test_event_pair_offset_is_removed_from_the_averages():
+    # mdlg_timing_offset reads the clock wait's excess over its span; the
+    # 0.6 us of the wait's own dispatch stays in every kernel's duration
+    class FakeSystem:
+        def __init__(self, ms):
+            self.ms = ms
+
+        def timing_offset(self):
+            return self.ms
+
+    assert bench.event_pair_offset(FakeSystem(0.0046)) == pytest.approx(0.004)
+    assert bench.event_pair_offset(FakeSystem(0.0003)) == 0.0
+    lay = {"n_velocities": 49, "n_moments": 7, "margin": 0.4, "skin": 0.25, "pair_slots": 48,
+           "n_cells": 100}
+    # 10 launches of 0.2 ms by their events, 2 of 0.003 ms
+    tim = {"force": (2.0, 10), "scan": (0.006, 2)}
+    k, _ = bench.kernel_table(tim, 2, 800, 0.5, lay, 100, offset_ms=0.004)
+    assert k["force"]["event_ms"] == pytest.approx(0.2)
+    assert k["force"]["avg_ms"] == pytest.approx(0.196)
+    # graded on the corrected time
+    assert k["force"]["achieved"] == pytest.approx(k["force"]["work_per_launch"] / 0.196e-3 / 1e12)
+    # an average at or below the offset is left as measured
+    assert k["scan"]["avg_ms"] == pytest.approx(0.003)
+    assert k["scan"]["achieved"] > 0.0
+
+
 def test_ensemble_statistics():
     import numpy as np
     rng = np.random.default_rng(3)
