@@ -34,6 +34,9 @@
 //   k_fsum / k_ffinal / k_site_avg   f_i^eq readout (eq. fieq)
 //   k_kin      FP64 momentum / kinetic energy per replica, thermostat factor
 //   k_export / k_import              state in id order
+//   k_clock_wait                     a wait of known length on the device's
+//              wall clock (timing aid: the event pairs' own excess, and a
+//              head start for an event-timed pass)
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
