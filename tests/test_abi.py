@@ -156,4 +156,9 @@ def test_null_handle_calls_are_invalid():
     assert lib.mdlg_step(None, 1) == -1
     assert lib.mdlg_coarse_grain(None, 1) == -1
     assert lib.mdlg_sync(None) == -1
+    v = C.c_double(0.0)
+    assert lib.mdlg_timing_offset(None, 10, C.byref(v)) == -1
+    assert lib.mdlg_timing_head_start(None, 10.0) == -1
+    n = C.c_int64(0)
+    assert lib.mdlg_get_list_fallbacks(None, C.byref(n)) == -1
     lib.mdlg_destroy(None)
