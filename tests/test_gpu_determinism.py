@@ -120,18 +120,24 @@ def test_long_lattice_steps_graph_blocks_with_forces():
     _assert_same(a, b)
 
 
-def test_batched_equals_separate_with_forces():
-    sizes, lats = (968, 2048, 1568), (11, 16, 14)
-    say("batched vs separate replicas, forces on")
-    pos, vel = _state(2, sizes, lats, seed=421)
-    kw = dict(md_cell_split=1, sort_every=10, brick=(8, 2, 1), block_threads=128)
-    both = _run(_cfg(2, sizes, lats, **kw), pos, vel)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_batched_equals_separate_with_forces(dim):
+    if dim == 2:
+        sizes, lats = (968, 2048, 1568), (11, 16, 14)
+        kw = dict(md_cell_split=1, sort_every=10, brick=(8, 2, 1), block_threads=128)
+    else:
+        # rho = 0.593 on lattices of 4, 5 and 6 cells of 4 sigma (partial bricks)
+        sizes, lats = (2429, 4744, 8198), (4, 5, 6)
+        kw = dict(md_cell_split=2, sort_every=10, brick=(4, 3, 3), block_threads=256)
+    say(f"batched vs separate replicas, forces on, {dim}D")
+    pos, vel = _state(dim, sizes, lats, seed=421)
+    both = _run(_cfg(dim, sizes, lats, **kw), pos, vel)
     fb, sb, kb = both.get_f(per_site=True), both.get_state(), both.kinetics()
     p0, s0 = 0, 0
     for r, (n, m) in enumerate(zip(sizes, lats)):
-        one = _run(_cfg(2, (n,), (m,), **kw), pos[p0:p0 + n], vel[p0:p0 + n])
+        one = _run(_cfg(dim, (n,), (m,), **kw), pos[p0:p0 + n], vel[p0:p0 + n])
         f1, s1 = one.get_f(per_site=True), one.get_state()
-        ns = m * m
+        ns = m ** dim
         np.testing.assert_array_equal(fb["f_site"][s0:s0 + ns], f1["f_site"])
         np.testing.assert_array_equal(fb["mom_site"][s0:s0 + ns], f1["mom_site"])
         for key in STATE_KEYS:

@@ -277,16 +277,22 @@ def test_batched_replicas_equal_separate_runs():
         off_part += n
 
 
-def test_batched_replica_forces_match_oracle():
+@pytest.mark.parametrize("dim", [2, 3])
+def test_batched_replica_forces_match_oracle(dim):
     from paper_1705_04368_amd import make_config
-    sizes, lats = [968, 2048, 1250], [11, 16, 10]
+    if dim == 2:
+        sizes, lats, kT = [968, 2048, 1250], [11, 16, 10], 1.0
+    else:
+        # rho = 0.593 on lattices of 4, 5 and 6 cells of 4 sigma
+        sizes, lats, kT = [2429, 4744, 8198], [4, 5, 6], 1.5
     pos_all, vel_all = [], []
     for r, (n, m) in enumerate(zip(sizes, lats)):
-        p, v = synth.lj_initial_state(2, n, 4.0 * m, 1.0, seed=300 + r)
+        p, v = synth.lj_initial_state(dim, n, 4.0 * m, kT, seed=300 + r)
         pos_all.append(p)
         vel_all.append(v)
-    say("replica forces")
-    cfg = make_config(2, sizes, [[m, m] for m in lats], lattice_dx=4.0, dt=0.005, vmax=3, kT=1.0)
+    say(f"replica forces, {dim}D")
+    cfg = make_config(dim, sizes, [[m] * dim for m in lats], lattice_dx=4.0,
+                      dt=0.005 if dim == 2 else 0.004, vmax=3 if dim == 2 else 2, kT=kT)
     sysg = make_system(cfg, np.concatenate(pos_all), np.concatenate(vel_all))
     st = sysg.get_state()
     s = sysg.layout["cell_side"]
@@ -297,7 +303,7 @@ def test_batched_replica_forces_match_oracle():
         sub = {key: val[sl] for key, val in st.items()}
         xw = wrapped(sub, s, m * k)
         np.testing.assert_array_equal(xw, pos_all[r].astype(np.float64))
-        acc, _ = oracle.forces(oracle.make_md(2, n, 4.0 * m), xw)
+        acc, _ = oracle.forces(oracle.make_md(dim, n, 4.0 * m), xw)
         assert force_error(sub["acc"], acc).max() <= 1e-5
         off += n
 
