@@ -88,3 +88,49 @@ def test_xi_chain_restarts_after_md_steps():
     assert sysg.get_xi()["n_steps"] == 3
     sysg.reset_accumulators()
     assert sysg.get_xi()["n_steps"] == 0
+
+
+def test_xi_batched_replicas():
+    """Two replicas of different lattices in one batch: each replica's Xi
+    wraps on its own lattice (x + v_i taken modulo that replica's sites);
+    the per-site fields are the replicas' fields one after the other and the
+    moments their sums."""
+    from paper_1705_04368_amd import make_config
+    say("xi batched replicas")
+    sizes, lats, dx = (968, 2048), (11, 16), 4.0
+    ps, vs = [], []
+    for r, (n, m) in enumerate(zip(sizes, lats)):
+        p, v = synth.lj_initial_state(2, n, m * dx, 1.0, seed=61 + r)
+        ps.append(p)
+        vs.append(v)
+    cfg = make_config(2, list(sizes), [[m, m] for m in lats], lattice_dx=dx, dt=0.005,
+                      md_steps_per_lattice_step=40, vmax=3, kT=1.0, collision_stats=True)
+    sysg = make_system(cfg, np.concatenate(ps), np.concatenate(vs))
+    s = sysg.layout["cell_side"]
+    Q = sysg.layout["n_velocities"]
+    lat = [oracle.make_lattice(2, (m, m), dx, 3) for m in lats]
+    poff = np.concatenate([[0], np.cumsum(sizes)])
+    prev = unwrapped(sysg.get_state(), s)
+    n_prev = None
+    ref_sum = np.zeros((5, Q), np.int64)
+    ref_site = np.zeros((sum(m * m for m in lats), Q), np.int64)
+    for t in range(1, 5):
+        sysg.coarse_grain(1)
+        now = unwrapped(sysg.get_state(), s)
+        n_now = [oracle.bin_step(lat[r], 2, prev[poff[r]:poff[r + 1]],
+                                 now[poff[r]:poff[r + 1]])["A"].astype(np.int64)
+                 for r in range(len(sizes))]
+        out = sysg.get_xi(per_site=True, last=True)
+        if n_prev is not None:
+            xi = [oracle.collision_operator(lat[r], 2, n_prev[r], n_now[r]) for r in range(len(sizes))]
+            np.testing.assert_array_equal(out["xi_last"], np.concatenate(xi))
+            ref_site += np.concatenate(xi)
+            for r in range(len(sizes)):
+                ref_sum += np.stack([xi[r].sum(0), (xi[r] * xi[r]).sum(0), (xi[r] * n_prev[r]).sum(0),
+                                     n_prev[r].sum(0), (n_prev[r] * n_prev[r]).sum(0)])
+        np.testing.assert_array_equal(np.stack([out[k] for k in ("xi", "xi2", "xi_n", "n", "n2")]),
+                                      ref_sum)
+        np.testing.assert_array_equal(out["xi_site"], ref_site)
+        assert out["n_steps"] == t - 1
+        prev, n_prev = now, n_now
+    assert np.abs(ref_sum[0]).sum() > 0
