@@ -55,6 +55,45 @@ def test_shifted_lattices_match_oracle(dim, M, V, steps):
     assert int(out["counts"][0, -1]) == f["n_overflow"]
 
 
+def test_shifted_lattices_batched_replicas():
+    """A batch of two replicas on lattices of different sizes: every extra
+    lattice bins each replica on that replica's own lattice; the counts and
+    moments are the sums over the replicas."""
+    from paper_1705_04368_amd import make_config
+    say("shifted lattices, batched replicas")
+    sizes, lats, dx, V, steps = (968, 2048), (11, 16), 4.0, 3, 4
+    shifts = np.array(SHIFTS_2D)
+    ps, vs = [], []
+    for r, (n, m) in enumerate(zip(sizes, lats)):
+        p, v = synth.lj_initial_state(2, n, m * dx, 1.0, seed=71 + r)
+        ps.append(p)
+        vs.append(v)
+    cfg = make_config(2, list(sizes), [[m, m] for m in lats], lattice_dx=dx, dt=0.005,
+                      md_steps_per_lattice_step=40, vmax=V, kT=1.0, shifts=shifts)
+    sysg = make_system(cfg, np.concatenate(ps), np.concatenate(vs))
+    s = sysg.layout["cell_side"]
+    lat = [oracle.make_lattice(2, (m, m), dx, V) for m in lats]
+    poff = np.concatenate([[0], np.cumsum(sizes)])
+    prev = unwrapped(sysg.get_state(), s)
+    ref_c = np.zeros((len(shifts), sysg.Q + 1), np.int64)
+    ref_m = np.zeros((len(shifts), 5), np.int64)
+    for k in range(1, steps + 1):
+        sysg.coarse_grain(1)
+        now = unwrapped(sysg.get_state(), s)
+        for r in range(len(sizes)):
+            sl = slice(poff[r], poff[r + 1])
+            for j, (a, b) in enumerate(shifts):
+                c, m = oracle.bin_shifted(lat[r], 2, prev[sl], now[sl], a, b, k)
+                ref_c[j] += c
+                ref_m[j] += m
+        out = sysg.get_shifts()
+        np.testing.assert_array_equal(out["counts"].astype(np.int64), ref_c)
+        np.testing.assert_array_equal(out["moments"], ref_m)
+        prev = now
+    f = sysg.get_f()
+    np.testing.assert_array_equal(out["counts"][0, :-1], f["counts"])
+
+
 def test_shift_counter_restarts_with_the_accumulators():
     from paper_1705_04368_amd import make_config
     say("shift reset")
