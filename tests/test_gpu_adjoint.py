@@ -223,3 +223,51 @@ def test_adjoint_graph_replay_equals_eager():
         np.testing.assert_array_equal(a[3], b[3])
     for key in ("ucell", "off", "vel"):
         np.testing.assert_array_equal(outs[True][3][key], outs[False][3][key])
+
+
+def test_adjoint_batched_replicas():
+    """Two replicas in one batch: the loss runs over all N = N_1 + N_2
+    particles, so the loss and its eps and sigma gradients are the particle-
+    weighted means of the replicas' own, and dL/dv0 of a replica's particles
+    is N_r / N times that replica's own (each replica against the oracle
+    adjoint of that replica alone)."""
+    from paper_1705_04368_amd import make_config
+    sizes, lats, dx = (968, 2048), (11, 16), 4.0
+    parts = []
+    for r, (n, m) in enumerate(zip(sizes, lats)):
+        box = m * dx
+        pos, vel = synth.lj_initial_state(2, n, box, 1.0, seed=90 + r)
+        st = oracle.OracleState(oracle.make_md(2, n, box, dt=H), pos, vel)
+        st.run(200, thermo_every=10, kT=1.0)
+        p = st.x.astype(np.float32)
+        p = np.where(p >= np.float32(box), np.float32(0.0), p)
+        parts.append((p, st.v.astype(np.float32), oracle.make_md(2, n, box, dt=H)))
+    say("adjoint of a batch of two replicas")
+    cfg = make_config(2, list(sizes), [[m, m] for m in lats], lattice_dx=dx, dt=H, vmax=3, kT=1.0,
+                      adjoint_window=W, adjoint_every=K)
+    N = sum(sizes)
+    for loss in ("msd", "mean_x"):
+        # (a window leaves its system at the window's end: a fresh one each)
+        sysg = make_system(cfg, np.concatenate([p for p, _, _ in parts]),
+                           np.concatenate([v for _, v, _ in parts]))
+        L, ge, gs, gv = sysg.adjoint(W, K, loss)
+        gv = gv.cpu().numpy().astype(np.float64)
+        refs = [oracle.adjoint(md, p.astype(np.float64), v.astype(np.float64), W, loss)
+                for p, v, md in parts]
+        wts = [n / N for n in sizes]
+        ref_L = sum(w * r["L"] for w, r in zip(wts, refs))
+        ref_e = sum(w * r["eps"] for w, r in zip(wts, refs))
+        ref_s = sum(w * r["sigma"] for w, r in zip(wts, refs))
+        ref_v = np.concatenate([w * r["v0"] for w, r in zip(wts, refs)])
+        say(f"  {loss}: L {L:.8g} / {ref_L:.8g}  eps {ge:.6g} / {ref_e:.6g}  "
+            f"sigma {gs:.6g} / {ref_s:.6g}")
+        assert np.abs(gv - ref_v).max() <= 1e-3 * np.abs(ref_v).max()
+        if loss == "msd":
+            assert L == pytest.approx(ref_L, rel=1e-3)
+            assert ge == pytest.approx(ref_e, rel=1e-3)
+            assert gs == pytest.approx(ref_s, rel=1e-3)
+        else:
+            # momentum conservation: the mean x displacement does not depend
+            # on eps and sigma; the loss against the oracle's
+            assert L == pytest.approx(ref_L, rel=1e-3, abs=1e-6)
+            assert abs(ge) <= 1e-6 and abs(gs) <= 1e-6
