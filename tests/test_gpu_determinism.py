@@ -147,12 +147,17 @@ def test_batched_equals_separate_with_forces(dim):
         s0 += ns
 
 
-@pytest.mark.parametrize("dim,extra_steps", [(2, 0), (2, 7), (3, 0)])
-def test_checkpoint_resume_bitwise(dim, extra_steps):
+@pytest.mark.parametrize("dim,extra_steps,batch", [(2, 0, False), (2, 7, False), (3, 0, False),
+                                                   (2, 7, True)])
+def test_checkpoint_resume_bitwise(dim, extra_steps, batch):
     # extra_steps: plain MD steps before the checkpoint, so that it is taken
-    # between cell-list rebuilds (the pair lists travel in the blob)
-    n, lat = ((2048,), (16,)) if dim == 2 else ((4740,), (5,))
-    say(f"checkpoint dim={dim} extra_steps={extra_steps}")
+    # between cell-list rebuilds (the pair lists travel in the blob); batch:
+    # three replicas of different lattices in one handle
+    if batch:
+        n, lat = (968, 2048, 1568), (11, 16, 14)
+    else:
+        n, lat = ((2048,), (16,)) if dim == 2 else ((4740,), (5,))
+    say(f"checkpoint dim={dim} extra_steps={extra_steps} replicas={len(n)}")
     sh = np.zeros((1, 2, dim))
     sh[0, 1, 0] = 0.25
     cfg = _cfg(dim, n, lat, xi=True, shifts=sh)
