@@ -839,6 +839,12 @@ def main():
     kd = kernels[dom]
     roofline = {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
                 "unit": kd["unit"], "frac": kd["frac"], "traffic": load_traffic(args.workload, dom)}
+    if roofline["traffic"] is not None:
+        # the counted HBM bytes per launch over the launch's time, beside the
+        # graded bound
+        gbs = roofline["traffic"] / (kd["avg_ms"] * 1e-3) / 1e9
+        roofline["traffic_GBs"] = gbs
+        roofline["traffic_frac_of_hbm"] = gbs / PEAK_HBM_GBS
 
     plain = None
     fi = None
